@@ -1,0 +1,548 @@
+/*
+ * bsde_oracle.c -- plain, serial, FP64 CPU oracle for the fully discrete
+ * multistep scheme for BSDEs of Kapllani & Teng, "Multistep schemes for
+ * solving backward stochastic differential equations on GPU"
+ * (arXiv:1909.13560).
+ *
+ * TEST INFRASTRUCTURE ONLY.  The test suite, the smoke check and the
+ * benchmark's CPU-baseline leg are the only callers.  The GPU library never
+ * links, loads or calls this file, and this file includes nothing of it.
+ *
+ * What it follows, step by step and in the paper's order:
+ *   - Section 3.1 step 1: uniform time grid t_n = n*dt, dt = T/N; uniform
+ *     truncated space grid x_i = x_min + i*dx.
+ *   - Section 3.1 step 2: the K = max(K_y, K_z) newest layers are inputs.
+ *   - Section 3.1 step 3 and Section 2.2 eq (20): backward loop
+ *     n = N-K, ..., 0; the z equation is explicit, the y equation is implicit
+ *     and solved by Picard iteration.
+ *   - Section 2.2 eq (21): conditional expectations by Gauss-Hermite
+ *     quadrature, E[phi](x) ~ pi^(-d/2) sum_L w_L phi(x + sqrt(2 j dt) a_L),
+ *     tensor product for d = 2.
+ *   - Section 3.2: nodes outside the truncated domain take the boundary
+ *     values; the interval that holds a node is found in O(1) as
+ *     floor((X - x_min)/dx) on the uniform grid.
+ *   - Table 1 (gamma^{K_y}_{K_y,j}) and Table 2 (gamma^1_{K_z,j}).
+ *
+ * Readings where the paper is silent or ambiguous:
+ *   - the spatial interpolant is the natural cubic spline, written in
+ *     second-derivative form (d = 2: the tensor-product natural spline);
+ *   - the forward process is X_{t+h} = X_t + drift*h + vol*(W_{t+h} - W_t)
+ *     with constant drift and vol (X = W is drift 0, vol 1; the log-price of
+ *     eq (33) is drift mu - sigma^2/2, vol sigma); the z equation uses the
+ *     Brownian increment dW, as in eq (12)-(13);
+ *   - the driver is evaluated as f(t_{n+j}, X_node, y_hat, z_hat) inside the
+ *     expectations and as f(t_n, x_i, y, z^n_i) in the implicit term;
+ *   - Picard starts from y^{n+1}_i and stops after picard_max iterations, or
+ *     earlier when |y_new - y| <= picard_tol * max(1, |y_new|) if tol > 0.
+ *
+ * Built with -O2 -ffp-contract=off and no fast-math.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "bsde_oracle.h"
+
+/* ------------------------------------------------------------------------- */
+/* Table 1: gamma^{K_y}_{K_y,j}, j = 0..K_y, for K_y = 1..6 (numerator,      */
+/* denominator), as printed in the paper.                                     */
+/* ------------------------------------------------------------------------- */
+static const int TAB1[6][7][2] = {
+    {{1, 2}, {1, 2}},
+    {{1, 6}, {2, 3}, {1, 6}},
+    {{1, 8}, {3, 8}, {3, 8}, {1, 8}},
+    {{1, 12}, {1, 3}, {1, 6}, {1, 3}, {1, 12}},
+    {{41, 600}, {19, 75}, {107, 600}, {107, 600}, {19, 75}, {41, 600}},
+    {{19, 336}, {3, 14}, {15, 112}, {4, 21}, {15, 112}, {3, 14}, {19, 336}},
+};
+
+/* Table 2: gamma^1_{K_z,j}, j = 0..K_z, for K_z = 1..6, as printed. */
+static const int TAB2[6][7][2] = {
+    {{1, 2}, {1, 2}},
+    {{5, 12}, {2, 3}, {-1, 12}},
+    {{3, 8}, {19, 24}, {-5, 24}, {1, 24}},
+    {{35, 96}, {5, 6}, {-13, 48}, {1, 12}, {-1, 96}},
+    {{131, 360}, {151, 180}, {-103, 360}, {37, 360}, {-1, 45}, {1, 360}},
+    {{163, 448}, {47, 56}, {-129, 448}, {3, 28}, {-37, 1344}, {1, 168}, {-1, 1344}},
+};
+
+int oracle_gamma(int table, int K, double *g)
+{
+    if (K < 1 || K > 6 || (table != 1 && table != 2)) return ORACLE_EINVAL;
+    for (int j = 0; j <= K; ++j) {
+        const int *q = table == 1 ? TAB1[K - 1][j] : TAB2[K - 1][j];
+        g[j] = (double)q[0] / (double)q[1];
+    }
+    return ORACLE_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Gauss-Hermite rule for the weight exp(-x^2) (eq (21)).                     */
+/*                                                                            */
+/* Roots: the zeros of the degree-L orthonormal Hermite polynomial p_L,      */
+/* bracketed by a sign scan and refined by bisection.  Weights: the          */
+/* Christoffel numbers w_l = 1 / sum_{k<L} p_k(a_l)^2.  p_k comes from the   */
+/* orthonormal three-term recurrence                                          */
+/*   p_0 = pi^(-1/4),  p_1 = sqrt(2) x p_0,                                   */
+/*   p_{k+1} = sqrt(2/(k+1)) x p_k - sqrt(k/(k+1)) p_{k-1}.                   */
+/* ------------------------------------------------------------------------- */
+static double hermite_orthonormal(int L, double x, double *sumsq)
+{
+    double pm1 = 0.0, p = pow(M_PI, -0.25), s = 0.0;
+    for (int k = 0; k < L; ++k) {
+        s += p * p;
+        double pn = sqrt(2.0 / (k + 1)) * x * p - sqrt((double)k / (k + 1)) * pm1;
+        pm1 = p;
+        p = pn;
+    }
+    if (sumsq) *sumsq = s;
+    return p;
+}
+
+int oracle_gauss_hermite(int L, double *a, double *w)
+{
+    if (L < 1 || L > ORACLE_MAX_L) return ORACLE_EINVAL;
+    /* every zero lies inside |x| < sqrt(2L+1) */
+    double lim = sqrt(2.0 * L + 1.0) + 0.5;
+    int nscan = 200 * L + 1000, found = 0;
+    double h = 2.0 * lim / nscan;
+    double xl = -lim, fl = hermite_orthonormal(L, xl, NULL);
+    for (int s = 1; s <= nscan && found < L; ++s) {
+        double xr = -lim + s * h, fr = hermite_orthonormal(L, xr, NULL);
+        /* a value of exactly zero counts as non-negative, so an exact zero
+         * on a scan point is bracketed once */
+        if ((fl < 0.0) != (fr < 0.0)) {
+            double lo = xl, hi = xr;
+            const int neg_lo = fl < 0.0;
+            for (int it = 0; it < 200; ++it) {
+                double mid = 0.5 * (lo + hi);
+                if (mid <= lo || mid >= hi) break;
+                double fm = hermite_orthonormal(L, mid, NULL);
+                if ((fm < 0.0) == neg_lo) lo = mid;
+                else hi = mid;
+            }
+            a[found++] = 0.5 * (lo + hi);
+        }
+        xl = xr;
+        fl = fr;
+    }
+    if (found != L) return ORACLE_EINTERNAL;
+    for (int l = 0; l < L; ++l) {
+        double s;
+        hermite_orthonormal(L, a[l], &s);
+        w[l] = 1.0 / s;
+    }
+    return ORACLE_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Natural cubic spline in second-derivative form on a uniform grid.          */
+/*   M_0 = M_{N-1} = 0,                                                       */
+/*   M_{i-1} + 4 M_i + M_{i+1} = 6/dx^2 (y_{i+1} - 2 y_i + y_{i-1}),          */
+/* solved by the Thomas algorithm.  'stride' walks a strided line so the      */
+/* same routine serves both axes of a 2-D grid.                               */
+/* ------------------------------------------------------------------------- */
+static void natural_spline(int n, double dx, const double *y, long ystride,
+                           double *M, long mstride, double *work)
+{
+    for (int i = 0; i < n; ++i) M[(long)i * mstride] = 0.0;
+    if (n < 3) return;
+    int m = n - 2; /* unknowns M_1..M_{n-2} */
+    double *c = work, *r = work + m;
+    double s = 6.0 / (dx * dx);
+    for (int k = 0; k < m; ++k) {
+        int i = k + 1;
+        r[k] = s * (y[(long)(i + 1) * ystride] - 2.0 * y[(long)i * ystride] +
+                    y[(long)(i - 1) * ystride]);
+    }
+    /* forward elimination with diagonal 4, off-diagonals 1 */
+    double beta = 4.0;
+    c[0] = 1.0 / beta;
+    r[0] = r[0] / beta;
+    for (int k = 1; k < m; ++k) {
+        beta = 4.0 - c[k - 1];
+        c[k] = 1.0 / beta;
+        r[k] = (r[k] - r[k - 1]) / beta;
+    }
+    /* back substitution */
+    for (int k = m - 2; k >= 0; --k) r[k] -= c[k] * r[k + 1];
+    for (int k = 0; k < m; ++k) M[(long)(k + 1) * mstride] = r[k];
+}
+
+/* Locate X on the uniform grid (Section 3.2): returns the left index p and   */
+/* the fraction theta in [0,1]; nodes outside the domain are clamped to the   */
+/* boundary (the boundary value is then returned by the evaluation).          */
+static void locate(double X, double xmin, double dx, int n, int *p, double *theta)
+{
+    double xmax = xmin + (n - 1) * dx;
+    if (X <= xmin) { *p = 0; *theta = 0.0; return; }
+    if (X >= xmax) { *p = n - 2; *theta = 1.0; return; }
+    int q = (int)floor((X - xmin) / dx);
+    if (q > n - 2) q = n - 2;
+    if (q < 0) q = 0;
+    *p = q;
+    *theta = (X - (xmin + q * dx)) / dx;
+}
+
+/* the two cubic basis functions of the second-derivative form */
+static double basis_c(double theta, double dx)
+{
+    double u = 1.0 - theta;
+    return dx * dx / 6.0 * (u * u * u - u);
+}
+static double basis_d(double theta, double dx)
+{
+    return dx * dx / 6.0 * (theta * theta * theta - theta);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Drivers f(t, x, y, z).                                                      */
+/* ------------------------------------------------------------------------- */
+static double driver(const oracle_problem *pb, double t, double y, const double *z)
+{
+    const double *p = pb->p;
+    switch (pb->driver) {
+    case ORACLE_DRIVER_LINEAR: /* a y + b1 z1 (+ b2 z2) + c */
+        return pb->d == 1 ? p[0] * y + p[1] * z[0] + p[3]
+                          : p[0] * y + p[1] * z[0] + p[2] * z[1] + p[3];
+    case ORACLE_DRIVER_BIDASK: { /* -r y - theta z + s (R - r) min(y - z/sigma, 0) */
+        double r = p[0], R = p[1], th = p[2], sg = p[3], s = p[4];
+        double m = y - z[0] / sg;
+        if (m > 0.0) m = 0.0;
+        return -r * y - th * z[0] + s * (R - r) * m;
+    }
+    case ORACLE_DRIVER_CUBIC: /* Example 1, eq (22) */
+        return -y * y * y + 2.5 * y * y - 1.5 * y;
+    case ORACLE_DRIVER_EXP: { /* Example 2, eq (24) */
+        double et = exp(t * t), emt = exp(-t * t);
+        return 0.5 * (et - 4.0 * t * y - 3.0 * exp(t * t - y * emt) + z[0] * z[0] * emt);
+    }
+    default:
+        return NAN;
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Validation.                                                                 */
+/* ------------------------------------------------------------------------- */
+static int validate(const oracle_problem *pb)
+{
+    if (pb->d != 1 && pb->d != 2) return ORACLE_EINVAL;
+    if (pb->k_y < 1 || pb->k_y > 6 || pb->k_z < 1 || pb->k_z > 6) return ORACLE_EINVAL;
+    int K = pb->k_y > pb->k_z ? pb->k_y : pb->k_z;
+    if (pb->n_t < K || !(pb->T > 0.0)) return ORACLE_EINVAL;
+    if (pb->L < 1 || pb->L > ORACLE_MAX_L) return ORACLE_EINVAL;
+    for (int a = 0; a < pb->d; ++a)
+        if (pb->n_x[a] < 4 || !(pb->x_max[a] > pb->x_min[a])) return ORACLE_EINVAL;
+    if (pb->driver < 0 || pb->driver > ORACLE_DRIVER_EXP) return ORACLE_EINVAL;
+    if (pb->d == 2 && pb->driver != ORACLE_DRIVER_LINEAR) return ORACLE_EINVAL;
+    if (pb->picard_max < 1) return ORACLE_EINVAL;
+    if (pb->n_stop < 0 || pb->n_stop > pb->n_t - K) return ORACLE_EINVAL;
+    return ORACLE_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* 1-D solve.                                                                   */
+/* Layer storage: a ring of K+1 layers, each holding y, M_y, z, M_z.          */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    double *y, *My, *z, *Mz;
+} layer1;
+
+static int solve1(const oracle_problem *pb, const double *init_y, const double *init_z,
+                  double *y_out, double *z_out, oracle_stats *st)
+{
+    const int N = pb->n_t, Ky = pb->k_y, Kz = pb->k_z, K = Ky > Kz ? Ky : Kz;
+    const int L = pb->L, nx = pb->n_x[0];
+    const double dt = pb->T / N;
+    const double xmin = pb->x_min[0], dx = (pb->x_max[0] - pb->x_min[0]) / (nx - 1);
+    const double drift = pb->drift[0], vol = pb->vol[0][0];
+
+    double a[ORACLE_MAX_L], w[ORACLE_MAX_L], gy[7], gz[7];
+    int rc = oracle_gauss_hermite(L, a, w);
+    if (rc) return rc;
+    for (int l = 0; l < L; ++l) w[l] /= sqrt(M_PI); /* pi^(-1/2) of eq (21) */
+    oracle_gamma(1, Ky, gy);
+    oracle_gamma(2, Kz, gz);
+
+    layer1 ring[7];
+    double *mem = (double *)malloc(sizeof(double) * (size_t)nx * 4 * (K + 1));
+    double *work = (double *)malloc(sizeof(double) * (size_t)2 * nx);
+    if (!mem || !work) { free(mem); free(work); return ORACLE_ENOMEM; }
+    for (int s = 0; s <= K; ++s) {
+        ring[s].y = mem + (size_t)nx * (4 * s + 0);
+        ring[s].My = mem + (size_t)nx * (4 * s + 1);
+        ring[s].z = mem + (size_t)nx * (4 * s + 2);
+        ring[s].Mz = mem + (size_t)nx * (4 * s + 3);
+    }
+#define SLOT(n) (ring[(n) % (K + 1)])
+    /* inputs: init[r] is the layer at t_{N-K+1+r}, r = 0..K-1 */
+    for (int r = 0; r < K; ++r) {
+        int n = N - K + 1 + r;
+        memcpy(SLOT(n).y, init_y + (size_t)r * nx, sizeof(double) * nx);
+        memcpy(SLOT(n).z, init_z + (size_t)r * nx, sizeof(double) * nx);
+        natural_spline(nx, dx, SLOT(n).y, 1, SLOT(n).My, 1, work);
+        natural_spline(nx, dx, SLOT(n).z, 1, SLOT(n).Mz, 1, work);
+    }
+
+    int it_max = 0;
+    long nonconv = 0;
+    for (int n = N - K; n >= pb->n_stop; --n) {
+        layer1 out = SLOT(n);
+        const double tn = n * dt;
+        for (int i = 0; i < nx; ++i) {
+            const double xi = xmin + i * dx;
+            double Ef[7] = {0}, EfW[7] = {0}, Ez[7] = {0}, EyK = 0.0;
+            for (int j = 1; j <= K; ++j) {
+                layer1 lj = SLOT(n + j);
+                const double tj = (n + j) * dt, sq = sqrt(2.0 * j * dt);
+                for (int l = 0; l < L; ++l) {
+                    const double dW = sq * a[l];
+                    const double X = xi + drift * j * dt + vol * dW;
+                    int p;
+                    double th;
+                    double yh, zh;
+                    if (X <= xmin) { yh = lj.y[0]; zh = lj.z[0]; }
+                    else if (X >= xmin + (nx - 1) * dx) { yh = lj.y[nx - 1]; zh = lj.z[nx - 1]; }
+                    else {
+                        locate(X, xmin, dx, nx, &p, &th);
+                        double cA = 1.0 - th, cB = th, cC = basis_c(th, dx), cD = basis_d(th, dx);
+                        yh = cA * lj.y[p] + cB * lj.y[p + 1] + cC * lj.My[p] + cD * lj.My[p + 1];
+                        zh = cA * lj.z[p] + cB * lj.z[p + 1] + cC * lj.Mz[p] + cD * lj.Mz[p + 1];
+                    }
+                    const double fh = driver(pb, tj, yh, &zh);
+                    Ef[j] += w[l] * fh;
+                    EfW[j] += w[l] * fh * dW;
+                    Ez[j] += w[l] * zh;
+                    if (j == Ky) EyK += w[l] * yh;
+                }
+            }
+            /* z equation of eq (20), explicit */
+            double zs = Ez[1];
+            for (int j = 1; j <= Kz; ++j) zs += gz[j] * (EfW[j] - Ez[j]);
+            const double zn = zs / gz[0];
+            /* y equation of eq (20), implicit: Picard iteration */
+            double Cy = EyK;
+            for (int j = 1; j <= Ky; ++j) Cy += Ky * dt * gy[j] * Ef[j];
+            const double h0 = Ky * dt * gy[0];
+            double y = SLOT(n + 1).y[i];
+            int it = 0, conv = 0;
+            while (it < pb->picard_max) {
+                double yn = Cy + h0 * driver(pb, tn, y, &zn);
+                ++it;
+                double dy = fabs(yn - y);
+                y = yn;
+                if (pb->picard_tol > 0.0 && dy <= pb->picard_tol * fmax(1.0, fabs(y))) {
+                    conv = 1;
+                    break;
+                }
+            }
+            if (pb->picard_tol > 0.0 && !conv) ++nonconv;
+            if (it > it_max) it_max = it;
+            out.y[i] = y;
+            out.z[i] = zn;
+        }
+        natural_spline(nx, dx, out.y, 1, out.My, 1, work);
+        natural_spline(nx, dx, out.z, 1, out.Mz, 1, work);
+    }
+    memcpy(y_out, SLOT(pb->n_stop).y, sizeof(double) * nx);
+    memcpy(z_out, SLOT(pb->n_stop).z, sizeof(double) * nx);
+#undef SLOT
+    if (st) {
+        st->picard_iter_max = it_max;
+        st->picard_nonconverged = nonconv;
+    }
+    free(mem);
+    free(work);
+    return ORACLE_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* 2-D solve (tensor grid, tensor Gauss-Hermite, tensor natural spline).       */
+/* Layer storage per layer: y, z1, z2 and, for each of them, the tensor-spline */
+/* derivative arrays Mxx (along axis 0), Myy (along axis 1), Mxxyy.            */
+/* Index (i0, i1) -> i0 * n1 + i1.                                              */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    double *v, *Mxx, *Myy, *Mxxyy;
+} tspline;
+
+static void tensor_spline(int n0, int n1, double dx0, double dx1, tspline *s, double *work)
+{
+    /* along axis 0 for every column i1: Mxx */
+    for (int i1 = 0; i1 < n1; ++i1)
+        natural_spline(n0, dx0, s->v + i1, n1, s->Mxx + i1, n1, work);
+    /* along axis 1 for every row i0: Myy, and the spline of Mxx: Mxxyy */
+    for (int i0 = 0; i0 < n0; ++i0) {
+        natural_spline(n1, dx1, s->v + (long)i0 * n1, 1, s->Myy + (long)i0 * n1, 1, work);
+        natural_spline(n1, dx1, s->Mxx + (long)i0 * n1, 1, s->Mxxyy + (long)i0 * n1, 1, work);
+    }
+}
+
+/* evaluate the tensor spline at (X0, X1) with coordinates clamped to the box */
+static double tensor_eval(const tspline *s, int n0, int n1, double xmin0, double dx0,
+                          double xmin1, double dx1, double X0, double X1)
+{
+    int p, q;
+    double t0, t1;
+    locate(X0, xmin0, dx0, n0, &p, &t0);
+    locate(X1, xmin1, dx1, n1, &q, &t1);
+    double a0[2] = {1.0 - t0, t0}, b0[2] = {basis_c(t0, dx0), basis_d(t0, dx0)};
+    double a1[2] = {1.0 - t1, t1}, b1[2] = {basis_c(t1, dx1), basis_d(t1, dx1)};
+    double acc = 0.0;
+    for (int u = 0; u < 2; ++u)
+        for (int v = 0; v < 2; ++v) {
+            long k = (long)(p + u) * n1 + (q + v);
+            acc += a0[u] * a1[v] * s->v[k] + b0[u] * a1[v] * s->Mxx[k] +
+                   a0[u] * b1[v] * s->Myy[k] + b0[u] * b1[v] * s->Mxxyy[k];
+        }
+    return acc;
+}
+
+static int solve2(const oracle_problem *pb, const double *init_y, const double *init_z,
+                  double *y_out, double *z_out, oracle_stats *st)
+{
+    const int N = pb->n_t, Ky = pb->k_y, Kz = pb->k_z, K = Ky > Kz ? Ky : Kz;
+    const int L = pb->L, n0 = pb->n_x[0], n1 = pb->n_x[1];
+    const long np = (long)n0 * n1;
+    const double dt = pb->T / N;
+    const double xmin0 = pb->x_min[0], dx0 = (pb->x_max[0] - pb->x_min[0]) / (n0 - 1);
+    const double xmin1 = pb->x_min[1], dx1 = (pb->x_max[1] - pb->x_min[1]) / (n1 - 1);
+
+    double a[ORACLE_MAX_L], w[ORACLE_MAX_L], gy[7], gz[7];
+    int rc = oracle_gauss_hermite(L, a, w);
+    if (rc) return rc;
+    for (int l = 0; l < L; ++l) w[l] /= sqrt(M_PI); /* one pi^(-1/2) per axis */
+    oracle_gamma(1, Ky, gy);
+    oracle_gamma(2, Kz, gz);
+
+    /* per ring slot: 3 fields (y, z1, z2) x 4 arrays */
+    tspline ring[7][3];
+    double *mem = (double *)malloc(sizeof(double) * (size_t)np * 12 * (K + 1));
+    int nmax = n0 > n1 ? n0 : n1;
+    double *work = (double *)malloc(sizeof(double) * (size_t)2 * nmax);
+    if (!mem || !work) { free(mem); free(work); return ORACLE_ENOMEM; }
+    for (int s = 0; s <= K; ++s)
+        for (int f = 0; f < 3; ++f) {
+            double *b = mem + (size_t)np * (12 * s + 4 * f);
+            ring[s][f].v = b;
+            ring[s][f].Mxx = b + np;
+            ring[s][f].Myy = b + 2 * np;
+            ring[s][f].Mxxyy = b + 3 * np;
+        }
+#define SLOT2(n) (ring[(n) % (K + 1)])
+    for (int r = 0; r < K; ++r) {
+        int n = N - K + 1 + r;
+        memcpy(SLOT2(n)[0].v, init_y + (size_t)r * np, sizeof(double) * np);
+        memcpy(SLOT2(n)[1].v, init_z + (size_t)r * 2 * np, sizeof(double) * np);
+        memcpy(SLOT2(n)[2].v, init_z + (size_t)r * 2 * np + np, sizeof(double) * np);
+        for (int f = 0; f < 3; ++f) tensor_spline(n0, n1, dx0, dx1, &SLOT2(n)[f], work);
+    }
+
+    int it_max = 0;
+    long nonconv = 0;
+    for (int n = N - K; n >= pb->n_stop; --n) {
+        tspline *out = SLOT2(n);
+        const double tn = n * dt;
+        for (int i0 = 0; i0 < n0; ++i0)
+            for (int i1 = 0; i1 < n1; ++i1) {
+                const double x0 = xmin0 + i0 * dx0, x1 = xmin1 + i1 * dx1;
+                double Ef[7] = {0}, EfW[7][2] = {{0}}, Ez[7][2] = {{0}}, EyK = 0.0;
+                for (int j = 1; j <= K; ++j) {
+                    tspline *lj = SLOT2(n + j);
+                    const double tj = (n + j) * dt, sq = sqrt(2.0 * j * dt);
+                    for (int l0 = 0; l0 < L; ++l0)
+                        for (int l1 = 0; l1 < L; ++l1) {
+                            const double dW0 = sq * a[l0], dW1 = sq * a[l1];
+                            const double wt = w[l0] * w[l1];
+                            const double X0 = x0 + pb->drift[0] * j * dt +
+                                              pb->vol[0][0] * dW0 + pb->vol[0][1] * dW1;
+                            const double X1 = x1 + pb->drift[1] * j * dt +
+                                              pb->vol[1][0] * dW0 + pb->vol[1][1] * dW1;
+                            double yh = tensor_eval(&lj[0], n0, n1, xmin0, dx0, xmin1, dx1, X0, X1);
+                            double zh[2];
+                            zh[0] = tensor_eval(&lj[1], n0, n1, xmin0, dx0, xmin1, dx1, X0, X1);
+                            zh[1] = tensor_eval(&lj[2], n0, n1, xmin0, dx0, xmin1, dx1, X0, X1);
+                            const double fh = driver(pb, tj, yh, zh);
+                            Ef[j] += wt * fh;
+                            EfW[j][0] += wt * fh * dW0;
+                            EfW[j][1] += wt * fh * dW1;
+                            Ez[j][0] += wt * zh[0];
+                            Ez[j][1] += wt * zh[1];
+                            if (j == Ky) EyK += wt * yh;
+                        }
+                }
+                double zn[2];
+                for (int c = 0; c < 2; ++c) {
+                    double zs = Ez[1][c];
+                    for (int j = 1; j <= Kz; ++j) zs += gz[j] * (EfW[j][c] - Ez[j][c]);
+                    zn[c] = zs / gz[0];
+                }
+                double Cy = EyK;
+                for (int j = 1; j <= Ky; ++j) Cy += Ky * dt * gy[j] * Ef[j];
+                const double h0 = Ky * dt * gy[0];
+                const long k = (long)i0 * n1 + i1;
+                double y = SLOT2(n + 1)[0].v[k];
+                int it = 0, conv = 0;
+                while (it < pb->picard_max) {
+                    double yn = Cy + h0 * driver(pb, tn, y, zn);
+                    ++it;
+                    double dy = fabs(yn - y);
+                    y = yn;
+                    if (pb->picard_tol > 0.0 && dy <= pb->picard_tol * fmax(1.0, fabs(y))) {
+                        conv = 1;
+                        break;
+                    }
+                }
+                if (pb->picard_tol > 0.0 && !conv) ++nonconv;
+                if (it > it_max) it_max = it;
+                out[0].v[k] = y;
+                out[1].v[k] = zn[0];
+                out[2].v[k] = zn[1];
+            }
+        for (int f = 0; f < 3; ++f) tensor_spline(n0, n1, dx0, dx1, &out[f], work);
+    }
+    memcpy(y_out, SLOT2(pb->n_stop)[0].v, sizeof(double) * np);
+    memcpy(z_out, SLOT2(pb->n_stop)[1].v, sizeof(double) * np);
+    memcpy(z_out + np, SLOT2(pb->n_stop)[2].v, sizeof(double) * np);
+#undef SLOT2
+    if (st) {
+        st->picard_iter_max = it_max;
+        st->picard_nonconverged = nonconv;
+    }
+    free(mem);
+    free(work);
+    return ORACLE_OK;
+}
+
+int oracle_solve(const oracle_problem *pb, const double *init_y, const double *init_z,
+                 double *y_out, double *z_out, oracle_stats *st)
+{
+    int rc = validate(pb);
+    if (rc) return rc;
+    return pb->d == 1 ? solve1(pb, init_y, init_z, y_out, z_out, st)
+                      : solve2(pb, init_y, init_z, y_out, z_out, st);
+}
+
+/* Natural spline of one line and its evaluation: exposed so the tests can pin */
+/* the interpolation step against an independent library spline.               */
+int oracle_spline_eval(int n, double xmin, double xmax, const double *y, int m,
+                       const double *X, double *out)
+{
+    if (n < 4 || !(xmax > xmin)) return ORACLE_EINVAL;
+    double dx = (xmax - xmin) / (n - 1);
+    double *M = (double *)malloc(sizeof(double) * (size_t)3 * n);
+    if (!M) return ORACLE_ENOMEM;
+    natural_spline(n, dx, y, 1, M, 1, M + n);
+    for (int k = 0; k < m; ++k) {
+        if (X[k] <= xmin) { out[k] = y[0]; continue; }
+        if (X[k] >= xmin + (n - 1) * dx) { out[k] = y[n - 1]; continue; }
+        int p;
+        double th;
+        locate(X[k], xmin, dx, n, &p, &th);
+        out[k] = (1.0 - th) * y[p] + th * y[p + 1] + basis_c(th, dx) * M[p] +
+                 basis_d(th, dx) * M[p + 1];
+    }
+    free(M);
+    return ORACLE_OK;
+}

@@ -1,0 +1,288 @@
+"""Pins of the CPU oracle against facts fixed outside it.
+
+Each test checks the oracle against something it does not compute itself:
+values printed in the paper (golden files), a library routine that solves a
+special case, exact rational arithmetic from a definition, closed-form
+solutions, or invariants of the mathematics.
+"""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+from conftest import read_golden
+from scipy.interpolate import CubicSpline
+
+import workloads as W
+
+# ----------------------------------------------------------------------------
+# Gauss-Hermite rule, eq (21)
+# ----------------------------------------------------------------------------
+
+
+@pytest.mark.parametrize("L", [1, 2, 5, 8, 16, 32, 64])
+def test_gauss_hermite_matches_numpy(oracle_lib, L):
+    a, w = oracle_lib.gauss_hermite(L)
+    a_ref, w_ref = np.polynomial.hermite.hermgauss(L)
+    np.testing.assert_allclose(a, a_ref, rtol=0, atol=2e-14 * max(1.0, np.max(abs(a_ref))))
+    np.testing.assert_allclose(w, w_ref, rtol=5e-13, atol=1e-300)
+
+
+@pytest.mark.parametrize("L", [4, 16, 32])
+def test_gauss_hermite_gaussian_moments(oracle_lib, L):
+    # pi^(-1/2) sum w a^(2m) = E[X^(2m)] for X ~ N(0, 1/2) = (2m-1)!!/2^m, m < L
+    a, w = oracle_lib.gauss_hermite(L)
+    wh = w / math.sqrt(math.pi)
+    for m in range(L):
+        exact = 1.0
+        for q in range(1, 2 * m, 2):
+            exact *= q / 2.0
+        got = float(np.sum(wh * a ** (2 * m)))
+        assert got == pytest.approx(exact, rel=1e-11), m
+        odd = float(np.sum(wh * a ** (2 * m + 1)))
+        assert abs(odd) < 1e-12 * max(1.0, exact)
+
+
+# ----------------------------------------------------------------------------
+# Tables 1 and 2
+# ----------------------------------------------------------------------------
+
+
+def _not_a_knot_weights(K: int):
+    """Integrals of the K+1 cardinal not-a-knot cubic splines on knots 0..K.
+
+    The spline is written in second-derivative form on unit cells:
+    M_{i-1} + 4 M_i + M_{i+1} = 6 (y_{i+1} - 2 y_i + y_{i-1}) inside, third
+    derivative continuous at knots 1 and K-1 (not-a-knot); with fewer than
+    four knots the interpolant is the polynomial through them.  Returns
+    (over [0, K], over [0, 1]) as lists of Fractions, exact.
+    """
+    def solve(A, b):
+        n = len(b)
+        M = [row[:] + [b[i]] for i, row in enumerate(A)]
+        for c in range(n):
+            p = next(r for r in range(c, n) if M[r][c] != 0)
+            M[c], M[p] = M[p], M[c]
+            for r in range(n):
+                if r != c and M[r][c] != 0:
+                    f = M[r][c] / M[c][c]
+                    M[r] = [x - f * y for x, y in zip(M[r], M[c])]
+        return [M[i][n] / M[i][i] for i in range(n)]
+
+    full, first = [], []
+    for j in range(K + 1):
+        y = [Fraction(int(i == j)) for i in range(K + 1)]
+        if K == 1:
+            Ms = [Fraction(0)] * 2
+        elif K == 2:
+            c = y[0] - 2 * y[1] + y[2]
+            Ms = [c, c, c]
+        else:
+            A, b = [], []
+            for i in range(1, K):
+                row = [Fraction(0)] * (K + 1)
+                row[i - 1], row[i], row[i + 1] = Fraction(1), Fraction(4), Fraction(1)
+                A.append(row)
+                b.append(6 * (y[i + 1] - 2 * y[i] + y[i - 1]))
+            for k in (1, K - 1):
+                row = [Fraction(0)] * (K + 1)
+                row[k - 1], row[k], row[k + 1] = Fraction(1), Fraction(-2), Fraction(1)
+                A.append(row)
+                b.append(Fraction(0))
+            Ms = solve(A, b)
+        cell = [(y[i] + y[i + 1]) / 2 - (Ms[i] + Ms[i + 1]) / 24 for i in range(K)]
+        full.append(sum(cell) / K)
+        first.append(cell[0])
+    return full, first
+
+
+def _printed_tables():
+    tab = {}
+    for t, K, j, num, den in read_golden("gamma_tables.txt"):
+        tab.setdefault((int(t), int(K)), {})[int(j)] = Fraction(int(num), int(den))
+    return tab
+
+
+@pytest.mark.parametrize("K", range(1, 7))
+def test_gamma_tables_are_not_a_knot_integrals(oracle_lib, K):
+    full, first = _not_a_knot_weights(K)
+    printed = _printed_tables()
+    assert [printed[(1, K)][j] for j in range(K + 1)] == full
+    assert [printed[(2, K)][j] for j in range(K + 1)] == first
+    np.testing.assert_allclose(oracle_lib.gamma(1, K), [float(v) for v in full], rtol=1e-15)
+    np.testing.assert_allclose(oracle_lib.gamma(2, K), [float(v) for v in first], rtol=1e-15,
+                               atol=1e-17)
+
+
+@pytest.mark.parametrize("K", range(3, 7))
+def test_gamma_tables_match_library_spline(oracle_lib, K):
+    t = np.arange(K + 1, dtype=float)
+    g1 = [CubicSpline(t, np.eye(K + 1)[j], bc_type="not-a-knot").integrate(0, K) / K
+          for j in range(K + 1)]
+    g2 = [CubicSpline(t, np.eye(K + 1)[j], bc_type="not-a-knot").integrate(0, 1)
+          for j in range(K + 1)]
+    np.testing.assert_allclose(oracle_lib.gamma(1, K), g1, rtol=1e-13, atol=1e-15)
+    np.testing.assert_allclose(oracle_lib.gamma(2, K), g2, rtol=1e-13, atol=1e-15)
+
+
+def test_gamma_rows_sum_to_one(oracle_lib):
+    for K in range(1, 7):
+        assert sum(oracle_lib.gamma(1, K)) == pytest.approx(1.0, abs=1e-15)
+        assert sum(oracle_lib.gamma(2, K)) == pytest.approx(1.0, abs=1e-15)
+
+
+# ----------------------------------------------------------------------------
+# Spatial interpolation (natural cubic spline, boundary values outside)
+# ----------------------------------------------------------------------------
+
+
+@pytest.mark.parametrize("n", [4, 7, 33, 1000])
+def test_spline_matches_library_natural_spline(oracle_lib, n):
+    rng = np.random.default_rng(n)
+    x = np.linspace(-2.0, 3.0, n)
+    y = np.sin(3 * x) + 0.1 * rng.standard_normal(n)
+    X = rng.uniform(-2.0, 3.0, 500)
+    X[:3] = [-2.0, 3.0, x[n // 2]]
+    ref = CubicSpline(x, y, bc_type="natural")(X)
+    got = oracle_lib.spline_eval(y, -2.0, 3.0, X)
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-13 * np.max(abs(y)))
+
+
+def test_spline_outside_domain_takes_boundary_values(oracle_lib):
+    x = np.linspace(0.0, 1.0, 11)
+    y = np.exp(x)
+    got = oracle_lib.spline_eval(y, 0.0, 1.0, np.array([-5.0, -1e-9, 1.0 + 1e-9, 7.0]))
+    np.testing.assert_array_equal(got, [y[0], y[0], y[-1], y[-1]])
+
+
+# ----------------------------------------------------------------------------
+# The whole scheme against the paper's printed errors
+# ----------------------------------------------------------------------------
+
+
+def _err_at_x0(oracle_lib, wl):
+    iy, iz = wl.init_layers()
+    y, z, _ = oracle_lib.solve(wl.problem, iy, iz)
+    ye, ze = wl.exact_at_t0()
+    i = wl.node_index()
+    return abs(y[i] - ye[i]), abs(z[0, i] - ze[i])
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("row", read_golden("table4_example1.txt"), ids=lambda r: "-".join(r[:3]))
+def test_table4_example1_errors(oracle_lib, row):
+    K, N, M = (int(v) for v in row[:3])
+    ey, ez = _err_at_x0(oracle_lib, W.paper_example1(K, N, M))
+    # the table prints three significant digits
+    assert ey == pytest.approx(float(row[3]), rel=0.02)
+    assert ez == pytest.approx(float(row[4]), rel=0.02)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("row", read_golden("table5_example2.txt"), ids=lambda r: "-".join(r[:3]))
+def test_table5_example2_errors(oracle_lib, row):
+    K, N, M = (int(v) for v in row[:3])
+    ey, ez = _err_at_x0(oracle_lib, W.paper_example2(K, N, M))
+    assert ey == pytest.approx(float(row[3]), rel=0.02)
+    assert ez == pytest.approx(float(row[4]), rel=0.02)
+
+
+def test_grid_rule_reproduces_printed_M():
+    for T, xm, K, N, M in read_golden("grid_rule_M.txt"):
+        assert W.grid_rule_M(int(K), int(K), int(N), float(T), float(xm)) == int(M)
+
+
+def test_black_scholes_closed_form_matches_example3():
+    (T, K, S0, r, dl, sg, y0, z0), = [[float(v) for v in r] for r in
+                                      read_golden("example3_black_scholes.txt")]
+    y, z = W.bs_call(T, math.log(S0), K, r, sg, dl)
+    assert round(float(y), 4) == y0
+    assert round(float(z), 4) == z0
+
+
+# ----------------------------------------------------------------------------
+# Closed forms and special cases
+# ----------------------------------------------------------------------------
+
+
+def test_sine_problem_closed_form(oracle_lib):
+    # f = y/2 - z, y = sin(W + t): the default 1025-point, 64-step, k = 2 case
+    ey, ez = _err_at_x0(oracle_lib, W.sine_1d())
+    assert ey < 1e-4 and ez < 2e-4
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 6])
+def test_quadratic_terminal_is_reproduced_in_the_interior(oracle_lib, k):
+    # f = 0, g = x^2: Gauss-Hermite is exact for quadratics and the spline is
+    # exact for them away from the natural boundary condition, so
+    # y = x^2 + T - t and z = 2x hold to rounding in the interior.
+    # The horizon is short enough that the clamp at +-8 never reaches |x| < 3.
+    wl = W.quadratic_heat(k=k, T=0.25)
+    iy, iz = wl.init_layers()
+    y, z, _ = oracle_lib.solve(wl.problem, iy, iz)
+    ye, ze = wl.exact_at_t0()
+    inner = np.abs(wl.grid()) < 3.0
+    np.testing.assert_allclose(y[inner], ye[inner], rtol=0, atol=1e-12)
+    np.testing.assert_allclose(z[0][inner], ze[inner], rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6])
+def test_space_independent_terminal_gives_zero_z(oracle_lib, k):
+    wl = W.discount_const(k=k)
+    iy, iz = wl.init_layers()
+    y, z, _ = oracle_lib.solve(wl.problem, iy, iz)
+    assert np.max(np.abs(z)) < 1e-14
+    assert np.ptp(y) < 1e-14
+    ye, _ = wl.exact_at_t0()
+    assert abs(y[0] - ye[0]) < 1e-5
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_time_order_on_space_independent_problem(oracle_lib, k):
+    # f = -r y with constant g: the scheme is a linear multistep method for
+    # y' = r y; its global error must fall at least like dt^(k+1)
+    # (Theorem 1: order min(K_y + 1, 4)).
+    errs = []
+    for nt in (16, 32, 64):
+        wl = W.discount_const(k=k, n_t=nt, r=1.0)
+        iy, iz = wl.init_layers()
+        y, _, _ = oracle_lib.solve(wl.problem, iy, iz)
+        errs.append(abs(y[0] - wl.exact_at_t0()[0][0]))
+    orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(orders > k + 1 - 0.3), orders
+
+
+def test_linear_driver_superposition(oracle_lib):
+    # for a linear driver with c = 0 the discrete scheme is linear in the data
+    wl = W.sine_1d(n_x=129, n_t=12, k=3, L=8)
+    iy, iz = wl.init_layers()
+    rng = np.random.default_rng(7)
+    dy, dz = rng.standard_normal(iy.shape), rng.standard_normal(iz.shape)
+    y1, z1, _ = oracle_lib.solve(wl.problem, iy, iz)
+    y2, z2, _ = oracle_lib.solve(wl.problem, dy, dz)
+    y3, z3, _ = oracle_lib.solve(wl.problem, iy + 2.0 * dy, iz + 2.0 * dz)
+    np.testing.assert_allclose(y3, y1 + 2 * y2, atol=1e-11 * np.max(abs(y3)))
+    np.testing.assert_allclose(z3, z1 + 2 * z2, atol=1e-11 * np.max(abs(z3)))
+
+
+def test_black_scholes_smoothed_problem(oracle_lib):
+    # log-price grid with drift and volatility; stability ratio 16
+    nx, nt = 2048, 64
+    hw = 0.2 * math.sqrt(2 * 0.33 / nt) / 16 * (nx - 1) / 2
+    wl = W.bs_call_1d(n_x=nx, n_t=nt, k=3, half_width=hw)
+    ey, ez = _err_at_x0(oracle_lib, wl)
+    assert ey < 1e-8 and ez < 1e-8
+
+
+@pytest.mark.parametrize("sign", [1.0, -1.0])
+def test_bid_ask_call_matches_effective_rate_price(oracle_lib, sign):
+    wl = W.bidask_call_1d(n_x=2048, n_t=64, half_width=None, sign=sign)
+    ey, ez = _err_at_x0(oracle_lib, wl)
+    assert ey < 1e-5 and ez < 1e-6
+
+
+def test_picard_tolerance_stops_early(oracle_lib):
+    wl = W.bidask_call_1d(n_x=257, n_t=16, half_width=None)
+    iy, iz = wl.init_layers()
+    _, _, st = oracle_lib.solve(wl.problem, iy, iz)
+    assert 1 < st["picard_iter_max"] < 10 and st["picard_nonconverged"] == 0

@@ -1,0 +1,319 @@
+"""Seeded synthetic inputs shared by the GPU path's tests and the oracle's tests.
+
+This module holds problem descriptions, closed-form solutions and the initial
+layers built from them.  It holds none of the multistep scheme's arithmetic:
+no quadrature, no interpolation, no time stepping.  Both the GPU binding and
+the CPU oracle take the plain dictionaries it returns.
+
+A problem dictionary has the keys
+    d, T, n_t, k_y, k_z, L, n_x, x_min, x_max, drift, vol, driver, p,
+    picard_max, picard_tol
+with the forward process X_{t+h} = X_t + drift*h + vol*(W_{t+h} - W_t)
+(X = W: drift 0, vol 1; log-price, eq (33): drift mu - sigma^2/2, vol sigma)
+and the driver kinds
+    "linear"  p = [a, b1, b2, c]          f = a y + b1 z1 + b2 z2 + c
+    "bidask"  p = [r, R, theta, sigma, s] f = -r y - theta z + s (R-r) min(y - z/sigma, 0)
+    "cubic"   Example 1, eq (22)
+    "exp"     Example 2, eq (24)
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import Callable
+
+import numpy as np
+from scipy.special import ndtr
+
+# ----------------------------------------------------------------------------
+# Closed forms
+# ----------------------------------------------------------------------------
+
+
+def sine_solution(t, x):
+    """y = sin(x + t), z = cos(x + t): solves f = y/2 - z with X = W."""
+    return np.sin(x + t), np.cos(x + t)
+
+
+def ex1_solution(t, x):
+    """Example 1, eq (23): y = e^{x+t}/(e^{x+t}+1), z = e^{x+t}/(e^{x+t}+1)^2."""
+    e = np.exp(-(x + t))  # written with e^{-(x+t)} to stay finite for large x
+    y = 1.0 / (1.0 + e)
+    return y, y * (1.0 - y)
+
+
+def ex2_solution(t, x):
+    """Example 2, eq (25): y = ln(sin x + 3) e^{t^2}, z = e^{t^2} cos x/(sin x + 3)."""
+    et = np.exp(t * t)
+    return np.log(np.sin(x) + 3.0) * et, et * np.cos(x) / (np.sin(x) + 3.0)
+
+
+def bs_call(tau, x, K, r, sigma, delta=0.0):
+    """Black-Scholes call on S = e^x with time to expiry tau and dividend yield delta.
+
+    Returns (y, z) with y the price and z = sigma S dV/dS, eq (31) with the
+    dividend term kept in d_{1,2}.
+    """
+    tau = np.asarray(tau, dtype=float)
+    S = np.exp(x)
+    sq = sigma * np.sqrt(tau)
+    d1 = (x - math.log(K) + (r - delta + 0.5 * sigma * sigma) * tau) / sq
+    d2 = d1 - sq
+    disc_q = np.exp(-delta * tau)
+    y = S * disc_q * ndtr(d1) - K * np.exp(-r * tau) * ndtr(d2)
+    z = sigma * S * disc_q * ndtr(d1)
+    return y, z
+
+
+def margrabe(tau, x1, x2, sigma1, sigma2, rho):
+    """Margrabe exchange option max(S1 - S2, 0), S_k = e^{x_k}; returns (V, dV/dx1, dV/dx2)."""
+    s = math.sqrt(sigma1 ** 2 + sigma2 ** 2 - 2 * rho * sigma1 * sigma2)
+    S1, S2 = np.exp(x1), np.exp(x2)
+    sq = s * np.sqrt(tau)
+    d1 = (x1 - x2 + 0.5 * s * s * tau) / sq
+    d2 = d1 - sq
+    return S1 * ndtr(d1) - S2 * ndtr(d2), S1 * ndtr(d1), -S2 * ndtr(d2)
+
+
+# ----------------------------------------------------------------------------
+# Workload container
+# ----------------------------------------------------------------------------
+
+
+@dataclass
+class Workload:
+    name: str
+    problem: dict
+    exact: Callable  # exact(t, x) -> (y, z) on the grid (1-D), or (y, (z1, z2)) (2-D)
+    x0: float | tuple = 0.0  # evaluation point of the headline value (a grid node)
+    notes: str = ""
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def K(self) -> int:
+        return max(self.problem["k_y"], self.problem["k_z"])
+
+    def grid(self, axis: int = 0) -> np.ndarray:
+        pb = self.problem
+        n = _as_list(pb["n_x"])[axis]
+        lo = _as_list(pb["x_min"])[axis]
+        hi = _as_list(pb["x_max"])[axis]
+        return lo + np.arange(n) * ((hi - lo) / (n - 1))
+
+    def dt(self) -> float:
+        return self.problem["T"] / self.problem["n_t"]
+
+    def init_layers(self):
+        """The K newest layers t_{N-K+1}..t_N from the closed form (Section 3.1 step 2).
+
+        Returns (init_y, init_z) of shapes (K, points) and (K, d, points).
+        """
+        pb = self.problem
+        N, K, d = pb["n_t"], self.K, pb["d"]
+        dt = self.dt()
+        if d == 1:
+            x = self.grid(0)
+            iy = np.empty((K, x.size))
+            iz = np.empty((K, 1, x.size))
+            for r in range(K):
+                y, z = self.exact((N - K + 1 + r) * dt, x)
+                iy[r], iz[r, 0] = y, z
+            return iy, iz
+        x1, x2 = np.meshgrid(self.grid(0), self.grid(1), indexing="ij")
+        iy = np.empty((K, x1.size))
+        iz = np.empty((K, 2, x1.size))
+        for r in range(K):
+            y, (z1, z2) = self.exact((N - K + 1 + r) * dt, (x1, x2))
+            iy[r] = np.ravel(y)
+            iz[r, 0] = np.ravel(z1)
+            iz[r, 1] = np.ravel(z2)
+        return iy, iz
+
+    def exact_at_t0(self):
+        """Exact (y, z) at t = 0 on the whole grid."""
+        if self.problem["d"] == 1:
+            return self.exact(0.0, self.grid(0))
+        x1, x2 = np.meshgrid(self.grid(0), self.grid(1), indexing="ij")
+        y, (z1, z2) = self.exact(0.0, (x1, x2))
+        return np.ravel(y), np.stack([np.ravel(z1), np.ravel(z2)])
+
+    def node_index(self) -> int:
+        """Flat grid index of x0 (x0 must be a grid node)."""
+        if self.problem["d"] == 1:
+            x = self.grid(0)
+            i = int(round((self.x0 - x[0]) / (x[1] - x[0])))
+            assert abs(x[i] - self.x0) < 1e-9 * max(1.0, abs(self.x0)), "x0 is not a node"
+            return i
+        idx = []
+        for a in range(2):
+            x = self.grid(a)
+            i = int(round((self.x0[a] - x[0]) / (x[1] - x[0])))
+            assert abs(x[i] - self.x0[a]) < 1e-9 * max(1.0, abs(self.x0[a]))
+            idx.append(i)
+        return idx[0] * self.problem["n_x"][1] + idx[1]
+
+
+def _as_list(v):
+    return list(v) if isinstance(v, (list, tuple, np.ndarray)) else [v]
+
+
+def _problem(**kw) -> dict:
+    base = dict(d=1, drift=0.0, vol=1.0, picard_max=30, picard_tol=0.0)
+    base.update(kw)
+    return base
+
+
+# ----------------------------------------------------------------------------
+# The paper's examples (used as pins of the oracle)
+# ----------------------------------------------------------------------------
+
+
+def paper_example1(K: int, N: int, M: int, L: int = 32, T: float = 1.0) -> Workload:
+    """Example 1 (eq (22)-(23)) on [-16, 16] with M intervals, as in Table 4."""
+    pb = _problem(T=T, n_t=N, k_y=K, k_z=K, L=L, n_x=M + 1, x_min=-16.0, x_max=16.0,
+                  driver="cubic", p=[])
+    return Workload(f"ex1_K{K}_N{N}_M{M}", pb, ex1_solution, 0.0)
+
+
+def paper_example2(K: int, N: int, M: int, L: int = 32, T: float = 1.0) -> Workload:
+    """Example 2 (eq (24)-(25)) on [-16, 16] with M intervals, as in Table 5."""
+    pb = _problem(T=T, n_t=N, k_y=K, k_z=K, L=L, n_x=M + 1, x_min=-16.0, x_max=16.0,
+                  driver="exp", p=[])
+    return Workload(f"ex2_K{K}_N{N}_M{M}", pb, ex2_solution, 0.0)
+
+
+def grid_rule_M(K_y: int, K_z: int, N: int, T: float, x_max: float) -> int:
+    """Number of space intervals on [-x_max, x_max] that balances the errors
+    (Section 3.1 step 1, with r = 4 for the cubic spline): dx = dt^((q+1)/4)
+    with q = min(K_y + 1, K_z, 3), the z order of eq (19)."""
+    q = min(K_y + 1, K_z, 3)
+    dx = (T / N) ** ((q + 1) / 4.0)
+    return 2 * math.ceil(x_max / dx)
+
+
+# ----------------------------------------------------------------------------
+# Workloads of the measured path
+# ----------------------------------------------------------------------------
+
+
+def sine_1d(n_x: int = 1025, n_t: int = 64, k: int = 2, L: int = 16,
+            picard_tol: float = 0.0) -> Workload:
+    """X = W, T = 1, f = y/2 - z, g = sin(x + 1) on [-8, 8]; exact y = sin(W+t)."""
+    pb = _problem(T=1.0, n_t=n_t, k_y=k, k_z=k, L=L, n_x=n_x, x_min=-8.0, x_max=8.0,
+                  driver="linear", p=[0.5, -1.0, 0.0, 0.0], picard_tol=picard_tol)
+    return Workload(f"sine1d_nx{n_x}_nt{n_t}_k{k}_L{L}", pb, sine_solution, 0.0)
+
+
+def _snap_domain(c: float, lo: float, hi: float, n_x: int):
+    """Shift [lo, hi] (keeping its width) so that c falls on a grid node."""
+    dx = (hi - lo) / (n_x - 1)
+    i0 = int(round((c - lo) / dx))
+    lo = c - i0 * dx
+    return lo, lo + (n_x - 1) * dx
+
+
+def bs_call_1d(n_x: int = 16384, n_t: int = 256, k: int = 4, L: int = 32,
+               half_width: float | None = 5.2, K: float = 100.0, S0: float = 100.0,
+               r: float = 0.05, mu: float = 0.1, sigma: float = 0.2, T: float = 0.33,
+               delta: float = 0.0, smooth: bool = True) -> Workload:
+    """Black-Scholes call as a linear BSDE on the log-price grid.
+
+    f = -r y - ((mu - r + delta)/sigma) z (eq (29)-(30)), X = ln S (eq (33)).
+    With ``smooth`` the terminal layer is the closed-form price with dt left
+    to expiry, so the solved problem has maturity T + dt and a smooth terminal
+    condition; the exact solution is the price at that maturity.
+    ``half_width=None`` gives the interval [ln S0 - 6 sigma sqrt(T) - |mu - sigma^2/2| T,
+    ln S0 + 6 sigma sqrt(T)]; a number gives ln S0 +- half_width.  The interval
+    is shifted by less than one cell so that ln S0 is a grid node.
+    """
+    c = math.log(S0)
+    if half_width is None:
+        lo = c - 6 * sigma * math.sqrt(T) - abs(mu - 0.5 * sigma ** 2) * T
+        hi = c + 6 * sigma * math.sqrt(T)
+    else:
+        lo, hi = c - half_width, c + half_width
+    lo, hi = _snap_domain(c, lo, hi, n_x)
+    tau_s = T / n_t if smooth else 0.0
+    theta = (mu - r + delta) / sigma
+    pb = _problem(T=T, n_t=n_t, k_y=k, k_z=k, L=L, n_x=n_x, x_min=lo, x_max=hi,
+                  drift=mu - 0.5 * sigma ** 2, vol=sigma, driver="linear",
+                  p=[-r, -theta, 0.0, 0.0])
+
+    def exact(t, x):
+        tau = T + tau_s - t
+        if tau <= 0:
+            return np.maximum(np.exp(x) - K, 0.0), sigma * np.exp(x) * (x > math.log(K))
+        return bs_call(tau, x, K, r, sigma, delta)
+
+    w = Workload(f"bs1d_nx{n_x}_nt{n_t}_k{k}_L{L}", pb, exact, math.log(S0))
+    w.extra.update(dict(K=K, S0=S0, r=r, mu=mu, sigma=sigma, delta=delta, tau_s=tau_s))
+    return w
+
+
+def bidask_call_1d(n_x: int = 262144, n_t: int = 1024, k: int = 4, L: int = 16,
+                   half_width: float | None = 52.0, K: float = 100.0, S0: float = 100.0,
+                   r: float = 0.01, R: float = 0.06, mu: float = 0.05, sigma: float = 0.2,
+                   T: float = 0.5, sign: float = 1.0, smooth: bool = True,
+                   picard_tol: float = 1e-14, picard_max: int = 30) -> Workload:
+    """Call under different lending (r) and borrowing (R) rates.
+
+    f = -r y - theta z + s (R - r) min(y - z/sigma, 0), theta = (mu - r)/sigma.
+    A call's replicating portfolio always borrows (y - z/sigma < 0), so the
+    exact solution is the Black-Scholes price at rate r' = r - s (R - r):
+    s = +1 (the sign as written in the workload statement) gives 2r - R,
+    s = -1 (the usual borrowing-rate driver) gives R.
+    ``half_width=None`` gives ln S0 +- 6 sigma sqrt(T).
+    """
+    c = math.log(S0)
+    hw = 6 * sigma * math.sqrt(T) if half_width is None else half_width
+    lo, hi = _snap_domain(c, c - hw, c + hw, n_x)
+    tau_s = T / n_t if smooth else 0.0
+    theta = (mu - r) / sigma
+    r_eff = r - sign * (R - r)
+    pb = _problem(T=T, n_t=n_t, k_y=k, k_z=k, L=L, n_x=n_x, x_min=lo, x_max=hi,
+                  drift=mu - 0.5 * sigma ** 2, vol=sigma, driver="bidask",
+                  p=[r, R, theta, sigma, sign], picard_tol=picard_tol, picard_max=picard_max)
+
+    def exact(t, x):
+        tau = T + tau_s - t
+        if tau <= 0:
+            return np.maximum(np.exp(x) - K, 0.0), sigma * np.exp(x) * (x > math.log(K))
+        return bs_call(tau, x, K, r_eff, sigma)
+
+    w = Workload(f"bidask1d_nx{n_x}_nt{n_t}_k{k}_L{L}", pb, exact, c)
+    w.extra.update(dict(K=K, S0=S0, r=r, R=R, mu=mu, sigma=sigma, sign=sign, tau_s=tau_s,
+                        r_eff=r_eff))
+    return w
+
+
+def quadratic_heat(n_x: int = 513, n_t: int = 32, k: int = 3, L: int = 16,
+                   half_width: float = 8.0, T: float = 1.0) -> Workload:
+    """f = 0, g = x^2 with X = W: y = x^2 + (T - t), z = 2x (special case)."""
+    pb = _problem(T=T, n_t=n_t, k_y=k, k_z=k, L=L, n_x=n_x, x_min=-half_width,
+                  x_max=half_width, driver="linear", p=[0.0, 0.0, 0.0, 0.0])
+
+    def exact(t, x):
+        return x * x + (T - t), 2.0 * x
+
+    return Workload(f"quad_nx{n_x}_nt{n_t}_k{k}", pb, exact, 0.0)
+
+
+def discount_const(n_x: int = 65, n_t: int = 32, k: int = 3, L: int = 8, r: float = 0.3,
+                   T: float = 1.0) -> Workload:
+    """f = -r y, g = 1: y = e^{-r(T - t)}, z = 0 (x-independent special case)."""
+    pb = _problem(T=T, n_t=n_t, k_y=k, k_z=k, L=L, n_x=n_x, x_min=-4.0, x_max=4.0,
+                  driver="linear", p=[-r, 0.0, 0.0, 0.0])
+
+    def exact(t, x):
+        return np.full_like(x, math.exp(-r * (T - t))), np.zeros_like(x)
+
+    return Workload(f"disc_nx{n_x}_nt{n_t}_k{k}", pb, exact, 0.0)
+
+
+def stability_ratio(pb: dict, axis: int = 0) -> float:
+    """R = (spread of one Gauss-Hermite step, vol*sqrt(2 dt)) / dx in cells."""
+    n = _as_list(pb["n_x"])[axis]
+    dx = (_as_list(pb["x_max"])[axis] - _as_list(pb["x_min"])[axis]) / (n - 1)
+    vol = np.atleast_2d(np.asarray(pb.get("vol", 1.0), dtype=float))
+    v = float(np.sqrt(np.sum(vol[axis] ** 2))) if pb["d"] == 2 else float(vol[0, 0])
+    return v * math.sqrt(2.0 * pb["T"] / pb["n_t"]) / dx
