@@ -1,0 +1,193 @@
+"""Throughput of the backward sweep of the multistep BSDE scheme on one MI355X.
+
+A "step" of this benchmark is one full backward solve (every time layer of
+the sweep, every kernel of the hot path) of the workload below, with the
+initial layers already resident in HBM.  The metric is
+grid-point x time-step updates per second: n_x * N / (seconds per solve).
+
+Default workload: the call under different lending and borrowing rates
+(r = 0.01, R = 0.06, sigma = 0.2, mu = 0.05, K = S0 = 100, T = 0.5) on a
+262144-point log-price grid, N = 1024 steps, k = 4, L = 16, Picard to 1e-14,
+FP64.  The log-price interval is ln S0 +- 52, which keeps the Gauss-Hermite
+spread at about 16 cells per unit (stability ratio 15.8).
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+FP64_VALU_PEAK_TFLOPS = 78.6  # 256 CU x 64 FP64 FMA lanes x 2 flop x 2.4 GHz
+HBM_PEAK_GBS = 8000.0
+
+
+def workload(name: str):
+    import workloads as W
+
+    if name == "bidask1d":
+        return W.bidask_call_1d(n_x=262144, n_t=1024, k=4, L=16, half_width=52.0,
+                                picard_tol=1e-14, picard_max=30)
+    if name == "bidask1d_literal":
+        return W.bidask_call_1d(n_x=262144, n_t=1024, k=4, L=16, half_width=None,
+                                picard_tol=1e-14, picard_max=30)
+    if name == "sine1d":
+        return W.sine_1d()
+    raise SystemExit(f"unknown workload {name}")
+
+
+def flops_per_point_step(pb: dict, picard_mean: float) -> float:
+    """Algorithmic FP64 operations of one grid point and one time step.
+
+    Per Gauss-Hermite node (j, l): two spline evaluations (4 mul + 3 add
+    each), the driver, and three weighted accumulations (f, f dW, z: 2 each).
+    Per layer j = K_y one more accumulation of y.  Then the z combination
+    (3K + 1), the y constant (2K) and each Picard iteration (driver + 2).
+    Driver cost: linear 4, bid-ask 8, cubic 5, exp 14 (exp counted as 1).
+    """
+    drv = {"linear": 4, "bidask": 8, "cubic": 5, "exp": 14}[pb["driver"]]
+    K, L = max(pb["k_y"], pb["k_z"]), pb["L"]
+    per_node = 7 + 7 + drv + 6
+    return K * L * per_node + 2 * L + (3 * K + 1) + 2 * K + picard_mean * (drv + 2)
+
+
+def bytes_per_point_step(pb: dict) -> float:
+    """Algorithmic HBM bytes of the sweep kernel per point-step (FP64):
+    read the K layers' records (y, M_y, z, M_z: 32 B) and write y, z (16 B)."""
+    K = max(pb["k_y"], pb["k_z"])
+    return 32.0 * K + 16.0
+
+
+def cpu_baseline(wl, budget_s: float = 15.0) -> dict:
+    """Serial oracle on the first steps of the same workload (bounded sample)."""
+    import oracle
+
+    oracle.build(force=False)
+    pb = dict(wl.problem)
+    K = wl.K
+    iy, iz = wl.init_layers()
+    # probe one step, then size the sample to the budget
+    t0 = time.perf_counter()
+    oracle.solve(pb, iy, iz, n_stop=pb["n_t"] - K)
+    one = time.perf_counter() - t0
+    steps = max(1, min(pb["n_t"] - K + 1, int(budget_s / max(one, 1e-3))))
+    t0 = time.perf_counter()
+    oracle.solve(pb, iy, iz, n_stop=pb["n_t"] - K + 1 - steps)
+    el = time.perf_counter() - t0
+    nx = pb["n_x"]
+    return {"value": nx * steps / el, "unit": "grid-point*time-step/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"first {steps} of {pb['n_t'] - K + 1} backward steps at full grid "
+                      f"({nx} points), serial FP64 C oracle, {el:.1f} s"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="bidask1d")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the method has no cross-GPU communication and this "
+              "build runs on a single MI355X; --gpus must be 1", file=sys.stderr)
+        return 2
+
+    import torch
+
+    import paper_1909_13560_amd as B
+
+    wl = workload(args.workload)
+    pb = wl.problem
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    plan = B.bsde_plan(pb)
+    ws = B.workspace(plan, dev)
+    iy, iz = wl.init_layers()
+    K, nx = wl.K, pb["n_x"]
+    t_iy = torch.as_tensor(iy, device=dev).contiguous()
+    t_iz = torch.as_tensor(iz.reshape(K, nx), device=dev).contiguous()
+    y0 = torch.empty(nx, dtype=torch.float64, device=dev)
+    z0 = torch.empty(nx, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    # one checked solve: status and Picard statistics
+    rc, st = B.bsde_solve(plan, ws, t_iy, t_iz, y0, z0, stream=stream, stats=True)
+    print(f"[bench] workload {wl.name} status {B.bsde_status_string(rc)} stats {st}",
+          file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        B.bsde_solve(plan, ws, t_iy, t_iz, y0, z0, stream=stream)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        B.bsde_solve(plan, ws, t_iy, t_iz, y0, z0, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    value = nx * pb["n_t"] / (ms * 1e-3)
+    print(f"[bench] {args.steps} solves, {ms:.3f} ms per solve", file=sys.stderr, flush=True)
+
+    # per-kernel durations from hipEvents around every launch of one solve
+    kt = B.bsde_profile_kernels(plan, ws, t_iy, t_iz, y0, z0, stream=stream)
+    sweep_ms = kt["sweep_ms"] / kt["sweep_launches"]
+    spline_ms = kt["spline_ms"] / kt["spline_launches"]
+    fl = flops_per_point_step(pb, st["picard_iter_mean"]) * nx
+    achieved = fl / (sweep_ms * 1e-3) / 1e12
+    print(f"[bench] sweep kernel {sweep_ms * 1e3:.1f} us/launch, spline {spline_ms * 1e3:.1f} "
+          f"us/launch", file=sys.stderr, flush=True)
+
+    # error of the headline value against the closed form
+    y_h = y0.cpu().numpy()
+    z_h = z0.cpu().numpy()
+    ye, ze = wl.exact_at_t0()
+    i = wl.node_index()
+    err = {"y0": float(y_h[i]), "z0": float(z_h[i]),
+           "abs_err_y0": float(abs(y_h[i] - ye[i])), "abs_err_z0": float(abs(z_h[i] - ze[i]))}
+
+    out = {
+        "metric": "grid-point*time-step updates/sec (k=4, L=16)",
+        "value": value,
+        "unit": "grid-point*time-step/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "n_x": nx, "n_t": pb["n_t"], "k": pb["k_y"],
+                   "L": pb["L"], "driver": pb["driver"], "x_min": pb["x_min"],
+                   "x_max": pb["x_max"], "picard_tol": pb["picard_tol"],
+                   "stability_ratio": st["stability_ratio"]},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_VALU_PEAK_TFLOPS,
+                     "traffic": None, "kernel": "sweep_f64",
+                     "kernel_us": sweep_ms * 1e3,
+                     "flops_per_launch": fl,
+                     "hbm_bytes_per_launch_algorithmic": bytes_per_point_step(pb) * nx},
+        "spline_kernel_us": spline_ms * 1e3,
+        "accuracy": err,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

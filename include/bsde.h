@@ -1,0 +1,212 @@
+/*
+ * bsde.h -- C ABI of the MI355X (gfx950) library for the multistep scheme for
+ * backward stochastic differential equations of Kapllani & Teng,
+ * "Multistep schemes for solving backward stochastic differential equations
+ * on GPU" (arXiv:1909.13560).
+ *
+ * The library runs the backward time sweep of the fully discrete scheme
+ * (Section 2.2 eq (20), Gauss-Hermite expectations eq (21), algorithm step 3
+ * of Section 3.1) on one GPU.  The problem statement follows the paper: the
+ * BSDE -dy = f(t, y, z) dt - z dW with X_t = x + drift t + vol W_t (eq (1)-(2),
+ * eq (33) for the log-price), the time grid N, the multistep orders K_y, K_z,
+ * the truncated uniform space grid (Section 3.1 step 1), the Gauss-Hermite
+ * order L and the Picard iteration (step 3).  The terminal condition g and the
+ * K - 1 further initial layers (step 2) are computed by the caller on the host
+ * and handed over as device arrays.
+ *
+ * Conventions shared by all entry points:
+ *   - Every function returns a bsde_status; nothing aborts or throws across
+ *     the ABI.  On an error no output is written unless stated otherwise.
+ *   - Device pointers are HIP device addresses on the current device; the
+ *     caller owns them.  Host pointers are plain host memory.
+ *   - "stream" is a hipStream_t passed as void*; NULL is the default stream.
+ *     Work is enqueued asynchronously on it; an entry point that fills a
+ *     bsde_stats synchronises that stream before it returns.
+ *   - Grid values are double precision in the caller's buffers for both
+ *     precision modes; BSDE_FP32_COMP only changes the arithmetic inside.
+ */
+#ifndef BSDE_H
+#define BSDE_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    BSDE_OK = 0,
+    BSDE_EINVAL = 1,       /* invalid argument or problem                         */
+    BSDE_ENOMEM = 2,       /* host or device allocation failed                    */
+    BSDE_EDEVICE = 3,      /* a HIP call failed (no device, launch failure, ...)  */
+    BSDE_EUNSUPPORTED = 4, /* valid problem outside what this build implements    */
+    BSDE_ENOCONV = 5,      /* Picard did not reach the tolerance at some point    */
+    BSDE_ENONFINITE = 6    /* a non-finite value appeared in the output layer     */
+} bsde_status;
+
+typedef enum {
+    /* f = p0 y + p1 z1 + p2 z2 + p3 (Black-Scholes, eq (29)-(30), with
+     * p0 = -r, p1 = -(mu - r + delta)/sigma; the sine problem f = y/2 - z)   */
+    BSDE_DRIVER_LINEAR = 0,
+    /* f = -r y - theta z + s (R - r) min(y - z/sigma, 0),
+     * p = {r, R, theta, sigma, s}: lending rate r, borrowing rate R          */
+    BSDE_DRIVER_BIDASK = 1,
+    /* Example 1, eq (22): f = -y^3 + 5/2 y^2 - 3/2 y                          */
+    BSDE_DRIVER_CUBIC = 2,
+    /* Example 2, eq (24): f = (e^{t^2} - 4 t y - 3 e^{t^2 - y e^{-t^2}}
+     *                          + z^2 e^{-t^2}) / 2                              */
+    BSDE_DRIVER_EXP = 3
+} bsde_driver_kind;
+
+typedef enum {
+    BSDE_FP64 = 0,      /* all arithmetic in double precision                   */
+    BSDE_FP32_COMP = 1  /* quadrature and interpolation in single precision with
+                           compensated (error-free transformation) sums; spline
+                           solve, z combination and Picard in double precision */
+} bsde_precision;
+
+/* One BSDE.  d = 1 in this release; the d = 2 fields are reserved. */
+typedef struct {
+    int d;              /* space dimension (1)                                   */
+    double T;           /* terminal time, > 0                                    */
+    int n_t;            /* N: time steps, dt = T/N, N >= max(k_y, k_z)           */
+    int k_y, k_z;       /* multistep orders K_y, K_z in [1, 6] (Tables 1-2)       */
+    int L;              /* Gauss-Hermite points, 1..64 (eq (21))                 */
+    int n_x[2];         /* grid points per axis, >= 4 (x_i = x_min + i dx)       */
+    double x_min[2], x_max[2];
+    double drift[2];    /* X_{t+h} = X_t + drift h + vol (W_{t+h} - W_t)          */
+    double vol[2][2];   /* row-major; d = 1 uses vol[0][0] > 0                    */
+    int driver;         /* bsde_driver_kind                                      */
+    double p[8];        /* driver parameters                                     */
+    int picard_max;     /* Picard iterations, >= 1                               */
+    double picard_tol;  /* > 0: stop a point when |dy| <= tol max(1, |y|);
+                           <= 0: exactly picard_max iterations                   */
+    int prec;           /* bsde_precision                                        */
+    int n_stop;         /* last layer computed, 0 <= n_stop <= N - K; 0 is the
+                           full sweep.  A larger value stops early (a checkpoint
+                           of the backward loop) and y0, z0 then receive layer
+                           n_stop.                                               */
+} bsde_problem;
+
+/* Opaque, immutable after creation.  A plan may be shared by threads, but
+ * solves that use one workspace must not overlap. */
+typedef struct bsde_plan_s *bsde_plan_t;
+
+typedef struct {
+    int picard_iter_max;           /* largest Picard count over all points/steps */
+    double picard_iter_mean;       /* mean Picard count per point-step            */
+    long long picard_nonconverged; /* point-steps that hit picard_max (tol mode)  */
+    long long nonfinite;           /* non-finite y or z values in the output      */
+    double stability_ratio;        /* R = vol sqrt(2 dt) / dx: Gauss-Hermite
+                                      spread per cell; the scheme loses linear
+                                      stability for large R (about R > 16)        */
+    float elapsed_ms;              /* device time of the solve (hipEvents)        */
+} bsde_stats;
+
+/* Per-instance buffers of a batched solve (all device pointers). */
+typedef struct {
+    const double *init_y; /* K x n_x: layer r at t_{N-K+1+r}, r = 0..K-1         */
+    const double *init_z; /* K x n_x                                             */
+    double *y0;           /* n_x: y at t_0 on the grid                           */
+    double *z0;           /* n_x: z at t_0 on the grid                           */
+} bsde_io;
+
+/*
+ * bsde_plan -- validate `batch` problems at pb[0..batch-1] and build their
+ * plan: Gauss-Hermite nodes and weights (eq (21), Golub-Welsch), the
+ * coefficients of Tables 1 and 2 (not-a-knot spline integrals, Section 2.1),
+ * and for every j = 1..K and node l the shifted-node offset on the uniform
+ * grid split into an integer cell and a fraction (Section 3.2, O(1)
+ * location), with the spline basis weights at that fraction.  Small constant
+ * tables are copied to the current device.
+ * Errors: BSDE_EINVAL for an invalid problem or batch < 1, BSDE_EUNSUPPORTED
+ * for d != 1, BSDE_ENOMEM, BSDE_EDEVICE.  *out is set only on success.
+ */
+bsde_status bsde_plan(const bsde_problem *pb, int batch, bsde_plan_t *out);
+
+/* Release a plan and its device tables (NULL is a no-op). */
+void bsde_plan_destroy(bsde_plan_t plan);
+
+/*
+ * bsde_workspace_bytes -- size of the caller-owned device workspace a solve
+ * with this plan needs: the ring of K + 1 time layers (y, its spline second
+ * derivatives, z, its second derivatives, ghost-padded), accumulators and
+ * statistics.  0 on a NULL plan.
+ */
+size_t bsde_workspace_bytes(bsde_plan_t plan);
+
+/*
+ * bsde_solve -- run the backward sweep of eq (20) for instance 0 of the plan:
+ * for n = N-K, ..., 0 and every grid point, the Gauss-Hermite expectations of
+ * the spline-interpolated layers n+1..n+K, the explicit z^n, the Picard solve
+ * of the implicit y^n, and the natural spline of the new layer.
+ *   ws      device workspace of at least bsde_workspace_bytes(plan) bytes,
+ *           256-byte aligned; its contents on entry do not matter.
+ *   init_y  device, K x n_x doubles: row r is y at t_{N-K+1+r} (row K-1 is the
+ *           terminal layer g(x_i)); K = max(k_y, k_z).
+ *   init_z  device, K x n_x doubles, same layout for z.
+ *   y0, z0  device, n_x doubles each: receive y and z at t_0 on the grid.
+ *   stream  hipStream_t or NULL.
+ *   st      NULL: fully asynchronous.  Non-NULL: the call synchronises the
+ *           stream, fills *st and returns BSDE_ENOCONV / BSDE_ENONFINITE when
+ *           those counts are non-zero (outputs are written in both cases).
+ * Errors: BSDE_EINVAL (NULL pointer, misaligned workspace), BSDE_EDEVICE.
+ */
+bsde_status bsde_solve(bsde_plan_t plan, void *ws, const double *init_y, const double *init_z,
+                       double *y0, double *z0, void *stream, bsde_stats *st);
+
+/*
+ * bsde_solve_batched -- bsde_solve for every instance b of a plan built with
+ * batch > 1 (instances may differ in every field except d and prec), with
+ * io[b] (host array of `batch` entries holding device pointers) giving the
+ * buffers of instance b, laid out as in bsde_solve.  One workspace serves the
+ * whole batch.  Stats, when requested, aggregate over the batch.
+ * Errors: as bsde_solve.
+ */
+bsde_status bsde_solve_batched(bsde_plan_t plan, void *ws, const bsde_io *io, void *stream,
+                               bsde_stats *st);
+
+/* Per-kernel device time of one solve, from hipEvent pairs around launches. */
+typedef struct {
+    double sweep_ms;      /* summed duration of the sweep launches (one per step) */
+    int sweep_launches;
+    double spline_ms;     /* summed duration of the spline launches of the loop   */
+    int spline_launches;
+} bsde_kernel_times;
+
+/*
+ * bsde_profile_kernels -- bsde_solve of instance 0 (same arguments, same
+ * results in y0, z0) with a hipEvent pair recorded around every launch of
+ * the sweep and spline kernels of the backward loop, so their average
+ * durations can be set against their algorithmic work.  Synchronises the
+ * stream and fills *kt.  Meant for measurement; bsde_solve is the fast path.
+ * Errors: as bsde_solve.
+ */
+bsde_status bsde_profile_kernels(bsde_plan_t plan, void *ws, const double *init_y,
+                                 const double *init_z, double *y0, double *z0, void *stream,
+                                 bsde_kernel_times *kt);
+
+/* Static text for a status code (never NULL). */
+const char *bsde_status_string(bsde_status s);
+
+/*
+ * Host-only helpers (no device needed), exposed for inspection and tests.
+ *
+ * bsde_gauss_hermite -- the L-point Gauss-Hermite rule for the weight
+ * exp(-x^2) used in eq (21): nodes a[0..L-1] ascending and weights w[0..L-1]
+ * (they sum to sqrt(pi)).  Golub-Welsch: eigen-decomposition of the Jacobi
+ * matrix of the Hermite recurrence.  BSDE_EINVAL unless 1 <= L <= 64.
+ *
+ * bsde_gamma -- table = 1: gamma^{K}_{K,j}, j = 0..K (Table 1, the spline
+ * quadrature over K steps divided by K dt); table = 2: gamma^{1}_{K,j}
+ * (Table 2, over the first step).  Computed from the not-a-knot cubic spline
+ * through K+1 equispaced points; g receives K+1 values.  BSDE_EINVAL unless
+ * table is 1 or 2 and 1 <= K <= 6.
+ */
+bsde_status bsde_gauss_hermite(int L, double *a, double *w);
+bsde_status bsde_gamma(int table, int K, double *g);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BSDE_H */

@@ -1,0 +1,295 @@
+"""Python binding of the MI355X library for the multistep BSDE scheme.
+
+Thin ctypes marshalling over the C ABI of ``include/bsde.h``: the functions
+below carry the C names and only convert arguments.  Every step of the
+backward sweep runs in the HIP kernels of ``libbsde_hip.so``; there is no
+CPU fallback, and loading fails loudly when the library is missing.
+PyTorch is used only for device memory (tensors) and streams.
+
+A problem is the plain dictionary built by ``workloads`` (keys d, T, n_t,
+k_y, k_z, L, n_x, x_min, x_max, drift, vol, driver, p, picard_max,
+picard_tol) plus an optional ``prec`` ("fp64" or "fp32_comp").
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbsde_hip.so")
+
+BSDE_OK, BSDE_EINVAL, BSDE_ENOMEM, BSDE_EDEVICE, BSDE_EUNSUPPORTED, BSDE_ENOCONV, \
+    BSDE_ENONFINITE = range(7)
+DRIVERS = {"linear": 0, "bidask": 1, "cubic": 2, "exp": 3}
+PRECISIONS = {"fp64": 0, "fp32_comp": 1}
+
+EXPORTED = ["bsde_plan", "bsde_plan_destroy", "bsde_workspace_bytes", "bsde_solve",
+            "bsde_solve_batched", "bsde_profile_kernels", "bsde_status_string",
+            "bsde_gauss_hermite", "bsde_gamma"]
+
+
+class BsdeError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        super().__init__(f"{where}: {bsde_status_string(code)} (status {code})")
+        self.code = code
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [
+        ("d", ctypes.c_int),
+        ("T", ctypes.c_double),
+        ("n_t", ctypes.c_int),
+        ("k_y", ctypes.c_int),
+        ("k_z", ctypes.c_int),
+        ("L", ctypes.c_int),
+        ("n_x", ctypes.c_int * 2),
+        ("x_min", ctypes.c_double * 2),
+        ("x_max", ctypes.c_double * 2),
+        ("drift", ctypes.c_double * 2),
+        ("vol", ctypes.c_double * 4),
+        ("driver", ctypes.c_int),
+        ("p", ctypes.c_double * 8),
+        ("picard_max", ctypes.c_int),
+        ("picard_tol", ctypes.c_double),
+        ("prec", ctypes.c_int),
+        ("n_stop", ctypes.c_int),
+    ]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [
+        ("picard_iter_max", ctypes.c_int),
+        ("picard_iter_mean", ctypes.c_double),
+        ("picard_nonconverged", ctypes.c_longlong),
+        ("nonfinite", ctypes.c_longlong),
+        ("stability_ratio", ctypes.c_double),
+        ("elapsed_ms", ctypes.c_float),
+    ]
+
+
+class _KernelTimes(ctypes.Structure):
+    _fields_ = [("sweep_ms", ctypes.c_double), ("sweep_launches", ctypes.c_int),
+                ("spline_ms", ctypes.c_double), ("spline_launches", ctypes.c_int)]
+
+
+class _Io(ctypes.Structure):
+    _fields_ = [("init_y", ctypes.c_void_p), ("init_z", ctypes.c_void_p),
+                ("y0", ctypes.c_void_p), ("z0", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libbsde_hip.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_1909_13560_amd/build.py")
+        lib = ctypes.CDLL(LIB_PATH)
+        vp, dp, ip = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int
+        lib.bsde_plan.argtypes = [ctypes.POINTER(_Problem), ip, ctypes.POINTER(vp)]
+        lib.bsde_plan.restype = ip
+        lib.bsde_plan_destroy.argtypes = [vp]
+        lib.bsde_plan_destroy.restype = None
+        lib.bsde_workspace_bytes.argtypes = [vp]
+        lib.bsde_workspace_bytes.restype = ctypes.c_size_t
+        lib.bsde_solve.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(_Stats)]
+        lib.bsde_solve.restype = ip
+        lib.bsde_solve_batched.argtypes = [vp, vp, ctypes.POINTER(_Io), vp, ctypes.POINTER(_Stats)]
+        lib.bsde_solve_batched.restype = ip
+        lib.bsde_profile_kernels.argtypes = [vp, vp, vp, vp, vp, vp, vp,
+                                             ctypes.POINTER(_KernelTimes)]
+        lib.bsde_profile_kernels.restype = ip
+        lib.bsde_status_string.argtypes = [ip]
+        lib.bsde_status_string.restype = ctypes.c_char_p
+        lib.bsde_gauss_hermite.argtypes = [ip, dp, dp]
+        lib.bsde_gauss_hermite.restype = ip
+        lib.bsde_gamma.argtypes = [ip, ip, dp]
+        lib.bsde_gamma.restype = ip
+        _lib = lib
+    return _lib
+
+
+def _pair(v, fill):
+    v = list(v) if isinstance(v, (list, tuple, np.ndarray)) else [v]
+    return (v + [fill, fill])[:2]
+
+
+def problem_struct(pb: dict) -> _Problem:
+    s = _Problem()
+    s.d = int(pb["d"])
+    s.T = float(pb["T"])
+    s.n_t = int(pb["n_t"])
+    s.k_y = int(pb["k_y"])
+    s.k_z = int(pb["k_z"])
+    s.L = int(pb["L"])
+    s.n_x[:] = [int(v) for v in _pair(pb["n_x"], 0)]
+    s.x_min[:] = [float(v) for v in _pair(pb["x_min"], 0.0)]
+    s.x_max[:] = [float(v) for v in _pair(pb["x_max"], 0.0)]
+    s.drift[:] = [float(v) for v in _pair(pb.get("drift", 0.0), 0.0)]
+    vol = np.zeros((2, 2))
+    v = np.atleast_2d(np.asarray(pb.get("vol", 1.0), dtype=float))
+    vol[: v.shape[0], : v.shape[1]] = v
+    s.vol[:] = [float(x) for x in vol.ravel()]
+    s.driver = DRIVERS[pb["driver"]]
+    p = list(pb.get("p", [])) + [0.0] * 8
+    s.p[:] = [float(x) for x in p[:8]]
+    s.picard_max = int(pb.get("picard_max", 30))
+    s.picard_tol = float(pb.get("picard_tol", 0.0))
+    s.prec = PRECISIONS[pb.get("prec", "fp64")]
+    s.n_stop = int(pb.get("n_stop", 0))
+    return s
+
+
+class Plan:
+    """Owns a bsde_plan_t handle."""
+
+    def __init__(self, handle: int, problems: list[dict]):
+        self.handle = handle
+        self.problems = problems
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            load().bsde_plan_destroy(ctypes.c_void_p(self.handle))
+            self.handle = None
+
+
+# ----------------------------------------------------------------------------
+# C ABI, same names
+# ----------------------------------------------------------------------------
+
+
+def bsde_status_string(code: int) -> str:
+    return load().bsde_status_string(int(code)).decode()
+
+
+def bsde_plan(problems) -> Plan:
+    """bsde_plan(pb, batch, &out) for a problem dict or a list of them."""
+    if isinstance(problems, dict):
+        problems = [problems]
+    arr = (_Problem * len(problems))(*[problem_struct(p) for p in problems])
+    h = ctypes.c_void_p()
+    rc = load().bsde_plan(arr, len(problems), ctypes.byref(h))
+    if rc != BSDE_OK:
+        raise BsdeError(rc, "bsde_plan")
+    return Plan(h.value, list(problems))
+
+
+def bsde_workspace_bytes(plan: Plan) -> int:
+    return int(load().bsde_workspace_bytes(ctypes.c_void_p(plan.handle)))
+
+
+def _stats_dict(st: _Stats) -> dict:
+    return {k: getattr(st, k) for k, _ in _Stats._fields_}
+
+
+def _dptr(t) -> int:
+    import torch
+
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return t.data_ptr()
+
+
+def _stream_ptr(stream) -> int | None:
+    if stream is None:
+        import torch
+
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def bsde_solve(plan: Plan, ws, init_y, init_z, y0, z0, stream=None, stats: bool = False,
+               check: bool = True):
+    """bsde_solve on torch device tensors (float64).  Returns (status, stats or None)."""
+    for t in (init_y, init_z, y0, z0):
+        if t.dtype != __import__("torch").float64:
+            raise TypeError("grid buffers are float64")
+    st = _Stats() if stats else None
+    rc = load().bsde_solve(ctypes.c_void_p(plan.handle), ctypes.c_void_p(_dptr(ws)),
+                           ctypes.c_void_p(_dptr(init_y)), ctypes.c_void_p(_dptr(init_z)),
+                           ctypes.c_void_p(_dptr(y0)), ctypes.c_void_p(_dptr(z0)),
+                           ctypes.c_void_p(_stream_ptr(stream)),
+                           ctypes.byref(st) if st is not None else None)
+    if check and rc not in (BSDE_OK, BSDE_ENOCONV, BSDE_ENONFINITE):
+        raise BsdeError(rc, "bsde_solve")
+    return rc, (_stats_dict(st) if st is not None else None)
+
+
+def bsde_solve_batched(plan: Plan, ws, ios, stream=None, stats: bool = False, check: bool = True):
+    """bsde_solve_batched; ``ios`` is a list of (init_y, init_z, y0, z0) tensors."""
+    arr = (_Io * len(ios))(*[_Io(_dptr(a), _dptr(b), _dptr(c), _dptr(d)) for a, b, c, d in ios])
+    st = _Stats() if stats else None
+    rc = load().bsde_solve_batched(ctypes.c_void_p(plan.handle), ctypes.c_void_p(_dptr(ws)), arr,
+                                   ctypes.c_void_p(_stream_ptr(stream)),
+                                   ctypes.byref(st) if st is not None else None)
+    if check and rc not in (BSDE_OK, BSDE_ENOCONV, BSDE_ENONFINITE):
+        raise BsdeError(rc, "bsde_solve_batched")
+    return rc, (_stats_dict(st) if st is not None else None)
+
+
+def bsde_profile_kernels(plan: Plan, ws, init_y, init_z, y0, z0, stream=None) -> dict:
+    """bsde_profile_kernels: per-kernel hipEvent times of one solve."""
+    kt = _KernelTimes()
+    rc = load().bsde_profile_kernels(ctypes.c_void_p(plan.handle), ctypes.c_void_p(_dptr(ws)),
+                                     ctypes.c_void_p(_dptr(init_y)), ctypes.c_void_p(_dptr(init_z)),
+                                     ctypes.c_void_p(_dptr(y0)), ctypes.c_void_p(_dptr(z0)),
+                                     ctypes.c_void_p(_stream_ptr(stream)), ctypes.byref(kt))
+    if rc != BSDE_OK:
+        raise BsdeError(rc, "bsde_profile_kernels")
+    return {k: getattr(kt, k) for k, _ in _KernelTimes._fields_}
+
+
+def bsde_gauss_hermite(L: int):
+    a = np.empty(L)
+    w = np.empty(L)
+    dp = ctypes.POINTER(ctypes.c_double)
+    rc = load().bsde_gauss_hermite(int(L), a.ctypes.data_as(dp), w.ctypes.data_as(dp))
+    if rc != BSDE_OK:
+        raise BsdeError(rc, "bsde_gauss_hermite")
+    return a, w
+
+
+def bsde_gamma(table: int, K: int):
+    g = np.empty(K + 1)
+    rc = load().bsde_gamma(int(table), int(K), g.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    if rc != BSDE_OK:
+        raise BsdeError(rc, "bsde_gamma")
+    return g
+
+
+# ----------------------------------------------------------------------------
+# Convenience: one solve from host arrays (allocation and copies only)
+# ----------------------------------------------------------------------------
+
+
+def workspace(plan: Plan, device="cuda"):
+    """A caller-owned workspace tensor, 256-byte aligned (torch allocations are)."""
+    import torch
+
+    nbytes = bsde_workspace_bytes(plan)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+    assert ws.data_ptr() % 256 == 0
+    return ws
+
+
+def solve(pb: dict, init_y: np.ndarray, init_z: np.ndarray, device="cuda", stats: bool = True):
+    """Plan, copy the K initial layers to the device, solve, copy y0/z0 back."""
+    import torch
+
+    plan = bsde_plan(pb)
+    ws = workspace(plan, device)
+    n = int(np.prod(_pair(pb["n_x"], 1)[: int(pb["d"])]))
+    K = max(int(pb["k_y"]), int(pb["k_z"]))
+    iy = torch.as_tensor(np.ascontiguousarray(init_y, dtype=np.float64).reshape(K, n), device=device)
+    iz = torch.as_tensor(np.ascontiguousarray(init_z, dtype=np.float64).reshape(K, -1), device=device)
+    y0 = torch.empty(n, dtype=torch.float64, device=device)
+    z0 = torch.empty(iz.shape[1], dtype=torch.float64, device=device)
+    rc, st = bsde_solve(plan, ws, iy, iz, y0, z0, stats=stats)
+    torch.cuda.synchronize()
+    return y0.cpu().numpy(), z0.cpu().numpy().reshape(-1, n), rc, st

@@ -1,0 +1,104 @@
+"""Host-side checks of the C-ABI library (no GPU needed).
+
+The library loads and exports every function declared in include/bsde.h; the
+host-only helpers (Gauss-Hermite rule, Tables 1-2) match independent
+references; invalid problems are rejected before any device call.
+"""
+import math
+import os
+import re
+from fractions import Fraction
+
+import numpy as np
+import pytest
+from conftest import ROOT, read_golden
+
+import paper_1909_13560_amd as B
+import workloads as W
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "bsde.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(bsde_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = B.load()
+    names = _declared_functions()
+    assert "bsde_solve" in names and "bsde_plan" in names
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(B.EXPORTED) == sorted(names)
+
+
+def test_library_has_no_oracle_dependency():
+    # the product library must not link or embed the CPU oracle
+    data = open(B.LIB_PATH, "rb").read()
+    assert b"oracle_solve" not in data and b"bsde_oracle" not in data
+
+
+@pytest.mark.parametrize("L", [1, 2, 7, 16, 32, 64])
+def test_gauss_hermite_rule_matches_numpy(L):
+    a, w = B.bsde_gauss_hermite(L)
+    a_ref, w_ref = np.polynomial.hermite.hermgauss(L)
+    np.testing.assert_allclose(a, a_ref, rtol=0, atol=3e-14 * max(1.0, np.max(abs(a_ref))))
+    np.testing.assert_allclose(w, w_ref, rtol=5e-12)
+    assert np.sum(w) == pytest.approx(math.sqrt(math.pi), rel=1e-14)
+
+
+@pytest.mark.parametrize("K", range(1, 7))
+def test_gamma_matches_printed_tables(K):
+    printed = {}
+    for t, k, j, num, den in read_golden("gamma_tables.txt"):
+        printed[(int(t), int(k), int(j))] = float(Fraction(int(num), int(den)))
+    for table in (1, 2):
+        g = B.bsde_gamma(table, K)
+        ref = [printed[(table, K, j)] for j in range(K + 1)]
+        np.testing.assert_allclose(g, ref, rtol=1e-14, atol=1e-16)
+
+
+def test_helpers_reject_bad_arguments():
+    with pytest.raises(B.BsdeError):
+        B.bsde_gauss_hermite(0)
+    with pytest.raises(B.BsdeError):
+        B.bsde_gauss_hermite(65)
+    with pytest.raises(B.BsdeError):
+        B.bsde_gamma(3, 2)
+    with pytest.raises(B.BsdeError):
+        B.bsde_gamma(1, 7)
+
+
+def test_status_strings():
+    for code in range(7):
+        assert B.bsde_status_string(code)
+    assert B.bsde_status_string(99) == "unknown status"
+
+
+@pytest.mark.parametrize("field,value", [
+    ("k_y", 0), ("k_y", 7), ("k_z", 0), ("L", 0), ("L", 65), ("n_x", 3), ("n_t", 1),
+    ("T", -1.0), ("picard_max", 0), ("x_max", -9.0), ("vol", 0.0), ("n_stop", 63),
+    ("driver", "bogus"), ("d", 3),
+])
+def test_plan_rejects_invalid_problems(field, value):
+    pb = dict(W.sine_1d().problem)
+    if field == "driver":
+        s = B.problem_struct(pb)
+        s.driver = 9
+        arr = (B._Problem * 1)(s)
+        import ctypes
+        h = ctypes.c_void_p()
+        assert B.load().bsde_plan(arr, 1, ctypes.byref(h)) == B.BSDE_EINVAL
+        return
+    pb[field] = value
+    with pytest.raises(B.BsdeError) as e:
+        B.bsde_plan(pb)
+    assert e.value.code == B.BSDE_EINVAL
+
+
+def test_plan_rejects_empty_batch():
+    import ctypes
+    h = ctypes.c_void_p()
+    arr = (B._Problem * 1)(B.problem_struct(W.sine_1d().problem))
+    assert B.load().bsde_plan(arr, 0, ctypes.byref(h)) == B.BSDE_EINVAL
+    assert B.load().bsde_plan(None, 1, ctypes.byref(h)) == B.BSDE_EINVAL

@@ -1,0 +1,192 @@
+"""GPU parity: the HIP path against the CPU oracle, element by element.
+
+Every case runs the same seeded/closed-form inputs through the C ABI (on the
+GPU) and through the serial FP64 oracle, and compares the whole output layer.
+FP64 bar: max_i |gpu_i - oracle_i| / max(|oracle_i|, 1) <= 1e-10.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-10
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1909_13560_amd as B
+
+    B.load()
+    return B
+
+
+@pytest.fixture(scope="module")
+def orc():
+    import oracle
+
+    oracle.build(force=False)
+    return oracle
+
+
+def rel_err(g, o):
+    return float(np.max(np.abs(g - o) / np.maximum(np.abs(o), 1.0)))
+
+
+def run_both(lib, orc, wl, n_stop=0, tol=TOL64, stats=True):
+    pb = dict(wl.problem)
+    pb["n_stop"] = n_stop
+    print(f"[case] {wl.name} n_stop={n_stop} R={W.stability_ratio(pb):.2f}", flush=True)
+    sys.stdout.flush()
+    iy, iz = wl.init_layers()
+    y, z, rc, st = lib.solve(pb, iy, iz, stats=stats)
+    yo, zo, sto = orc.solve(pb, iy, iz, n_stop=n_stop)
+    ey, ez = rel_err(y, yo), rel_err(z[0], zo[0])
+    print(f"  rel err y {ey:.3e} z {ez:.3e} stats {st}", flush=True)
+    assert ey <= tol and ez <= tol, (ey, ez)
+    return y, z, yo, zo, rc, st, sto
+
+
+def twin_half_width(sigma, T, n_t, n_x, R=16.0):
+    """Half-width of the log-price interval that gives stability ratio R."""
+    return sigma * math.sqrt(2 * T / n_t) / R * (n_x - 1) / 2
+
+
+def test_sine_problem(lib, orc):
+    wl = W.sine_1d()
+    y, z, yo, zo, rc, st, _ = run_both(lib, orc, wl)
+    assert rc == lib.BSDE_OK and st["picard_iter_max"] == 30
+    i = wl.node_index()
+    assert abs(y[i] - 0.0) < 1e-4 and abs(z[0, i] - 1.0) < 2e-4
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6])
+def test_black_scholes_all_orders(lib, orc, k):
+    nx, nt = 3001, 40
+    wl = W.bs_call_1d(n_x=nx, n_t=nt, k=k, L=32, half_width=twin_half_width(0.2, 0.33, nt, nx))
+    run_both(lib, orc, wl)
+
+
+@pytest.mark.parametrize("sign", [1.0, -1.0])
+def test_bid_ask_ragged_grid(lib, orc, sign):
+    nx, nt = 5003, 48
+    wl = W.bidask_call_1d(n_x=nx, n_t=nt, sign=sign, half_width=twin_half_width(0.2, 0.5, nt, nx))
+    _, _, _, _, rc, st, sto = run_both(lib, orc, wl)
+    assert rc == lib.BSDE_OK
+    assert st["picard_iter_max"] == sto["picard_iter_max"]
+    assert st["picard_nonconverged"] == 0
+
+
+def test_example1_table4_row(lib, orc):
+    # Example 1, K = 3, N = 128, M = 4096: the paper prints 1.44e-11 / 2.77e-8
+    wl = W.paper_example1(3, 128, 4096)
+    y, z, *_ = run_both(lib, orc, wl)
+    i = wl.node_index()
+    assert abs(y[i] - 0.5) == pytest.approx(1.44e-11, rel=0.03)
+    assert abs(z[0, i] - 0.25) == pytest.approx(2.77e-8, rel=0.02)
+
+
+def test_example2_exp_driver(lib, orc):
+    run_both(lib, orc, W.paper_example2(4, 32, 1024))
+
+
+@pytest.mark.parametrize("ky,kz", [(2, 3), (3, 1), (1, 4)])
+def test_unequal_orders(lib, orc, ky, kz):
+    wl = W.sine_1d(n_x=777, n_t=30)
+    wl.problem.update(k_y=ky, k_z=kz)
+    run_both(lib, orc, wl)
+
+
+@pytest.mark.parametrize("n_x", [4, 5, 63, 64, 65, 513])
+def test_small_and_ragged_grids(lib, orc, n_x):
+    wl = W.sine_1d(n_x=n_x, n_t=12, k=3)
+    run_both(lib, orc, wl)
+
+
+@pytest.mark.parametrize("L", [1, 2, 7, 64])
+def test_quadrature_orders(lib, orc, L):
+    wl = W.sine_1d(n_x=300, n_t=10, k=2, L=L)
+    run_both(lib, orc, wl)
+
+
+def test_single_step(lib, orc):
+    # N = K: exactly one backward step
+    wl = W.sine_1d(n_x=100, n_t=4, k=4)
+    run_both(lib, orc, wl)
+
+
+def test_checkpoint_layer(lib, orc):
+    wl = W.bidask_call_1d(n_x=2000, n_t=40, half_width=None)
+    run_both(lib, orc, wl, n_stop=17)
+
+
+def test_wide_reach_literal_domain(lib, orc):
+    # large stability ratio: nodes reach far beyond the tile, ghost cells wide
+    wl = W.bidask_call_1d(n_x=20000, n_t=16, half_width=None)
+    run_both(lib, orc, wl)
+
+
+def test_full_size_bidask_first_steps(lib, orc):
+    # the benchmarked shape: 262144 points, 1024 steps, k = 4, L = 16, stable
+    # domain; the oracle follows the first four steps
+    nx, nt = 262144, 1024
+    wl = W.bidask_call_1d(n_x=nx, n_t=nt, half_width=52.0)
+    run_both(lib, orc, wl, n_stop=nt - 4 - 3)
+
+
+def test_deterministic(lib):
+    wl = W.bidask_call_1d(n_x=3000, n_t=20, half_width=None)
+    iy, iz = wl.init_layers()
+    y1, z1, _, _ = lib.solve(wl.problem, iy, iz)
+    y2, z2, _, _ = lib.solve(wl.problem, iy, iz)
+    assert np.array_equal(y1, y2) and np.array_equal(z1, z2)
+
+
+def test_nonfinite_is_reported(lib):
+    wl = W.sine_1d(n_x=200, n_t=8)
+    iy, iz = wl.init_layers()
+    iy[-1, 100] = np.nan
+    y, z, rc, st = lib.solve(wl.problem, iy, iz)
+    assert rc == lib.BSDE_ENONFINITE and st["nonfinite"] > 0
+
+
+def test_picard_nonconvergence_is_reported(lib):
+    wl = W.bidask_call_1d(n_x=500, n_t=10, half_width=None, picard_tol=1e-300, picard_max=2)
+    iy, iz = wl.init_layers()
+    y, z, rc, st = lib.solve(wl.problem, iy, iz)
+    assert rc == lib.BSDE_ENOCONV
+    assert st["picard_nonconverged"] > 0 and st["picard_iter_max"] == 2
+
+
+def test_batched_equals_single(lib):
+    import torch
+
+    wls = [W.sine_1d(n_x=700, n_t=20, k=2), W.bidask_call_1d(n_x=1500, n_t=16, half_width=None),
+           W.bs_call_1d(n_x=999, n_t=12, k=5, L=16, half_width=None)]
+    plan = lib.bsde_plan([w.problem for w in wls])
+    ws = lib.workspace(plan)
+    ios, outs = [], []
+    for w in wls:
+        iy, iz = w.init_layers()
+        n = iy.shape[1]
+        t_iy = torch.as_tensor(iy, device="cuda").contiguous()
+        t_iz = torch.as_tensor(iz.reshape(iy.shape[0], n), device="cuda").contiguous()
+        y0 = torch.empty(n, dtype=torch.float64, device="cuda")
+        z0 = torch.empty(n, dtype=torch.float64, device="cuda")
+        ios.append((t_iy, t_iz, y0, z0))
+    rc, st = lib.bsde_solve_batched(plan, ws, ios, stats=True)
+    torch.cuda.synchronize()
+    assert rc == lib.BSDE_OK
+    for w, (t_iy, t_iz, y0, z0) in zip(wls, ios):
+        iy, iz = w.init_layers()
+        y, z, _, _ = lib.solve(w.problem, iy, iz)
+        assert np.array_equal(y0.cpu().numpy(), y)
+        assert np.array_equal(z0.cpu().numpy(), z[0])
