@@ -66,6 +66,35 @@ def bytes_per_point_step(pb: dict) -> float:
     return 32.0 * K + 16.0
 
 
+KERNEL_SOURCES = ["capi.hip", "kernels_f64.hip", "device_common.h", "kernels.h", "plan_math.cpp",
+                  "plan_math.h"]
+
+
+def sources_sha1() -> str:
+    """Hash of the library sources, to tie stored counter readings to a kernel version."""
+    import hashlib
+
+    h = hashlib.sha1()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1909_13560_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload_name: str):
+    """HBM bytes per sweep launch from the committed counter readings, or None
+    when they were taken on other kernel sources or another workload."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("sources_sha1") != sources_sha1() or t.get("workload") != workload_name:
+        return None
+    return 1024.0 * (t["fetch_kib"] * t["read_factor"] + t["write_kib"] * t["write_factor"])
+
+
 def cpu_baseline(wl, budget_s: float = 15.0) -> dict:
     """Serial oracle on the first steps of the same workload (bounded sample)."""
     import oracle
@@ -97,7 +126,24 @@ def main() -> int:
     ap.add_argument("--workload", default="bidask1d")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--profile-steps", type=int, default=0,
+                    help="profiling runs: stop each solve after this many backward steps "
+                         "(same per-step kernel shape; throughput then counts those steps)")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="run only a plain device-to-device copy of this many MiB (for "
+                         "scaling the hardware byte counters) and exit")
     args = ap.parse_args()
+    if args.calibrate_copy_mib:
+        import torch
+
+        n = args.calibrate_copy_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "copies": 3}))
+        return 0
     if args.gpus != 1:
         print("bench.py measures one GPU: the method has no cross-GPU communication and this "
               "build runs on a single MI355X; --gpus must be 1", file=sys.stderr)
@@ -109,6 +155,11 @@ def main() -> int:
 
     wl = workload(args.workload)
     pb = wl.problem
+    steps_run = pb["n_t"] - wl.K + 1
+    if args.profile_steps:
+        steps_run = min(args.profile_steps, steps_run)
+        pb["n_stop"] = pb["n_t"] - wl.K + 1 - steps_run
+        args.no_cpu_baseline = True
     dev = "cuda:0"
     torch.cuda.set_device(0)
     plan = B.bsde_plan(pb)
@@ -137,17 +188,17 @@ def main() -> int:
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / args.steps
-    value = nx * pb["n_t"] / (ms * 1e-3)
+    value = nx * (pb["n_t"] if not args.profile_steps else steps_run) / (ms * 1e-3)
     print(f"[bench] {args.steps} solves, {ms:.3f} ms per solve", file=sys.stderr, flush=True)
 
     # per-kernel durations from hipEvents around every launch of one solve
     kt = B.bsde_profile_kernels(plan, ws, t_iy, t_iz, y0, z0, stream=stream)
     sweep_ms = kt["sweep_ms"] / kt["sweep_launches"]
-    spline_ms = kt["spline_ms"] / kt["spline_launches"]
+    spline_ms = kt["spline_ms"] / kt["spline_launches"] if kt["spline_launches"] else 0.0
     fl = flops_per_point_step(pb, st["picard_iter_mean"]) * nx
     achieved = fl / (sweep_ms * 1e-3) / 1e12
     print(f"[bench] sweep kernel {sweep_ms * 1e3:.1f} us/launch, spline {spline_ms * 1e3:.1f} "
-          f"us/launch", file=sys.stderr, flush=True)
+          f"us/launch, config {kt}", file=sys.stderr, flush=True)
 
     # error of the headline value against the closed form
     y_h = y0.cpu().numpy()
@@ -176,7 +227,7 @@ def main() -> int:
                    "stability_ratio": st["stability_ratio"]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_VALU_PEAK_TFLOPS,
-                     "traffic": None, "kernel": "sweep_f64",
+                     "traffic": measured_traffic(wl.name), "kernel": "sweep_fused",
                      "kernel_us": sweep_ms * 1e3,
                      "flops_per_launch": fl,
                      "hbm_bytes_per_launch_algorithmic": bytes_per_point_step(pb) * nx},

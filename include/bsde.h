@@ -170,8 +170,15 @@ bsde_status bsde_solve_batched(bsde_plan_t plan, void *ws, const bsde_io *io, vo
 typedef struct {
     double sweep_ms;      /* summed duration of the sweep launches (one per step) */
     int sweep_launches;
-    double spline_ms;     /* summed duration of the spline launches of the loop   */
+    double spline_ms;     /* summed duration of the separate spline launches of
+                             the loop (0 launches when the sweep kernel builds
+                             the splines itself)                                  */
     int spline_launches;
+    int path;             /* sweep kernel: 0 = LDS-staged windows with the spline
+                             of the newest layer in-kernel, 1 = direct loads     */
+    int points_per_lane;  /* grid points per lane of the sweep kernel            */
+    int blocks;           /* blocks per sweep launch                             */
+    long long lds_bytes;  /* dynamic LDS per block of the sweep kernel           */
 } bsde_kernel_times;
 
 /*

@@ -71,7 +71,9 @@ class _Stats(ctypes.Structure):
 
 class _KernelTimes(ctypes.Structure):
     _fields_ = [("sweep_ms", ctypes.c_double), ("sweep_launches", ctypes.c_int),
-                ("spline_ms", ctypes.c_double), ("spline_launches", ctypes.c_int)]
+                ("spline_ms", ctypes.c_double), ("spline_launches", ctypes.c_int),
+                ("path", ctypes.c_int), ("points_per_lane", ctypes.c_int),
+                ("blocks", ctypes.c_int), ("lds_bytes", ctypes.c_longlong)]
 
 
 class _Io(ctypes.Structure):

@@ -1,0 +1,351 @@
+// device_common.h -- data layout, drivers and shared device helpers of the
+// backward sweep of the multistep BSDE scheme (arXiv:1909.13560).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/bsde.h"
+
+namespace bsde {
+
+// One grid point of one time layer: the value and the natural-spline second
+// derivative of y and of z.  32 bytes, so one record is two 16-byte halves
+// (y, M_y) and (z, M_z).
+struct alignas(16) Rec64 {
+    double y, My, z, Mz;
+};
+
+constexpr int kBlock = 256;        // threads per block of every kernel
+constexpr int kPcrRounds = 5;      // PCR strides 1, 2, 4, 8, 16
+constexpr int kHalo = 32;          // > 1 + 2 + 4 + 8 + 16: reach of the truncated PCR
+constexpr int kPcrMaxPerThread = 8;// spline windows of at most kBlock * 8 records
+constexpr int kSplineTile = 1024;  // grid points per block of the standalone spline kernel
+
+// Coefficients of one Gauss-Hermite node (j, l): the same for every grid
+// point, so a block copies the whole table to LDS once and every lane reads
+// the same address (a broadcast).
+struct alignas(16) NodeRec {
+    double A, B;   // spline basis weights at the fraction phi: A = 1-phi, B = phi,
+    double C, D;   //   C = dx^2/6 ((1-phi)^3 - (1-phi)), D = dx^2/6 (phi^3 - phi)
+    double cfy;    // weight of f-hat in the constant of the y equation
+    double cfz;    // weight of f-hat in z^n
+    double cz;     // weight of z-hat in z^n
+    double cy;     // weight of y-hat in the y constant (non-zero only for j = K_y)
+};
+
+// Node table of one instance (device memory).  K*L entries, row j-1 holds the
+// L nodes of layer n+j.
+struct NodeTable {
+    const NodeRec *rec;
+    const int *m;       // integer cell offset of the node from x_i
+    const int *win_lo;  // [K+1]: lowest node offset of layer j (j = 1 also <= 0)
+    const int *win_hi;  // [K+1]: highest node offset of layer j (j = 1 also >= 0)
+};
+
+constexpr int kMaxNodes = 6 * 64;  // K * L at most
+
+struct DriverParams {
+    double p0, p1, p2, p3, p4;
+};
+
+// Coefficients of the truncated parallel cyclic reduction of (1, 4, 1).
+struct PcrCoef {
+    double s6;                   // 6 / dx^2
+    double kappa[kPcrRounds];    // elimination factor of each round
+    double inv_b;                // 1 / diagonal after the last round
+};
+
+struct SweepArgs {
+    Rec64 *ring;
+    NodeTable tab;
+    DriverParams drv;
+    PcrCoef pcr;
+    int n;            // time index of the layer being computed
+    int nx, npad, pad_l, pad_r;
+    int K, Ky, L;
+    int lds_cap, lds_cap1;  // records of the window arrays / of the PCR arrays
+    double dt;
+    double h0;        // K_y dt gamma_{K_y,0}: weight of the implicit f(t_n, y^n, z^n)
+    int picard_max;
+    double picard_tol;
+    unsigned int *st_iter_max;        // per-wave running maximum (NULL: no stats)
+    unsigned long long *st_iter_sum;  // per-wave running sum
+    unsigned long long *st_nonconv;   // per-wave count of unconverged point-steps
+};
+
+// ---------------------------------------------------------------------------
+// Drivers f(t, y, z) (problem statement eq (2); Examples 1-3 of Section 5)
+// ---------------------------------------------------------------------------
+template <int DRV>
+struct Driver;
+
+template <>
+struct Driver<BSDE_DRIVER_LINEAR> {  // p0 y + p1 z + p3
+    double a, b, c;
+    __device__ Driver(const DriverParams &p, double) : a(p.p0), b(p.p1), c(p.p3) {}
+    __device__ double operator()(double y, double z) const { return fma(a, y, fma(b, z, c)); }
+};
+
+template <>
+struct Driver<BSDE_DRIVER_BIDASK> {  // -r y - theta z + s (R - r) min(y - z/sigma, 0)
+    double mr, mth, c, inv_sg;
+    __device__ Driver(const DriverParams &p, double)
+        : mr(-p.p0), mth(-p.p2), c(p.p4 * (p.p1 - p.p0)), inv_sg(1.0 / p.p3) {}
+    __device__ double operator()(double y, double z) const
+    {
+        const double m = fmin(fma(-z, inv_sg, y), 0.0);
+        return fma(mr, y, fma(mth, z, c * m));
+    }
+};
+
+template <>
+struct Driver<BSDE_DRIVER_CUBIC> {  // Example 1: -y^3 + 5/2 y^2 - 3/2 y
+    __device__ Driver(const DriverParams &, double) {}
+    __device__ double operator()(double y, double) const
+    {
+        return y * fma(y, 2.5 - y, -1.5);
+    }
+};
+
+template <>
+struct Driver<BSDE_DRIVER_EXP> {  // Example 2: (e^{t^2} - 4ty - 3e^{t^2 - y e^{-t^2}} + z^2 e^{-t^2})/2
+    double t, t2, et, emt;
+    __device__ Driver(const DriverParams &, double tt)
+        : t(tt), t2(tt * tt), et(exp(tt * tt)), emt(exp(-tt * tt)) {}
+    __device__ double operator()(double y, double z) const
+    {
+        return 0.5 * (et - 4.0 * t * y - 3.0 * exp(t2 - y * emt) + z * z * emt);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Wavefront reductions (64 lanes) and the XCD-aware block order
+// ---------------------------------------------------------------------------
+__device__ inline unsigned int wave_max_u32(unsigned int v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = max(v, (unsigned int)__shfl_xor((int)v, o, 64));
+    return v;
+}
+__device__ inline unsigned int wave_sum_u32(unsigned int v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += (unsigned int)__shfl_xor((int)v, o, 64);
+    return v;
+}
+
+// Blocks are handed to the 8 XCDs round-robin; remap so that each XCD works
+// on one contiguous range of tiles (neighbouring tiles share node windows,
+// hence L2 lines).  A bijection of [0, nb).
+__device__ inline int xcd_tile(int b, int nb)
+{
+    const int per = nb >> 3, rem = nb & 7;
+    const int x = b & 7, r = b >> 3;
+    return x * per + min(x, rem) + r;
+}
+
+// ---------------------------------------------------------------------------
+// Natural cubic spline of a layer on a window, second-derivative form:
+//   M_0 = M_{N-1} = 0,  M_{i-1} + 4 M_i + M_{i+1} = r_i = 6/dx^2 (y_{i+1} - 2 y_i + y_{i-1}).
+// Extending r oddly about 0 and N-1 (period 2(N-1)) gives the bi-infinite
+// system (1, 4, 1) M = r~ whose solution is the odd extension of M.  Five
+// rounds of parallel cyclic reduction leave a coupling below 1e-18 of the
+// diagonal, so M_i = r~^(5)_i / b_5, which depends on r~ within 31 cells.
+// ---------------------------------------------------------------------------
+
+// r~_k / (6/dx^2) for any integer k, from the layer in HBM (used where the
+// window does not hold the neighbours or k is outside [1, N-2]).
+__device__ inline double rtilde_global(const Rec64 *__restrict__ g, int nx, int k, bool zf)
+{
+    const int per = 2 * (nx - 1);
+    int kk = k % per;
+    if (kk < 0) kk += per;
+    double sign = 1.0;
+    if (kk > nx - 1) {
+        kk = per - kk;
+        sign = -1.0;
+    }
+    if (kk == 0 || kk == nx - 1) return 0.0;
+    const double vm = zf ? g[kk - 1].z : g[kk - 1].y;
+    const double v0 = zf ? g[kk].z : g[kk].y;
+    const double vp = zf ? g[kk + 1].z : g[kk + 1].y;
+    return sign * ((vp - v0) - (v0 - vm));
+}
+
+// Stage y and z of layer g over records [lo - kHalo, lo + W + kHalo) into
+// wy[.].x / wz[.].x (index e = k - lo + kHalo; outside [0, N) the boundary
+// value, i.e. the ghost record), then leave M_y, M_z for the records
+// [lo, lo + W) in wy[.].y / wz[.].y (0 outside (0, N-1)).  Ry, Rz hold
+// W + 2 kHalo doubles each.  Called by all kBlock threads; ends synchronised.
+__device__ inline void spline_window(const Rec64 *__restrict__ g, int nx, int lo, int W,
+                                     double2 *wy, double2 *wz, double *Ry, double *Rz,
+                                     const PcrCoef &c)
+{
+    const int tid = threadIdx.x;
+    const int WE = W + 2 * kHalo;
+    for (int e = tid; e < WE; e += kBlock) {
+        const int k = lo - kHalo + e;
+        const int kc = min(max(k, 0), nx - 1);
+        wy[e].x = g[kc].y;
+        wz[e].x = g[kc].z;
+    }
+    __syncthreads();
+    for (int e = tid; e < WE; e += kBlock) {
+        const int k = lo - kHalo + e;
+        double ry, rz;
+        if (k >= 1 && k <= nx - 2 && e >= 1 && e <= WE - 2) {
+            const double ym = wy[e - 1].x, y0 = wy[e].x, yp = wy[e + 1].x;
+            const double zm = wz[e - 1].x, z0 = wz[e].x, zp = wz[e + 1].x;
+            ry = (yp - y0) - (y0 - ym);
+            rz = (zp - z0) - (z0 - zm);
+        } else {
+            ry = rtilde_global(g, nx, k, false);
+            rz = rtilde_global(g, nx, k, true);
+        }
+        Ry[e] = c.s6 * ry;
+        Rz[e] = c.s6 * rz;
+    }
+    __syncthreads();
+    int h = 1;
+    for (int s = 0; s < kPcrRounds; ++s, h <<= 1) {
+        const double kap = c.kappa[s];
+        double ny[kPcrMaxPerThread], nz[kPcrMaxPerThread];
+#pragma unroll
+        for (int u = 0; u < kPcrMaxPerThread; ++u) {
+            const int e = tid + u * kBlock;
+            if (e >= h && e < WE - h) {
+                ny[u] = fma(-kap, Ry[e - h] + Ry[e + h], Ry[e]);
+                nz[u] = fma(-kap, Rz[e - h] + Rz[e + h], Rz[e]);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kPcrMaxPerThread; ++u) {
+            const int e = tid + u * kBlock;
+            if (e >= h && e < WE - h) {
+                Ry[e] = ny[u];
+                Rz[e] = nz[u];
+            }
+        }
+        __syncthreads();
+    }
+    for (int e = kHalo + tid; e < kHalo + W; e += kBlock) {
+        const int k = lo - kHalo + e;
+        const bool inner = (k > 0 && k < nx - 1);
+        wy[e].y = inner ? Ry[e] * c.inv_b : 0.0;
+        wz[e].y = inner ? Rz[e] * c.inv_b : 0.0;
+    }
+    __syncthreads();
+}
+
+// Copy the node table (K*L records and offsets) of an instance into LDS,
+// where every lane of a wavefront reads the same address (a broadcast).
+// Called by all kBlock threads; ends synchronised.
+__device__ inline void load_node_table(const NodeTable &t, int nodes, NodeRec *trec, int *tm)
+{
+    for (int i = threadIdx.x; i < nodes; i += kBlock) {
+        trec[i] = t.rec[i];
+        tm[i] = t.m[i];
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Per-node work shared by the sweep kernels: interpolate y and z at the node
+// for P consecutive points from P+1 consecutive records, evaluate f, and
+// accumulate into the y-equation constant Y and into z^n (Z).  LASTY adds
+// the expectation of y itself (the layer j = K_y).
+// ---------------------------------------------------------------------------
+template <int P, int DRV, bool LASTY>
+__device__ inline void node_accumulate(const double2 (&ry)[P + 1], const double2 (&rz)[P + 1],
+                                       const NodeRec &c, const Driver<DRV> &f, double (&Y)[P],
+                                       double (&Z)[P])
+{
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+        const double yh =
+            fma(c.A, ry[q].x, fma(c.B, ry[q + 1].x, fma(c.C, ry[q].y, c.D * ry[q + 1].y)));
+        const double zh =
+            fma(c.A, rz[q].x, fma(c.B, rz[q + 1].x, fma(c.C, rz[q].y, c.D * rz[q + 1].y)));
+        const double fh = f(yh, zh);
+        double y = fma(c.cfy, fh, Y[q]);
+        if (LASTY) y = fma(c.cy, yh, y);
+        Y[q] = y;
+        Z[q] = fma(c.cfz, fh, fma(c.cz, zh, Z[q]));
+    }
+}
+
+// All L nodes of one layer, reading P+1 consecutive records per lane from
+// the window arrays wy / wz starting at index ebase + m (LDS or HBM).  The
+// coefficients of the next node are fetched before the current one is used.
+template <int P, int DRV, bool LASTY, typename Src>
+__device__ inline void layer_nodes(const Src &src, const NodeRec *trec, const int *tm, int row,
+                                   int L, const Driver<DRV> &f, double (&Y)[P], double (&Z)[P])
+{
+    NodeRec cur = trec[row];
+    int mcur = tm[row];
+    for (int l = 0; l < L; ++l) {
+        double2 ry[P + 1], rz[P + 1];
+        src.template fetch<P>(mcur, ry, rz);
+        const int nx = row + min(l + 1, L - 1);
+        const NodeRec nxt = trec[nx];
+        const int mnxt = tm[nx];
+        node_accumulate<P, DRV, LASTY>(ry, rz, cur, f, Y, Z);
+        cur = nxt;
+        mcur = mnxt;
+    }
+}
+
+// z^n is complete in Z; the implicit y equation y = Y + h0 f(t_n, y, z^n) is
+// solved by Picard iteration from y^{n+1}_i; results go to layer n.
+template <int P, int DRV>
+__device__ inline void finish_points(const SweepArgs &a, int first, const double (&Y)[P],
+                                     const double (&Z)[P])
+{
+    const int S = a.K + 1;
+    const Driver<DRV> f0(a.drv, a.n * a.dt);
+    const Rec64 *__restrict__ prev = a.ring + (size_t)((a.n + 1) % S) * a.npad + a.pad_l;
+    Rec64 *__restrict__ out = a.ring + (size_t)(a.n % S) * a.npad + a.pad_l;
+    unsigned int it_max = 0, it_sum = 0, nonconv = 0;
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+        const int i = first + q;
+        const bool valid = i < a.nx;
+        double y = prev[min(i, a.nx - 1)].y;
+        int it = 0;
+        bool conv = true;
+        if (a.picard_tol > 0.0) {
+            conv = false;
+            while (it < a.picard_max) {
+                const double yn = fma(a.h0, f0(y, Z[q]), Y[q]);
+                ++it;
+                const double dy = fabs(yn - y);
+                y = yn;
+                if (dy <= a.picard_tol * fmax(1.0, fabs(y))) {
+                    conv = true;
+                    break;
+                }
+            }
+        } else {
+            for (; it < a.picard_max; ++it) y = fma(a.h0, f0(y, Z[q]), Y[q]);
+        }
+        if (valid) {
+            out[i].y = y;
+            out[i].z = Z[q];
+            it_max = max(it_max, (unsigned int)it);
+            it_sum += it;
+            nonconv += conv ? 0u : 1u;
+        }
+    }
+    if (a.st_iter_max) {
+        it_max = wave_max_u32(it_max);
+        it_sum = wave_sum_u32(it_sum);
+        nonconv = wave_sum_u32(nonconv);
+        if ((threadIdx.x & 63) == 0) {
+            const int w = (blockIdx.x * kBlock + threadIdx.x) >> 6;
+            a.st_iter_max[w] = max(a.st_iter_max[w], it_max);
+            a.st_iter_sum[w] += it_sum;
+            a.st_nonconv[w] += nonconv;
+        }
+    }
+}
+
+}  // namespace bsde

@@ -1,0 +1,391 @@
+// kernels_f64.hip -- FP64 kernels of the backward sweep (arXiv:1909.13560,
+// Section 2.2 eq (20)-(21), Section 3.1 step 3, Section 3.2) and their
+// host-side launchers.
+//
+// Two sweep kernels compute layer n from layers n+1..n+K:
+//   sweep_fused  (one launch per time step): a block owns a tile of
+//                kBlock*P consecutive grid points.  For each layer j it stages
+//                the records its nodes touch (the tile widened by the node
+//                offsets of layer j) in LDS; for j = 1 it first solves that
+//                layer's natural spline on the window by truncated PCR and
+//                writes the tile's second derivatives back to HBM, so no
+//                separate spline launch is needed.  Each lane handles P
+//                consecutive points; P is odd, which makes the 16-byte LDS
+//                reads of a wavefront bank-conflict free.
+//   sweep_direct (wide node reach, window too big for LDS): records are read
+//                straight from HBM/L2, P consecutive points per lane; the
+//                natural spline of the new layer is a separate launch of
+//                spline_f64.
+#include "device_common.h"
+#include "kernels.h"
+
+namespace bsde {
+
+// Node records read from the LDS window arrays (fused kernel).
+struct LdsWindow {
+    const double2 *wy, *wz;
+    int ebase;  // window index of the lane's first point at node offset 0
+    template <int P>
+    __device__ void fetch(int m, double2 (&ry)[P + 1], double2 (&rz)[P + 1]) const
+    {
+        const int e0 = ebase + m;
+#pragma unroll
+        for (int q = 0; q <= P; ++q) {
+            ry[q] = wy[e0 + q];
+            rz[q] = wz[e0 + q];
+        }
+    }
+};
+
+// Node records read straight from the layer in HBM (direct kernel).
+struct GlobalWindow {
+    const Rec64 *lay;  // record of the lane's first point
+    template <int P>
+    __device__ void fetch(int m, double2 (&ry)[P + 1], double2 (&rz)[P + 1]) const
+    {
+        const Rec64 *__restrict__ s = lay + m;
+#pragma unroll
+        for (int q = 0; q <= P; ++q) {
+            const Rec64 r = s[q];
+            ry[q] = make_double2(r.y, r.My);
+            rz[q] = make_double2(r.z, r.Mz);
+        }
+    }
+};
+
+template <int P, int DRV, typename Src>
+__device__ inline void layer_dispatch(const Src &src, const NodeRec *trec, const int *tm, int j,
+                                      const SweepArgs &a, double (&Y)[P], double (&Z)[P])
+{
+    const Driver<DRV> f(a.drv, (a.n + j) * a.dt);
+    const int row = (j - 1) * a.L;
+    if (j == a.Ky)
+        layer_nodes<P, DRV, true>(src, trec, tm, row, a.L, f, Y, Z);
+    else
+        layer_nodes<P, DRV, false>(src, trec, tm, row, a.L, f, Y, Z);
+}
+
+// ---------------------------------------------------------------------------
+// Fused sweep: LDS-staged windows, in-kernel spline of layer n+1.
+// Dynamic LDS: wy[cap], wz[cap] (double2), Ry[cap1], Rz[cap1] (double),
+// node table (K*L NodeRec, K*L int).
+// ---------------------------------------------------------------------------
+template <int P, int DRV>
+__global__ void __launch_bounds__(kBlock) sweep_fused(const SweepArgs a)
+{
+    constexpr int T = kBlock * P;
+    extern __shared__ double2 smem[];
+    double2 *wy = smem;
+    double2 *wz = wy + a.lds_cap;
+    double *Ry = reinterpret_cast<double *>(wz + a.lds_cap);
+    double *Rz = Ry + a.lds_cap1;
+    NodeRec *trec = reinterpret_cast<NodeRec *>(Rz + a.lds_cap1);
+    int *tm = reinterpret_cast<int *>(trec + a.K * a.L);
+
+    const int tid = threadIdx.x;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int t0 = tile * T;
+    const int S = a.K + 1;
+    load_node_table(a.tab, a.K * a.L, trec, tm);
+
+    double Y[P], Z[P];
+#pragma unroll
+    for (int q = 0; q < P; ++q) Y[q] = Z[q] = 0.0;
+
+    for (int j = 1; j <= a.K; ++j) {
+        Rec64 *__restrict__ g = a.ring + (size_t)((a.n + j) % S) * a.npad + a.pad_l;
+        const int mlo = a.tab.win_lo[j], mhi = a.tab.win_hi[j];
+        const int W = T + (mhi - mlo) + 1;
+        const int lo = t0 + mlo;
+        if (j == 1) {
+            // layer n+1 was produced by the previous launch: build its spline
+            // on the window, and store the tile's part for the later steps
+            spline_window(g, a.nx, lo, W, wy, wz, Ry, Rz, a.pcr);
+            const int kend = min(t0 + T, a.nx);
+            for (int k = t0 + tid; k < kend; k += kBlock) {
+                const int e = k - lo + kHalo;
+                g[k].My = wy[e].y;
+                g[k].Mz = wz[e].y;
+            }
+            if (tile == 0) {
+                const double y0 = g[0].y, z0 = g[0].z;
+                for (int k = tid; k < a.pad_l; k += kBlock)
+                    g[k - a.pad_l] = Rec64{y0, 0.0, z0, 0.0};
+            }
+            if (tile == (int)gridDim.x - 1) {
+                const double yn = g[a.nx - 1].y, zn = g[a.nx - 1].z;
+                for (int k = tid; k < a.pad_r; k += kBlock) g[a.nx + k] = Rec64{yn, 0.0, zn, 0.0};
+            }
+        } else {
+            for (int e = tid; e < W; e += kBlock) {
+                const Rec64 r = g[lo + e];
+                wy[kHalo + e] = make_double2(r.y, r.My);
+                wz[kHalo + e] = make_double2(r.z, r.Mz);
+            }
+            __syncthreads();
+        }
+        const LdsWindow src{wy, wz, kHalo - mlo + tid * P};
+        layer_dispatch<P, DRV>(src, trec, tm, j, a, Y, Z);
+        __syncthreads();  // the window is reused by the next layer
+    }
+    finish_points<P, DRV>(a, t0 + tid * P, Y, Z);
+}
+
+// ---------------------------------------------------------------------------
+// Direct sweep: records from HBM/L2, P consecutive points per lane.
+// Dynamic LDS: node table only.
+// ---------------------------------------------------------------------------
+template <int P, int DRV>
+__global__ void __launch_bounds__(kBlock) sweep_direct(const SweepArgs a)
+{
+    extern __shared__ double2 smem[];
+    NodeRec *trec = reinterpret_cast<NodeRec *>(smem);
+    int *tm = reinterpret_cast<int *>(trec + a.K * a.L);
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int first = (tile * kBlock + (int)threadIdx.x) * P;
+    const int i0 = min(first, a.nx - 1);  // lanes past the end read in bounds, store nothing
+    const int S = a.K + 1;
+    load_node_table(a.tab, a.K * a.L, trec, tm);
+    double Y[P], Z[P];
+#pragma unroll
+    for (int q = 0; q < P; ++q) Y[q] = Z[q] = 0.0;
+    for (int j = 1; j <= a.K; ++j) {
+        const GlobalWindow src{a.ring + (size_t)((a.n + j) % S) * a.npad + a.pad_l + i0};
+        layer_dispatch<P, DRV>(src, trec, tm, j, a, Y, Z);
+    }
+    finish_points<P, DRV>(a, first, Y, Z);
+}
+
+// ---------------------------------------------------------------------------
+// Standalone natural spline of one layer (initial layers; direct path).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock) spline_f64(Rec64 *slot, int nx, int pad_l, int pad_r,
+                                                     const PcrCoef c)
+{
+    constexpr int WE = kSplineTile + 2 * kHalo;
+    __shared__ double2 wy[WE], wz[WE];
+    __shared__ double Ry[WE], Rz[WE];
+    Rec64 *__restrict__ g = slot + pad_l;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int t0 = tile * kSplineTile;
+    spline_window(g, nx, t0, kSplineTile, wy, wz, Ry, Rz, c);
+    const int kend = min(t0 + kSplineTile, nx);
+    for (int k = t0 + (int)threadIdx.x; k < kend; k += kBlock) {
+        g[k].My = wy[k - t0 + kHalo].y;
+        g[k].Mz = wz[k - t0 + kHalo].y;
+    }
+    if (tile == 0) {
+        const double y0 = g[0].y, z0 = g[0].z;
+        for (int k = threadIdx.x; k < pad_l; k += kBlock) slot[k] = Rec64{y0, 0.0, z0, 0.0};
+    }
+    if (tile == (int)gridDim.x - 1) {
+        const double yn = g[nx - 1].y, zn = g[nx - 1].z;
+        for (int k = threadIdx.x; k < pad_r; k += kBlock) g[nx + k] = Rec64{yn, 0.0, zn, 0.0};
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Input / output / statistics kernels
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock)
+scatter_layers(Rec64 *ring, int npad, int pad_l, int nx, int N, int K,
+               const double *__restrict__ iy, const double *__restrict__ iz)
+{
+    const int r = blockIdx.y;  // layer t_{N-K+1+r}
+    const int n = N - K + 1 + r;
+    Rec64 *__restrict__ g = ring + (size_t)(n % (K + 1)) * npad + pad_l;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < nx; i += gridDim.x * kBlock) {
+        g[i].y = iy[(size_t)r * nx + i];
+        g[i].z = iz[(size_t)r * nx + i];
+    }
+}
+
+__global__ void __launch_bounds__(kBlock)
+gather_layer(const Rec64 *__restrict__ g, int nx, double *__restrict__ y0,
+             double *__restrict__ z0, unsigned long long *nonfinite)
+{
+    unsigned int bad = 0;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < nx; i += gridDim.x * kBlock) {
+        const double y = g[i].y, z = g[i].z;
+        y0[i] = y;
+        z0[i] = z;
+        bad += (isfinite(y) && isfinite(z)) ? 0u : 1u;
+    }
+    bad = wave_sum_u32(bad);
+    if (nonfinite && (threadIdx.x & 63) == 0 && bad) atomicAdd(nonfinite, (unsigned long long)bad);
+}
+
+__global__ void __launch_bounds__(kBlock) clear_u64(unsigned long long *p, size_t n)
+{
+    for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * kBlock)
+        p[i] = 0ull;
+}
+
+// totals[0] = max iterations, [1] = sum, [2] = unconverged
+__global__ void __launch_bounds__(kBlock)
+reduce_stats(const unsigned int *imax, const unsigned long long *isum,
+             const unsigned long long *nonc, int nw, unsigned long long *totals)
+{
+    __shared__ unsigned long long sm[3][kBlock];
+    unsigned long long m = 0, s = 0, c = 0;
+    for (int w = threadIdx.x; w < nw; w += kBlock) {
+        m = max(m, (unsigned long long)imax[w]);
+        s += isum[w];
+        c += nonc[w];
+    }
+    sm[0][threadIdx.x] = m;
+    sm[1][threadIdx.x] = s;
+    sm[2][threadIdx.x] = c;
+    __syncthreads();
+    for (int o = kBlock / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            sm[0][threadIdx.x] = max(sm[0][threadIdx.x], sm[0][threadIdx.x + o]);
+            sm[1][threadIdx.x] += sm[1][threadIdx.x + o];
+            sm[2][threadIdx.x] += sm[2][threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        totals[0] = sm[0][0];
+        totals[1] = sm[1][0];
+        totals[2] = sm[2][0];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+namespace {
+
+template <int P, int DRV>
+hipError_t launch_fused_t(const SweepArgs &a, int blocks, size_t lds, hipStream_t s)
+{
+    hipLaunchKernelGGL((sweep_fused<P, DRV>), dim3(blocks), dim3(kBlock), lds, s, a);
+    return hipGetLastError();
+}
+
+template <int P, int DRV>
+hipError_t launch_direct_t(const SweepArgs &a, int blocks, hipStream_t s)
+{
+    const size_t lds = (size_t)a.K * a.L * (sizeof(NodeRec) + sizeof(int));
+    hipLaunchKernelGGL((sweep_direct<P, DRV>), dim3(blocks), dim3(kBlock), lds, s, a);
+    return hipGetLastError();
+}
+
+template <int P>
+hipError_t fused_by_driver(const SweepArgs &a, int driver, int blocks, size_t lds, hipStream_t s)
+{
+    switch (driver) {
+    case BSDE_DRIVER_LINEAR: return launch_fused_t<P, BSDE_DRIVER_LINEAR>(a, blocks, lds, s);
+    case BSDE_DRIVER_BIDASK: return launch_fused_t<P, BSDE_DRIVER_BIDASK>(a, blocks, lds, s);
+    case BSDE_DRIVER_CUBIC: return launch_fused_t<P, BSDE_DRIVER_CUBIC>(a, blocks, lds, s);
+    default: return launch_fused_t<P, BSDE_DRIVER_EXP>(a, blocks, lds, s);
+    }
+}
+
+template <int P>
+hipError_t direct_by_driver(const SweepArgs &a, int driver, int blocks, hipStream_t s)
+{
+    switch (driver) {
+    case BSDE_DRIVER_LINEAR: return launch_direct_t<P, BSDE_DRIVER_LINEAR>(a, blocks, s);
+    case BSDE_DRIVER_BIDASK: return launch_direct_t<P, BSDE_DRIVER_BIDASK>(a, blocks, s);
+    case BSDE_DRIVER_CUBIC: return launch_direct_t<P, BSDE_DRIVER_CUBIC>(a, blocks, s);
+    default: return launch_direct_t<P, BSDE_DRIVER_EXP>(a, blocks, s);
+    }
+}
+
+template <int P, int DRV>
+hipError_t allow_lds(size_t lds)
+{
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(&sweep_fused<P, DRV>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+template <int P>
+hipError_t allow_lds_by_driver(int driver, size_t lds)
+{
+    switch (driver) {
+    case BSDE_DRIVER_LINEAR: return allow_lds<P, BSDE_DRIVER_LINEAR>(lds);
+    case BSDE_DRIVER_BIDASK: return allow_lds<P, BSDE_DRIVER_BIDASK>(lds);
+    case BSDE_DRIVER_CUBIC: return allow_lds<P, BSDE_DRIVER_CUBIC>(lds);
+    default: return allow_lds<P, BSDE_DRIVER_EXP>(lds);
+    }
+}
+
+}  // namespace
+
+bool fused_p_supported(int P) { return P == 1 || P == 3 || P == 5; }
+bool direct_p_supported(int P) { return P == 1 || P == 2 || P == 4; }
+
+hipError_t launch_sweep_fused(int P, const SweepArgs &a, int driver, int blocks, size_t lds,
+                              hipStream_t s)
+{
+    switch (P) {
+    case 1: return fused_by_driver<1>(a, driver, blocks, lds, s);
+    case 3: return fused_by_driver<3>(a, driver, blocks, lds, s);
+    case 5: return fused_by_driver<5>(a, driver, blocks, lds, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t set_fused_lds_limit(int P, int driver, size_t lds)
+{
+    switch (P) {
+    case 1: return allow_lds_by_driver<1>(driver, lds);
+    case 3: return allow_lds_by_driver<3>(driver, lds);
+    case 5: return allow_lds_by_driver<5>(driver, lds);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_sweep_direct(int P, const SweepArgs &a, int driver, int blocks, hipStream_t s)
+{
+    switch (P) {
+    case 1: return direct_by_driver<1>(a, driver, blocks, s);
+    case 2: return direct_by_driver<2>(a, driver, blocks, s);
+    case 4: return direct_by_driver<4>(a, driver, blocks, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_spline(Rec64 *slot, int nx, int pad_l, int pad_r, const PcrCoef &c,
+                         hipStream_t s)
+{
+    const int blocks = (nx + kSplineTile - 1) / kSplineTile;
+    hipLaunchKernelGGL(spline_f64, dim3(blocks), dim3(kBlock), 0, s, slot, nx, pad_l, pad_r, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter(Rec64 *ring, int npad, int pad_l, int nx, int N, int K,
+                          const double *iy, const double *iz, hipStream_t s)
+{
+    const int gx = std::min(1024, (nx + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(scatter_layers, dim3(gx, K), dim3(kBlock), 0, s, ring, npad, pad_l, nx, N,
+                       K, iy, iz);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(const Rec64 *g, int nx, double *y0, double *z0,
+                         unsigned long long *nonfinite, hipStream_t s)
+{
+    const int gx = std::min(1024, (nx + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(gather_layer, dim3(gx), dim3(kBlock), 0, s, g, nx, y0, z0, nonfinite);
+    return hipGetLastError();
+}
+
+hipError_t launch_clear(unsigned long long *p, size_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(clear_u64, dim3(64), dim3(kBlock), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_stats(const unsigned int *imax, const unsigned long long *isum,
+                               const unsigned long long *nonc, int nw, unsigned long long *totals,
+                               hipStream_t s)
+{
+    hipLaunchKernelGGL(reduce_stats, dim3(1), dim3(kBlock), 0, s, imax, isum, nonc, nw, totals);
+    return hipGetLastError();
+}
+
+}  // namespace bsde
