@@ -150,6 +150,10 @@ size_t bsde_workspace_bytes(bsde_plan_t plan);
  *   st      NULL: fully asynchronous.  Non-NULL: the call synchronises the
  *           stream, fills *st and returns BSDE_ENOCONV / BSDE_ENONFINITE when
  *           those counts are non-zero (outputs are written in both cases).
+ * The kernels of one solve are captured once per (workspace, buffers,
+ * statistics flag) into a hipGraph held by the plan (at most 4 are kept);
+ * later solves with the same buffers replay it as a single launch.  Set the
+ * environment variable BSDE_GRAPH=0 before bsde_plan to launch directly.
  * Errors: BSDE_EINVAL (NULL pointer, misaligned workspace), BSDE_EDEVICE.
  */
 bsde_status bsde_solve(bsde_plan_t plan, void *ws, const double *init_y, const double *init_z,
@@ -177,6 +181,7 @@ typedef struct {
     int path;             /* sweep kernel: 0 = LDS-staged windows with the spline
                              of the newest layer in-kernel, 1 = direct loads     */
     int points_per_lane;  /* grid points per lane of the sweep kernel            */
+    int node_groups;      /* thread groups sharing the nodes of one tile         */
     int blocks;           /* blocks per sweep launch                             */
     long long lds_bytes;  /* dynamic LDS per block of the sweep kernel           */
 } bsde_kernel_times;

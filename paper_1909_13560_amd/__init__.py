@@ -73,6 +73,7 @@ class _KernelTimes(ctypes.Structure):
     _fields_ = [("sweep_ms", ctypes.c_double), ("sweep_launches", ctypes.c_int),
                 ("spline_ms", ctypes.c_double), ("spline_launches", ctypes.c_int),
                 ("path", ctypes.c_int), ("points_per_lane", ctypes.c_int),
+                ("node_groups", ctypes.c_int),
                 ("blocks", ctypes.c_int), ("lds_bytes", ctypes.c_longlong)]
 
 

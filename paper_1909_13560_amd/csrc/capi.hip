@@ -34,6 +34,7 @@ enum SweepPath { PATH_FUSED = 0, PATH_DIRECT = 1 };
 struct SweepConfig {
     int path = PATH_DIRECT;
     int P = 2;
+    int G = 1;       // node groups per tile (fused path)
     int blocks = 0;
     size_t lds = 0;  // dynamic LDS bytes (fused path)
     int cap = 0, cap1 = 0;
@@ -61,6 +62,17 @@ struct Instance {
 
 }  // namespace
 
+// A captured backward solve (hipGraph) for one set of buffers.
+struct GraphEntry {
+    const void *ws = nullptr;
+    std::vector<bsde_io> io;
+    bool stats = false;
+    hipGraphExec_t exec = nullptr;
+    unsigned long long last_use = 0;
+};
+
+constexpr int kMaxGraphs = 4;
+
 struct bsde_plan_s {
     int device = 0;
     size_t max_lds = 65536;
@@ -69,6 +81,11 @@ struct bsde_plan_s {
     size_t ws_bytes = 0;
     size_t totals_off = 0;
     bsde::PcrCoef pcr_base;  // kappa, inv_b (s6 set per instance)
+    bool use_graphs = true;
+    std::mutex mu;                    // guards the graph cache
+    hipStream_t capture_stream = nullptr;
+    std::vector<GraphEntry> graphs;
+    unsigned long long clock = 0;
 };
 
 namespace {
@@ -174,23 +191,33 @@ bool build_instance(const bsde_problem &p, Instance &in)
     return true;
 }
 
-// Dynamic LDS of the fused kernel with P points per lane, or 0 if the windows
-// exceed the PCR work split or the device limit.
-SweepConfig fused_config(const Instance &in, int P, size_t max_lds)
+// Dynamic LDS of the fused kernel with P points per lane and G node groups,
+// or lds = 0 if the windows exceed the PCR work split or the device limit.
+SweepConfig fused_config(const Instance &in, int P, int G, size_t max_lds)
 {
     SweepConfig c;
     c.path = PATH_FUSED;
     c.P = P;
-    const int T = kBlock * P;
-    int wmax = 0;
-    for (int j = 2; j <= in.K; ++j) wmax = std::max(wmax, T + in.win_hi[j] - in.win_lo[j] + 1);
+    c.G = G;
+    const int T = kBlock * P, NT = kBlock * G;
+    int wmax = 0, reach = 0;
+    for (int j = 2; j <= in.K; ++j) {
+        wmax = std::max(wmax, T + in.win_hi[j] - in.win_lo[j] + 1);
+        reach = std::max(reach, in.win_hi[j] - in.win_lo[j] + 1);
+    }
     const int w1 = T + in.win_hi[1] - in.win_lo[1] + 1;
-    c.cap1 = w1 + 2 * bsde::kHalo;
-    c.cap = std::max(c.cap1, wmax + bsde::kHalo);
-    c.lds = (size_t)c.cap * 2 * sizeof(double2) + (size_t)c.cap1 * 2 * sizeof(double) +
-            (size_t)in.K * in.pb.L * (sizeof(bsde::NodeRec) + sizeof(int));
+    const int elems = std::max(w1 + 2 * bsde::kHalo, wmax + bsde::kHalo);
+    c.cap = (P % 2 == 0) ? elems + elems / P + 1 : elems;  // window slots (padded layout)
+    c.cap1 = w1 + 2 * bsde::kHalo + 2;                       // PCR values per array
+    c.cap1 += c.cap1 & 1;  // keep the node table 16-byte aligned
+    const size_t window_bytes = (size_t)c.cap * 2 * sizeof(double2) +
+                                (size_t)c.cap1 * 4 * sizeof(double);
+    c.lds = window_bytes + bsde::node_table_lds(in.K * in.pb.L);
     c.blocks = (in.nx + T - 1) / T;
-    if (c.cap1 > kBlock * bsde::kPcrMaxPerThread || c.lds > max_lds) c.lds = 0;
+    const size_t reduce_bytes = (size_t)(G - 1) * kBlock * P * 2 * sizeof(double);
+    if (c.cap1 > NT * bsde::pcr_slots(P, NT) || c.lds > max_lds || reduce_bytes > window_bytes ||
+        reach > bsde::kMaxReach2)
+        c.lds = 0;
     return c;
 }
 
@@ -200,37 +227,32 @@ SweepConfig direct_config(const Instance &in, int P)
     c.path = PATH_DIRECT;
     c.P = P;
     c.blocks = (in.nx + kBlock * P - 1) / (kBlock * P);
-    c.lds = (size_t)in.K * in.pb.L * (sizeof(bsde::NodeRec) + sizeof(int));
+    c.lds = bsde::node_table_lds(in.K * in.pb.L);
     return c;
 }
 
-// Default choice: the fused kernel with the widest tile that still gives
-// about two blocks per compute unit; the direct kernel when no window fits.
+// Default choice: the fused kernel with one point per lane (most waves for
+// latency hiding at the grid sizes of interest), the widest tile otherwise
+// fitting; the direct kernel when no window fits in LDS.  BSDE_SWEEP =
+// "fused:P:G" or "direct:P" overrides.
 SweepConfig choose_config(const Instance &in, size_t max_lds, int num_cu)
 {
     const char *env = std::getenv("BSDE_SWEEP");
     if (env) {
-        int P = 0;
-        if (std::sscanf(env, "fused:%d", &P) == 1 && bsde::fused_p_supported(P)) {
-            SweepConfig c = fused_config(in, P, max_lds);
+        int P = 0, G = 1;
+        if (std::sscanf(env, "fused:%d:%d", &P, &G) >= 1 && bsde::fused_supported(P, G)) {
+            SweepConfig c = fused_config(in, P, G, max_lds);
             if (c.lds) return c;
         }
         if (std::sscanf(env, "direct:%d", &P) == 1 && bsde::direct_p_supported(P))
             return direct_config(in, P);
     }
-    const int ps[3] = {5, 3, 1};
-    SweepConfig best;
-    bool have = false;
+    (void)num_cu;
+    const int ps[3] = {1, 2, 4};
     for (int P : ps) {
-        SweepConfig c = fused_config(in, P, max_lds);
-        if (!c.lds) continue;
-        if (!have || c.blocks >= 2 * num_cu) {
-            best = c;
-            have = true;
-        }
-        if (c.blocks >= 2 * num_cu) break;
+        SweepConfig c = fused_config(in, P, 1, max_lds);
+        if (c.lds) return c;
     }
-    if (have) return best;
     return direct_config(in, 2);
 }
 
@@ -296,7 +318,7 @@ bsde_status enqueue_step(const Instance &in, bsde::SweepArgs &a, int n, hipStrea
     const SweepConfig &c = in.cfg;
     if (tm) HIP_OK(tm->mark(tm->sweep, s));
     if (c.path == PATH_FUSED) {
-        HIP_OK(bsde::launch_sweep_fused(c.P, a, in.pb.driver, c.blocks, c.lds, s));
+        HIP_OK(bsde::launch_sweep_fused(c.P, c.G, a, in.pb.driver, c.blocks, c.lds, s));
         if (tm) HIP_OK(tm->mark(tm->sweep, s));
     } else {
         HIP_OK(bsde::launch_sweep_direct(c.P, a, in.pb.driver, c.blocks, s));
@@ -371,6 +393,66 @@ bsde_status finish_stats(bsde_plan_t plan, char *ws, hipStream_t s, hipEvent_t e
     return BSDE_OK;
 }
 
+bool same_io(const std::vector<bsde_io> &a, const bsde_io *b, int count)
+{
+    if ((int)a.size() != count) return false;
+    for (int i = 0; i < count; ++i)
+        if (a[i].init_y != b[i].init_y || a[i].init_z != b[i].init_z || a[i].y0 != b[i].y0 ||
+            a[i].z0 != b[i].z0)
+            return false;
+    return true;
+}
+
+// The whole backward loop of every instance, replayed as one hipGraph launch:
+// one capture per (workspace, buffers, statistics flag), kept in a small
+// least-recently-used cache.  The graph holds kernel nodes only.
+bsde_status launch_graph(bsde_plan_t plan, char *w, const bsde_io *io, int count, bool stats,
+                         unsigned long long *nonfinite, hipStream_t s)
+{
+    std::lock_guard<std::mutex> lock(plan->mu);
+    GraphEntry *hit = nullptr;
+    for (GraphEntry &g : plan->graphs)
+        if (g.ws == w && g.stats == stats && same_io(g.io, io, count)) hit = &g;
+    if (!hit) {
+        if (!plan->capture_stream)
+            HIP_OK(hipStreamCreateWithFlags(&plan->capture_stream, hipStreamNonBlocking));
+        hipStream_t cs = plan->capture_stream;
+        HIP_OK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        bsde_status rc = BSDE_OK;
+        for (int b = 0; b < count && rc == BSDE_OK; ++b)
+            rc = enqueue_instance(*plan, plan->inst[b], w, io[b].init_y, io[b].init_z, io[b].y0,
+                                  io[b].z0, cs, stats, nonfinite);
+        hipGraph_t graph = nullptr;
+        const hipError_t ec = hipStreamEndCapture(cs, &graph);
+        if (rc != BSDE_OK || ec != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc != BSDE_OK ? rc : BSDE_EDEVICE;
+        }
+        hipGraphExec_t exec = nullptr;
+        const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ei != hipSuccess) return BSDE_EDEVICE;
+        if ((int)plan->graphs.size() >= kMaxGraphs) {
+            auto lru = std::min_element(plan->graphs.begin(), plan->graphs.end(),
+                                        [](const GraphEntry &x, const GraphEntry &y) {
+                                            return x.last_use < y.last_use;
+                                        });
+            (void)hipGraphExecDestroy(lru->exec);
+            plan->graphs.erase(lru);
+        }
+        GraphEntry e;
+        e.ws = w;
+        e.io.assign(io, io + count);
+        e.stats = stats;
+        e.exec = exec;
+        plan->graphs.push_back(e);
+        hit = &plan->graphs.back();
+    }
+    hit->last_use = ++plan->clock;
+    HIP_OK(hipGraphLaunch(hit->exec, s));
+    return BSDE_OK;
+}
+
 bsde_status solve_impl(bsde_plan_t plan, void *ws, const bsde_io *io, int count, void *stream,
                        bsde_stats *st)
 {
@@ -393,11 +475,16 @@ bsde_status solve_impl(bsde_plan_t plan, void *ws, const bsde_io *io, int count,
         HIP_OK(bsde::launch_clear(reinterpret_cast<unsigned long long *>(w + first), n64, s));
         nonfinite = reinterpret_cast<unsigned long long *>(w + plan->totals_off) + 3;
     }
-    for (int b = 0; b < count; ++b) {
-        const Instance &in = plan->inst[b];
-        bsde_status rc = enqueue_instance(*plan, in, w, io[b].init_y, io[b].init_z, io[b].y0,
-                                          io[b].z0, s, stats, nonfinite);
+    if (plan->use_graphs) {
+        bsde_status rc = launch_graph(plan, w, io, count, stats, nonfinite, s);
         if (rc != BSDE_OK) return rc;
+    } else {
+        for (int b = 0; b < count; ++b) {
+            const Instance &in = plan->inst[b];
+            bsde_status rc = enqueue_instance(*plan, in, w, io[b].init_y, io[b].init_z, io[b].y0,
+                                              io[b].z0, s, stats, nonfinite);
+            if (rc != BSDE_OK) return rc;
+        }
     }
     if (!stats) return BSDE_OK;
     HIP_OK(hipEventRecord(e1, s));
@@ -484,10 +571,14 @@ bsde_status bsde_plan(const bsde_problem *pb, int batch, bsde_plan_t *out)
         return BSDE_EDEVICE;
     }
     pl->max_lds = (size_t)lds_limit;
+    {
+        const char *g = std::getenv("BSDE_GRAPH");
+        pl->use_graphs = !(g && g[0] == '0');
+    }
     for (Instance &in : pl->inst) {
         in.cfg = choose_config(in, pl->max_lds, num_cu);
         if (in.cfg.path == PATH_FUSED && in.cfg.lds > 65536 &&
-            bsde::set_fused_lds_limit(in.cfg.P, in.pb.driver, in.cfg.lds) != hipSuccess)
+            bsde::set_fused_lds_limit(in.cfg.P, in.cfg.G, in.pb.driver, in.cfg.lds) != hipSuccess)
             in.cfg = direct_config(in, 2);
     }
     // device tables
@@ -498,7 +589,7 @@ bsde_status bsde_plan(const bsde_problem *pb, int batch, bsde_plan_t *out)
         toff[b] = tbytes;
         const size_t kl = (size_t)in.K * in.pb.L;
         tbytes += align_up(kl * sizeof(int), 256) + align_up(kl * sizeof(bsde::NodeRec), 256) +
-                  2 * align_up((in.K + 1) * sizeof(int), 256);
+                  align_up(kl * sizeof(double), 256) + 2 * align_up((in.K + 1) * sizeof(int), 256);
     }
     if (hipMalloc(&pl->d_tables, std::max<size_t>(tbytes, 256)) != hipSuccess) {
         delete pl;
@@ -517,13 +608,15 @@ bsde_status bsde_plan(const bsde_problem *pb, int batch, bsde_plan_t *out)
             return d;
         };
         std::vector<bsde::NodeRec> recs(kl);
+        std::vector<double> cyk(kl, 0.0);
         for (size_t k = 0; k < kl; ++k) {
             const int l = (int)(k % in.pb.L), j = (int)(k / in.pb.L) + 1;
-            recs[k] = bsde::NodeRec{in.A[k],   in.B[k],   in.C[k],  in.D[k],
-                                    in.cfy[k], in.cfz[k], in.cz[k], j == in.pb.k_y ? in.cy[l] : 0.0};
+            recs[k] = bsde::NodeRec{in.B[k], in.C[k], in.D[k], in.cfy[k], in.cfz[k], in.cz[k]};
+            if (j == in.pb.k_y) cyk[k] = in.cy[l];
         }
         in.dtab.rec = static_cast<const bsde::NodeRec *>(put(recs.data(), kl * sizeof(bsde::NodeRec)));
         in.dtab.m = static_cast<const int *>(put(in.m.data(), kl * sizeof(int)));
+        in.dtab.cy = static_cast<const double *>(put(cyk.data(), kl * sizeof(double)));
         in.dtab.win_lo = static_cast<const int *>(put(in.win_lo.data(), (in.K + 1) * sizeof(int)));
         in.dtab.win_hi = static_cast<const int *>(put(in.win_hi.data(), (in.K + 1) * sizeof(int)));
     }
@@ -553,6 +646,8 @@ bsde_status bsde_plan(const bsde_problem *pb, int batch, bsde_plan_t *out)
 void bsde_plan_destroy(bsde_plan_t plan)
 {
     if (!plan) return;
+    for (GraphEntry &g : plan->graphs) (void)hipGraphExecDestroy(g.exec);
+    if (plan->capture_stream) (void)hipStreamDestroy(plan->capture_stream);
     if (plan->d_tables) (void)hipFree(plan->d_tables);
     delete plan;
 }
@@ -605,6 +700,7 @@ bsde_status bsde_profile_kernels(bsde_plan_t plan, void *ws, const double *init_
     const SweepConfig &c = plan->inst[0].cfg;
     kt->path = c.path;
     kt->points_per_lane = c.P;
+    kt->node_groups = c.G;
     kt->blocks = c.blocks;
     kt->lds_bytes = (long long)c.lds;
     return BSDE_OK;

@@ -19,18 +19,18 @@ constexpr int kBlock = 256;        // threads per block of every kernel
 constexpr int kPcrRounds = 5;      // PCR strides 1, 2, 4, 8, 16
 constexpr int kHalo = 32;          // > 1 + 2 + 4 + 8 + 16: reach of the truncated PCR
 constexpr int kPcrMaxPerThread = 8;// spline windows of at most kBlock * 8 records
-constexpr int kSplineTile = 1024;  // grid points per block of the standalone spline kernel
+constexpr int kSplineTile = 512;   // grid points per block of the standalone spline kernel
 
-// Coefficients of one Gauss-Hermite node (j, l): the same for every grid
-// point, so a block copies the whole table to LDS once and every lane reads
-// the same address (a broadcast).
+// Coefficients of one Gauss-Hermite node (j, l), the same for every grid
+// point.  With phi the fraction of the node's cell offset, the spline value
+// at the node is  v0 + B (v1 - v0) + C M0 + D M1  (second-derivative form).
 struct alignas(16) NodeRec {
-    double A, B;   // spline basis weights at the fraction phi: A = 1-phi, B = phi,
-    double C, D;   //   C = dx^2/6 ((1-phi)^3 - (1-phi)), D = dx^2/6 (phi^3 - phi)
+    double B;      // phi
+    double C;      // dx^2/6 ((1-phi)^3 - (1-phi))
+    double D;      // dx^2/6 (phi^3 - phi)
     double cfy;    // weight of f-hat in the constant of the y equation
     double cfz;    // weight of f-hat in z^n
     double cz;     // weight of z-hat in z^n
-    double cy;     // weight of y-hat in the y constant (non-zero only for j = K_y)
 };
 
 // Node table of one instance (device memory).  K*L entries, row j-1 holds the
@@ -38,11 +38,33 @@ struct alignas(16) NodeRec {
 struct NodeTable {
     const NodeRec *rec;
     const int *m;       // integer cell offset of the node from x_i
+    const double *cy;   // weight of y-hat in the y constant (non-zero only for j = K_y)
     const int *win_lo;  // [K+1]: lowest node offset of layer j (j = 1 also <= 0)
     const int *win_hi;  // [K+1]: highest node offset of layer j (j = 1 also >= 0)
 };
 
-constexpr int kMaxNodes = 6 * 64;  // K * L at most
+constexpr int kMaxNodes = 6 * 64;      // K * L at most
+constexpr int kMaxReach1 = 512;        // widest node reach of layer n+1 in the fused kernel
+constexpr int kMaxReach2 = 768;        // widest node reach of layers n+2.. in the fused kernel
+constexpr size_t kNodeLdsBytes = sizeof(NodeRec) + sizeof(int) + sizeof(double);
+
+// PCR slots per thread of a fused block of NT threads and P points per lane
+// (the newest layer's window, its halo and the two extra staged values).
+__host__ __device__ constexpr int pcr_slots(int P, int NT)
+{
+    return (kBlock * P + 2 * kHalo + 2 + kMaxReach1 + NT - 1) / NT;
+}
+
+// Slot of window element e in the LDS window arrays.  With an even number P
+// of points per lane a pad slot follows every P elements, so the lanes of a
+// wavefront, P elements apart, read 16-byte slots an odd multiple of 16 bytes
+// apart and the reads are bank-conflict free (odd P needs no pad).
+template <int P>
+struct WinLayout {
+    static constexpr bool kPad = (P % 2) == 0;
+    __device__ static int slot(int e) { return kPad ? e + e / P : e; }
+    __host__ __device__ static constexpr int slots(int n) { return kPad ? n + n / P + 1 : n; }
+};
 
 struct DriverParams {
     double p0, p1, p2, p3, p4;
@@ -170,80 +192,89 @@ __device__ inline double rtilde_global(const Rec64 *__restrict__ g, int nx, int 
     return sign * ((vp - v0) - (v0 - vm));
 }
 
-// Stage y and z of layer g over records [lo - kHalo, lo + W + kHalo) into
-// wy[.].x / wz[.].x (index e = k - lo + kHalo; outside [0, N) the boundary
-// value, i.e. the ghost record), then leave M_y, M_z for the records
-// [lo, lo + W) in wy[.].y / wz[.].y (0 outside (0, N-1)).  Ry, Rz hold
-// W + 2 kHalo doubles each.  Called by all kBlock threads; ends synchronised.
+// Natural spline of layer g on the window of records [lo, lo + W).
+// y and z over [lo - kHalo - 1, lo + W + kHalo] are staged (outside [0, N)
+// the boundary value, i.e. the ghost record), the right-hand sides r~ of the
+// records [lo - kHalo, lo + W + kHalo) follow from them in LDS (from HBM only
+// at the true domain boundaries, where the reflection applies), and five
+// ping-pong PCR rounds leave M.  Results: window element e = k - lo + kHalo
+// holds (y, M_y) in wy[slot(e)] and (z, M_z) in wz[slot(e)] for the records
+// [lo, lo + W) (M = 0 outside (0, N-1)).  R holds 4 arrays of cap1 >= W +
+// 2 kHalo + 2 doubles.  Called by all NT threads; ends synchronised.
+template <int NT, int U, int P>
 __device__ inline void spline_window(const Rec64 *__restrict__ g, int nx, int lo, int W,
-                                     double2 *wy, double2 *wz, double *Ry, double *Rz,
+                                     double2 *wy, double2 *wz, double *R, int cap1,
                                      const PcrCoef &c)
 {
     const int tid = threadIdx.x;
-    const int WE = W + 2 * kHalo;
-    for (int e = tid; e < WE; e += kBlock) {
-        const int k = lo - kHalo + e;
-        const int kc = min(max(k, 0), nx - 1);
-        wy[e].x = g[kc].y;
-        wz[e].x = g[kc].z;
+    const int WE = W + 2 * kHalo, WS = WE + 2;
+    double *Ay = R, *Az = R + cap1, *By = R + 2 * cap1, *Bz = R + 3 * cap1;
+    for (int e = tid; e < WS; e += NT) {
+        const int k = lo - kHalo - 1 + e;
+        const Rec64 r = g[min(max(k, 0), nx - 1)];
+        Ay[e] = r.y;
+        Az[e] = r.z;
     }
     __syncthreads();
-    for (int e = tid; e < WE; e += kBlock) {
+    for (int e = tid; e < WE; e += NT) {
         const int k = lo - kHalo + e;
+        const double y0 = Ay[e + 1], z0 = Az[e + 1];
         double ry, rz;
-        if (k >= 1 && k <= nx - 2 && e >= 1 && e <= WE - 2) {
-            const double ym = wy[e - 1].x, y0 = wy[e].x, yp = wy[e + 1].x;
-            const double zm = wz[e - 1].x, z0 = wz[e].x, zp = wz[e + 1].x;
-            ry = (yp - y0) - (y0 - ym);
-            rz = (zp - z0) - (z0 - zm);
+        if (k >= 1 && k <= nx - 2) {
+            ry = (Ay[e + 2] - y0) - (y0 - Ay[e]);
+            rz = (Az[e + 2] - z0) - (z0 - Az[e]);
         } else {
             ry = rtilde_global(g, nx, k, false);
             rz = rtilde_global(g, nx, k, true);
         }
-        Ry[e] = c.s6 * ry;
-        Rz[e] = c.s6 * rz;
+        By[e] = c.s6 * ry;
+        Bz[e] = c.s6 * rz;
+        const int sl = WinLayout<P>::slot(e);
+        wy[sl].x = y0;
+        wz[sl].x = z0;
     }
     __syncthreads();
+    double *sy = By, *sz = Bz, *dy = Ay, *dz = Az;
     int h = 1;
     for (int s = 0; s < kPcrRounds; ++s, h <<= 1) {
         const double kap = c.kappa[s];
-        double ny[kPcrMaxPerThread], nz[kPcrMaxPerThread];
 #pragma unroll
-        for (int u = 0; u < kPcrMaxPerThread; ++u) {
-            const int e = tid + u * kBlock;
+        for (int u = 0; u < U; ++u) {
+            const int e = tid + u * NT;
             if (e >= h && e < WE - h) {
-                ny[u] = fma(-kap, Ry[e - h] + Ry[e + h], Ry[e]);
-                nz[u] = fma(-kap, Rz[e - h] + Rz[e + h], Rz[e]);
+                dy[e] = fma(-kap, sy[e - h] + sy[e + h], sy[e]);
+                dz[e] = fma(-kap, sz[e - h] + sz[e + h], sz[e]);
             }
         }
         __syncthreads();
-#pragma unroll
-        for (int u = 0; u < kPcrMaxPerThread; ++u) {
-            const int e = tid + u * kBlock;
-            if (e >= h && e < WE - h) {
-                Ry[e] = ny[u];
-                Rz[e] = nz[u];
-            }
-        }
-        __syncthreads();
+        double *t = sy;
+        sy = dy;
+        dy = t;
+        t = sz;
+        sz = dz;
+        dz = t;
     }
-    for (int e = kHalo + tid; e < kHalo + W; e += kBlock) {
+    for (int e = kHalo + tid; e < kHalo + W; e += NT) {
         const int k = lo - kHalo + e;
         const bool inner = (k > 0 && k < nx - 1);
-        wy[e].y = inner ? Ry[e] * c.inv_b : 0.0;
-        wz[e].y = inner ? Rz[e] * c.inv_b : 0.0;
+        const int sl = WinLayout<P>::slot(e);
+        wy[sl].y = inner ? sy[e] * c.inv_b : 0.0;
+        wz[sl].y = inner ? sz[e] * c.inv_b : 0.0;
     }
     __syncthreads();
 }
 
-// Copy the node table (K*L records and offsets) of an instance into LDS,
-// where every lane of a wavefront reads the same address (a broadcast).
-// Called by all kBlock threads; ends synchronised.
-__device__ inline void load_node_table(const NodeTable &t, int nodes, NodeRec *trec, int *tm)
+// Copy the node table (K*L records, offsets and y weights) of an instance
+// into LDS, where every lane of a wavefront reads the same address (a
+// broadcast).  Called by all NT threads; ends synchronised.
+template <int NT>
+__device__ inline void load_node_table(const NodeTable &t, int nodes, NodeRec *trec, int *tm,
+                                       double *tcy)
 {
-    for (int i = threadIdx.x; i < nodes; i += kBlock) {
+    for (int i = threadIdx.x; i < nodes; i += NT) {
         trec[i] = t.rec[i];
         tm[i] = t.m[i];
+        tcy[i] = t.cy[i];
     }
     __syncthreads();
 }
@@ -256,41 +287,35 @@ __device__ inline void load_node_table(const NodeTable &t, int nodes, NodeRec *t
 // ---------------------------------------------------------------------------
 template <int P, int DRV, bool LASTY>
 __device__ inline void node_accumulate(const double2 (&ry)[P + 1], const double2 (&rz)[P + 1],
-                                       const NodeRec &c, const Driver<DRV> &f, double (&Y)[P],
-                                       double (&Z)[P])
+                                       const NodeRec &c, double cy, const Driver<DRV> &f,
+                                       double (&Y)[P], double (&Z)[P])
 {
 #pragma unroll
     for (int q = 0; q < P; ++q) {
-        const double yh =
-            fma(c.A, ry[q].x, fma(c.B, ry[q + 1].x, fma(c.C, ry[q].y, c.D * ry[q + 1].y)));
-        const double zh =
-            fma(c.A, rz[q].x, fma(c.B, rz[q + 1].x, fma(c.C, rz[q].y, c.D * rz[q + 1].y)));
+        const double yh = fma(c.B, ry[q + 1].x - ry[q].x,
+                              fma(c.C, ry[q].y, fma(c.D, ry[q + 1].y, ry[q].x)));
+        const double zh = fma(c.B, rz[q + 1].x - rz[q].x,
+                              fma(c.C, rz[q].y, fma(c.D, rz[q + 1].y, rz[q].x)));
         const double fh = f(yh, zh);
         double y = fma(c.cfy, fh, Y[q]);
-        if (LASTY) y = fma(c.cy, yh, y);
+        if (LASTY) y = fma(cy, yh, y);
         Y[q] = y;
         Z[q] = fma(c.cfz, fh, fma(c.cz, zh, Z[q]));
     }
 }
 
-// All L nodes of one layer, reading P+1 consecutive records per lane from
-// the window arrays wy / wz starting at index ebase + m (LDS or HBM).  The
-// coefficients of the next node are fetched before the current one is used.
+// Nodes l = l0, l0 + LS, l0 + 2 LS, ... < L of one layer, reading P+1
+// consecutive records per lane from src at node offset m.
 template <int P, int DRV, bool LASTY, typename Src>
-__device__ inline void layer_nodes(const Src &src, const NodeRec *trec, const int *tm, int row,
-                                   int L, const Driver<DRV> &f, double (&Y)[P], double (&Z)[P])
+__device__ inline void layer_nodes(const Src &src, const NodeRec *trec, const int *tm,
+                                   const double *tcy, int row, int l0, int LS, int L,
+                                   const Driver<DRV> &f, double (&Y)[P], double (&Z)[P])
 {
-    NodeRec cur = trec[row];
-    int mcur = tm[row];
-    for (int l = 0; l < L; ++l) {
+#pragma unroll 1
+    for (int l = l0; l < L; l += LS) {
         double2 ry[P + 1], rz[P + 1];
-        src.template fetch<P>(mcur, ry, rz);
-        const int nx = row + min(l + 1, L - 1);
-        const NodeRec nxt = trec[nx];
-        const int mnxt = tm[nx];
-        node_accumulate<P, DRV, LASTY>(ry, rz, cur, f, Y, Z);
-        cur = nxt;
-        mcur = mnxt;
+        src.template fetch<P>(tm[row + l], ry, rz);
+        node_accumulate<P, DRV, LASTY>(ry, rz, trec[row + l], LASTY ? tcy[row + l] : 0.0, f, Y, Z);
     }
 }
 
@@ -340,6 +365,7 @@ __device__ inline void finish_points(const SweepArgs &a, int first, const double
         it_sum = wave_sum_u32(it_sum);
         nonconv = wave_sum_u32(nonconv);
         if ((threadIdx.x & 63) == 0) {
+            // finish_points runs on the first kBlock threads of a block
             const int w = (blockIdx.x * kBlock + threadIdx.x) >> 6;
             a.st_iter_max[w] = max(a.st_iter_max[w], it_max);
             a.st_iter_sum[w] += it_sum;

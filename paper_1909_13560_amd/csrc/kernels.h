@@ -10,12 +10,13 @@
 
 namespace bsde {
 
-bool fused_p_supported(int P);
+bool fused_supported(int P, int G);
 bool direct_p_supported(int P);
+size_t node_table_lds(int nodes);
 
-hipError_t launch_sweep_fused(int P, const SweepArgs &a, int driver, int blocks, size_t lds,
-                              hipStream_t s);
-hipError_t set_fused_lds_limit(int P, int driver, size_t lds);
+hipError_t launch_sweep_fused(int P, int G, const SweepArgs &a, int driver, int blocks,
+                              size_t lds, hipStream_t s);
+hipError_t set_fused_lds_limit(int P, int G, int driver, size_t lds);
 hipError_t launch_sweep_direct(int P, const SweepArgs &a, int driver, int blocks, hipStream_t s);
 hipError_t launch_spline(Rec64 *slot, int nx, int pad_l, int pad_r, const PcrCoef &c,
                          hipStream_t s);

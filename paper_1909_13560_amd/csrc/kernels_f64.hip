@@ -21,18 +21,43 @@
 
 namespace bsde {
 
-// Node records read from the LDS window arrays (fused kernel).
+// Node records read from the LDS window arrays (fused kernel).  Window
+// element e of the lane's q-th record is lane_pt + off + q with off =
+// ebase + m >= 0; with the padded layout its slot is
+//   (P+1) tig + off + off/P + q + [q >= P - off % P]   (tig = lane_pt / P),
+// so the per-record offsets are one of P compile-time patterns.
+template <int P, int B, bool PAD>
+__device__ inline void fetch_slots(const double2 *wy, const double2 *wz, int base,
+                                   double2 (&ry)[P + 1], double2 (&rz)[P + 1])
+{
+#pragma unroll
+    for (int q = 0; q <= P; ++q) {
+        const int sl = base + q + ((PAD && q >= P - B) ? 1 : 0);
+        ry[q] = wy[sl];
+        rz[q] = wz[sl];
+    }
+}
+
+template <int P>
 struct LdsWindow {
     const double2 *wy, *wz;
-    int ebase;  // window index of the lane's first point at node offset 0
-    template <int P>
-    __device__ void fetch(int m, double2 (&ry)[P + 1], double2 (&rz)[P + 1]) const
+    int ebase;  // kHalo - (lowest node offset of the layer): off = ebase + m
+    int lane;   // slot of the lane's first element at off = 0: (P+1) tig padded, P tig not
+    template <int PP>
+    __device__ void fetch(int m, double2 (&ry)[PP + 1], double2 (&rz)[PP + 1]) const
     {
-        const int e0 = ebase + m;
-#pragma unroll
-        for (int q = 0; q <= P; ++q) {
-            ry[q] = wy[e0 + q];
-            rz[q] = wz[e0 + q];
+        static_assert(PP == P, "window layout and fetch width differ");
+        const int off = ebase + m;
+        if constexpr (!WinLayout<P>::kPad) {
+            fetch_slots<P, 0, false>(wy, wz, lane + off, ry, rz);
+        } else {
+            const int base = lane + off + off / P;
+            switch (off % P) {
+            case 0: fetch_slots<P, 0, true>(wy, wz, base, ry, rz); break;
+            case 1: fetch_slots<P, 1, true>(wy, wz, base, ry, rz); break;
+            case 2: fetch_slots<P, (P > 2 ? 2 : 1), true>(wy, wz, base, ry, rz); break;
+            default: fetch_slots<P, (P > 3 ? 3 : 1), true>(wy, wz, base, ry, rz); break;
+            }
         }
     }
 };
@@ -54,43 +79,67 @@ struct GlobalWindow {
 };
 
 template <int P, int DRV, typename Src>
-__device__ inline void layer_dispatch(const Src &src, const NodeRec *trec, const int *tm, int j,
+__device__ inline void layer_dispatch(const Src &src, const NodeRec *trec, const int *tm,
+                                      const double *tcy, int j, int l0, int LS,
                                       const SweepArgs &a, double (&Y)[P], double (&Z)[P])
 {
     const Driver<DRV> f(a.drv, (a.n + j) * a.dt);
     const int row = (j - 1) * a.L;
     if (j == a.Ky)
-        layer_nodes<P, DRV, true>(src, trec, tm, row, a.L, f, Y, Z);
+        layer_nodes<P, DRV, true>(src, trec, tm, tcy, row, l0, LS, a.L, f, Y, Z);
     else
-        layer_nodes<P, DRV, false>(src, trec, tm, row, a.L, f, Y, Z);
+        layer_nodes<P, DRV, false>(src, trec, tm, tcy, row, l0, LS, a.L, f, Y, Z);
 }
 
 // ---------------------------------------------------------------------------
 // Fused sweep: LDS-staged windows, in-kernel spline of layer n+1.
+// A block of G*kBlock threads owns a tile of kBlock*P points; thread group g
+// (kBlock threads) takes the nodes l = g, g+G, ... of every layer, and the G
+// partial sums meet in LDS before group 0 finishes the points.
 // Dynamic LDS: wy[cap], wz[cap] (double2), Ry[cap1], Rz[cap1] (double),
-// node table (K*L NodeRec, K*L int).
+// node table (K*L NodeRec, K*L int, K*L double).
 // ---------------------------------------------------------------------------
-template <int P, int DRV>
-__global__ void __launch_bounds__(kBlock) sweep_fused(const SweepArgs a)
+template <int P, int G, int DRV>
+__global__ void __launch_bounds__(kBlock * G) sweep_fused(const SweepArgs a)
 {
     constexpr int T = kBlock * P;
+    constexpr int NT = kBlock * G;
     extern __shared__ double2 smem[];
     double2 *wy = smem;
     double2 *wz = wy + a.lds_cap;
-    double *Ry = reinterpret_cast<double *>(wz + a.lds_cap);
-    double *Rz = Ry + a.lds_cap1;
-    NodeRec *trec = reinterpret_cast<NodeRec *>(Rz + a.lds_cap1);
+    double *R = reinterpret_cast<double *>(wz + a.lds_cap);
+    NodeRec *trec = reinterpret_cast<NodeRec *>(R + 4 * a.lds_cap1);
     int *tm = reinterpret_cast<int *>(trec + a.K * a.L);
+    double *tcy = reinterpret_cast<double *>(tm + ((a.K * a.L + 1) & ~1));
 
     const int tid = threadIdx.x;
+    // kBlock is a multiple of the wavefront size: the group is wave-uniform
+    const int grp = __builtin_amdgcn_readfirstlane(tid / kBlock);
+    const int lane_pt = (tid % kBlock) * P;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int t0 = tile * T;
     const int S = a.K + 1;
-    load_node_table(a.tab, a.K * a.L, trec, tm);
+    load_node_table<NT>(a.tab, a.K * a.L, trec, tm, tcy);
 
     double Y[P], Z[P];
 #pragma unroll
     for (int q = 0; q < P; ++q) Y[q] = Z[q] = 0.0;
+
+    // records of the next layer's window, loaded while the current layer's
+    // nodes are evaluated (kPre per thread covers windows of NT * kPre records)
+    constexpr int kPre = (T + kMaxReach2 + NT - 1) / NT;
+    Rec64 pre[kPre];
+    auto prefetch = [&](int j) {
+        const Rec64 *__restrict__ g = a.ring + (size_t)((a.n + j) % S) * a.npad + a.pad_l;
+        const int lo = t0 + a.tab.win_lo[j];
+        const int W = T + (a.tab.win_hi[j] - a.tab.win_lo[j]) + 1;
+#pragma unroll
+        for (int u = 0; u < kPre; ++u) {
+            const int e = tid + u * NT;
+            if (e < W) pre[u] = g[lo + e];
+        }
+    };
+    if (a.K >= 2) prefetch(2);
 
     for (int j = 1; j <= a.K; ++j) {
         Rec64 *__restrict__ g = a.ring + (size_t)((a.n + j) % S) * a.npad + a.pad_l;
@@ -100,35 +149,59 @@ __global__ void __launch_bounds__(kBlock) sweep_fused(const SweepArgs a)
         if (j == 1) {
             // layer n+1 was produced by the previous launch: build its spline
             // on the window, and store the tile's part for the later steps
-            spline_window(g, a.nx, lo, W, wy, wz, Ry, Rz, a.pcr);
+            spline_window<NT, pcr_slots(P, NT), P>(g, a.nx, lo, W, wy, wz, R, a.lds_cap1, a.pcr);
             const int kend = min(t0 + T, a.nx);
-            for (int k = t0 + tid; k < kend; k += kBlock) {
-                const int e = k - lo + kHalo;
-                g[k].My = wy[e].y;
-                g[k].Mz = wz[e].y;
+            for (int k = t0 + tid; k < kend; k += NT) {
+                const int sl = WinLayout<P>::slot(k - lo + kHalo);
+                g[k].My = wy[sl].y;
+                g[k].Mz = wz[sl].y;
             }
             if (tile == 0) {
                 const double y0 = g[0].y, z0 = g[0].z;
-                for (int k = tid; k < a.pad_l; k += kBlock)
-                    g[k - a.pad_l] = Rec64{y0, 0.0, z0, 0.0};
+                for (int k = tid; k < a.pad_l; k += NT) g[k - a.pad_l] = Rec64{y0, 0.0, z0, 0.0};
             }
             if (tile == (int)gridDim.x - 1) {
                 const double yn = g[a.nx - 1].y, zn = g[a.nx - 1].z;
-                for (int k = tid; k < a.pad_r; k += kBlock) g[a.nx + k] = Rec64{yn, 0.0, zn, 0.0};
+                for (int k = tid; k < a.pad_r; k += NT) g[a.nx + k] = Rec64{yn, 0.0, zn, 0.0};
             }
         } else {
-            for (int e = tid; e < W; e += kBlock) {
-                const Rec64 r = g[lo + e];
-                wy[kHalo + e] = make_double2(r.y, r.My);
-                wz[kHalo + e] = make_double2(r.z, r.Mz);
+#pragma unroll
+            for (int u = 0; u < kPre; ++u) {
+                const int e = tid + u * NT;
+                if (e < W) {
+                    const int sl = WinLayout<P>::slot(kHalo + e);
+                    wy[sl] = make_double2(pre[u].y, pre[u].My);
+                    wz[sl] = make_double2(pre[u].z, pre[u].Mz);
+                }
             }
+            if (j < a.K) prefetch(j + 1);
             __syncthreads();
         }
-        const LdsWindow src{wy, wz, kHalo - mlo + tid * P};
-        layer_dispatch<P, DRV>(src, trec, tm, j, a, Y, Z);
+        const LdsWindow<P> src{wy, wz, kHalo - mlo,
+                               WinLayout<P>::kPad ? lane_pt + lane_pt / P : lane_pt};
+        layer_dispatch<P, DRV>(src, trec, tm, tcy, j, grp, G, a, Y, Z);
         __syncthreads();  // the window is reused by the next layer
     }
-    finish_points<P, DRV>(a, t0 + tid * P, Y, Z);
+    if (G > 1) {  // partial sums of groups 1..G-1 meet group 0 in LDS, in group order
+        double *red = reinterpret_cast<double *>(smem);
+        if (grp > 0) {
+#pragma unroll
+            for (int q = 0; q < P; ++q) {
+                red[(((grp - 1) * kBlock + tid % kBlock) * P + q) * 2] = Y[q];
+                red[(((grp - 1) * kBlock + tid % kBlock) * P + q) * 2 + 1] = Z[q];
+            }
+        }
+        __syncthreads();
+        if (grp > 0) return;
+        for (int h = 1; h < G; ++h) {
+#pragma unroll
+            for (int q = 0; q < P; ++q) {
+                Y[q] += red[(((h - 1) * kBlock + tid) * P + q) * 2];
+                Z[q] += red[(((h - 1) * kBlock + tid) * P + q) * 2 + 1];
+            }
+        }
+    }
+    finish_points<P, DRV>(a, t0 + lane_pt, Y, Z);
 }
 
 // ---------------------------------------------------------------------------
@@ -141,17 +214,18 @@ __global__ void __launch_bounds__(kBlock) sweep_direct(const SweepArgs a)
     extern __shared__ double2 smem[];
     NodeRec *trec = reinterpret_cast<NodeRec *>(smem);
     int *tm = reinterpret_cast<int *>(trec + a.K * a.L);
+    double *tcy = reinterpret_cast<double *>(tm + ((a.K * a.L + 1) & ~1));
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int first = (tile * kBlock + (int)threadIdx.x) * P;
     const int i0 = min(first, a.nx - 1);  // lanes past the end read in bounds, store nothing
     const int S = a.K + 1;
-    load_node_table(a.tab, a.K * a.L, trec, tm);
+    load_node_table<kBlock>(a.tab, a.K * a.L, trec, tm, tcy);
     double Y[P], Z[P];
 #pragma unroll
     for (int q = 0; q < P; ++q) Y[q] = Z[q] = 0.0;
     for (int j = 1; j <= a.K; ++j) {
         const GlobalWindow src{a.ring + (size_t)((a.n + j) % S) * a.npad + a.pad_l + i0};
-        layer_dispatch<P, DRV>(src, trec, tm, j, a, Y, Z);
+        layer_dispatch<P, DRV>(src, trec, tm, tcy, j, 0, 1, a, Y, Z);
     }
     finish_points<P, DRV>(a, first, Y, Z);
 }
@@ -162,13 +236,13 @@ __global__ void __launch_bounds__(kBlock) sweep_direct(const SweepArgs a)
 __global__ void __launch_bounds__(kBlock) spline_f64(Rec64 *slot, int nx, int pad_l, int pad_r,
                                                      const PcrCoef c)
 {
-    constexpr int WE = kSplineTile + 2 * kHalo;
+    constexpr int WE = kSplineTile + 2 * kHalo, WS = WE + 2;
     __shared__ double2 wy[WE], wz[WE];
-    __shared__ double Ry[WE], Rz[WE];
+    __shared__ double R[4 * WS];
     Rec64 *__restrict__ g = slot + pad_l;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int t0 = tile * kSplineTile;
-    spline_window(g, nx, t0, kSplineTile, wy, wz, Ry, Rz, c);
+    spline_window<kBlock, (WS + kBlock - 1) / kBlock, 1>(g, nx, t0, kSplineTile, wy, wz, R, WS, c);
     const int kend = min(t0 + kSplineTile, nx);
     for (int k = t0 + (int)threadIdx.x; k < kend; k += kBlock) {
         g[k].My = wy[k - t0 + kHalo].y;
@@ -258,29 +332,29 @@ reduce_stats(const unsigned int *imax, const unsigned long long *isum,
 // ---------------------------------------------------------------------------
 namespace {
 
-template <int P, int DRV>
+template <int P, int G, int DRV>
 hipError_t launch_fused_t(const SweepArgs &a, int blocks, size_t lds, hipStream_t s)
 {
-    hipLaunchKernelGGL((sweep_fused<P, DRV>), dim3(blocks), dim3(kBlock), lds, s, a);
+    hipLaunchKernelGGL((sweep_fused<P, G, DRV>), dim3(blocks), dim3(kBlock * G), lds, s, a);
     return hipGetLastError();
 }
 
 template <int P, int DRV>
 hipError_t launch_direct_t(const SweepArgs &a, int blocks, hipStream_t s)
 {
-    const size_t lds = (size_t)a.K * a.L * (sizeof(NodeRec) + sizeof(int));
-    hipLaunchKernelGGL((sweep_direct<P, DRV>), dim3(blocks), dim3(kBlock), lds, s, a);
+    hipLaunchKernelGGL((sweep_direct<P, DRV>), dim3(blocks), dim3(kBlock),
+                       node_table_lds(a.K * a.L), s, a);
     return hipGetLastError();
 }
 
-template <int P>
+template <int P, int G>
 hipError_t fused_by_driver(const SweepArgs &a, int driver, int blocks, size_t lds, hipStream_t s)
 {
     switch (driver) {
-    case BSDE_DRIVER_LINEAR: return launch_fused_t<P, BSDE_DRIVER_LINEAR>(a, blocks, lds, s);
-    case BSDE_DRIVER_BIDASK: return launch_fused_t<P, BSDE_DRIVER_BIDASK>(a, blocks, lds, s);
-    case BSDE_DRIVER_CUBIC: return launch_fused_t<P, BSDE_DRIVER_CUBIC>(a, blocks, lds, s);
-    default: return launch_fused_t<P, BSDE_DRIVER_EXP>(a, blocks, lds, s);
+    case BSDE_DRIVER_LINEAR: return launch_fused_t<P, G, BSDE_DRIVER_LINEAR>(a, blocks, lds, s);
+    case BSDE_DRIVER_BIDASK: return launch_fused_t<P, G, BSDE_DRIVER_BIDASK>(a, blocks, lds, s);
+    case BSDE_DRIVER_CUBIC: return launch_fused_t<P, G, BSDE_DRIVER_CUBIC>(a, blocks, lds, s);
+    default: return launch_fused_t<P, G, BSDE_DRIVER_EXP>(a, blocks, lds, s);
     }
 }
 
@@ -295,48 +369,61 @@ hipError_t direct_by_driver(const SweepArgs &a, int driver, int blocks, hipStrea
     }
 }
 
-template <int P, int DRV>
+template <int P, int G, int DRV>
 hipError_t allow_lds(size_t lds)
 {
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(&sweep_fused<P, DRV>),
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(&sweep_fused<P, G, DRV>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
-template <int P>
+template <int P, int G>
 hipError_t allow_lds_by_driver(int driver, size_t lds)
 {
     switch (driver) {
-    case BSDE_DRIVER_LINEAR: return allow_lds<P, BSDE_DRIVER_LINEAR>(lds);
-    case BSDE_DRIVER_BIDASK: return allow_lds<P, BSDE_DRIVER_BIDASK>(lds);
-    case BSDE_DRIVER_CUBIC: return allow_lds<P, BSDE_DRIVER_CUBIC>(lds);
-    default: return allow_lds<P, BSDE_DRIVER_EXP>(lds);
+    case BSDE_DRIVER_LINEAR: return allow_lds<P, G, BSDE_DRIVER_LINEAR>(lds);
+    case BSDE_DRIVER_BIDASK: return allow_lds<P, G, BSDE_DRIVER_BIDASK>(lds);
+    case BSDE_DRIVER_CUBIC: return allow_lds<P, G, BSDE_DRIVER_CUBIC>(lds);
+    default: return allow_lds<P, G, BSDE_DRIVER_EXP>(lds);
     }
 }
 
 }  // namespace
 
-bool fused_p_supported(int P) { return P == 1 || P == 3 || P == 5; }
+bool fused_supported(int P, int G)
+{
+    return (P == 1 || P == 2 || P == 4) && (G == 1 || G == 2 || G == 4);
+}
 bool direct_p_supported(int P) { return P == 1 || P == 2 || P == 4; }
 
-hipError_t launch_sweep_fused(int P, const SweepArgs &a, int driver, int blocks, size_t lds,
-                              hipStream_t s)
+size_t node_table_lds(int nodes)
 {
-    switch (P) {
-    case 1: return fused_by_driver<1>(a, driver, blocks, lds, s);
-    case 3: return fused_by_driver<3>(a, driver, blocks, lds, s);
-    case 5: return fused_by_driver<5>(a, driver, blocks, lds, s);
-    default: return hipErrorInvalidValue;
-    }
+    return (size_t)nodes * (sizeof(NodeRec) + sizeof(double)) +
+           (size_t)((nodes + 1) & ~1) * sizeof(int);
 }
 
-hipError_t set_fused_lds_limit(int P, int driver, size_t lds)
-{
-    switch (P) {
-    case 1: return allow_lds_by_driver<1>(driver, lds);
-    case 3: return allow_lds_by_driver<3>(driver, lds);
-    case 5: return allow_lds_by_driver<5>(driver, lds);
-    default: return hipErrorInvalidValue;
+#define BSDE_FUSED_CASES(F, ...)                                       \
+    switch (P * 8 + G) {                                               \
+    case 1 * 8 + 1: return F<1, 1>(__VA_ARGS__);                       \
+    case 1 * 8 + 2: return F<1, 2>(__VA_ARGS__);                       \
+    case 1 * 8 + 4: return F<1, 4>(__VA_ARGS__);                       \
+    case 2 * 8 + 1: return F<2, 1>(__VA_ARGS__);                       \
+    case 2 * 8 + 2: return F<2, 2>(__VA_ARGS__);                       \
+    case 2 * 8 + 4: return F<2, 4>(__VA_ARGS__);                       \
+    case 4 * 8 + 1: return F<4, 1>(__VA_ARGS__);                       \
+    case 4 * 8 + 2: return F<4, 2>(__VA_ARGS__);                       \
+    case 4 * 8 + 4: return F<4, 4>(__VA_ARGS__);                       \
+    default: return hipErrorInvalidValue;                              \
     }
+
+hipError_t launch_sweep_fused(int P, int G, const SweepArgs &a, int driver, int blocks,
+                              size_t lds, hipStream_t s)
+{
+    BSDE_FUSED_CASES(fused_by_driver, a, driver, blocks, lds, s)
+}
+
+hipError_t set_fused_lds_limit(int P, int G, int driver, size_t lds)
+{
+    BSDE_FUSED_CASES(allow_lds_by_driver, driver, lds)
 }
 
 hipError_t launch_sweep_direct(int P, const SweepArgs &a, int driver, int blocks, hipStream_t s)

@@ -190,3 +190,33 @@ def test_batched_equals_single(lib):
         y, z, _, _ = lib.solve(w.problem, iy, iz)
         assert np.array_equal(y0.cpu().numpy(), y)
         assert np.array_equal(z0.cpu().numpy(), z[0])
+
+
+def test_graph_replays_match_direct_launches(lib, monkeypatch):
+    # the solve is captured once per buffer set and replayed; every replay,
+    # with eager work in between, must equal a directly launched solve
+    import torch
+
+    wl = W.bidask_call_1d(n_x=4000, n_t=30, half_width=None)
+    iy, iz = wl.init_layers()
+    monkeypatch.setenv("BSDE_GRAPH", "0")
+    plan_d = lib.bsde_plan(wl.problem)
+    monkeypatch.setenv("BSDE_GRAPH", "1")
+    plan_g = lib.bsde_plan(wl.problem)
+    ws_d, ws_g = lib.workspace(plan_d), lib.workspace(plan_g)
+    t_iy = torch.as_tensor(iy, device="cuda").contiguous()
+    t_iz = torch.as_tensor(iz.reshape(iy.shape), device="cuda").contiguous()
+    n = iy.shape[1]
+    yd, zd = (torch.empty(n, dtype=torch.float64, device="cuda") for _ in range(2))
+    yg, zg = (torch.empty(n, dtype=torch.float64, device="cuda") for _ in range(2))
+    lib.bsde_solve(plan_d, ws_d, t_iy, t_iz, yd, zd)
+    torch.cuda.synchronize()
+    ref_y, ref_z = yd.clone(), zd.clone()
+    for rep in range(4):
+        yg.fill_(float("nan"))
+        zg.fill_(float("nan"))
+        lib.bsde_solve(plan_g, ws_g, t_iy, t_iz, yg, zg)
+        lib.bsde_solve(plan_d, ws_d, t_iy, t_iz, yd, zd)  # eager work between replays
+        torch.cuda.synchronize()
+        assert torch.equal(yg, ref_y) and torch.equal(zg, ref_z), rep
+        assert torch.equal(yd, ref_y) and torch.equal(zd, ref_z), rep
