@@ -206,17 +206,18 @@ SweepConfig fused_config(const Instance &in, int P, int G, size_t max_lds)
         reach = std::max(reach, in.win_hi[j] - in.win_lo[j] + 1);
     }
     const int w1 = T + in.win_hi[1] - in.win_lo[1] + 1;
-    const int elems = std::max(w1 + 2 * bsde::kHalo, wmax + bsde::kHalo);
-    c.cap = (P % 2 == 0) ? elems + elems / P + 1 : elems;  // window slots (padded layout)
-    c.cap1 = w1 + 2 * bsde::kHalo + 2;                       // PCR values per array
-    c.cap1 += c.cap1 & 1;  // keep the node table 16-byte aligned
+    c.cap = bsde::window_slots(P);  // fixed per P: windows must fit, checked below
+    c.cap1 = bsde::pcr_values(P);
     const size_t window_bytes = (size_t)c.cap * 2 * sizeof(double2) +
                                 (size_t)c.cap1 * 4 * sizeof(double);
     c.lds = window_bytes + bsde::node_table_lds(in.K * in.pb.L);
+    const bool fits = w1 + 2 * bsde::kHalo + 2 <= c.cap1 && w1 + 2 * bsde::kHalo <= bsde::window_elems(P) &&
+                      wmax + bsde::kHalo <= bsde::window_elems(P) && in.pb.L <= 64;
     c.blocks = (in.nx + T - 1) / T;
     const size_t reduce_bytes = (size_t)(G - 1) * kBlock * P * 2 * sizeof(double);
-    if (c.cap1 > NT * bsde::pcr_slots(P, NT) || c.lds > max_lds || reduce_bytes > window_bytes ||
-        reach > bsde::kMaxReach2)
+    if (!fits || w1 + 2 * bsde::kHalo + 2 > NT * bsde::pcr_slots(P, NT) || c.lds > max_lds ||
+        reduce_bytes > window_bytes || reach > bsde::kMaxReach2 ||
+        in.win_hi[1] - in.win_lo[1] + 1 > bsde::kMaxReach1)
         c.lds = 0;
     return c;
 }

@@ -44,8 +44,9 @@ struct NodeTable {
 };
 
 constexpr int kMaxNodes = 6 * 64;      // K * L at most
-constexpr int kMaxReach1 = 512;        // widest node reach of layer n+1 in the fused kernel
-constexpr int kMaxReach2 = 768;        // widest node reach of layers n+2.. in the fused kernel
+constexpr int kMaxReach1 = 160;        // widest node reach of layer n+1 in the fused kernel
+constexpr int kMaxReach2 = 320;        // widest node reach of layers n+2.. in the fused kernel
+static_assert(kMaxReach2 >= kMaxReach1 + kHalo, "layer n+1 window must fit the window arrays");
 constexpr size_t kNodeLdsBytes = sizeof(NodeRec) + sizeof(int) + sizeof(double);
 
 // PCR slots per thread of a fused block of NT threads and P points per lane
@@ -54,6 +55,20 @@ __host__ __device__ constexpr int pcr_slots(int P, int NT)
 {
     return (kBlock * P + 2 * kHalo + 2 + kMaxReach1 + NT - 1) / NT;
 }
+
+// Fixed LDS window capacity (slots) of the fused kernel with P points per
+// lane: the widest window of any layer plus the spline halo.  Being a
+// compile-time constant, the z array sits at an immediate offset from y.
+// The reach limits are sized so that the fused kernel with one point per
+// lane keeps four 256-thread blocks on a CU (LDS <= 40 KB per block) up to a
+// stability ratio of about 17 at K = 4, L = 16; wider reaches take the
+// direct path.
+__host__ __device__ constexpr int window_elems(int P) { return kBlock * P + kMaxReach2 + kHalo; }
+__host__ __device__ constexpr int window_slots(int P)
+{
+    return (P % 2 == 0) ? window_elems(P) + window_elems(P) / P + 1 : window_elems(P);
+}
+__host__ __device__ constexpr int pcr_values(int P) { return kBlock * P + kMaxReach1 + 2 * kHalo + 2; }
 
 // Slot of window element e in the LDS window arrays.  With an even number P
 // of points per lane a pad slot follows every P elements, so the lanes of a
@@ -201,19 +216,45 @@ __device__ inline double rtilde_global(const Rec64 *__restrict__ g, int nx, int 
 // holds (y, M_y) in wy[slot(e)] and (z, M_z) in wz[slot(e)] for the records
 // [lo, lo + W) (M = 0 outside (0, N-1)).  R holds 4 arrays of cap1 >= W +
 // 2 kHalo + 2 doubles.  Called by all NT threads; ends synchronised.
+// y and z of the staged range of spline_window, loaded into registers ahead
+// of use (U slots per thread; element e = tid + u NT).
+template <int U>
+struct SplineRaw {
+    double y[U], z[U];
+};
+
+template <int NT, int U>
+__device__ inline void spline_load(const Rec64 *__restrict__ g, int nx, int lo, int W,
+                                   SplineRaw<U> &raw)
+{
+    const int WS = W + 2 * kHalo + 2;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int e = threadIdx.x + u * NT;
+        if (e < WS) {
+            const int k = lo - kHalo - 1 + e;
+            const Rec64 r = g[min(max(k, 0), nx - 1)];
+            raw.y[u] = r.y;
+            raw.z[u] = r.z;
+        }
+    }
+}
+
 template <int NT, int U, int P>
 __device__ inline void spline_window(const Rec64 *__restrict__ g, int nx, int lo, int W,
                                      double2 *wy, double2 *wz, double *R, int cap1,
-                                     const PcrCoef &c)
+                                     const PcrCoef &c, const SplineRaw<U> &raw)
 {
     const int tid = threadIdx.x;
     const int WE = W + 2 * kHalo, WS = WE + 2;
     double *Ay = R, *Az = R + cap1, *By = R + 2 * cap1, *Bz = R + 3 * cap1;
-    for (int e = tid; e < WS; e += NT) {
-        const int k = lo - kHalo - 1 + e;
-        const Rec64 r = g[min(max(k, 0), nx - 1)];
-        Ay[e] = r.y;
-        Az[e] = r.z;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int e = tid + u * NT;
+        if (e < WS) {
+            Ay[e] = raw.y[u];
+            Az[e] = raw.z[u];
+        }
     }
     __syncthreads();
     for (int e = tid; e < WE; e += NT) {
@@ -306,15 +347,22 @@ __device__ inline void node_accumulate(const double2 (&ry)[P + 1], const double2
 
 // Nodes l = l0, l0 + LS, l0 + 2 LS, ... < L of one layer, reading P+1
 // consecutive records per lane from src at node offset m.
+// The node offsets of a layer are held one per lane (L <= 64) and moved to
+// a scalar register per node with readlane, so the records of a node are
+// addressed without waiting for an LDS read; the coefficients are read from
+// LDS together with the records.
 template <int P, int DRV, bool LASTY, typename Src>
 __device__ inline void layer_nodes(const Src &src, const NodeRec *trec, const int *tm,
                                    const double *tcy, int row, int l0, int LS, int L,
                                    const Driver<DRV> &f, double (&Y)[P], double (&Z)[P])
 {
+    const int lane = threadIdx.x & 63;
+    const int mv = tm[row + min(lane, L - 1)];
 #pragma unroll 1
     for (int l = l0; l < L; l += LS) {
+        const int m = __builtin_amdgcn_readlane(mv, l);
         double2 ry[P + 1], rz[P + 1];
-        src.template fetch<P>(tm[row + l], ry, rz);
+        src.template fetch<P>(m, ry, rz);
         node_accumulate<P, DRV, LASTY>(ry, rz, trec[row + l], LASTY ? tcy[row + l] : 0.0, f, Y, Z);
     }
 }

@@ -27,20 +27,21 @@ namespace bsde {
 //   (P+1) tig + off + off/P + q + [q >= P - off % P]   (tig = lane_pt / P),
 // so the per-record offsets are one of P compile-time patterns.
 template <int P, int B, bool PAD>
-__device__ inline void fetch_slots(const double2 *wy, const double2 *wz, int base,
-                                   double2 (&ry)[P + 1], double2 (&rz)[P + 1])
+__device__ inline void fetch_slots(const double2 *wy, int base, double2 (&ry)[P + 1],
+                                   double2 (&rz)[P + 1])
 {
+    const double2 *p = wy + base;
 #pragma unroll
     for (int q = 0; q <= P; ++q) {
-        const int sl = base + q + ((PAD && q >= P - B) ? 1 : 0);
-        ry[q] = wy[sl];
-        rz[q] = wz[sl];
+        const int sl = q + ((PAD && q >= P - B) ? 1 : 0);
+        ry[q] = p[sl];
+        rz[q] = p[sl + window_slots(P)];  // z array at a fixed distance
     }
 }
 
 template <int P>
 struct LdsWindow {
-    const double2 *wy, *wz;
+    const double2 *wy;  // z array follows at window_slots(P)
     int ebase;  // kHalo - (lowest node offset of the layer): off = ebase + m
     int lane;   // slot of the lane's first element at off = 0: (P+1) tig padded, P tig not
     template <int PP>
@@ -49,14 +50,14 @@ struct LdsWindow {
         static_assert(PP == P, "window layout and fetch width differ");
         const int off = ebase + m;
         if constexpr (!WinLayout<P>::kPad) {
-            fetch_slots<P, 0, false>(wy, wz, lane + off, ry, rz);
+            fetch_slots<P, 0, false>(wy, lane + off, ry, rz);
         } else {
             const int base = lane + off + off / P;
             switch (off % P) {
-            case 0: fetch_slots<P, 0, true>(wy, wz, base, ry, rz); break;
-            case 1: fetch_slots<P, 1, true>(wy, wz, base, ry, rz); break;
-            case 2: fetch_slots<P, (P > 2 ? 2 : 1), true>(wy, wz, base, ry, rz); break;
-            default: fetch_slots<P, (P > 3 ? 3 : 1), true>(wy, wz, base, ry, rz); break;
+            case 0: fetch_slots<P, 0, true>(wy, base, ry, rz); break;
+            case 1: fetch_slots<P, 1, true>(wy, base, ry, rz); break;
+            case 2: fetch_slots<P, (P > 2 ? 2 : 1), true>(wy, base, ry, rz); break;
+            default: fetch_slots<P, (P > 3 ? 3 : 1), true>(wy, base, ry, rz); break;
             }
         }
     }
@@ -96,8 +97,8 @@ __device__ inline void layer_dispatch(const Src &src, const NodeRec *trec, const
 // A block of G*kBlock threads owns a tile of kBlock*P points; thread group g
 // (kBlock threads) takes the nodes l = g, g+G, ... of every layer, and the G
 // partial sums meet in LDS before group 0 finishes the points.
-// Dynamic LDS: wy[cap], wz[cap] (double2), Ry[cap1], Rz[cap1] (double),
-// node table (K*L NodeRec, K*L int, K*L double).
+// Dynamic LDS: wy, wz (window_slots(P) double2 each), the four PCR arrays
+// (pcr_values(P) doubles each), node table (K*L NodeRec, K*L int, K*L double).
 // ---------------------------------------------------------------------------
 template <int P, int G, int DRV>
 __global__ void __launch_bounds__(kBlock * G) sweep_fused(const SweepArgs a)
@@ -105,10 +106,11 @@ __global__ void __launch_bounds__(kBlock * G) sweep_fused(const SweepArgs a)
     constexpr int T = kBlock * P;
     constexpr int NT = kBlock * G;
     extern __shared__ double2 smem[];
+    constexpr int CAP = window_slots(P), CAP1 = pcr_values(P);
     double2 *wy = smem;
-    double2 *wz = wy + a.lds_cap;
-    double *R = reinterpret_cast<double *>(wz + a.lds_cap);
-    NodeRec *trec = reinterpret_cast<NodeRec *>(R + 4 * a.lds_cap1);
+    double2 *wz = wy + CAP;
+    double *R = reinterpret_cast<double *>(wz + CAP);
+    NodeRec *trec = reinterpret_cast<NodeRec *>(R + 4 * CAP1);
     int *tm = reinterpret_cast<int *>(trec + a.K * a.L);
     double *tcy = reinterpret_cast<double *>(tm + ((a.K * a.L + 1) & ~1));
 
@@ -125,9 +127,13 @@ __global__ void __launch_bounds__(kBlock * G) sweep_fused(const SweepArgs a)
 #pragma unroll
     for (int q = 0; q < P; ++q) Y[q] = Z[q] = 0.0;
 
-    // records of the next layer's window, loaded while the current layer's
-    // nodes are evaluated (kPre per thread covers windows of NT * kPre records)
+    // Layers are processed in the order 2, 3, ..., K, 1: the records of layers
+    // n+2.. are complete (their splines were built by earlier launches) and
+    // their windows are prefetched into registers one layer ahead, while the
+    // raw values of layer n+1 (written by the previous launch) are loaded at
+    // the start and only turned into its spline after the other layers.
     constexpr int kPre = (T + kMaxReach2 + NT - 1) / NT;
+    constexpr int kRaw = pcr_slots(P, NT);
     Rec64 pre[kPre];
     auto prefetch = [&](int j) {
         const Rec64 *__restrict__ g = a.ring + (size_t)((a.n + j) % S) * a.npad + a.pad_l;
@@ -139,17 +145,24 @@ __global__ void __launch_bounds__(kBlock * G) sweep_fused(const SweepArgs a)
             if (e < W) pre[u] = g[lo + e];
         }
     };
-    if (a.K >= 2) prefetch(2);
+    SplineRaw<kRaw> raw1;
+    {
+        const Rec64 *__restrict__ g1 = a.ring + (size_t)((a.n + 1) % S) * a.npad + a.pad_l;
+        const int W1 = T + (a.tab.win_hi[1] - a.tab.win_lo[1]) + 1;
+        if (a.K >= 2) prefetch(2);
+        spline_load<NT, kRaw>(g1, a.nx, t0 + a.tab.win_lo[1], W1, raw1);
+    }
 
-    for (int j = 1; j <= a.K; ++j) {
+    for (int jj = 0; jj < a.K; ++jj) {
+        const int j = (jj + 1 < a.K) ? jj + 2 : 1;
         Rec64 *__restrict__ g = a.ring + (size_t)((a.n + j) % S) * a.npad + a.pad_l;
         const int mlo = a.tab.win_lo[j], mhi = a.tab.win_hi[j];
         const int W = T + (mhi - mlo) + 1;
         const int lo = t0 + mlo;
         if (j == 1) {
-            // layer n+1 was produced by the previous launch: build its spline
-            // on the window, and store the tile's part for the later steps
-            spline_window<NT, pcr_slots(P, NT), P>(g, a.nx, lo, W, wy, wz, R, a.lds_cap1, a.pcr);
+            // spline of layer n+1 on the window; the tile's part goes back to
+            // HBM for the later steps, with the ghost records
+            spline_window<NT, kRaw, P>(g, a.nx, lo, W, wy, wz, R, CAP1, a.pcr, raw1);
             const int kend = min(t0 + T, a.nx);
             for (int k = t0 + tid; k < kend; k += NT) {
                 const int sl = WinLayout<P>::slot(k - lo + kHalo);
@@ -174,10 +187,10 @@ __global__ void __launch_bounds__(kBlock * G) sweep_fused(const SweepArgs a)
                     wz[sl] = make_double2(pre[u].z, pre[u].Mz);
                 }
             }
-            if (j < a.K) prefetch(j + 1);
+            if (j + 1 <= a.K) prefetch(j + 1);
             __syncthreads();
         }
-        const LdsWindow<P> src{wy, wz, kHalo - mlo,
+        const LdsWindow<P> src{wy, kHalo - mlo,
                                WinLayout<P>::kPad ? lane_pt + lane_pt / P : lane_pt};
         layer_dispatch<P, DRV>(src, trec, tm, tcy, j, grp, G, a, Y, Z);
         __syncthreads();  // the window is reused by the next layer
@@ -242,7 +255,10 @@ __global__ void __launch_bounds__(kBlock) spline_f64(Rec64 *slot, int nx, int pa
     Rec64 *__restrict__ g = slot + pad_l;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int t0 = tile * kSplineTile;
-    spline_window<kBlock, (WS + kBlock - 1) / kBlock, 1>(g, nx, t0, kSplineTile, wy, wz, R, WS, c);
+    constexpr int U = (WS + kBlock - 1) / kBlock;
+    SplineRaw<U> raw;
+    spline_load<kBlock, U>(g, nx, t0, kSplineTile, raw);
+    spline_window<kBlock, U, 1>(g, nx, t0, kSplineTile, wy, wz, R, WS, c, raw);
     const int kend = min(t0 + kSplineTile, nx);
     for (int k = t0 + (int)threadIdx.x; k < kend; k += kBlock) {
         g[k].My = wy[k - t0 + kHalo].y;
