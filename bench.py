@@ -66,7 +66,7 @@ def bytes_per_point_step(pb: dict) -> float:
     return 32.0 * K + 16.0
 
 
-KERNEL_SOURCES = ["capi.hip", "kernels_f64.hip", "device_common.h", "kernels.h", "plan_math.cpp",
+KERNEL_SOURCES = ["capi.hip", "sweep.hip", "device_common.h", "kernels.h", "plan_math.cpp",
                   "plan_math.h"]
 
 
@@ -125,6 +125,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="bidask1d")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--fp64-only", action="store_true", help="skip the FP32-form run")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="profiling runs: stop each solve after this many backward steps "
@@ -149,6 +150,7 @@ def main() -> int:
               "build runs on a single MI355X; --gpus must be 1", file=sys.stderr)
         return 2
 
+    import numpy as np
     import torch
 
     import paper_1909_13560_amd as B
@@ -162,51 +164,70 @@ def main() -> int:
         args.no_cpu_baseline = True
     dev = "cuda:0"
     torch.cuda.set_device(0)
-    plan = B.bsde_plan(pb)
-    ws = B.workspace(plan, dev)
     iy, iz = wl.init_layers()
     K, nx = wl.K, pb["n_x"]
     t_iy = torch.as_tensor(iy, device=dev).contiguous()
     t_iz = torch.as_tensor(iz.reshape(K, nx), device=dev).contiguous()
-    y0 = torch.empty(nx, dtype=torch.float64, device=dev)
-    z0 = torch.empty(nx, dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
+    ye, ze = wl.exact_at_t0()
+    i = wl.node_index()
 
-    # one checked solve: status and Picard statistics
-    rc, st = B.bsde_solve(plan, ws, t_iy, t_iz, y0, z0, stream=stream, stats=True)
-    print(f"[bench] workload {wl.name} status {B.bsde_status_string(rc)} stats {st}",
-          file=sys.stderr, flush=True)
-    for _ in range(args.warmup):
-        B.bsde_solve(plan, ws, t_iy, t_iz, y0, z0, stream=stream)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(args.steps):
-        B.bsde_solve(plan, ws, t_iy, t_iz, y0, z0, stream=stream)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / args.steps
+    def run(prec: str):
+        """Time full solves of the workload in one precision form."""
+        p = dict(pb, prec=prec)
+        plan = B.bsde_plan(p)
+        ws = B.workspace(plan, dev)
+        y0 = torch.empty(nx, dtype=torch.float64, device=dev)
+        z0 = torch.empty(nx, dtype=torch.float64, device=dev)
+        # one checked solve: status and Picard statistics
+        rc, st = B.bsde_solve(plan, ws, t_iy, t_iz, y0, z0, stream=stream, stats=True)
+        print(f"[bench] workload {wl.name} {prec} status {B.bsde_status_string(rc)} stats {st}",
+              file=sys.stderr, flush=True)
+        for _ in range(args.warmup):
+            B.bsde_solve(plan, ws, t_iy, t_iz, y0, z0, stream=stream)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(args.steps):
+            B.bsde_solve(plan, ws, t_iy, t_iz, y0, z0, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        print(f"[bench] {prec}: {args.steps} solves, {ms:.3f} ms per solve", file=sys.stderr,
+              flush=True)
+        # per-kernel durations from hipEvents around every launch of one solve
+        kt = B.bsde_profile_kernels(plan, ws, [(t_iy, t_iz, y0, z0)], stream=stream)
+        print(f"[bench] {prec}: kernels {kt}", file=sys.stderr, flush=True)
+        return ms, st, kt, y0.cpu().numpy(), z0.cpu().numpy()
+
+    ms, st, kt, y_h, z_h = run("fp64")
     value = nx * (pb["n_t"] if not args.profile_steps else steps_run) / (ms * 1e-3)
-    print(f"[bench] {args.steps} solves, {ms:.3f} ms per solve", file=sys.stderr, flush=True)
-
-    # per-kernel durations from hipEvents around every launch of one solve
-    kt = B.bsde_profile_kernels(plan, ws, t_iy, t_iz, y0, z0, stream=stream)
     sweep_ms = kt["sweep_ms"] / kt["sweep_launches"]
     spline_ms = kt["spline_ms"] / kt["spline_launches"] if kt["spline_launches"] else 0.0
     fl = flops_per_point_step(pb, st["picard_iter_mean"]) * nx
     achieved = fl / (sweep_ms * 1e-3) / 1e12
-    print(f"[bench] sweep kernel {sweep_ms * 1e3:.1f} us/launch, spline {spline_ms * 1e3:.1f} "
-          f"us/launch, config {kt}", file=sys.stderr, flush=True)
-
     # error of the headline value against the closed form
-    y_h = y0.cpu().numpy()
-    z_h = z0.cpu().numpy()
-    ye, ze = wl.exact_at_t0()
-    i = wl.node_index()
     err = {"y0": float(y_h[i]), "z0": float(z_h[i]),
            "abs_err_y0": float(abs(y_h[i] - ye[i])), "abs_err_z0": float(abs(z_h[i] - ze[i]))}
+
+    fp32 = None
+    if not args.fp64_only:
+        ms32, st32, kt32, y32, z32 = run("fp32_comp")
+        sw32 = kt32["sweep_ms"] / kt32["sweep_launches"]
+        scale = np.maximum(np.abs(y_h), 1.0)
+        fp32 = {
+            "value": nx * (pb["n_t"] if not args.profile_steps else steps_run) / (ms32 * 1e-3),
+            "ms_per_step": ms32, "speedup_vs_fp64": ms / ms32, "kernel_us": sw32 * 1e3,
+            "vector_alu_tflops": flops_per_point_step(pb, st32["picard_iter_mean"]) * nx
+            / (sw32 * 1e-3) / 1e12,
+            "max_rel_err_vs_fp64_y": float(np.max(np.abs(y32 - y_h) / scale)),
+            "max_rel_err_vs_fp64_z": float(np.max(np.abs(z32 - z_h) / np.maximum(np.abs(z_h), 1.0))),
+            "rel_err_y0_vs_closed_form": float(abs(y32[i] - ye[i]) / max(abs(ye[i]), 1.0)),
+            "rel_err_z0_vs_closed_form": float(abs(z32[i] - ze[i]) / max(abs(ze[i]), 1.0)),
+            "config": {"points_per_lane": kt32["points_per_lane"],
+                       "node_groups": kt32["node_groups"], "path": kt32["path"]},
+        }
 
     out = {
         "metric": "grid-point*time-step updates/sec (k=4, L=16)",
@@ -232,7 +253,11 @@ def main() -> int:
                      "flops_per_launch": fl,
                      "hbm_bytes_per_launch_algorithmic": bytes_per_point_step(pb) * nx},
         "spline_kernel_us": spline_ms * 1e3,
+        "sweep_config": {"points_per_lane": kt["points_per_lane"],
+                         "node_groups": kt["node_groups"], "path": kt["path"],
+                         "blocks": kt["blocks"], "lds_bytes": kt["lds_bytes"]},
         "accuracy": err,
+        "fp32_comp": fp32,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget)

@@ -60,9 +60,15 @@ typedef enum {
 
 typedef enum {
     BSDE_FP64 = 0,      /* all arithmetic in double precision                   */
-    BSDE_FP32_COMP = 1  /* quadrature and interpolation in single precision with
-                           compensated (error-free transformation) sums; spline
-                           solve, z combination and Picard in double precision */
+    BSDE_FP32_COMP = 1  /* the ring of time layers and the node interpolation and
+                           driver evaluations in single precision; the terms
+                           that carry the size of the solution (the y-hat and
+                           z-hat expectations) summed in double precision, the
+                           small f-hat terms per layer in single precision and
+                           then added in double; spline solve, z combination
+                           and Picard in double precision.  Error against the
+                           FP64 form: a few 1e-7 relative (bid-ask call,
+                           262144 points, 1024 steps)                          */
 } bsde_precision;
 
 /* One BSDE.  d = 1 in this release; the d = 2 fields are reserved. */
@@ -160,11 +166,15 @@ bsde_status bsde_solve(bsde_plan_t plan, void *ws, const double *init_y, const d
                        double *y0, double *z0, void *stream, bsde_stats *st);
 
 /*
- * bsde_solve_batched -- bsde_solve for every instance b of a plan built with
- * batch > 1 (instances may differ in every field except d and prec), with
- * io[b] (host array of `batch` entries holding device pointers) giving the
- * buffers of instance b, laid out as in bsde_solve.  One workspace serves the
- * whole batch.  Stats, when requested, aggregate over the batch.
+ * bsde_solve_batched -- bsde_solve for every instance b of a plan (any batch
+ * size; instances may differ in every field except d), with io[b] (host
+ * array of `batch` entries holding device pointers) giving the buffers of
+ * instance b, laid out as in bsde_solve.  One workspace serves the whole
+ * batch.  Instances of equal precision and driver form a group; each time
+ * step is one kernel launch per group that advances every instance of the
+ * group still active by one layer (instances of fewer steps finish first).
+ * The whole solve is one hipGraph launch as for bsde_solve.  Stats, when
+ * requested, aggregate over the batch.
  * Errors: as bsde_solve.
  */
 bsde_status bsde_solve_batched(bsde_plan_t plan, void *ws, const bsde_io *io, void *stream,
@@ -172,51 +182,64 @@ bsde_status bsde_solve_batched(bsde_plan_t plan, void *ws, const bsde_io *io, vo
 
 /* Per-kernel device time of one solve, from hipEvent pairs around launches. */
 typedef struct {
-    double sweep_ms;      /* summed duration of the sweep launches (one per step) */
+    double sweep_ms;      /* summed duration of the sweep launches (one per step
+                             and group)                                         */
     int sweep_launches;
     double spline_ms;     /* summed duration of the separate spline launches of
                              the loop (0 launches when the sweep kernel builds
                              the splines itself)                                  */
     int spline_launches;
-    int path;             /* sweep kernel: 0 = LDS-staged windows with the spline
-                             of the newest layer in-kernel, 1 = direct loads     */
+    int path;             /* sweep kernel of group 0: 0 = LDS-staged windows with
+                             the spline of the newest layer in-kernel, 1 = direct
+                             loads                                              */
     int points_per_lane;  /* grid points per lane of the sweep kernel            */
     int node_groups;      /* thread groups sharing the nodes of one tile         */
-    int blocks;           /* blocks per sweep launch                             */
+    int blocks;           /* blocks of the first sweep launch of group 0         */
     long long lds_bytes;  /* dynamic LDS per block of the sweep kernel           */
 } bsde_kernel_times;
 
 /*
- * bsde_profile_kernels -- bsde_solve of instance 0 (same arguments, same
- * results in y0, z0) with a hipEvent pair recorded around every launch of
- * the sweep and spline kernels of the backward loop, so their average
- * durations can be set against their algorithmic work.  Synchronises the
- * stream and fills *kt.  Meant for measurement; bsde_solve is the fast path.
+ * bsde_profile_kernels -- bsde_solve_batched (same arguments, same results)
+ * launched directly, with a hipEvent pair recorded around every launch of the
+ * sweep and spline kernels of the backward loop, so their average durations
+ * can be set against their algorithmic work.  Synchronises the stream and
+ * fills *kt.  Meant for measurement; bsde_solve is the fast path.
  * Errors: as bsde_solve.
  */
-bsde_status bsde_profile_kernels(bsde_plan_t plan, void *ws, const double *init_y,
-                                 const double *init_z, double *y0, double *z0, void *stream,
+bsde_status bsde_profile_kernels(bsde_plan_t plan, void *ws, const bsde_io *io, void *stream,
                                  bsde_kernel_times *kt);
 
-/* Static text for a status code (never NULL). */
-const char *bsde_status_string(bsde_status s);
+typedef struct {
+    int path, points_per_lane, node_groups;  /* chosen shape of group 0           */
+    double best_ms_per_step;                 /* its measured time of one step      */
+    int candidates;                          /* shapes timed over all groups       */
+} bsde_tune_report;
 
 /*
- * Host-only helpers (no device needed), exposed for inspection and tests.
- *
- * bsde_gauss_hermite -- the L-point Gauss-Hermite rule for the weight
- * exp(-x^2) used in eq (21): nodes a[0..L-1] ascending and weights w[0..L-1]
- * (they sum to sqrt(pi)).  Golub-Welsch: eigen-decomposition of the Jacobi
- * matrix of the Hermite recurrence.  BSDE_EINVAL unless 1 <= L <= 64.
- *
- * bsde_gamma -- table = 1: gamma^{K}_{K,j}, j = 0..K (Table 1, the spline
- * quadrature over K steps divided by K dt); table = 2: gamma^{1}_{K,j}
- * (Table 2, over the first step).  Computed from the not-a-knot cubic spline
- * through K+1 equispaced points; g receives K+1 values.  BSDE_EINVAL unless
- * table is 1 or 2 and 1 <= K <= 6.
+ * bsde_autotune -- choose the sweep kernel shape of every group of the plan
+ * by measurement: the initial layers of io are loaded into ws, and for each
+ * shape that fits (fused kernel with 1, 2 or 4 points per lane and 1 or 2
+ * node groups; the direct kernel when none fits) the first time step of the
+ * group is launched `reps` times and timed with hipEvents; the fastest shape
+ * is kept in the plan.  Replaces the default shape (or BSDE_SWEEP); drops the
+ * plan's captured graphs.  Synchronises the stream.  Must not run while
+ * another solve uses the plan.  rep may be NULL.
+ * Errors: BSDE_EINVAL (as bsde_solve_batched, or reps < 1), BSDE_EDEVICE.
  */
+bsde_status bsde_autotune(bsde_plan_t plan, void *ws, const bsde_io *io, void *stream, int reps,
+                          bsde_tune_report *rep);
+
+/* Gauss-Hermite rule (nodes ascending, weights for exp(-x^2), sum sqrt(pi))
+ * as used by the plan; L in [1, 64].  Host arrays of L doubles. */
 bsde_status bsde_gauss_hermite(int L, double *a, double *w);
+
+/* Row K (1..6) of Table 1 (table = 1: gamma^K_{K,j}, integral over K steps
+ * divided by K dt) or Table 2 (table = 2: integral over the first step divided
+ * by dt) into g[0..K]: the not-a-knot spline quadrature weights. */
 bsde_status bsde_gamma(int table, int K, double *g);
+
+/* Human-readable name of a status code (static storage). */
+const char *bsde_status_string(bsde_status s);
 
 #ifdef __cplusplus
 }

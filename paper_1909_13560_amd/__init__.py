@@ -27,7 +27,7 @@ PRECISIONS = {"fp64": 0, "fp32_comp": 1}
 
 EXPORTED = ["bsde_plan", "bsde_plan_destroy", "bsde_workspace_bytes", "bsde_solve",
             "bsde_solve_batched", "bsde_profile_kernels", "bsde_status_string",
-            "bsde_gauss_hermite", "bsde_gamma"]
+            "bsde_gauss_hermite", "bsde_gamma", "bsde_autotune"]
 
 
 class BsdeError(RuntimeError):
@@ -77,6 +77,12 @@ class _KernelTimes(ctypes.Structure):
                 ("blocks", ctypes.c_int), ("lds_bytes", ctypes.c_longlong)]
 
 
+class _TuneReport(ctypes.Structure):
+    _fields_ = [("path", ctypes.c_int), ("points_per_lane", ctypes.c_int),
+                ("node_groups", ctypes.c_int), ("best_ms_per_step", ctypes.c_double),
+                ("candidates", ctypes.c_int)]
+
+
 class _Io(ctypes.Structure):
     _fields_ = [("init_y", ctypes.c_void_p), ("init_z", ctypes.c_void_p),
                 ("y0", ctypes.c_void_p), ("z0", ctypes.c_void_p)]
@@ -103,9 +109,12 @@ def load() -> ctypes.CDLL:
         lib.bsde_solve.restype = ip
         lib.bsde_solve_batched.argtypes = [vp, vp, ctypes.POINTER(_Io), vp, ctypes.POINTER(_Stats)]
         lib.bsde_solve_batched.restype = ip
-        lib.bsde_profile_kernels.argtypes = [vp, vp, vp, vp, vp, vp, vp,
+        lib.bsde_profile_kernels.argtypes = [vp, vp, ctypes.POINTER(_Io), vp,
                                              ctypes.POINTER(_KernelTimes)]
         lib.bsde_profile_kernels.restype = ip
+        lib.bsde_autotune.argtypes = [vp, vp, ctypes.POINTER(_Io), vp, ip,
+                                      ctypes.POINTER(_TuneReport)]
+        lib.bsde_autotune.restype = ip
         lib.bsde_status_string.argtypes = [ip]
         lib.bsde_status_string.restype = ctypes.c_char_p
         lib.bsde_gauss_hermite.argtypes = [ip, dp, dp]
@@ -224,9 +233,13 @@ def bsde_solve(plan: Plan, ws, init_y, init_z, y0, z0, stream=None, stats: bool 
     return rc, (_stats_dict(st) if st is not None else None)
 
 
+def _io_array(ios):
+    return (_Io * len(ios))(*[_Io(_dptr(a), _dptr(b), _dptr(c), _dptr(d)) for a, b, c, d in ios])
+
+
 def bsde_solve_batched(plan: Plan, ws, ios, stream=None, stats: bool = False, check: bool = True):
     """bsde_solve_batched; ``ios`` is a list of (init_y, init_z, y0, z0) tensors."""
-    arr = (_Io * len(ios))(*[_Io(_dptr(a), _dptr(b), _dptr(c), _dptr(d)) for a, b, c, d in ios])
+    arr = _io_array(ios)
     st = _Stats() if stats else None
     rc = load().bsde_solve_batched(ctypes.c_void_p(plan.handle), ctypes.c_void_p(_dptr(ws)), arr,
                                    ctypes.c_void_p(_stream_ptr(stream)),
@@ -236,16 +249,26 @@ def bsde_solve_batched(plan: Plan, ws, ios, stream=None, stats: bool = False, ch
     return rc, (_stats_dict(st) if st is not None else None)
 
 
-def bsde_profile_kernels(plan: Plan, ws, init_y, init_z, y0, z0, stream=None) -> dict:
-    """bsde_profile_kernels: per-kernel hipEvent times of one solve."""
+def bsde_profile_kernels(plan: Plan, ws, ios, stream=None) -> dict:
+    """bsde_profile_kernels: per-kernel hipEvent times of one (batched) solve."""
     kt = _KernelTimes()
     rc = load().bsde_profile_kernels(ctypes.c_void_p(plan.handle), ctypes.c_void_p(_dptr(ws)),
-                                     ctypes.c_void_p(_dptr(init_y)), ctypes.c_void_p(_dptr(init_z)),
-                                     ctypes.c_void_p(_dptr(y0)), ctypes.c_void_p(_dptr(z0)),
-                                     ctypes.c_void_p(_stream_ptr(stream)), ctypes.byref(kt))
+                                     _io_array(ios), ctypes.c_void_p(_stream_ptr(stream)),
+                                     ctypes.byref(kt))
     if rc != BSDE_OK:
         raise BsdeError(rc, "bsde_profile_kernels")
     return {k: getattr(kt, k) for k, _ in _KernelTimes._fields_}
+
+
+def bsde_autotune(plan: Plan, ws, ios, stream=None, reps: int = 5) -> dict:
+    """bsde_autotune: time the sweep shapes on these buffers and keep the fastest."""
+    rep = _TuneReport()
+    rc = load().bsde_autotune(ctypes.c_void_p(plan.handle), ctypes.c_void_p(_dptr(ws)),
+                              _io_array(ios), ctypes.c_void_p(_stream_ptr(stream)), int(reps),
+                              ctypes.byref(rep))
+    if rc != BSDE_OK:
+        raise BsdeError(rc, "bsde_autotune")
+    return {k: getattr(rep, k) for k, _ in _TuneReport._fields_}
 
 
 def bsde_gauss_hermite(L: int):

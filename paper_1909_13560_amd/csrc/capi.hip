@@ -27,6 +27,7 @@
 namespace {
 
 using bsde::kBlock;
+using bsde::Rec32;
 using bsde::Rec64;
 
 enum SweepPath { PATH_FUSED = 0, PATH_DIRECT = 1 };
@@ -35,13 +36,10 @@ struct SweepConfig {
     int path = PATH_DIRECT;
     int P = 2;
     int G = 1;       // node groups per tile (fused path)
-    int blocks = 0;
-    size_t lds = 0;  // dynamic LDS bytes (fused path)
-    int cap = 0, cap1 = 0;
+    size_t lds = 0;  // dynamic LDS bytes; 0 marks a fused shape that does not fit
 };
 
-constexpr int kMaxFusedP = 5;
-constexpr int kMaxDirectP = 4;
+constexpr int kMaxP = 4;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -51,13 +49,41 @@ struct Instance {
     double dx, dt, h0;
     int m_min, m_max;
     double R;
+    bool f32;
+    int steps;  // layers computed: N - K - n_stop + 1
     bsde::DriverParams drv;
     std::vector<int> m, win_lo, win_hi;
-    std::vector<double> A, B, C, D, cfy, cfz, cz, cy;
+    std::vector<double> B, C, D, cfy, cfz, cz, cy;
     bsde::NodeTable dtab;
-    size_t ring_off, stat_off;
-    int nwaves;  // per-wave statistics slots (largest launch of any configuration)
+    size_t ring_off, fin_off, stat_off;
+    int nwaves;  // per-wave statistics slots (P = 1 has the most waves)
+    int group;
+};
+
+// Instances sharing precision, driver and kernel shape: one launch per step
+// serves all of them.  Members are sorted by their number of steps (most
+// first), so the instances active at step s are a prefix.
+struct Group {
+    bool f32 = false;
+    int driver = 0;
     SweepConfig cfg;
+    std::vector<int> members;
+    std::vector<int> tile_prefix, spline_prefix;  // members + 1 entries
+    int *d_tile_inst = nullptr;    // grid tile -> instance (sized for P = 1)
+    int *d_spline_inst = nullptr;  // spline tile -> instance
+    int max_steps = 0;
+    int active(int s, const std::vector<Instance> &inst) const
+    {
+        int lo = 0, hi = (int)members.size();  // members[0..lo) have steps > s
+        while (lo < hi) {
+            const int mid = (lo + hi) / 2;
+            if (inst[members[mid]].steps > s)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        return lo;
+    }
 };
 
 }  // namespace
@@ -77,15 +103,24 @@ struct bsde_plan_s {
     int device = 0;
     size_t max_lds = 65536;
     std::vector<Instance> inst;
+    std::vector<Group> groups;
+    std::vector<bsde::InstDesc> desc;       // host copy of the descriptors
+    bsde::InstDesc *d_desc = nullptr;
     void *d_tables = nullptr;
     size_t ws_bytes = 0;
-    size_t totals_off = 0;
-    bsde::PcrCoef pcr_base;  // kappa, inv_b (s6 set per instance)
+    size_t stats_off = 0, stats_bytes = 0;  // statistics region of the workspace
+    size_t totals_off = 0;                  // 3 u64 per instance + non-finite count
+    bsde::PcrCoef pcr_base;                 // kappa, inv_b (s6 set per instance)
     bool use_graphs = true;
-    std::mutex mu;                    // guards the graph cache
+    std::mutex mu;                          // guards the graph cache
     hipStream_t capture_stream = nullptr;
     std::vector<GraphEntry> graphs;
     unsigned long long clock = 0;
+    void drop_graphs()
+    {
+        for (GraphEntry &g : graphs) (void)hipGraphExecDestroy(g.exec);
+        graphs.clear();
+    }
 };
 
 namespace {
@@ -131,6 +166,8 @@ bool build_instance(const bsde_problem &p, Instance &in)
     in.nx = p.n_x[0];
     in.dt = p.T / p.n_t;
     in.dx = (p.x_max[0] - p.x_min[0]) / (in.nx - 1);
+    in.f32 = p.prec == BSDE_FP32_COMP;
+    in.steps = p.n_t - in.K - p.n_stop + 1;
     const double vol = p.vol[0][0];
     in.R = vol * std::sqrt(2.0 * in.dt) / in.dx;
     double a[bsde::kMaxL], w[bsde::kMaxL], gy[8], gz[8];
@@ -139,8 +176,8 @@ bool build_instance(const bsde_problem &p, Instance &in)
     const double inv_sqrt_pi = 0.56418958354775628695;
     const int K = in.K, L = p.L;
     in.m.assign(K * L, 0);
-    in.A.assign(K * L, 0.0);
-    in.B = in.C = in.D = in.cfy = in.cfz = in.cz = in.A;
+    in.B.assign(K * L, 0.0);
+    in.C = in.D = in.cfy = in.cfz = in.cz = in.B;
     in.cy.assign(L, 0.0);
     in.win_lo.assign(K + 1, 0);
     in.win_hi.assign(K + 1, 0);
@@ -161,7 +198,6 @@ bool build_instance(const bsde_problem &p, Instance &in)
             const double u = 1.0 - phi;
             const double wl = w[l] * inv_sqrt_pi;
             in.m[k] = m;
-            in.A[k] = u;
             in.B[k] = phi;
             in.C[k] = dx26 * (u * u * u - u);
             in.D[k] = dx26 * (phi * phi * phi - phi);
@@ -184,113 +220,118 @@ bool build_instance(const bsde_problem &p, Instance &in)
     in.h0 = p.k_y * in.dt * gy[0];
     in.pad_l = std::max(0, -in.m_min) + 1;
     // right ghosts cover the overhang of the last tile of any configuration
-    in.pad_r = std::max(0, in.m_max) + kBlock * std::max(kMaxFusedP, kMaxDirectP) + 2;
+    in.pad_r = std::max(0, in.m_max) + kBlock * kMaxP + 2;
     in.npad = in.pad_l + in.nx + in.pad_r;
     in.drv = bsde::DriverParams{p.p[0], p.p[1], p.p[2], p.p[3], p.p[4]};
-    in.nwaves = (in.nx + kBlock - 1) / kBlock * (kBlock / 64);  // P = 1 has the most waves
+    in.nwaves = (in.nx + kBlock - 1) / kBlock * (kBlock / 64);
     return true;
 }
 
-// Dynamic LDS of the fused kernel with P points per lane and G node groups,
-// or lds = 0 if the windows exceed the PCR work split or the device limit.
-SweepConfig fused_config(const Instance &in, int P, int G, size_t max_lds)
+// The fused kernel with P points per lane and G node groups for every
+// member of a group, or lds = 0 if some member's windows do not fit.
+SweepConfig fused_config(const std::vector<Instance> &all, const std::vector<int> &members,
+                         bool f32, int P, int G, size_t max_lds)
 {
     SweepConfig c;
     c.path = PATH_FUSED;
     c.P = P;
     c.G = G;
     const int T = kBlock * P, NT = kBlock * G;
-    int wmax = 0, reach = 0;
-    for (int j = 2; j <= in.K; ++j) {
-        wmax = std::max(wmax, T + in.win_hi[j] - in.win_lo[j] + 1);
-        reach = std::max(reach, in.win_hi[j] - in.win_lo[j] + 1);
+    size_t lds = 0;
+    for (int b : members) {
+        const Instance &in = all[b];
+        int wmax = 0, reach = 0;
+        for (int j = 2; j <= in.K; ++j) {
+            wmax = std::max(wmax, T + in.win_hi[j] - in.win_lo[j] + 1);
+            reach = std::max(reach, in.win_hi[j] - in.win_lo[j] + 1);
+        }
+        const int reach1 = in.win_hi[1] - in.win_lo[1] + 1;
+        const int w1 = T + reach1;
+        const size_t window = bsde::fused_window_lds(P, f32);
+        const size_t need = window + bsde::node_table_lds(in.K * in.pb.L, f32);
+        const size_t reduce_bytes = (size_t)(G - 1) * kBlock * P * 2 * sizeof(double);
+        const bool fits = reach <= bsde::kMaxReach2 && reach1 <= bsde::kMaxReach1 &&
+                          wmax + bsde::kHalo <= bsde::window_elems(P) &&
+                          w1 + 2 * bsde::kHalo <= bsde::window_elems(P) &&
+                          w1 + 2 * bsde::kHalo + 2 <= bsde::pcr_values(P) &&
+                          w1 + 2 * bsde::kHalo + 2 <= NT * bsde::pcr_slots(P, NT) &&
+                          in.pb.L <= 64 && reduce_bytes <= window && need <= max_lds;
+        if (!fits) return SweepConfig{PATH_FUSED, P, G, 0};
+        lds = std::max(lds, need);
     }
-    const int w1 = T + in.win_hi[1] - in.win_lo[1] + 1;
-    c.cap = bsde::window_slots(P);  // fixed per P: windows must fit, checked below
-    c.cap1 = bsde::pcr_values(P);
-    const size_t window_bytes = (size_t)c.cap * 2 * sizeof(double2) +
-                                (size_t)c.cap1 * 4 * sizeof(double);
-    c.lds = window_bytes + bsde::node_table_lds(in.K * in.pb.L);
-    const bool fits = w1 + 2 * bsde::kHalo + 2 <= c.cap1 && w1 + 2 * bsde::kHalo <= bsde::window_elems(P) &&
-                      wmax + bsde::kHalo <= bsde::window_elems(P) && in.pb.L <= 64;
-    c.blocks = (in.nx + T - 1) / T;
-    const size_t reduce_bytes = (size_t)(G - 1) * kBlock * P * 2 * sizeof(double);
-    if (!fits || w1 + 2 * bsde::kHalo + 2 > NT * bsde::pcr_slots(P, NT) || c.lds > max_lds ||
-        reduce_bytes > window_bytes || reach > bsde::kMaxReach2 ||
-        in.win_hi[1] - in.win_lo[1] + 1 > bsde::kMaxReach1)
-        c.lds = 0;
+    c.lds = lds;
     return c;
 }
 
-SweepConfig direct_config(const Instance &in, int P)
+SweepConfig direct_config(const std::vector<Instance> &all, const std::vector<int> &members,
+                          bool f32, int P)
 {
     SweepConfig c;
     c.path = PATH_DIRECT;
     c.P = P;
-    c.blocks = (in.nx + kBlock * P - 1) / (kBlock * P);
-    c.lds = bsde::node_table_lds(in.K * in.pb.L);
+    size_t lds = 0;
+    for (int b : members)
+        lds = std::max(lds, bsde::node_table_lds(all[b].K * all[b].pb.L, f32));
+    c.lds = lds;
     return c;
 }
 
-// Default choice: the fused kernel with one point per lane (most waves for
-// latency hiding at the grid sizes of interest), the widest tile otherwise
-// fitting; the direct kernel when no window fits in LDS.  BSDE_SWEEP =
-// "fused:P:G" or "direct:P" overrides.
-SweepConfig choose_config(const Instance &in, size_t max_lds, int num_cu)
+// Default shape: the fused kernel with one point per lane (most waves for
+// latency hiding), else the widest tile that fits; the direct kernel when no
+// window fits in LDS.  BSDE_SWEEP = "fused:P:G" or "direct:P" overrides;
+// bsde_autotune replaces the choice by the fastest measured shape.
+SweepConfig default_config(const std::vector<Instance> &all, const Group &g, size_t max_lds)
 {
     const char *env = std::getenv("BSDE_SWEEP");
     if (env) {
         int P = 0, G = 1;
         if (std::sscanf(env, "fused:%d:%d", &P, &G) >= 1 && bsde::fused_supported(P, G)) {
-            SweepConfig c = fused_config(in, P, G, max_lds);
+            SweepConfig c = fused_config(all, g.members, g.f32, P, G, max_lds);
             if (c.lds) return c;
         }
         if (std::sscanf(env, "direct:%d", &P) == 1 && bsde::direct_p_supported(P))
-            return direct_config(in, P);
+            return direct_config(all, g.members, g.f32, P);
     }
-    (void)num_cu;
     const int ps[3] = {1, 2, 4};
     for (int P : ps) {
-        SweepConfig c = fused_config(in, P, 1, max_lds);
+        SweepConfig c = fused_config(all, g.members, g.f32, P, 1, max_lds);
         if (c.lds) return c;
     }
-    return direct_config(in, 2);
+    return direct_config(all, g.members, g.f32, 2);
 }
 
-bsde::PcrCoef pcr_for(const bsde_plan_s &pl, const Instance &in)
-{
-    bsde::PcrCoef c = pl.pcr_base;
-    c.s6 = 6.0 / (in.dx * in.dx);
-    return c;
-}
+int sweep_tiles(const Instance &in, int P) { return (in.nx + kBlock * P - 1) / (kBlock * P); }
+int spline_tiles(const Instance &in) { return (in.nx + bsde::kSplineTile - 1) / bsde::kSplineTile; }
 
-bsde::SweepArgs sweep_args(const bsde_plan_s &pl, const Instance &in, char *ws, bool stats)
+// Bind a kernel shape to a group: tile numbering, descriptors, LDS limit.
+bsde_status apply_config(bsde_plan_s &pl, Group &g, const SweepConfig &c)
 {
-    bsde::SweepArgs a{};
-    a.ring = reinterpret_cast<Rec64 *>(ws + in.ring_off);
-    a.tab = in.dtab;
-    a.drv = in.drv;
-    a.pcr = pcr_for(pl, in);
-    a.nx = in.nx;
-    a.npad = in.npad;
-    a.pad_l = in.pad_l;
-    a.pad_r = in.pad_r;
-    a.K = in.K;
-    a.Ky = in.pb.k_y;
-    a.L = in.pb.L;
-    a.lds_cap = in.cfg.cap;
-    a.lds_cap1 = in.cfg.cap1;
-    a.dt = in.dt;
-    a.h0 = in.h0;
-    a.picard_max = in.pb.picard_max;
-    a.picard_tol = in.pb.picard_tol;
-    if (stats) {
-        unsigned long long *sum = reinterpret_cast<unsigned long long *>(ws + in.stat_off);
-        a.st_iter_sum = sum;
-        a.st_nonconv = sum + in.nwaves;
-        a.st_iter_max = reinterpret_cast<unsigned int *>(sum + 2 * in.nwaves);
+    if (c.path == PATH_FUSED && c.lds > 65536)
+        HIP_OK(bsde::set_fused_lds_limit(c.P, c.G, g.f32, g.driver, c.lds));
+    g.cfg = c;
+    g.tile_prefix.assign(g.members.size() + 1, 0);
+    g.spline_prefix.assign(g.members.size() + 1, 0);
+    std::vector<int> tmap, smap;
+    for (size_t k = 0; k < g.members.size(); ++k) {
+        const int b = g.members[k];
+        const Instance &in = pl.inst[b];
+        bsde::InstDesc &d = pl.desc[b];
+        d.tile_base = g.tile_prefix[k];
+        d.spline_base = g.spline_prefix[k];
+        d.spline_tiles = spline_tiles(in);
+        d.a.ntiles = sweep_tiles(in, c.P);
+        g.tile_prefix[k + 1] = g.tile_prefix[k] + d.a.ntiles;
+        g.spline_prefix[k + 1] = g.spline_prefix[k] + d.spline_tiles;
+        tmap.insert(tmap.end(), d.a.ntiles, b);
+        smap.insert(smap.end(), d.spline_tiles, b);
     }
-    return a;
+    HIP_OK(hipMemcpy(g.d_tile_inst, tmap.data(), tmap.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(g.d_spline_inst, smap.data(), smap.size() * sizeof(int),
+                     hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(pl.d_desc, pl.desc.data(), pl.desc.size() * sizeof(bsde::InstDesc),
+                     hipMemcpyHostToDevice));
+    pl.drop_graphs();
+    return BSDE_OK;
 }
 
 // Optional per-launch timing with hipEvent pairs (profiling entry point).
@@ -311,82 +352,134 @@ struct KernelTimer {
     }
 };
 
-// One time step n: layer n from layers n+1..n+K.
-bsde_status enqueue_step(const Instance &in, bsde::SweepArgs &a, int n, hipStream_t s,
-                         KernelTimer *tm)
+bsde::StepArgs step_args(const bsde_plan_s &pl, const Group &g, char *ws, int s, bool stats,
+                         bool spline_map)
 {
-    a.n = n;
-    const SweepConfig &c = in.cfg;
-    if (tm) HIP_OK(tm->mark(tm->sweep, s));
+    bsde::StepArgs a;
+    a.ws = ws;
+    a.desc = pl.d_desc;
+    a.tile_inst = spline_map ? g.d_spline_inst : g.d_tile_inst;
+    a.s = s;
+    a.stats = stats ? 1 : 0;
+    return a;
+}
+
+// Step s of a group: layer n0 - s of every active member.
+bsde_status enqueue_step(const bsde_plan_s &pl, const Group &g, char *ws, int s, bool stats,
+                         hipStream_t st, KernelTimer *tm)
+{
+    const int act = g.active(s, pl.inst);
+    if (act == 0) return BSDE_OK;
+    const SweepConfig &c = g.cfg;
+    const bsde::StepArgs a = step_args(pl, g, ws, s, stats, false);
+    const int blocks = g.tile_prefix[act];
+    if (tm) HIP_OK(tm->mark(tm->sweep, st));
     if (c.path == PATH_FUSED) {
-        HIP_OK(bsde::launch_sweep_fused(c.P, c.G, a, in.pb.driver, c.blocks, c.lds, s));
-        if (tm) HIP_OK(tm->mark(tm->sweep, s));
+        HIP_OK(bsde::launch_sweep_fused(c.P, c.G, g.f32, g.driver, a, blocks, c.lds, st));
+        if (tm) HIP_OK(tm->mark(tm->sweep, st));
     } else {
-        HIP_OK(bsde::launch_sweep_direct(c.P, a, in.pb.driver, c.blocks, s));
-        if (tm) HIP_OK(tm->mark(tm->sweep, s));
+        HIP_OK(bsde::launch_sweep_direct(c.P, g.f32, g.driver, a, blocks, c.lds, st));
+        if (tm) HIP_OK(tm->mark(tm->sweep, st));
         // natural spline of the new layer (the fused kernel does this in-kernel)
-        if (n > in.pb.n_stop) {
-            if (tm) HIP_OK(tm->mark(tm->spline, s));
-            Rec64 *slot = a.ring + (size_t)(n % (in.K + 1)) * in.npad;
-            HIP_OK(bsde::launch_spline(slot, in.nx, in.pad_l, in.pad_r, a.pcr, s));
-            if (tm) HIP_OK(tm->mark(tm->spline, s));
-        }
+        if (tm) HIP_OK(tm->mark(tm->spline, st));
+        HIP_OK(bsde::launch_spline(g.f32, step_args(pl, g, ws, s, false, true), 1,
+                                   g.spline_prefix[act], st));
+        if (tm) HIP_OK(tm->mark(tm->spline, st));
     }
     return BSDE_OK;
 }
 
-// One instance: initial layers (with their splines) -> backward loop -> output.
-bsde_status enqueue_instance(const bsde_plan_s &pl, const Instance &in, char *ws,
-                             const double *iy, const double *iz, double *y0, double *z0,
-                             hipStream_t s, bool stats, unsigned long long *nonfinite,
-                             KernelTimer *tm = nullptr)
+// Initial layers (scatter + splines) of every instance.
+bsde_status enqueue_init(const bsde_plan_s &pl, char *ws, const bsde_io *io, hipStream_t s)
 {
-    const int K = in.K, N = in.pb.n_t;
-    bsde::SweepArgs a = sweep_args(pl, in, ws, stats);
-    HIP_OK(bsde::launch_scatter(a.ring, in.npad, in.pad_l, in.nx, N, K, iy, iz, s));
-    for (int r = 0; r < K; ++r) {
-        const int n = N - K + 1 + r;
-        HIP_OK(bsde::launch_spline(a.ring + (size_t)(n % (K + 1)) * in.npad, in.nx, in.pad_l,
-                                   in.pad_r, a.pcr, s));
+    const int count = (int)pl.inst.size();
+    for (int b0 = 0; b0 < count; b0 += bsde::kChunk) {
+        bsde::ScatterChunk c{};
+        c.count = std::min(bsde::kChunk, count - b0);
+        int nxmax = 1;
+        for (int k = 0; k < c.count; ++k) {
+            c.inst[k] = b0 + k;
+            c.iy[k] = io[b0 + k].init_y;
+            c.iz[k] = io[b0 + k].init_z;
+            nxmax = std::max(nxmax, pl.inst[b0 + k].nx);
+        }
+        const int bx = std::min(1024, (nxmax + kBlock - 1) / kBlock);
+        HIP_OK(bsde::launch_scatter(c, ws, pl.d_desc, bx, s));
     }
-    for (int n = N - K; n >= in.pb.n_stop; --n) {
-        bsde_status rc = enqueue_step(in, a, n, s, tm);
-        if (rc != BSDE_OK) return rc;
+    for (const Group &g : pl.groups) {
+        int kmax = 0;
+        for (int b : g.members) kmax = std::max(kmax, pl.inst[b].K);
+        for (int r = 0; r < kmax; ++r)
+            HIP_OK(bsde::launch_spline(g.f32, step_args(pl, g, ws, r, false, true), 0,
+                                       g.spline_prefix.back(), s));
     }
-    const Rec64 *g = a.ring + (size_t)(in.pb.n_stop % (K + 1)) * in.npad + in.pad_l;
-    HIP_OK(bsde::launch_gather(g, in.nx, y0, z0, nonfinite, s));
     return BSDE_OK;
+}
+
+bsde_status enqueue_gather(const bsde_plan_s &pl, char *ws, const bsde_io *io,
+                           unsigned long long *nonfinite, hipStream_t s)
+{
+    const int count = (int)pl.inst.size();
+    for (int b0 = 0; b0 < count; b0 += bsde::kChunk) {
+        bsde::GatherChunk c{};
+        c.count = std::min(bsde::kChunk, count - b0);
+        int nxmax = 1;
+        for (int k = 0; k < c.count; ++k) {
+            c.inst[k] = b0 + k;
+            c.y0[k] = io[b0 + k].y0;
+            c.z0[k] = io[b0 + k].z0;
+            nxmax = std::max(nxmax, pl.inst[b0 + k].nx);
+        }
+        const int bx = std::min(1024, (nxmax + kBlock - 1) / kBlock);
+        HIP_OK(bsde::launch_gather(c, ws, pl.d_desc, bx, nonfinite, s));
+    }
+    return BSDE_OK;
+}
+
+// The whole solve: initial layers -> backward loop (all groups, step by
+// step) -> outputs.
+bsde_status enqueue_solve(const bsde_plan_s &pl, char *ws, const bsde_io *io, bool stats,
+                          unsigned long long *nonfinite, hipStream_t s, KernelTimer *tm = nullptr)
+{
+    bsde_status rc = enqueue_init(pl, ws, io, s);
+    if (rc != BSDE_OK) return rc;
+    int smax = 0;
+    for (const Group &g : pl.groups) smax = std::max(smax, g.max_steps);
+    for (int st = 0; st < smax; ++st)
+        for (const Group &g : pl.groups) {
+            rc = enqueue_step(pl, g, ws, st, stats, s, tm);
+            if (rc != BSDE_OK) return rc;
+        }
+    return enqueue_gather(pl, ws, io, nonfinite, s);
 }
 
 bsde_status finish_stats(bsde_plan_t plan, char *ws, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
                          bsde_stats *st)
 {
+    const int count = (int)plan->inst.size();
     unsigned long long *tot = reinterpret_cast<unsigned long long *>(ws + plan->totals_off);
-    unsigned long long agg[4] = {0, 0, 0, 0};
-    unsigned long long h[4];
-    long long point_steps = 0;
-    for (const Instance &in : plan->inst) {
-        unsigned long long *sum = reinterpret_cast<unsigned long long *>(ws + in.stat_off);
-        unsigned int *mx = reinterpret_cast<unsigned int *>(sum + 2 * in.nwaves);
-        HIP_OK(bsde::launch_reduce_stats(mx, sum, sum + in.nwaves, in.nwaves, tot, s));
-        HIP_OK(hipMemcpyAsync(h, tot, 3 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
-        HIP_OK(hipStreamSynchronize(s));
-        agg[0] = std::max(agg[0], h[0]);
-        agg[1] += h[1];
-        agg[2] += h[2];
-        point_steps += (long long)in.nx * (in.pb.n_t - in.K + 1 - in.pb.n_stop);
-    }
-    HIP_OK(hipMemcpyAsync(h, tot + 3, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    HIP_OK(bsde::launch_reduce_stats(ws, plan->d_desc, count, tot, s));
+    std::vector<unsigned long long> h(3 * (size_t)count + 1);
+    HIP_OK(hipMemcpyAsync(h.data(), tot, h.size() * sizeof(unsigned long long),
+                          hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
-    agg[3] = h[0];
+    unsigned long long mx = 0, sum = 0, nonc = 0;
+    long long point_steps = 0;
+    double R = 0.0;
+    for (int b = 0; b < count; ++b) {
+        const Instance &in = plan->inst[b];
+        mx = std::max(mx, h[3 * b]);
+        sum += h[3 * b + 1];
+        nonc += h[3 * b + 2];
+        point_steps += (long long)in.nx * in.steps;
+        R = std::max(R, in.R);
+    }
     float ms = 0.0f;
     HIP_OK(hipEventElapsedTime(&ms, e0, e1));
-    st->picard_iter_max = (int)agg[0];
-    st->picard_iter_mean = point_steps ? (double)agg[1] / (double)point_steps : 0.0;
-    st->picard_nonconverged = (long long)agg[2];
-    st->nonfinite = (long long)agg[3];
-    double R = 0.0;
-    for (const Instance &in : plan->inst) R = std::max(R, in.R);
+    st->picard_iter_max = (int)mx;
+    st->picard_iter_mean = point_steps ? (double)sum / (double)point_steps : 0.0;
+    st->picard_nonconverged = (long long)nonc;
+    st->nonfinite = (long long)h[3 * (size_t)count];
     st->stability_ratio = R;
     st->elapsed_ms = ms;
     if (st->nonfinite) return BSDE_ENONFINITE;
@@ -404,9 +497,9 @@ bool same_io(const std::vector<bsde_io> &a, const bsde_io *b, int count)
     return true;
 }
 
-// The whole backward loop of every instance, replayed as one hipGraph launch:
-// one capture per (workspace, buffers, statistics flag), kept in a small
-// least-recently-used cache.  The graph holds kernel nodes only.
+// The whole solve, replayed as one hipGraph launch: one capture per
+// (workspace, buffers, statistics flag), kept in a small least-recently-used
+// cache.  The graph holds kernel nodes only.
 bsde_status launch_graph(bsde_plan_t plan, char *w, const bsde_io *io, int count, bool stats,
                          unsigned long long *nonfinite, hipStream_t s)
 {
@@ -419,10 +512,7 @@ bsde_status launch_graph(bsde_plan_t plan, char *w, const bsde_io *io, int count
             HIP_OK(hipStreamCreateWithFlags(&plan->capture_stream, hipStreamNonBlocking));
         hipStream_t cs = plan->capture_stream;
         HIP_OK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-        bsde_status rc = BSDE_OK;
-        for (int b = 0; b < count && rc == BSDE_OK; ++b)
-            rc = enqueue_instance(*plan, plan->inst[b], w, io[b].init_y, io[b].init_z, io[b].y0,
-                                  io[b].z0, cs, stats, nonfinite);
+        const bsde_status rc = enqueue_solve(*plan, w, io, stats, nonfinite, cs);
         hipGraph_t graph = nullptr;
         const hipError_t ec = hipStreamEndCapture(cs, &graph);
         if (rc != BSDE_OK || ec != hipSuccess) {
@@ -454,13 +544,19 @@ bsde_status launch_graph(bsde_plan_t plan, char *w, const bsde_io *io, int count
     return BSDE_OK;
 }
 
+bool valid_io(bsde_plan_t plan, void *ws, const bsde_io *io, int count)
+{
+    if (!plan || !ws || !io) return false;
+    if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return false;
+    for (int b = 0; b < count; ++b)
+        if (!io[b].init_y || !io[b].init_z || !io[b].y0 || !io[b].z0) return false;
+    return true;
+}
+
 bsde_status solve_impl(bsde_plan_t plan, void *ws, const bsde_io *io, int count, void *stream,
                        bsde_stats *st)
 {
-    if (!plan || !ws || !io) return BSDE_EINVAL;
-    if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return BSDE_EINVAL;
-    for (int b = 0; b < count; ++b)
-        if (!io[b].init_y || !io[b].init_z || !io[b].y0 || !io[b].z0) return BSDE_EINVAL;
+    if (!valid_io(plan, ws, io, count)) return BSDE_EINVAL;
     hipStream_t s = static_cast<hipStream_t>(stream);
     char *w = static_cast<char *>(ws);
     const bool stats = st != nullptr;
@@ -471,26 +567,17 @@ bsde_status solve_impl(bsde_plan_t plan, void *ws, const bsde_io *io, int count,
         HIP_OK(hipEventCreate(&e1));
         HIP_OK(hipEventRecord(e0, s));
         // per-wave counters and the totals start at zero
-        const size_t first = plan->inst[0].stat_off;
-        const size_t n64 = (plan->totals_off - first) / 8 + 4;
-        HIP_OK(bsde::launch_clear(reinterpret_cast<unsigned long long *>(w + first), n64, s));
-        nonfinite = reinterpret_cast<unsigned long long *>(w + plan->totals_off) + 3;
+        HIP_OK(bsde::launch_clear(reinterpret_cast<unsigned long long *>(w + plan->stats_off),
+                                  plan->stats_bytes / 8, s));
+        nonfinite = reinterpret_cast<unsigned long long *>(w + plan->totals_off) + 3 * count;
     }
-    if (plan->use_graphs) {
-        bsde_status rc = launch_graph(plan, w, io, count, stats, nonfinite, s);
-        if (rc != BSDE_OK) return rc;
-    } else {
-        for (int b = 0; b < count; ++b) {
-            const Instance &in = plan->inst[b];
-            bsde_status rc = enqueue_instance(*plan, in, w, io[b].init_y, io[b].init_z, io[b].y0,
-                                              io[b].z0, s, stats, nonfinite);
-            if (rc != BSDE_OK) return rc;
-        }
-    }
+    bsde_status rc = plan->use_graphs ? launch_graph(plan, w, io, count, stats, nonfinite, s)
+                                      : enqueue_solve(*plan, w, io, stats, nonfinite, s);
+    if (rc != BSDE_OK) return rc;
     if (!stats) return BSDE_OK;
     HIP_OK(hipEventRecord(e1, s));
     HIP_OK(hipEventSynchronize(e1));
-    bsde_status rc = finish_stats(plan, w, s, e0, e1, st);
+    rc = finish_stats(plan, w, s, e0, e1, st);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return rc;
@@ -535,7 +622,6 @@ bsde_status bsde_plan(const bsde_problem *pb, int batch, bsde_plan_t *out)
     for (int b = 0; b < batch; ++b) {
         if (!valid_problem(pb[b])) return BSDE_EINVAL;
         if (pb[b].d != 1) return BSDE_EUNSUPPORTED;
-        if (pb[b].prec != BSDE_FP64) return BSDE_EUNSUPPORTED;
     }
     bsde_plan_s *pl = new (std::nothrow) bsde_plan_s;
     if (!pl) return BSDE_ENOMEM;
@@ -563,11 +649,9 @@ bsde_status bsde_plan(const bsde_problem *pb, int batch, bsde_plan_t *out)
         delete pl;
         return BSDE_EDEVICE;
     }
-    int lds_limit = 65536, num_cu = 256;
+    int lds_limit = 65536;
     if (hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock,
-                              pl->device) != hipSuccess ||
-        hipDeviceGetAttribute(&num_cu, hipDeviceAttributeMultiprocessorCount, pl->device) !=
-            hipSuccess) {
+                              pl->device) != hipSuccess) {
         delete pl;
         return BSDE_EDEVICE;
     }
@@ -576,13 +660,41 @@ bsde_status bsde_plan(const bsde_problem *pb, int batch, bsde_plan_t *out)
         const char *g = std::getenv("BSDE_GRAPH");
         pl->use_graphs = !(g && g[0] == '0');
     }
-    for (Instance &in : pl->inst) {
-        in.cfg = choose_config(in, pl->max_lds, num_cu);
-        if (in.cfg.path == PATH_FUSED && in.cfg.lds > 65536 &&
-            bsde::set_fused_lds_limit(in.cfg.P, in.cfg.G, in.pb.driver, in.cfg.lds) != hipSuccess)
-            in.cfg = direct_config(in, 2);
+    // groups: same precision, driver and default kernel shape (an instance
+    // whose windows do not fit a shape does not force it on the others);
+    // members by number of steps, most first
+    std::vector<SweepConfig> own(batch);
+    for (int b = 0; b < batch; ++b) {
+        Instance &in = pl->inst[b];
+        Group one;
+        one.f32 = in.f32;
+        one.members = {b};
+        own[b] = default_config(pl->inst, one, pl->max_lds);
+        int gi = -1;
+        for (size_t k = 0; k < pl->groups.size(); ++k) {
+            const Group &g = pl->groups[k];
+            const SweepConfig &c = own[g.members[0]];
+            if (g.f32 == in.f32 && g.driver == in.pb.driver && c.path == own[b].path &&
+                c.P == own[b].P && c.G == own[b].G)
+                gi = (int)k;
+        }
+        if (gi < 0) {
+            pl->groups.emplace_back();
+            pl->groups.back().f32 = in.f32;
+            pl->groups.back().driver = in.pb.driver;
+            gi = (int)pl->groups.size() - 1;
+        }
+        in.group = gi;
+        pl->groups[gi].members.push_back(b);
     }
-    // device tables
+    for (Group &g : pl->groups) {
+        std::stable_sort(g.members.begin(), g.members.end(), [&](int x, int y) {
+            return pl->inst[x].steps > pl->inst[y].steps;
+        });
+        g.max_steps = pl->inst[g.members[0]].steps;
+    }
+    // device tables: per instance node records (both forms), offsets, y
+    // weights, windows; the descriptors; per group the tile maps
     size_t tbytes = 0;
     std::vector<size_t> toff(batch);
     for (int b = 0; b < batch; ++b) {
@@ -590,18 +702,31 @@ bsde_status bsde_plan(const bsde_problem *pb, int batch, bsde_plan_t *out)
         toff[b] = tbytes;
         const size_t kl = (size_t)in.K * in.pb.L;
         tbytes += align_up(kl * sizeof(int), 256) + align_up(kl * sizeof(bsde::NodeRec), 256) +
-                  align_up(kl * sizeof(double), 256) + 2 * align_up((in.K + 1) * sizeof(int), 256);
+                  align_up(kl * sizeof(bsde::NodeRec32), 256) + align_up(kl * sizeof(double), 256) +
+                  2 * align_up((in.K + 1) * sizeof(int), 256);
+    }
+    const size_t desc_off = tbytes;
+    tbytes += align_up((size_t)batch * sizeof(bsde::InstDesc), 256);
+    std::vector<size_t> map_off(pl->groups.size());
+    for (size_t k = 0; k < pl->groups.size(); ++k) {
+        size_t tiles = 0, stiles = 0;
+        for (int b : pl->groups[k].members) {
+            tiles += sweep_tiles(pl->inst[b], 1);
+            stiles += spline_tiles(pl->inst[b]);
+        }
+        map_off[k] = tbytes;
+        tbytes += align_up(tiles * sizeof(int), 256) + align_up(stiles * sizeof(int), 256);
     }
     if (hipMalloc(&pl->d_tables, std::max<size_t>(tbytes, 256)) != hipSuccess) {
         delete pl;
         return BSDE_ENOMEM;
     }
+    char *dev = static_cast<char *>(pl->d_tables);
     std::vector<char> host(tbytes);
     for (int b = 0; b < batch; ++b) {
         Instance &in = pl->inst[b];
         const size_t kl = (size_t)in.K * in.pb.L;
         size_t o = toff[b];
-        char *dev = static_cast<char *>(pl->d_tables);
         auto put = [&](const void *src, size_t bytes) {
             std::memcpy(host.data() + o, src, bytes);
             void *d = dev + o;
@@ -609,37 +734,94 @@ bsde_status bsde_plan(const bsde_problem *pb, int batch, bsde_plan_t *out)
             return d;
         };
         std::vector<bsde::NodeRec> recs(kl);
+        std::vector<bsde::NodeRec32> recs32(kl);
         std::vector<double> cyk(kl, 0.0);
         for (size_t k = 0; k < kl; ++k) {
             const int l = (int)(k % in.pb.L), j = (int)(k / in.pb.L) + 1;
             recs[k] = bsde::NodeRec{in.B[k], in.C[k], in.D[k], in.cfy[k], in.cfz[k], in.cz[k]};
+            recs32[k] = bsde::NodeRec32{(float)in.B[k],   (float)in.C[k],   (float)in.D[k],
+                                        (float)in.cfy[k], (float)in.cfz[k], (float)in.cz[k],
+                                        in.cz[k]};
             if (j == in.pb.k_y) cyk[k] = in.cy[l];
         }
         in.dtab.rec = static_cast<const bsde::NodeRec *>(put(recs.data(), kl * sizeof(bsde::NodeRec)));
+        in.dtab.rec32 =
+            static_cast<const bsde::NodeRec32 *>(put(recs32.data(), kl * sizeof(bsde::NodeRec32)));
         in.dtab.m = static_cast<const int *>(put(in.m.data(), kl * sizeof(int)));
         in.dtab.cy = static_cast<const double *>(put(cyk.data(), kl * sizeof(double)));
         in.dtab.win_lo = static_cast<const int *>(put(in.win_lo.data(), (in.K + 1) * sizeof(int)));
         in.dtab.win_hi = static_cast<const int *>(put(in.win_hi.data(), (in.K + 1) * sizeof(int)));
     }
-    if (hipMemcpy(pl->d_tables, host.data(), tbytes, hipMemcpyHostToDevice) != hipSuccess) {
-        (void)hipFree(pl->d_tables);
-        delete pl;
+    if (hipMemcpy(pl->d_tables, host.data(), desc_off, hipMemcpyHostToDevice) != hipSuccess) {
+        bsde_plan_destroy(pl);
         return BSDE_EDEVICE;
     }
-    // workspace: rings back to back, then per-wave stats, then totals
+    pl->d_desc = reinterpret_cast<bsde::InstDesc *>(dev + desc_off);
+    for (size_t k = 0; k < pl->groups.size(); ++k) {
+        Group &g = pl->groups[k];
+        size_t tiles = 0;
+        for (int b : g.members) tiles += sweep_tiles(pl->inst[b], 1);
+        g.d_tile_inst = reinterpret_cast<int *>(dev + map_off[k]);
+        g.d_spline_inst = reinterpret_cast<int *>(dev + map_off[k] + align_up(tiles * sizeof(int), 256));
+    }
+    // workspace: rings, then the final layers, then the statistics (per-wave
+    // slots of every instance, then the totals)
     size_t off = 0;
     for (Instance &in : pl->inst) {
         in.ring_off = off;
-        off += align_up((size_t)(in.K + 1) * in.npad * sizeof(Rec64), 256);
+        off += align_up((size_t)(in.K + 1) * in.npad * (in.f32 ? sizeof(Rec32) : sizeof(Rec64)), 256);
     }
+    for (Instance &in : pl->inst) {
+        in.fin_off = off;
+        off += align_up((size_t)2 * in.nx * sizeof(double), 256);
+    }
+    pl->stats_off = off;
     for (Instance &in : pl->inst) {
         in.stat_off = off;
         off += align_up((size_t)in.nwaves * (2 * sizeof(unsigned long long) + sizeof(unsigned int)),
                         256);
     }
     pl->totals_off = off;
-    off += 256;
+    off += align_up((3 * (size_t)batch + 1) * sizeof(unsigned long long), 256);
+    pl->stats_bytes = off - pl->stats_off;
     pl->ws_bytes = off;
+    // descriptors
+    pl->desc.resize(batch);
+    for (int b = 0; b < batch; ++b) {
+        const Instance &in = pl->inst[b];
+        bsde::InstDesc &d = pl->desc[b];
+        std::memset(&d, 0, sizeof(d));
+        bsde::SweepArgs &a = d.a;
+        a.n_stop = in.pb.n_stop;
+        a.tab = in.dtab;
+        a.drv = in.drv;
+        a.pcr = pl->pcr_base;
+        a.pcr.s6 = 6.0 / (in.dx * in.dx);
+        a.nx = in.nx;
+        a.npad = in.npad;
+        a.pad_l = in.pad_l;
+        a.pad_r = in.pad_r;
+        a.K = in.K;
+        a.Ky = in.pb.k_y;
+        a.L = in.pb.L;
+        a.dt = in.dt;
+        a.h0 = in.h0;
+        a.picard_max = in.pb.picard_max;
+        a.picard_tol = in.pb.picard_tol;
+        d.ring_off = in.ring_off;
+        d.fin_off = in.fin_off;
+        d.stat_off = in.stat_off;
+        d.nwaves = in.nwaves;
+        d.n0 = in.pb.n_t - in.K;
+        d.f32 = in.f32 ? 1 : 0;
+    }
+    for (Group &g : pl->groups) {
+        bsde_status rc = apply_config(*pl, g, default_config(pl->inst, g, pl->max_lds));
+        if (rc != BSDE_OK) {
+            bsde_plan_destroy(pl);
+            return rc;
+        }
+    }
     *out = pl;
     return BSDE_OK;
 }
@@ -647,7 +829,7 @@ bsde_status bsde_plan(const bsde_problem *pb, int batch, bsde_plan_t *out)
 void bsde_plan_destroy(bsde_plan_t plan)
 {
     if (!plan) return;
-    for (GraphEntry &g : plan->graphs) (void)hipGraphExecDestroy(g.exec);
+    plan->drop_graphs();
     if (plan->capture_stream) (void)hipStreamDestroy(plan->capture_stream);
     if (plan->d_tables) (void)hipFree(plan->d_tables);
     delete plan;
@@ -659,6 +841,7 @@ bsde_status bsde_solve(bsde_plan_t plan, void *ws, const double *init_y, const d
                        double *y0, double *z0, void *stream, bsde_stats *st)
 {
     if (!plan) return BSDE_EINVAL;
+    if (plan->inst.size() != 1) return BSDE_EINVAL;
     bsde_io io{init_y, init_z, y0, z0};
     return solve_impl(plan, ws, &io, 1, stream, st);
 }
@@ -670,17 +853,15 @@ bsde_status bsde_solve_batched(bsde_plan_t plan, void *ws, const bsde_io *io, vo
     return solve_impl(plan, ws, io, (int)plan->inst.size(), stream, st);
 }
 
-bsde_status bsde_profile_kernels(bsde_plan_t plan, void *ws, const double *init_y,
-                                 const double *init_z, double *y0, double *z0, void *stream,
+bsde_status bsde_profile_kernels(bsde_plan_t plan, void *ws, const bsde_io *io, void *stream,
                                  bsde_kernel_times *kt)
 {
-    if (!plan || !ws || !init_y || !init_z || !y0 || !z0 || !kt) return BSDE_EINVAL;
-    if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return BSDE_EINVAL;
+    const int count = plan ? (int)plan->inst.size() : 0;
+    if (!kt || !valid_io(plan, ws, io, count)) return BSDE_EINVAL;
     hipStream_t s = static_cast<hipStream_t>(stream);
     char *w = static_cast<char *>(ws);
     KernelTimer tm;
-    bsde_status rc =
-        enqueue_instance(*plan, plan->inst[0], w, init_y, init_z, y0, z0, s, false, nullptr, &tm);
+    bsde_status rc = enqueue_solve(*plan, w, io, false, nullptr, s, &tm);
     if (rc != BSDE_OK) return rc;
     HIP_OK(hipStreamSynchronize(s));
     double sw = 0.0, sp = 0.0;
@@ -698,13 +879,79 @@ bsde_status bsde_profile_kernels(bsde_plan_t plan, void *ws, const double *init_
     kt->sweep_launches = (int)(tm.sweep.size() / 2);
     kt->spline_ms = sp;
     kt->spline_launches = (int)(tm.spline.size() / 2);
-    const SweepConfig &c = plan->inst[0].cfg;
-    kt->path = c.path;
-    kt->points_per_lane = c.P;
-    kt->node_groups = c.G;
-    kt->blocks = c.blocks;
-    kt->lds_bytes = (long long)c.lds;
+    const Group &g = plan->groups[0];
+    kt->path = g.cfg.path;
+    kt->points_per_lane = g.cfg.P;
+    kt->node_groups = g.cfg.G;
+    kt->blocks = g.tile_prefix.back();
+    kt->lds_bytes = (long long)g.cfg.lds;
     return BSDE_OK;
+}
+
+bsde_status bsde_autotune(bsde_plan_t plan, void *ws, const bsde_io *io, void *stream, int reps,
+                          bsde_tune_report *rep)
+{
+    const int count = plan ? (int)plan->inst.size() : 0;
+    if (!valid_io(plan, ws, io, count) || reps < 1) return BSDE_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char *w = static_cast<char *>(ws);
+    std::lock_guard<std::mutex> lock(plan->mu);
+    bsde_status rc = enqueue_init(*plan, w, io, s);
+    if (rc != BSDE_OK) return rc;
+    // the descriptors are rewritten (synchronously) for every candidate shape:
+    // no kernel of the stream may still read them
+    HIP_OK(hipStreamSynchronize(s));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_OK(hipEventCreate(&e0));
+    HIP_OK(hipEventCreate(&e1));
+    int tried = 0;
+    for (Group &g : plan->groups) {
+        std::vector<SweepConfig> cand;
+        const int ps[3] = {1, 2, 4};
+        for (int P : ps)
+            for (int G = 1; G <= 2; ++G) {
+                SweepConfig c = fused_config(plan->inst, g.members, g.f32, P, G, plan->max_lds);
+                if (c.lds) cand.push_back(c);
+            }
+        if (cand.empty()) cand.push_back(direct_config(plan->inst, g.members, g.f32, 2));
+        float best = 0.0f;
+        SweepConfig best_c = g.cfg;
+        for (const SweepConfig &c : cand) {
+            rc = apply_config(*plan, g, c);
+            if (rc != BSDE_OK) break;
+            // step 0 recomputes the same layer from the initial layers on
+            // every repetition: the timed launches are idempotent
+            rc = enqueue_step(*plan, g, w, 0, false, s, nullptr);  // warm-up
+            if (rc != BSDE_OK) break;
+            if (hipEventRecord(e0, s) != hipSuccess) { rc = BSDE_EDEVICE; break; }
+            for (int r = 0; r < reps && rc == BSDE_OK; ++r)
+                rc = enqueue_step(*plan, g, w, 0, false, s, nullptr);
+            if (rc != BSDE_OK) break;
+            float ms = 0.0f;
+            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                rc = BSDE_EDEVICE;
+                break;
+            }
+            ++tried;
+            if (best == 0.0f || ms < best) {
+                best = ms;
+                best_c = c;
+            }
+        }
+        if (rc == BSDE_OK) rc = apply_config(*plan, g, best_c);
+        if (rc != BSDE_OK) break;
+        if (rep && &g == &plan->groups[0]) {
+            rep->path = best_c.path;
+            rep->points_per_lane = best_c.P;
+            rep->node_groups = best_c.G;
+            rep->best_ms_per_step = best / reps;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rep) rep->candidates = tried;
+    return rc;
 }
 
 }  // extern "C"

@@ -15,6 +15,12 @@ struct alignas(16) Rec64 {
     double y, My, z, Mz;
 };
 
+// The same record in single precision (the FP32 form's ring): 16 bytes, one
+// aligned vector load.
+struct alignas(16) Rec32 {
+    float y, My, z, Mz;
+};
+
 constexpr int kBlock = 256;        // threads per block of every kernel
 constexpr int kPcrRounds = 5;      // PCR strides 1, 2, 4, 8, 16
 constexpr int kHalo = 32;          // > 1 + 2 + 4 + 8 + 16: reach of the truncated PCR
@@ -33,10 +39,21 @@ struct alignas(16) NodeRec {
     double cz;     // weight of z-hat in z^n
 };
 
+// The FP32 form's node coefficients: interpolation weights and the weights
+// of the small terms in single precision, the weight of the z record value
+// (which carries the magnitude of z^n) in double precision.  32 bytes.
+struct alignas(16) NodeRec32 {
+    float B, C, D;
+    float cfy, cfz;
+    float czf;  // cz in single precision (weight of the interpolation correction)
+    double cz;
+};
+
 // Node table of one instance (device memory).  K*L entries, row j-1 holds the
 // L nodes of layer n+j.
 struct NodeTable {
     const NodeRec *rec;
+    const NodeRec32 *rec32;  // the same coefficients for the FP32 form
     const int *m;       // integer cell offset of the node from x_i
     const double *cy;   // weight of y-hat in the y constant (non-zero only for j = K_y)
     const int *win_lo;  // [K+1]: lowest node offset of layer j (j = 1 also <= 0)
@@ -47,7 +64,6 @@ constexpr int kMaxNodes = 6 * 64;      // K * L at most
 constexpr int kMaxReach1 = 160;        // widest node reach of layer n+1 in the fused kernel
 constexpr int kMaxReach2 = 320;        // widest node reach of layers n+2.. in the fused kernel
 static_assert(kMaxReach2 >= kMaxReach1 + kHalo, "layer n+1 window must fit the window arrays");
-constexpr size_t kNodeLdsBytes = sizeof(NodeRec) + sizeof(int) + sizeof(double);
 
 // PCR slots per thread of a fused block of NT threads and P points per lane
 // (the newest layer's window, its halo and the two extra staged values).
@@ -93,14 +109,17 @@ struct PcrCoef {
 };
 
 struct SweepArgs {
-    Rec64 *ring;
+    Rec64 *ring;      // FP64 form
+    Rec32 *ring32;    // FP32 form
+    double *fin_y, *fin_z;  // layer n_stop in double precision (written when n == n_stop)
+    int n_stop;
     NodeTable tab;
     DriverParams drv;
     PcrCoef pcr;
     int n;            // time index of the layer being computed
     int nx, npad, pad_l, pad_r;
     int K, Ky, L;
-    int lds_cap, lds_cap1;  // records of the window arrays / of the PCR arrays
+    int ntiles;       // tiles of the sweep kernel over the grid
     double dt;
     double h0;        // K_y dt gamma_{K_y,0}: weight of the implicit f(t_n, y^n, z^n)
     int picard_max;
@@ -110,48 +129,71 @@ struct SweepArgs {
     unsigned long long *st_nonconv;   // per-wave count of unconverged point-steps
 };
 
+// One instance of a (batched) solve as the kernels see it: its SweepArgs
+// with the workspace parts given as byte offsets, bound to the workspace
+// address at launch.  The kernels of one launch serve a group of instances
+// (same precision, driver and tile shape); the grid's tiles are numbered
+// instance after instance.
+struct InstDesc {
+    SweepArgs a;          // ring, ring32, fin_*, st_* unset; n unset
+    size_t ring_off;      // ring of K+1 slots
+    size_t fin_off;       // layer n_stop: n_x doubles of y, then of z
+    size_t stat_off;      // per-wave statistics: sum (u64), unconverged (u64), max (u32)
+    int nwaves;           // per-wave statistics slots
+    int n0;               // first layer computed (N - K); step s computes n0 - s
+    int f32;              // FP32 form
+    int tile_base;        // first tile of the instance in its group's sweep grid
+    int spline_base;      // first tile of the instance in its group's spline grid
+    int spline_tiles;     // tiles of the standalone spline kernel
+};
+
+struct StepArgs {
+    char *ws;
+    const InstDesc *desc;
+    const int *tile_inst;  // grid tile -> descriptor index
+    int s;                 // step: each instance computes layer n0 - s
+    int stats;             // bind the statistics slots
+};
+
 // ---------------------------------------------------------------------------
 // Drivers f(t, y, z) (problem statement eq (2); Examples 1-3 of Section 5)
 // ---------------------------------------------------------------------------
-template <int DRV>
+template <int DRV, typename T = double>
 struct Driver;
 
-template <>
-struct Driver<BSDE_DRIVER_LINEAR> {  // p0 y + p1 z + p3
-    double a, b, c;
+template <typename T>
+struct Driver<BSDE_DRIVER_LINEAR, T> {  // p0 y + p1 z + p3
+    T a, b, c;
     __device__ Driver(const DriverParams &p, double) : a(p.p0), b(p.p1), c(p.p3) {}
-    __device__ double operator()(double y, double z) const { return fma(a, y, fma(b, z, c)); }
+    __device__ T operator()(T y, T z) const { return fma(a, y, fma(b, z, c)); }
 };
 
-template <>
-struct Driver<BSDE_DRIVER_BIDASK> {  // -r y - theta z + s (R - r) min(y - z/sigma, 0)
-    double mr, mth, c, inv_sg;
+template <typename T>
+struct Driver<BSDE_DRIVER_BIDASK, T> {  // -r y - theta z + s (R - r) min(y - z/sigma, 0)
+    T mr, mth, c, inv_sg;
     __device__ Driver(const DriverParams &p, double)
         : mr(-p.p0), mth(-p.p2), c(p.p4 * (p.p1 - p.p0)), inv_sg(1.0 / p.p3) {}
-    __device__ double operator()(double y, double z) const
+    __device__ T operator()(T y, T z) const
     {
-        const double m = fmin(fma(-z, inv_sg, y), 0.0);
+        const T m = fmin(fma(-z, inv_sg, y), T(0));
         return fma(mr, y, fma(mth, z, c * m));
     }
 };
 
-template <>
-struct Driver<BSDE_DRIVER_CUBIC> {  // Example 1: -y^3 + 5/2 y^2 - 3/2 y
+template <typename T>
+struct Driver<BSDE_DRIVER_CUBIC, T> {  // Example 1: -y^3 + 5/2 y^2 - 3/2 y
     __device__ Driver(const DriverParams &, double) {}
-    __device__ double operator()(double y, double) const
-    {
-        return y * fma(y, 2.5 - y, -1.5);
-    }
+    __device__ T operator()(T y, T) const { return y * fma(y, T(2.5) - y, T(-1.5)); }
 };
 
-template <>
-struct Driver<BSDE_DRIVER_EXP> {  // Example 2: (e^{t^2} - 4ty - 3e^{t^2 - y e^{-t^2}} + z^2 e^{-t^2})/2
-    double t, t2, et, emt;
+template <typename T>
+struct Driver<BSDE_DRIVER_EXP, T> {  // Example 2: (e^{t^2} - 4ty - 3e^{t^2 - y e^{-t^2}} + z^2 e^{-t^2})/2
+    T t, t2, et, emt;
     __device__ Driver(const DriverParams &, double tt)
         : t(tt), t2(tt * tt), et(exp(tt * tt)), emt(exp(-tt * tt)) {}
-    __device__ double operator()(double y, double z) const
+    __device__ T operator()(T y, T z) const
     {
-        return 0.5 * (et - 4.0 * t * y - 3.0 * exp(t2 - y * emt) + z * z * emt);
+        return T(0.5) * (et - T(4) * t * y - T(3) * exp(t2 - y * emt) + z * z * emt);
     }
 };
 
@@ -179,6 +221,27 @@ __device__ inline int xcd_tile(int b, int nb)
     return x * per + min(x, rem) + r;
 }
 
+__device__ inline SweepArgs bind_instance(const InstDesc &d, char *ws, int s, bool stats)
+{
+    SweepArgs a = d.a;
+    a.n = d.n0 - s;
+    a.ring = reinterpret_cast<Rec64 *>(ws + d.ring_off);
+    a.ring32 = reinterpret_cast<Rec32 *>(ws + d.ring_off);
+    a.fin_y = reinterpret_cast<double *>(ws + d.fin_off);
+    a.fin_z = a.fin_y + a.nx;
+    if (stats) {
+        unsigned long long *sum = reinterpret_cast<unsigned long long *>(ws + d.stat_off);
+        a.st_iter_sum = sum;
+        a.st_nonconv = sum + d.nwaves;
+        a.st_iter_max = reinterpret_cast<unsigned int *>(sum + 2 * d.nwaves);
+    } else {
+        a.st_iter_sum = nullptr;
+        a.st_nonconv = nullptr;
+        a.st_iter_max = nullptr;
+    }
+    return a;
+}
+
 // ---------------------------------------------------------------------------
 // Natural cubic spline of a layer on a window, second-derivative form:
 //   M_0 = M_{N-1} = 0,  M_{i-1} + 4 M_i + M_{i+1} = r_i = 6/dx^2 (y_{i+1} - 2 y_i + y_{i-1}).
@@ -190,7 +253,8 @@ __device__ inline int xcd_tile(int b, int nb)
 
 // r~_k / (6/dx^2) for any integer k, from the layer in HBM (used where the
 // window does not hold the neighbours or k is outside [1, N-2]).
-__device__ inline double rtilde_global(const Rec64 *__restrict__ g, int nx, int k, bool zf)
+template <typename Rec>
+__device__ inline double rtilde_global(const Rec *__restrict__ g, int nx, int k, bool zf)
 {
     const int per = 2 * (nx - 1);
     int kk = k % per;
@@ -207,25 +271,76 @@ __device__ inline double rtilde_global(const Rec64 *__restrict__ g, int nx, int 
     return sign * ((vp - v0) - (v0 - vm));
 }
 
+// Window of one layer in LDS.  Element e (slot WinLayout<P>::slot(e)) holds
+// the record of grid point lo - kHalo + e.
+//   FP64 form: (y, M_y) in wy[slot], (z, M_z) in wy[slot + window_slots(P)].
+//   FP32 form: (y, M_y, z, M_z) in w[slot].
+template <int P>
+struct WinStore64 {
+    double2 *wy;
+    static constexpr int kZ = window_slots(P);
+    __device__ void put(int sl, const Rec64 &r) const
+    {
+        wy[sl] = make_double2(r.y, r.My);
+        wy[sl + kZ] = make_double2(r.z, r.Mz);
+    }
+    __device__ void val(int sl, double y, double z) const
+    {
+        wy[sl].x = y;
+        wy[sl + kZ].x = z;
+    }
+    __device__ void der(int sl, double my, double mz) const
+    {
+        wy[sl].y = my;
+        wy[sl + kZ].y = mz;
+    }
+    __device__ void write_der(int sl, Rec64 &g) const
+    {
+        g.My = wy[sl].y;
+        g.Mz = wy[sl + kZ].y;
+    }
+};
+
+template <int P>
+struct WinStore32 {
+    float4 *w;
+    __device__ void put(int sl, const Rec32 &r) const { w[sl] = make_float4(r.y, r.My, r.z, r.Mz); }
+    __device__ void val(int sl, double y, double z) const
+    {
+        w[sl].x = (float)y;
+        w[sl].z = (float)z;
+    }
+    __device__ void der(int sl, double my, double mz) const
+    {
+        w[sl].y = (float)my;
+        w[sl].w = (float)mz;
+    }
+    __device__ void write_der(int sl, Rec32 &g) const
+    {
+        g.My = w[sl].y;
+        g.Mz = w[sl].w;
+    }
+};
+
 // Natural spline of layer g on the window of records [lo, lo + W).
 // y and z over [lo - kHalo - 1, lo + W + kHalo] are staged (outside [0, N)
 // the boundary value, i.e. the ghost record), the right-hand sides r~ of the
 // records [lo - kHalo, lo + W + kHalo) follow from them in LDS (from HBM only
 // at the true domain boundaries, where the reflection applies), and five
-// ping-pong PCR rounds leave M.  Results: window element e = k - lo + kHalo
-// holds (y, M_y) in wy[slot(e)] and (z, M_z) in wz[slot(e)] for the records
-// [lo, lo + W) (M = 0 outside (0, N-1)).  R holds 4 arrays of cap1 >= W +
+// ping-pong PCR rounds leave M, all in double precision.  Results: window
+// element e = k - lo + kHalo holds y, z and M_y, M_z (M = 0 outside
+// (0, N-1)) of the records [lo, lo + W).  R holds 4 arrays of cap1 >= W +
 // 2 kHalo + 2 doubles.  Called by all NT threads; ends synchronised.
 // y and z of the staged range of spline_window, loaded into registers ahead
 // of use (U slots per thread; element e = tid + u NT).
-template <int U>
+template <int U, typename V>
 struct SplineRaw {
-    double y[U], z[U];
+    V y[U], z[U];
 };
 
-template <int NT, int U>
-__device__ inline void spline_load(const Rec64 *__restrict__ g, int nx, int lo, int W,
-                                   SplineRaw<U> &raw)
+template <int NT, int U, typename Rec, typename V>
+__device__ inline void spline_load(const Rec *__restrict__ g, int nx, int lo, int W,
+                                   SplineRaw<U, V> &raw)
 {
     const int WS = W + 2 * kHalo + 2;
 #pragma unroll
@@ -233,17 +348,17 @@ __device__ inline void spline_load(const Rec64 *__restrict__ g, int nx, int lo, 
         const int e = threadIdx.x + u * NT;
         if (e < WS) {
             const int k = lo - kHalo - 1 + e;
-            const Rec64 r = g[min(max(k, 0), nx - 1)];
+            const Rec r = g[min(max(k, 0), nx - 1)];
             raw.y[u] = r.y;
             raw.z[u] = r.z;
         }
     }
 }
 
-template <int NT, int U, int P>
-__device__ inline void spline_window(const Rec64 *__restrict__ g, int nx, int lo, int W,
-                                     double2 *wy, double2 *wz, double *R, int cap1,
-                                     const PcrCoef &c, const SplineRaw<U> &raw)
+template <int NT, int U, int P, typename Rec, typename V, typename Win>
+__device__ inline void spline_window(const Rec *__restrict__ g, int nx, int lo, int W,
+                                     const Win &win, double *R, int cap1, const PcrCoef &c,
+                                     const SplineRaw<U, V> &raw)
 {
     const int tid = threadIdx.x;
     const int WE = W + 2 * kHalo, WS = WE + 2;
@@ -270,9 +385,7 @@ __device__ inline void spline_window(const Rec64 *__restrict__ g, int nx, int lo
         }
         By[e] = c.s6 * ry;
         Bz[e] = c.s6 * rz;
-        const int sl = WinLayout<P>::slot(e);
-        wy[sl].x = y0;
-        wz[sl].x = z0;
+        win.val(WinLayout<P>::slot(e), y0, z0);
     }
     __syncthreads();
     double *sy = By, *sz = Bz, *dy = Ay, *dz = Az;
@@ -298,27 +411,71 @@ __device__ inline void spline_window(const Rec64 *__restrict__ g, int nx, int lo
     for (int e = kHalo + tid; e < kHalo + W; e += NT) {
         const int k = lo - kHalo + e;
         const bool inner = (k > 0 && k < nx - 1);
-        const int sl = WinLayout<P>::slot(e);
-        wy[sl].y = inner ? sy[e] * c.inv_b : 0.0;
-        wz[sl].y = inner ? sz[e] * c.inv_b : 0.0;
+        win.der(WinLayout<P>::slot(e), inner ? sy[e] * c.inv_b : 0.0, inner ? sz[e] * c.inv_b : 0.0);
     }
     __syncthreads();
 }
 
+// The two precision forms.
+//   FP64: records Rec64, window fragments (y, M_y) and (z, M_z) as double2.
+//   FP32: records Rec32, one float4 (y, M_y, z, M_z) per record; node values
+//         and f-hat in single precision, accumulators in double precision.
+template <bool F32>
+struct Prec;
+template <>
+struct Prec<false> {
+    using Rec = Rec64;
+    using Node = NodeRec;
+    using V = double2;
+    using Raw = double;
+    static constexpr int NA = 2;  // fragments per record
+    template <int P>
+    using Win = WinStore64<P>;
+};
+template <>
+struct Prec<true> {
+    using Rec = Rec32;
+    using Node = NodeRec32;
+    using V = float4;
+    using Raw = float;
+    static constexpr int NA = 1;
+    template <int P>
+    using Win = WinStore32<P>;
+};
+
+__device__ inline const NodeRec *node_recs(const NodeTable &t, NodeRec *) { return t.rec; }
+__device__ inline const NodeRec32 *node_recs(const NodeTable &t, NodeRec32 *) { return t.rec32; }
+
 // Copy the node table (K*L records, offsets and y weights) of an instance
 // into LDS, where every lane of a wavefront reads the same address (a
 // broadcast).  Called by all NT threads; ends synchronised.
-template <int NT>
-__device__ inline void load_node_table(const NodeTable &t, int nodes, NodeRec *trec, int *tm,
+template <int NT, typename Node>
+__device__ inline void load_node_table(const NodeTable &t, int nodes, Node *trec, int *tm,
                                        double *tcy)
 {
+    const Node *src = node_recs(t, trec);
     for (int i = threadIdx.x; i < nodes; i += NT) {
-        trec[i] = t.rec[i];
+        trec[i] = src[i];
         tm[i] = t.m[i];
         tcy[i] = t.cy[i];
     }
     __syncthreads();
 }
+
+template <typename Node>
+__host__ __device__ constexpr size_t node_lds_bytes(int nodes)
+{
+    return (size_t)nodes * (sizeof(Node) + sizeof(double)) + (size_t)((nodes + 1) & ~1) * sizeof(int);
+}
+
+// Accumulators of P points: Y (constant of the y equation) and Z (= z^n) in
+// double precision; the FP32 form sums the f-hat terms of one layer in
+// single precision first (Yf, Zf) and adds them to Y, Z after the layer.
+template <int P>
+struct Acc {
+    double Y[P], Z[P];
+    float Yf[P], Zf[P];
+};
 
 // ---------------------------------------------------------------------------
 // Per-node work shared by the sweep kernels: interpolate y and z at the node
@@ -327,21 +484,51 @@ __device__ inline void load_node_table(const NodeTable &t, int nodes, NodeRec *t
 // the expectation of y itself (the layer j = K_y).
 // ---------------------------------------------------------------------------
 template <int P, int DRV, bool LASTY>
-__device__ inline void node_accumulate(const double2 (&ry)[P + 1], const double2 (&rz)[P + 1],
-                                       const NodeRec &c, double cy, const Driver<DRV> &f,
-                                       double (&Y)[P], double (&Z)[P])
+__device__ inline void node_accumulate(const double2 (&r)[2][P + 1], const NodeRec &c, double cy,
+                                       const Driver<DRV, double> &f, Acc<P> &acc)
 {
 #pragma unroll
     for (int q = 0; q < P; ++q) {
+        const double2 *ry = r[0], *rz = r[1];
         const double yh = fma(c.B, ry[q + 1].x - ry[q].x,
                               fma(c.C, ry[q].y, fma(c.D, ry[q + 1].y, ry[q].x)));
         const double zh = fma(c.B, rz[q + 1].x - rz[q].x,
                               fma(c.C, rz[q].y, fma(c.D, rz[q + 1].y, rz[q].x)));
         const double fh = f(yh, zh);
-        double y = fma(c.cfy, fh, Y[q]);
+        double y = fma(c.cfy, fh, acc.Y[q]);
         if (LASTY) y = fma(cy, yh, y);
-        Y[q] = y;
-        Z[q] = fma(c.cfz, fh, fma(c.cz, zh, Z[q]));
+        acc.Y[q] = y;
+        acc.Z[q] = fma(c.cfz, fh, fma(c.cz, zh, acc.Z[q]));
+    }
+}
+
+// FP32 form.  The interpolated value is kept as the unevaluated sum of the
+// record value v0 (exact) and the correction d = B (v1 - v0) + C M0 + D M1,
+// computed in single precision: d is small (a fraction of one cell's change
+// of v), so its rounding is far below that of v0 + d rounded to single.  The
+// record-value terms, which carry the size of the solution, go into the
+// double accumulators (single values are exact in double, so the only
+// rounding is that of the double FMA); the corrections and the f-hat terms,
+// whose weights are O(dt) and O(sqrt(dt)), are summed over the layer in
+// single precision.  f-hat itself is evaluated in single precision at
+// v0 + d.
+template <int P, int DRV, bool LASTY>
+__device__ inline void node_accumulate(const float4 (&r)[1][P + 1], const NodeRec32 &c, double cy,
+                                       const Driver<DRV, float> &f, Acc<P> &acc)
+{
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+        const float4 r0 = r[0][q], r1 = r[0][q + 1];
+        const float dy = fmaf(c.B, r1.x - r0.x, fmaf(c.C, r0.y, c.D * r1.y));
+        const float dz = fmaf(c.B, r1.z - r0.z, fmaf(c.C, r0.w, c.D * r1.w));
+        const float fh = f(r0.x + dy, r0.z + dz);
+        acc.Yf[q] = fmaf(c.cfy, fh, acc.Yf[q]);
+        acc.Zf[q] = fmaf(c.cfz, fh, fmaf(c.czf, dz, acc.Zf[q]));
+        acc.Z[q] = fma(c.cz, (double)r0.z, acc.Z[q]);
+        if (LASTY) {
+            acc.Yf[q] = fmaf((float)cy, dy, acc.Yf[q]);
+            acc.Y[q] = fma(cy, (double)r0.x, acc.Y[q]);
+        }
     }
 }
 
@@ -351,44 +538,67 @@ __device__ inline void node_accumulate(const double2 (&ry)[P + 1], const double2
 // a scalar register per node with readlane, so the records of a node are
 // addressed without waiting for an LDS read; the coefficients are read from
 // LDS together with the records.
-template <int P, int DRV, bool LASTY, typename Src>
-__device__ inline void layer_nodes(const Src &src, const NodeRec *trec, const int *tm,
-                                   const double *tcy, int row, int l0, int LS, int L,
-                                   const Driver<DRV> &f, double (&Y)[P], double (&Z)[P])
+template <int P, int DRV, bool LASTY, bool F32, typename Src>
+__device__ inline void layer_nodes(const Src &src, const typename Prec<F32>::Node *trec,
+                                   const int *tm, const double *tcy, int row, int l0, int LS,
+                                   int L, const Driver<DRV, typename Prec<F32>::Raw> &f,
+                                   Acc<P> &acc)
 {
+    using V = typename Prec<F32>::V;
+    constexpr int NA = Prec<F32>::NA;
+    if (F32) {
+#pragma unroll
+        for (int q = 0; q < P; ++q) acc.Yf[q] = acc.Zf[q] = 0.0f;
+    }
     const int lane = threadIdx.x & 63;
     const int mv = tm[row + min(lane, L - 1)];
 #pragma unroll 1
     for (int l = l0; l < L; l += LS) {
         const int m = __builtin_amdgcn_readlane(mv, l);
-        double2 ry[P + 1], rz[P + 1];
-        src.template fetch<P>(m, ry, rz);
-        node_accumulate<P, DRV, LASTY>(ry, rz, trec[row + l], LASTY ? tcy[row + l] : 0.0, f, Y, Z);
+        V r[NA][P + 1];
+        src.template fetch<P>(m, r);
+        node_accumulate<P, DRV, LASTY>(r, trec[row + l], LASTY ? tcy[row + l] : 0.0, f, acc);
+    }
+    if (F32) {
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+            acc.Y[q] += (double)acc.Yf[q];
+            acc.Z[q] += (double)acc.Zf[q];
+        }
     }
 }
 
 // z^n is complete in Z; the implicit y equation y = Y + h0 f(t_n, y, z^n) is
-// solved by Picard iteration from y^{n+1}_i; results go to layer n.
-template <int P, int DRV>
-__device__ inline void finish_points(const SweepArgs &a, int first, const double (&Y)[P],
-                                     const double (&Z)[P])
+// solved by Picard iteration (double precision in both forms) from
+// y^{n+1}_i; results go to layer n, and at n = n_stop also to fin_y, fin_z.
+template <int P, int DRV, bool F32>
+__device__ inline void finish_points(const SweepArgs &a, int first, const Acc<P> &acc,
+                                     int wave_slot)
 {
+    using Rec = typename Prec<F32>::Rec;
     const int S = a.K + 1;
-    const Driver<DRV> f0(a.drv, a.n * a.dt);
-    const Rec64 *__restrict__ prev = a.ring + (size_t)((a.n + 1) % S) * a.npad + a.pad_l;
-    Rec64 *__restrict__ out = a.ring + (size_t)(a.n % S) * a.npad + a.pad_l;
+    const Driver<DRV, double> f0(a.drv, a.n * a.dt);
+    Rec *ring = nullptr;
+    if constexpr (F32)
+        ring = a.ring32;
+    else
+        ring = a.ring;
+    const Rec *__restrict__ prev = ring + (size_t)((a.n + 1) % S) * a.npad + a.pad_l;
+    Rec *__restrict__ out = ring + (size_t)(a.n % S) * a.npad + a.pad_l;
+    const bool last = a.n == a.n_stop;
     unsigned int it_max = 0, it_sum = 0, nonconv = 0;
 #pragma unroll
     for (int q = 0; q < P; ++q) {
         const int i = first + q;
         const bool valid = i < a.nx;
         double y = prev[min(i, a.nx - 1)].y;
+        const double zq = acc.Z[q], Yq = acc.Y[q];
         int it = 0;
         bool conv = true;
         if (a.picard_tol > 0.0) {
             conv = false;
             while (it < a.picard_max) {
-                const double yn = fma(a.h0, f0(y, Z[q]), Y[q]);
+                const double yn = fma(a.h0, f0(y, zq), Yq);
                 ++it;
                 const double dy = fabs(yn - y);
                 y = yn;
@@ -398,11 +608,15 @@ __device__ inline void finish_points(const SweepArgs &a, int first, const double
                 }
             }
         } else {
-            for (; it < a.picard_max; ++it) y = fma(a.h0, f0(y, Z[q]), Y[q]);
+            for (; it < a.picard_max; ++it) y = fma(a.h0, f0(y, zq), Yq);
         }
         if (valid) {
             out[i].y = y;
-            out[i].z = Z[q];
+            out[i].z = zq;
+            if (last) {
+                a.fin_y[i] = y;
+                a.fin_z[i] = zq;
+            }
             it_max = max(it_max, (unsigned int)it);
             it_sum += it;
             nonconv += conv ? 0u : 1u;
@@ -413,11 +627,9 @@ __device__ inline void finish_points(const SweepArgs &a, int first, const double
         it_sum = wave_sum_u32(it_sum);
         nonconv = wave_sum_u32(nonconv);
         if ((threadIdx.x & 63) == 0) {
-            // finish_points runs on the first kBlock threads of a block
-            const int w = (blockIdx.x * kBlock + threadIdx.x) >> 6;
-            a.st_iter_max[w] = max(a.st_iter_max[w], it_max);
-            a.st_iter_sum[w] += it_sum;
-            a.st_nonconv[w] += nonconv;
+            a.st_iter_max[wave_slot] = max(a.st_iter_max[wave_slot], it_max);
+            a.st_iter_sum[wave_slot] += it_sum;
+            a.st_nonconv[wave_slot] += nonconv;
         }
     }
 }

@@ -1,4 +1,4 @@
-// kernels.h -- host-side launchers of the FP64 kernels (kernels_f64.hip).
+// kernels.h -- host-side launchers of the sweep kernels (sweep.hip).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -10,23 +10,43 @@
 
 namespace bsde {
 
+// Instances handled by one scatter / gather launch (pointers travel as
+// kernel arguments).
+constexpr int kChunk = 32;
+
+struct ScatterChunk {
+    int count;
+    int inst[kChunk];  // descriptor index
+    const double *iy[kChunk];
+    const double *iz[kChunk];
+};
+
+struct GatherChunk {
+    int count;
+    int inst[kChunk];
+    double *y0[kChunk];
+    double *z0[kChunk];
+};
+
 bool fused_supported(int P, int G);
 bool direct_p_supported(int P);
-size_t node_table_lds(int nodes);
+size_t node_table_lds(int nodes, bool f32);
+size_t fused_window_lds(int P, bool f32);  // window + PCR arrays
 
-hipError_t launch_sweep_fused(int P, int G, const SweepArgs &a, int driver, int blocks,
+hipError_t launch_sweep_fused(int P, int G, bool f32, int driver, const StepArgs &a, int blocks,
                               size_t lds, hipStream_t s);
-hipError_t set_fused_lds_limit(int P, int G, int driver, size_t lds);
-hipError_t launch_sweep_direct(int P, const SweepArgs &a, int driver, int blocks, hipStream_t s);
-hipError_t launch_spline(Rec64 *slot, int nx, int pad_l, int pad_r, const PcrCoef &c,
-                         hipStream_t s);
-hipError_t launch_scatter(Rec64 *ring, int npad, int pad_l, int nx, int N, int K,
-                          const double *iy, const double *iz, hipStream_t s);
-hipError_t launch_gather(const Rec64 *g, int nx, double *y0, double *z0,
+hipError_t set_fused_lds_limit(int P, int G, bool f32, int driver, size_t lds);
+hipError_t launch_sweep_direct(int P, bool f32, int driver, const StepArgs &a, int blocks,
+                               size_t lds, hipStream_t s);
+// mode 0: initial layer s of every instance; mode 1: layer n0 - s (direct path)
+hipError_t launch_spline(bool f32, const StepArgs &a, int mode, int blocks, hipStream_t s);
+hipError_t launch_scatter(const ScatterChunk &c, char *ws, const InstDesc *desc, int blocks_x,
+                          hipStream_t s);
+hipError_t launch_gather(const GatherChunk &c, char *ws, const InstDesc *desc, int blocks_x,
                          unsigned long long *nonfinite, hipStream_t s);
 hipError_t launch_clear(unsigned long long *p, size_t n, hipStream_t s);
-hipError_t launch_reduce_stats(const unsigned int *imax, const unsigned long long *isum,
-                               const unsigned long long *nonc, int nw, unsigned long long *totals,
-                               hipStream_t s);
+// totals[3 b + {0, 1, 2}] = max, sum, unconverged of descriptor b
+hipError_t launch_reduce_stats(char *ws, const InstDesc *desc, int count,
+                               unsigned long long *totals, hipStream_t s);
 
 }  // namespace bsde

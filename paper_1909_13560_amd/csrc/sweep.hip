@@ -1,0 +1,577 @@
+// sweep.hip -- kernels of the backward sweep (arXiv:1909.13560, Section 2.2
+// eq (20)-(21), Section 3.1 step 3, Section 3.2) and their host-side
+// launchers, in the FP64 and the FP32 form.
+//
+// Every kernel serves a group of instances: the grid's tiles are numbered
+// instance after instance, a device table maps a tile to its instance, and
+// each block reads that instance's descriptor (a single solve is a group of
+// one).  One launch per time step advances every instance still active by one
+// layer; instances are sorted by their number of steps, so the active ones
+// are a prefix of the group and the launch covers exactly their tiles.
+//
+// Two sweep kernels compute layer n from layers n+1..n+K:
+//   sweep_fused  a block owns a tile of kBlock*P consecutive grid points.  For
+//                each layer j it stages the records its nodes touch (the tile
+//                widened by the node offsets of layer j) in LDS; for j = 1 it
+//                first solves that layer's natural spline on the window by
+//                truncated PCR and writes the tile's second derivatives back
+//                to HBM, so no separate spline launch is needed.  Each lane
+//                handles P consecutive points.
+//   sweep_direct (node reach too wide for the LDS windows): records are read
+//                straight from HBM/L2, P consecutive points per lane; the
+//                natural spline of the new layer is a separate launch.
+#include "device_common.h"
+#include "kernels.h"
+
+namespace bsde {
+
+// Node records read from the LDS window (fused kernel).  Window element e of
+// the lane's q-th record is lane_pt + off + q with off = ebase + m >= 0; with
+// the padded layout its slot is
+//   (P+1) tig + off + off/P + q + [q >= P - off % P]   (tig = lane_pt / P),
+// so the per-record offsets are one of P compile-time patterns.  The FP64
+// form reads (y, M_y) and, window_slots(P) slots further, (z, M_z).
+template <int P, int B, bool PAD, int NA, typename V>
+__device__ inline void fetch_slots(const V *w, int base, V (&r)[NA][P + 1])
+{
+    const V *p = w + base;
+#pragma unroll
+    for (int q = 0; q <= P; ++q) {
+        const int sl = q + ((PAD && q >= P - B) ? 1 : 0);
+#pragma unroll
+        for (int k = 0; k < NA; ++k) r[k][q] = p[sl + k * window_slots(P)];
+    }
+}
+
+template <int P, bool F32>
+struct LdsWindow {
+    using V = typename Prec<F32>::V;
+    static constexpr int NA = Prec<F32>::NA;
+    const V *w;
+    int ebase;  // kHalo - (lowest node offset of the layer): off = ebase + m
+    int lane;   // slot of the lane's first element at off = 0: (P+1) tig padded, P tig not
+    template <int PP>
+    __device__ void fetch(int m, V (&r)[NA][PP + 1]) const
+    {
+        static_assert(PP == P, "window layout and fetch width differ");
+        const int off = ebase + m;
+        if constexpr (!WinLayout<P>::kPad) {
+            fetch_slots<P, 0, false, NA>(w, lane + off, r);
+        } else {
+            const int base = lane + off + off / P;
+            switch (off % P) {
+            case 0: fetch_slots<P, 0, true, NA>(w, base, r); break;
+            case 1: fetch_slots<P, 1, true, NA>(w, base, r); break;
+            case 2: fetch_slots<P, (P > 2 ? 2 : 1), true, NA>(w, base, r); break;
+            default: fetch_slots<P, (P > 3 ? 3 : 1), true, NA>(w, base, r); break;
+            }
+        }
+    }
+};
+
+// Node records read straight from the layer in HBM (direct kernel).
+template <bool F32>
+struct GlobalWindow {
+    using Rec = typename Prec<F32>::Rec;
+    using V = typename Prec<F32>::V;
+    static constexpr int NA = Prec<F32>::NA;
+    const Rec *lay;  // record of the lane's first point
+    template <int P>
+    __device__ void fetch(int m, V (&r)[NA][P + 1]) const
+    {
+        const Rec *__restrict__ s = lay + m;
+#pragma unroll
+        for (int q = 0; q <= P; ++q) {
+            const Rec x = s[q];
+            if constexpr (F32) {
+                r[0][q] = make_float4(x.y, x.My, x.z, x.Mz);
+            } else {
+                r[0][q] = make_double2(x.y, x.My);
+                r[1][q] = make_double2(x.z, x.Mz);
+            }
+        }
+    }
+};
+
+template <int P, int DRV, bool F32, typename Src>
+__device__ inline void layer_dispatch(const Src &src, const typename Prec<F32>::Node *trec,
+                                      const int *tm, const double *tcy, int j, int l0, int LS,
+                                      const SweepArgs &a, Acc<P> &acc)
+{
+    const Driver<DRV, typename Prec<F32>::Raw> f(a.drv, (a.n + j) * a.dt);
+    const int row = (j - 1) * a.L;
+    if (j == a.Ky)
+        layer_nodes<P, DRV, true, F32>(src, trec, tm, tcy, row, l0, LS, a.L, f, acc);
+    else
+        layer_nodes<P, DRV, false, F32>(src, trec, tm, tcy, row, l0, LS, a.L, f, acc);
+}
+
+template <bool F32>
+__device__ inline typename Prec<F32>::Rec *ring_of(const SweepArgs &a)
+{
+    if constexpr (F32)
+        return a.ring32;
+    else
+        return a.ring;
+}
+
+// LDS bytes of the window arrays of the fused kernel.
+template <bool F32>
+__host__ __device__ constexpr size_t window_lds_bytes(int P)
+{
+    return (size_t)window_slots(P) * (F32 ? sizeof(float4) : 2 * sizeof(double2));
+}
+
+// ---------------------------------------------------------------------------
+// Fused sweep of one tile: LDS-staged windows, in-kernel spline of layer n+1.
+// A block of G*kBlock threads owns a tile of kBlock*P points; thread group g
+// (kBlock threads) takes the nodes l = g, g+G, ... of every layer, and the G
+// partial sums meet in LDS before group 0 finishes the points.
+// Dynamic LDS: the window arrays, the four PCR arrays (pcr_values(P) doubles
+// each), the node table (K*L node records, K*L int, K*L double).
+// ---------------------------------------------------------------------------
+template <int P, int G, int DRV, bool F32>
+__device__ inline void fused_tile(const SweepArgs &a, int tile, char *smem)
+{
+    using PR = Prec<F32>;
+    using Rec = typename PR::Rec;
+    using Node = typename PR::Node;
+    using V = typename PR::V;
+    constexpr int T = kBlock * P;
+    constexpr int NT = kBlock * G;
+    constexpr int CAP1 = pcr_values(P);
+    V *wbase = reinterpret_cast<V *>(smem);
+    const typename PR::template Win<P> win{wbase};
+    double *R = reinterpret_cast<double *>(smem + window_lds_bytes<F32>(P));
+    Node *trec = reinterpret_cast<Node *>(R + 4 * CAP1);
+    int *tm = reinterpret_cast<int *>(trec + a.K * a.L);
+    double *tcy = reinterpret_cast<double *>(tm + ((a.K * a.L + 1) & ~1));
+
+    const int tid = threadIdx.x;
+    // kBlock is a multiple of the wavefront size: the group is wave-uniform
+    const int grp = __builtin_amdgcn_readfirstlane(tid / kBlock);
+    const int lane_pt = (tid % kBlock) * P;
+    const int t0 = tile * T;
+    const int S = a.K + 1;
+    Rec *ring = ring_of<F32>(a);
+    load_node_table<NT>(a.tab, a.K * a.L, trec, tm, tcy);
+
+    Acc<P> acc;
+#pragma unroll
+    for (int q = 0; q < P; ++q) acc.Y[q] = acc.Z[q] = 0.0;
+
+    // Layers are processed in the order 2, 3, ..., K, 1: the records of layers
+    // n+2.. are complete (their splines were built by earlier launches) and
+    // their windows are prefetched into registers one layer ahead, while the
+    // raw values of layer n+1 (written by the previous launch) are loaded at
+    // the start and only turned into its spline after the other layers.
+    constexpr int kPre = (T + kMaxReach2 + NT - 1) / NT;
+    constexpr int kRaw = pcr_slots(P, NT);
+    Rec pre[kPre];
+    auto prefetch = [&](int j) {
+        const Rec *__restrict__ g = ring + (size_t)((a.n + j) % S) * a.npad + a.pad_l;
+        const int lo = t0 + a.tab.win_lo[j];
+        const int W = T + (a.tab.win_hi[j] - a.tab.win_lo[j]) + 1;
+#pragma unroll
+        for (int u = 0; u < kPre; ++u) {
+            const int e = tid + u * NT;
+            if (e < W) pre[u] = g[lo + e];
+        }
+    };
+    SplineRaw<kRaw, typename PR::Raw> raw1;
+    {
+        const Rec *__restrict__ g1 = ring + (size_t)((a.n + 1) % S) * a.npad + a.pad_l;
+        const int W1 = T + (a.tab.win_hi[1] - a.tab.win_lo[1]) + 1;
+        if (a.K >= 2) prefetch(2);
+        spline_load<NT, kRaw>(g1, a.nx, t0 + a.tab.win_lo[1], W1, raw1);
+    }
+
+    for (int jj = 0; jj < a.K; ++jj) {
+        const int j = (jj + 1 < a.K) ? jj + 2 : 1;
+        Rec *__restrict__ g = ring + (size_t)((a.n + j) % S) * a.npad + a.pad_l;
+        const int mlo = a.tab.win_lo[j], mhi = a.tab.win_hi[j];
+        const int W = T + (mhi - mlo) + 1;
+        const int lo = t0 + mlo;
+        if (j == 1) {
+            // spline of layer n+1 on the window; the tile's part goes back to
+            // HBM for the later steps, with the ghost records
+            spline_window<NT, kRaw, P>(g, a.nx, lo, W, win, R, CAP1, a.pcr, raw1);
+            const int kend = min(t0 + T, a.nx);
+            for (int k = t0 + tid; k < kend; k += NT)
+                win.write_der(WinLayout<P>::slot(k - lo + kHalo), g[k]);
+            if (tile == 0) {
+                Rec gh{};
+                gh.y = g[0].y;
+                gh.z = g[0].z;
+                for (int k = tid; k < a.pad_l; k += NT) g[k - a.pad_l] = gh;
+            }
+            if (tile == a.ntiles - 1) {
+                Rec gh{};
+                gh.y = g[a.nx - 1].y;
+                gh.z = g[a.nx - 1].z;
+                for (int k = tid; k < a.pad_r; k += NT) g[a.nx + k] = gh;
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < kPre; ++u) {
+                const int e = tid + u * NT;
+                if (e < W) win.put(WinLayout<P>::slot(kHalo + e), pre[u]);
+            }
+            if (j + 1 <= a.K) prefetch(j + 1);
+            __syncthreads();
+        }
+        const LdsWindow<P, F32> src{wbase, kHalo - mlo,
+                                    WinLayout<P>::kPad ? lane_pt + lane_pt / P : lane_pt};
+        layer_dispatch<P, DRV, F32>(src, trec, tm, tcy, j, grp, G, a, acc);
+        __syncthreads();  // the window is reused by the next layer
+    }
+    if (G > 1) {  // partial sums of groups 1..G-1 meet group 0 in LDS, in group order
+        double *red = reinterpret_cast<double *>(smem);
+        if (grp > 0) {
+#pragma unroll
+            for (int q = 0; q < P; ++q) {
+                red[(((grp - 1) * kBlock + tid % kBlock) * P + q) * 2] = acc.Y[q];
+                red[(((grp - 1) * kBlock + tid % kBlock) * P + q) * 2 + 1] = acc.Z[q];
+            }
+        }
+        __syncthreads();
+        if (grp > 0) return;
+        for (int h = 1; h < G; ++h) {
+#pragma unroll
+            for (int q = 0; q < P; ++q) {
+                acc.Y[q] += red[(((h - 1) * kBlock + tid) * P + q) * 2];
+                acc.Z[q] += red[(((h - 1) * kBlock + tid) * P + q) * 2 + 1];
+            }
+        }
+    }
+    finish_points<P, DRV, F32>(a, t0 + lane_pt, acc, (tile * kBlock + tid) >> 6);
+}
+
+template <int P, int G, int DRV, bool F32>
+__global__ void __launch_bounds__(kBlock * G) sweep_fused(const StepArgs s)
+{
+    extern __shared__ double2 smem_fused[];
+    const int idx = xcd_tile(blockIdx.x, gridDim.x);
+    const InstDesc &d = s.desc[s.tile_inst[idx]];
+    const SweepArgs a = bind_instance(d, s.ws, s.s, s.stats != 0);
+    fused_tile<P, G, DRV, F32>(a, idx - d.tile_base, reinterpret_cast<char *>(smem_fused));
+}
+
+// ---------------------------------------------------------------------------
+// Direct sweep: records from HBM/L2, P consecutive points per lane.
+// Dynamic LDS: node table only.
+// ---------------------------------------------------------------------------
+template <int P, int DRV, bool F32>
+__global__ void __launch_bounds__(kBlock) sweep_direct(const StepArgs s)
+{
+    using Node = typename Prec<F32>::Node;
+    extern __shared__ double2 smem_direct[];
+    const int idx = xcd_tile(blockIdx.x, gridDim.x);
+    const InstDesc &d = s.desc[s.tile_inst[idx]];
+    const SweepArgs a = bind_instance(d, s.ws, s.s, s.stats != 0);
+    const int tile = idx - d.tile_base;
+    Node *trec = reinterpret_cast<Node *>(smem_direct);
+    int *tm = reinterpret_cast<int *>(trec + a.K * a.L);
+    double *tcy = reinterpret_cast<double *>(tm + ((a.K * a.L + 1) & ~1));
+    const int first = (tile * kBlock + (int)threadIdx.x) * P;
+    const int i0 = min(first, a.nx - 1);  // lanes past the end read in bounds, store nothing
+    const int S = a.K + 1;
+    load_node_table<kBlock>(a.tab, a.K * a.L, trec, tm, tcy);
+    Acc<P> acc;
+#pragma unroll
+    for (int q = 0; q < P; ++q) acc.Y[q] = acc.Z[q] = 0.0;
+    const auto *ring = ring_of<F32>(a);
+    for (int j = 1; j <= a.K; ++j) {
+        const GlobalWindow<F32> src{ring + (size_t)((a.n + j) % S) * a.npad + a.pad_l + i0};
+        layer_dispatch<P, DRV, F32>(src, trec, tm, tcy, j, 0, 1, a, acc);
+    }
+    finish_points<P, DRV, F32>(a, first, acc, (tile * kBlock + (int)threadIdx.x) >> 6);
+}
+
+// ---------------------------------------------------------------------------
+// Standalone natural spline of one layer per instance: the initial layers
+// (mode 0: layer n0 + 1 + s) and, on the direct path, the layer just computed
+// (mode 1: layer n0 - s, skipped at n_stop, which no later step reads).
+// ---------------------------------------------------------------------------
+template <bool F32>
+__global__ void __launch_bounds__(kBlock) spline_layer(const StepArgs s, int mode)
+{
+    using Rec = typename Prec<F32>::Rec;
+    using V = typename Prec<F32>::V;
+    constexpr int WE = kSplineTile + 2 * kHalo, WS = WE + 2;
+    static_assert(WE <= window_slots(1), "spline tile exceeds the window layout");
+    __shared__ V wsm[window_lds_bytes<F32>(1) / sizeof(V)];
+    __shared__ double R[4 * WS];
+    const int idx = xcd_tile(blockIdx.x, gridDim.x);
+    const InstDesc &d = s.desc[s.tile_inst[idx]];
+    const SweepArgs a = bind_instance(d, s.ws, 0, false);
+    const int tile = idx - d.spline_base;
+    const int n = mode == 0 ? d.n0 + 1 + s.s : d.n0 - s.s;
+    if (mode == 0 && s.s >= a.K) return;
+    if (mode == 1 && n <= a.n_stop) return;
+    Rec *slot = ring_of<F32>(a) + (size_t)(n % (a.K + 1)) * a.npad;
+    Rec *__restrict__ g = slot + a.pad_l;
+    const typename Prec<F32>::template Win<1> win{wsm};
+    const int t0 = tile * kSplineTile;
+    constexpr int U = (WS + kBlock - 1) / kBlock;
+    SplineRaw<U, typename Prec<F32>::Raw> raw;
+    spline_load<kBlock, U>(g, a.nx, t0, kSplineTile, raw);
+    spline_window<kBlock, U, 1>(g, a.nx, t0, kSplineTile, win, R, WS, a.pcr, raw);
+    const int kend = min(t0 + kSplineTile, a.nx);
+    for (int k = t0 + (int)threadIdx.x; k < kend; k += kBlock) win.write_der(k - t0 + kHalo, g[k]);
+    if (tile == 0) {
+        Rec gh{};
+        gh.y = g[0].y;
+        gh.z = g[0].z;
+        for (int k = threadIdx.x; k < a.pad_l; k += kBlock) slot[k] = gh;
+    }
+    if (tile == d.spline_tiles - 1) {
+        Rec gh{};
+        gh.y = g[a.nx - 1].y;
+        gh.z = g[a.nx - 1].z;
+        for (int k = threadIdx.x; k < a.pad_r; k += kBlock) g[a.nx + k] = gh;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Input / output / statistics kernels
+// ---------------------------------------------------------------------------
+// Initial layers r = 0..K-1 (t_{N-K+1+r}) of the instances of a chunk into
+// their rings (the records' y and z; the splines follow).
+__global__ void __launch_bounds__(kBlock) scatter_layers(const ScatterChunk c, char *ws,
+                                                         const InstDesc *desc)
+{
+    const int b = blockIdx.y;
+    const InstDesc &d = desc[c.inst[b]];
+    const SweepArgs a = bind_instance(d, ws, 0, false);
+    const double *__restrict__ iy = c.iy[b];
+    const double *__restrict__ iz = c.iz[b];
+    for (int r = 0; r < a.K; ++r) {
+        const int n = d.n0 + 1 + r;
+        const size_t off = (size_t)(n % (a.K + 1)) * a.npad + a.pad_l;
+        for (int i = blockIdx.x * kBlock + threadIdx.x; i < a.nx; i += gridDim.x * kBlock) {
+            const double y = iy[(size_t)r * a.nx + i], z = iz[(size_t)r * a.nx + i];
+            if (d.f32) {
+                a.ring32[off + i].y = (float)y;
+                a.ring32[off + i].z = (float)z;
+            } else {
+                a.ring[off + i].y = y;
+                a.ring[off + i].z = z;
+            }
+        }
+    }
+}
+
+// Layer n_stop (double precision, in the workspace) of the instances of a
+// chunk to the caller's buffers, counting non-finite values.
+__global__ void __launch_bounds__(kBlock) gather_layers(const GatherChunk c, char *ws,
+                                                        const InstDesc *desc,
+                                                        unsigned long long *nonfinite)
+{
+    const int b = blockIdx.y;
+    const InstDesc &d = desc[c.inst[b]];
+    const int nx = d.a.nx;
+    const double *__restrict__ fy = reinterpret_cast<const double *>(ws + d.fin_off);
+    const double *__restrict__ fz = fy + nx;
+    double *__restrict__ y0 = c.y0[b];
+    double *__restrict__ z0 = c.z0[b];
+    unsigned int bad = 0;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < nx; i += gridDim.x * kBlock) {
+        const double y = fy[i], z = fz[i];
+        y0[i] = y;
+        z0[i] = z;
+        bad += (isfinite(y) && isfinite(z)) ? 0u : 1u;
+    }
+    bad = wave_sum_u32(bad);
+    if (nonfinite && (threadIdx.x & 63) == 0 && bad) atomicAdd(nonfinite, (unsigned long long)bad);
+}
+
+__global__ void __launch_bounds__(kBlock) clear_u64(unsigned long long *p, size_t n)
+{
+    for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * kBlock)
+        p[i] = 0ull;
+}
+
+// Statistics of one instance: totals[0] = max iterations, [1] = sum,
+// [2] = unconverged.
+__global__ void __launch_bounds__(kBlock)
+reduce_stats(char *ws, const InstDesc *desc, unsigned long long *totals)
+{
+    __shared__ unsigned long long sm[3][kBlock];
+    const InstDesc &d = desc[blockIdx.x];
+    const int nw = d.nwaves;
+    const unsigned long long *isum = reinterpret_cast<const unsigned long long *>(ws + d.stat_off);
+    const unsigned long long *nonc = isum + nw;
+    const unsigned int *imax = reinterpret_cast<const unsigned int *>(isum + 2 * nw);
+    unsigned long long m = 0, s = 0, c = 0;
+    for (int w = threadIdx.x; w < nw; w += kBlock) {
+        m = max(m, (unsigned long long)imax[w]);
+        s += isum[w];
+        c += nonc[w];
+    }
+    sm[0][threadIdx.x] = m;
+    sm[1][threadIdx.x] = s;
+    sm[2][threadIdx.x] = c;
+    __syncthreads();
+    for (int o = kBlock / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            sm[0][threadIdx.x] = max(sm[0][threadIdx.x], sm[0][threadIdx.x + o]);
+            sm[1][threadIdx.x] += sm[1][threadIdx.x + o];
+            sm[2][threadIdx.x] += sm[2][threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        totals[3 * blockIdx.x + 0] = sm[0][0];
+        totals[3 * blockIdx.x + 1] = sm[1][0];
+        totals[3 * blockIdx.x + 2] = sm[2][0];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+namespace {
+
+template <int P, int G, int DRV, bool F32>
+hipError_t launch_fused_t(const StepArgs &a, int blocks, size_t lds, hipStream_t s)
+{
+    hipLaunchKernelGGL((sweep_fused<P, G, DRV, F32>), dim3(blocks), dim3(kBlock * G), lds, s, a);
+    return hipGetLastError();
+}
+
+template <int P, int DRV, bool F32>
+hipError_t launch_direct_t(const StepArgs &a, int blocks, size_t lds, hipStream_t s)
+{
+    hipLaunchKernelGGL((sweep_direct<P, DRV, F32>), dim3(blocks), dim3(kBlock), lds, s, a);
+    return hipGetLastError();
+}
+
+template <int P, int G, int DRV, bool F32>
+hipError_t allow_lds_t(size_t lds)
+{
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(&sweep_fused<P, G, DRV, F32>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+#define BSDE_BY_DRIVER(F, TP, ...)                                     \
+    switch (driver) {                                                  \
+    case BSDE_DRIVER_LINEAR: return F<TP, BSDE_DRIVER_LINEAR, F32>(__VA_ARGS__); \
+    case BSDE_DRIVER_BIDASK: return F<TP, BSDE_DRIVER_BIDASK, F32>(__VA_ARGS__); \
+    case BSDE_DRIVER_CUBIC: return F<TP, BSDE_DRIVER_CUBIC, F32>(__VA_ARGS__);   \
+    default: return F<TP, BSDE_DRIVER_EXP, F32>(__VA_ARGS__);                    \
+    }
+
+template <int P, int G, bool F32>
+hipError_t fused_by_driver(int driver, const StepArgs &a, int blocks, size_t lds, hipStream_t s)
+{
+#define BSDE_PG P, G
+    BSDE_BY_DRIVER(launch_fused_t, BSDE_PG, a, blocks, lds, s)
+}
+
+template <int P, int G, bool F32>
+hipError_t allow_by_driver(int driver, size_t lds)
+{
+    BSDE_BY_DRIVER(allow_lds_t, BSDE_PG, lds)
+#undef BSDE_PG
+}
+
+template <int P, bool F32>
+hipError_t direct_by_driver(int driver, const StepArgs &a, int blocks, size_t lds, hipStream_t s)
+{
+    BSDE_BY_DRIVER(launch_direct_t, P, a, blocks, lds, s)
+}
+
+#undef BSDE_BY_DRIVER
+
+#define BSDE_FUSED_CASES(F, ...)                                        \
+    switch (P * 8 + G) {                                                \
+    case 1 * 8 + 1: return F32 ? F<1, 1, true>(__VA_ARGS__) : F<1, 1, false>(__VA_ARGS__); \
+    case 1 * 8 + 2: return F32 ? F<1, 2, true>(__VA_ARGS__) : F<1, 2, false>(__VA_ARGS__); \
+    case 2 * 8 + 1: return F32 ? F<2, 1, true>(__VA_ARGS__) : F<2, 1, false>(__VA_ARGS__); \
+    case 2 * 8 + 2: return F32 ? F<2, 2, true>(__VA_ARGS__) : F<2, 2, false>(__VA_ARGS__); \
+    case 4 * 8 + 1: return F32 ? F<4, 1, true>(__VA_ARGS__) : F<4, 1, false>(__VA_ARGS__); \
+    case 4 * 8 + 2: return F32 ? F<4, 2, true>(__VA_ARGS__) : F<4, 2, false>(__VA_ARGS__); \
+    default: return hipErrorInvalidValue;                               \
+    }
+
+}  // namespace
+
+bool fused_supported(int P, int G) { return (P == 1 || P == 2 || P == 4) && (G == 1 || G == 2); }
+bool direct_p_supported(int P) { return P == 1 || P == 2 || P == 4; }
+
+size_t node_table_lds(int nodes, bool f32)
+{
+    return f32 ? node_lds_bytes<NodeRec32>(nodes) : node_lds_bytes<NodeRec>(nodes);
+}
+
+size_t fused_window_lds(int P, bool f32)
+{
+    return (f32 ? window_lds_bytes<true>(P) : window_lds_bytes<false>(P)) +
+           (size_t)pcr_values(P) * 4 * sizeof(double);
+}
+
+hipError_t launch_sweep_fused(int P, int G, bool F32, int driver, const StepArgs &a, int blocks,
+                              size_t lds, hipStream_t s)
+{
+    BSDE_FUSED_CASES(fused_by_driver, driver, a, blocks, lds, s)
+}
+
+hipError_t set_fused_lds_limit(int P, int G, bool F32, int driver, size_t lds)
+{
+    BSDE_FUSED_CASES(allow_by_driver, driver, lds)
+}
+
+hipError_t launch_sweep_direct(int P, bool F32, int driver, const StepArgs &a, int blocks,
+                               size_t lds, hipStream_t s)
+{
+    switch (P) {
+    case 1: return F32 ? direct_by_driver<1, true>(driver, a, blocks, lds, s)
+                       : direct_by_driver<1, false>(driver, a, blocks, lds, s);
+    case 2: return F32 ? direct_by_driver<2, true>(driver, a, blocks, lds, s)
+                       : direct_by_driver<2, false>(driver, a, blocks, lds, s);
+    case 4: return F32 ? direct_by_driver<4, true>(driver, a, blocks, lds, s)
+                       : direct_by_driver<4, false>(driver, a, blocks, lds, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_spline(bool f32, const StepArgs &a, int mode, int blocks, hipStream_t s)
+{
+    if (f32)
+        hipLaunchKernelGGL(spline_layer<true>, dim3(blocks), dim3(kBlock), 0, s, a, mode);
+    else
+        hipLaunchKernelGGL(spline_layer<false>, dim3(blocks), dim3(kBlock), 0, s, a, mode);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter(const ScatterChunk &c, char *ws, const InstDesc *desc, int blocks_x,
+                          hipStream_t s)
+{
+    hipLaunchKernelGGL(scatter_layers, dim3(blocks_x, c.count), dim3(kBlock), 0, s, c, ws, desc);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(const GatherChunk &c, char *ws, const InstDesc *desc, int blocks_x,
+                         unsigned long long *nonfinite, hipStream_t s)
+{
+    hipLaunchKernelGGL(gather_layers, dim3(blocks_x, c.count), dim3(kBlock), 0, s, c, ws, desc,
+                       nonfinite);
+    return hipGetLastError();
+}
+
+hipError_t launch_clear(unsigned long long *p, size_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(clear_u64, dim3(64), dim3(kBlock), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_stats(char *ws, const InstDesc *desc, int count,
+                               unsigned long long *totals, hipStream_t s)
+{
+    hipLaunchKernelGGL(reduce_stats, dim3(count), dim3(kBlock), 0, s, ws, desc, totals);
+    return hipGetLastError();
+}
+
+}  // namespace bsde

@@ -3,6 +3,10 @@
 Every case runs the same seeded/closed-form inputs through the C ABI (on the
 GPU) and through the serial FP64 oracle, and compares the whole output layer.
 FP64 bar: max_i |gpu_i - oracle_i| / max(|oracle_i|, 1) <= 1e-10.
+FP32 form: the same measure <= 1e-6 (single-precision ring and node
+arithmetic; the rounding of one layer, about 6e-8 relative, is averaged
+rather than amplified by the quadrature, so the error stays a small
+multiple of it over the whole sweep).
 """
 import math
 import sys
@@ -15,6 +19,7 @@ import workloads as W
 pytestmark = pytest.mark.gpu
 
 TOL64 = 1e-10
+TOL32 = 1e-6
 
 
 @pytest.fixture(scope="module")
@@ -41,10 +46,11 @@ def rel_err(g, o):
     return float(np.max(np.abs(g - o) / np.maximum(np.abs(o), 1.0)))
 
 
-def run_both(lib, orc, wl, n_stop=0, tol=TOL64, stats=True):
+def run_both(lib, orc, wl, n_stop=0, tol=TOL64, stats=True, prec="fp64"):
     pb = dict(wl.problem)
     pb["n_stop"] = n_stop
-    print(f"[case] {wl.name} n_stop={n_stop} R={W.stability_ratio(pb):.2f}", flush=True)
+    pb["prec"] = prec
+    print(f"[case] {wl.name} {prec} n_stop={n_stop} R={W.stability_ratio(pb):.2f}", flush=True)
     sys.stdout.flush()
     iy, iz = wl.init_layers()
     y, z, rc, st = lib.solve(pb, iy, iz, stats=stats)
@@ -220,3 +226,126 @@ def test_graph_replays_match_direct_launches(lib, monkeypatch):
         torch.cuda.synchronize()
         assert torch.equal(yg, ref_y) and torch.equal(zg, ref_z), rep
         assert torch.equal(yd, ref_y) and torch.equal(zd, ref_z), rep
+
+
+# ----------------------------------------------------------------------------
+# FP32 form
+# ----------------------------------------------------------------------------
+
+
+def test_fp32_sine_problem(lib, orc):
+    run_both(lib, orc, W.sine_1d(), tol=TOL32, prec="fp32_comp")
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6])
+def test_fp32_black_scholes_all_orders(lib, orc, k):
+    nx, nt = 3001, 40
+    wl = W.bs_call_1d(n_x=nx, n_t=nt, k=k, L=32, half_width=twin_half_width(0.2, 0.33, nt, nx))
+    run_both(lib, orc, wl, tol=TOL32, prec="fp32_comp")
+
+
+@pytest.mark.parametrize("sign", [1.0, -1.0])
+def test_fp32_bid_ask_ragged_grid(lib, orc, sign):
+    nx, nt = 5003, 48
+    wl = W.bidask_call_1d(n_x=nx, n_t=nt, sign=sign, half_width=twin_half_width(0.2, 0.5, nt, nx))
+    _, _, _, _, rc, st, _ = run_both(lib, orc, wl, tol=TOL32, prec="fp32_comp")
+    assert rc == lib.BSDE_OK and st["picard_nonconverged"] == 0
+
+
+def test_fp32_long_sweep_against_oracle_and_closed_form(lib, orc):
+    # the benchmarked time grid and stability ratio (1024 steps, R = 15.75) on
+    # a shorter grid the oracle sweeps in seconds
+    nx, nt = 4097, 1024
+    wl = W.bidask_call_1d(n_x=nx, n_t=nt, half_width=twin_half_width(0.2, 0.5, nt, nx, 15.75))
+    y, z, yo, zo, *_ = run_both(lib, orc, wl, tol=TOL32, prec="fp32_comp")
+    ye, ze = wl.exact_at_t0()
+    i = wl.node_index()
+    assert abs(y[i] - ye[i]) / abs(ye[i]) <= TOL32
+    assert abs(z[0, i] - ze[i]) / abs(ze[i]) <= TOL32
+
+
+def test_fp32_direct_path_wide_reach(lib, orc):
+    wl = W.bidask_call_1d(n_x=20000, n_t=16, half_width=None)
+    run_both(lib, orc, wl, tol=TOL32, prec="fp32_comp")
+
+
+def test_fp32_full_size_first_steps(lib, orc):
+    nx, nt = 262144, 1024
+    wl = W.bidask_call_1d(n_x=nx, n_t=nt, half_width=52.0)
+    run_both(lib, orc, wl, n_stop=nt - 4 - 3, tol=TOL32, prec="fp32_comp")
+
+
+def test_fp32_small_grids_and_orders(lib, orc):
+    for n_x, L in [(4, 16), (65, 7), (513, 64)]:
+        run_both(lib, orc, W.sine_1d(n_x=n_x, n_t=12, k=3, L=L), tol=TOL32, prec="fp32_comp")
+
+
+# ----------------------------------------------------------------------------
+# Batched solves
+# ----------------------------------------------------------------------------
+
+
+def batched_solve(lib, wls, autotune=False):
+    import torch
+
+    plan = lib.bsde_plan([w.problem for w in wls])
+    ws = lib.workspace(plan)
+    ios = []
+    for w in wls:
+        iy, iz = w.init_layers()
+        n = iy.shape[1]
+        ios.append((torch.as_tensor(iy, device="cuda").contiguous(),
+                    torch.as_tensor(iz.reshape(iy.shape[0], n), device="cuda").contiguous(),
+                    torch.empty(n, dtype=torch.float64, device="cuda"),
+                    torch.empty(n, dtype=torch.float64, device="cuda")))
+    rep = lib.bsde_autotune(plan, ws, ios, reps=2) if autotune else None
+    rc, st = lib.bsde_solve_batched(plan, ws, ios, stats=True)
+    torch.cuda.synchronize()
+    return rc, st, [(io[2].cpu().numpy(), io[3].cpu().numpy()) for io in ios], rep
+
+
+def test_batched_mixed_precisions_and_lengths(lib, orc):
+    wls = [W.sine_1d(n_x=700, n_t=20, k=2), W.bidask_call_1d(n_x=1500, n_t=16, half_width=None),
+           W.bs_call_1d(n_x=999, n_t=12, k=5, L=16, half_width=None),
+           W.bs_call_1d(n_x=2100, n_t=30, k=3, L=16, half_width=None),
+           W.bidask_call_1d(n_x=3001, n_t=40, half_width=None),
+           W.sine_1d(n_x=64, n_t=9, k=4)]
+    precs = ["fp64", "fp32_comp", "fp64", "fp32_comp", "fp64", "fp32_comp"]
+    for w, p in zip(wls, precs):
+        w.problem["prec"] = p
+    wls[4].problem["n_stop"] = 7
+    rc, st, outs, _ = batched_solve(lib, wls)
+    assert rc == lib.BSDE_OK
+    for w, p, (y, z) in zip(wls, precs, outs):
+        iy, iz = w.init_layers()
+        yo, zo, _ = orc.solve(w.problem, iy, iz, n_stop=w.problem.get("n_stop", 0))
+        tol = TOL64 if p == "fp64" else TOL32
+        e = max(rel_err(y, yo), rel_err(z, zo[0]))
+        print(f"[case] {w.name} {p}: {e:.3e}", flush=True)
+        assert e <= tol, (w.name, e)
+
+
+def test_option_batch_subsample(lib, orc):
+    # the seeded batched workload's recipe at small grids and few steps
+    wls = W.option_batch(count=12, log2_nx=(10.0, 12.0), n_ts=(64, 128))
+    rc, st, outs, _ = batched_solve(lib, wls)
+    assert rc == lib.BSDE_OK and st["picard_nonconverged"] == 0
+    assert st["stability_ratio"] <= 16.0 + 1e-9
+    for w, (y, z) in zip(wls, outs):
+        iy, iz = w.init_layers()
+        yo, zo, _ = orc.solve(w.problem, iy, iz)
+        e = max(rel_err(y, yo), rel_err(z, zo[0]))
+        print(f"[case] {w.name}: {e:.3e}", flush=True)
+        assert e <= TOL32, (w.name, e)
+
+
+def test_autotune_keeps_results(lib, orc):
+    wls = [W.bidask_call_1d(n_x=20011, n_t=24, half_width=twin_half_width(0.2, 0.5, 24, 20011)),
+           W.bs_call_1d(n_x=5000, n_t=16, k=4, L=16, half_width=None)]
+    rc, st, outs, rep = batched_solve(lib, wls, autotune=True)
+    print(f"[case] autotune report {rep}", flush=True)
+    assert rc == lib.BSDE_OK and rep["candidates"] >= 2 and rep["best_ms_per_step"] > 0
+    for w, (y, z) in zip(wls, outs):
+        iy, iz = w.init_layers()
+        yo, zo, _ = orc.solve(w.problem, iy, iz)
+        assert max(rel_err(y, yo), rel_err(z, zo[0])) <= TOL64

@@ -286,6 +286,50 @@ def bidask_call_1d(n_x: int = 262144, n_t: int = 1024, k: int = 4, L: int = 16,
     return w
 
 
+def option_batch(count: int = 4096, seed: int = 1909, log2_nx: tuple = (10.0, 16.0),
+                 n_ts: tuple = (64, 128, 256, 512), k: int = 4, L: int = 16,
+                 prec: str = "fp32_comp", shared_grid: int = 0) -> list:
+    """Independent European calls of uneven sizes (the batched workload).
+
+    Drawn from numpy's PCG64 generator seeded with ``seed``: strike
+    K ~ U[80, 120], sigma ~ U[0.1, 0.5], r ~ U[0, 0.06], T ~ U[0.1, 2],
+    n_x = round(2^U[log2_nx]), N uniform over ``n_ts``; S0 = 100,
+    mu = r + 0.05; even instances are Black-Scholes (linear driver), odd ones
+    the bid-ask call with R = r + 0.05 and the sign as written (s = +1).
+    The log-price interval around ln S0 has half-width
+    max(6 sigma sqrt(T) + |mu - sigma^2/2| T, sigma sqrt(2 dt) (n_x - 1) / 32),
+    so the stability ratio is at most 16 by construction.  The first
+    ``shared_grid`` instances share sigma = 0.2, mu = 0.1, T = 1, N = 256,
+    n_x = 16384 and the interval (Black-Scholes; K and r still vary).
+    """
+    rng = np.random.default_rng(seed)
+    out = []
+    for b in range(count):
+        Kb = rng.uniform(80.0, 120.0)
+        sg = rng.uniform(0.1, 0.5)
+        r = rng.uniform(0.0, 0.06)
+        T = rng.uniform(0.1, 2.0)
+        nx = int(round(2.0 ** rng.uniform(*log2_nx)))
+        nt = int(rng.choice(np.asarray(n_ts)))
+        mu = r + 0.05
+        bid_ask = b % 2 == 1
+        if b < shared_grid:
+            sg, mu, T, nt, nx, bid_ask = 0.2, 0.1, 1.0, 256, 16384, False
+        dt = T / nt
+        hw = max(6 * sg * math.sqrt(T) + abs(mu - 0.5 * sg ** 2) * T,
+                 sg * math.sqrt(2 * dt) * (nx - 1) / 32)
+        if bid_ask:
+            w = bidask_call_1d(n_x=nx, n_t=nt, k=k, L=L, half_width=hw, K=Kb, r=r, R=r + 0.05,
+                               mu=mu, sigma=sg, T=T, sign=1.0)
+        else:
+            w = bs_call_1d(n_x=nx, n_t=nt, k=k, L=L, half_width=hw, K=Kb, r=r, mu=mu, sigma=sg,
+                           T=T)
+        w.problem["prec"] = prec
+        w.name = f"batch{b}_" + w.name
+        out.append(w)
+    return out
+
+
 def quadratic_heat(n_x: int = 513, n_t: int = 32, k: int = 3, L: int = 16,
                    half_width: float = 8.0, T: float = 1.0) -> Workload:
     """f = 0, g = x^2 with X = W: y = x^2 + (T - t), z = 2x (special case)."""
