@@ -330,6 +330,98 @@ def option_batch(count: int = 4096, seed: int = 1909, log2_nx: tuple = (10.0, 16
     return out
 
 
+# ----------------------------------------------------------------------------
+# Two space dimensions (tensor grid; X = x + drift t + vol W with W in R^2)
+# ----------------------------------------------------------------------------
+
+
+def sine_2d(n_x: int = 129, n_t: int = 8, k: int = 3, L: int = 8, half: float = 8.0) -> Workload:
+    """Example 4: X = W in R^2, f = y - (z1 + z2)/2, g = sin(x1 + x2 + T), T = 1, on
+    [-half, half]^2; exact y = sin(x1 + x2 + t), z = (cos, cos)(x1 + x2 + t)."""
+    pb = _problem(d=2, T=1.0, n_t=n_t, k_y=k, k_z=k, L=L, n_x=[n_x, n_x], x_min=[-half, -half],
+                  x_max=[half, half], drift=[0.0, 0.0], vol=[[1.0, 0.0], [0.0, 1.0]],
+                  driver="linear", p=[1.0, -0.5, -0.5, 0.0])
+
+    def exact(t, x):
+        s = x[0] + x[1] + t
+        return np.sin(s), (np.cos(s), np.cos(s))
+
+    return Workload(f"sine2d_nx{n_x}_nt{n_t}_k{k}_L{L}", pb, exact, (0.0, 0.0))
+
+
+def _vol_2d(sigma, rho):
+    """diag(sigma) L_rho with L_rho the Cholesky factor of [[1, rho], [rho, 1]]."""
+    return [[sigma[0], 0.0], [rho * sigma[1], sigma[1] * math.sqrt(1.0 - rho * rho)]]
+
+
+def exchange_2d(n_x: int = 65, n_t: int = 16, k: int = 3, L: int = 8,
+                S0: tuple = (100.0, 100.0), r: float = 0.05, mu: tuple = (0.1, 0.1),
+                sigma: tuple = (0.25, 0.3), rho: float = 0.0, T: float = 1.0,
+                half_width: float | None = None, smooth: bool = True) -> Workload:
+    """Example 5: the zero-strike spread (exchange) call max(S1 - S2, 0) on the
+    log-price grid.  X = ln S, X_t = x + (mu - sigma^2/2) t + vol B with
+    vol = diag(sigma) L_rho, z is taken w.r.t. the independent B and
+    f = -r y - theta . z with vol theta = mu - r.  Exact: Margrabe's price,
+    z = (grad_x V) vol.  ``smooth`` starts from the price with dt to expiry
+    (maturity T + dt); ``half_width=None`` gives ln S0 +- 6 sigma sqrt(T) per axis."""
+    vol = _vol_2d(sigma, rho)
+    theta = np.linalg.solve(np.asarray(vol), np.asarray(mu) - r)
+    lo, hi = [], []
+    for a in range(2):
+        c = math.log(S0[a])
+        hw = 6 * sigma[a] * math.sqrt(T) if half_width is None else half_width
+        l_, h_ = _snap_domain(c, c - hw, c + hw, n_x)
+        lo.append(l_)
+        hi.append(h_)
+    tau_s = T / n_t if smooth else 0.0
+    pb = _problem(d=2, T=T, n_t=n_t, k_y=k, k_z=k, L=L, n_x=[n_x, n_x], x_min=lo, x_max=hi,
+                  drift=[mu[0] - 0.5 * sigma[0] ** 2, mu[1] - 0.5 * sigma[1] ** 2], vol=vol,
+                  driver="linear", p=[-r, -theta[0], -theta[1], 0.0])
+
+    def exact(t, x):
+        tau = T + tau_s - t
+        if tau <= 0:
+            S1, S2 = np.exp(x[0]), np.exp(x[1])
+            up = S1 > S2
+            g1, g2 = S1 * up, -S2 * up
+        else:
+            _, g1, g2 = margrabe(tau, x[0], x[1], sigma[0], sigma[1], rho)
+        V = g1 + g2  # S1 N(d1) - S2 N(d2), and the payoff at expiry
+        return V, (vol[0][0] * g1 + vol[1][0] * g2, vol[1][1] * g2)
+
+    w = Workload(f"exchange2d_nx{n_x}_nt{n_t}_k{k}_L{L}", pb, exact,
+                 (math.log(S0[0]), math.log(S0[1])))
+    w.extra.update(dict(sigma=sigma, rho=rho, r=r, mu=mu, tau_s=tau_s))
+    return w
+
+
+def basket_2d(n_x: int = 1024, n_t: int = 128, k: int = 3, L: int = 16, S0: float = 100.0,
+              K: float = 100.0, r: float = 0.05, mu: float = 0.1, sigma: float = 0.2,
+              rho: float = 0.5, T: float = 1.0) -> Workload:
+    """Basket call max((S1 + S2)/2 - K, 0) on two correlated log-prices with
+    equal parameters, f = -r y - theta . z as in exchange_2d, grid
+    ln S0 +- 6 sigma sqrt(T) per axis.  There is no closed form: the K initial
+    layers are the payoff itself (z its vol-weighted gradient where it is
+    differentiable), a deterministic input for parity checks."""
+    sg = (sigma, sigma)
+    vol = _vol_2d(sg, rho)
+    theta = np.linalg.solve(np.asarray(vol), np.asarray([mu, mu]) - r)
+    c = math.log(S0)
+    lo, hi = _snap_domain(c, c - 6 * sigma * math.sqrt(T), c + 6 * sigma * math.sqrt(T), n_x)
+    pb = _problem(d=2, T=T, n_t=n_t, k_y=k, k_z=k, L=L, n_x=[n_x, n_x], x_min=[lo, lo],
+                  x_max=[hi, hi], drift=[mu - 0.5 * sigma ** 2] * 2, vol=vol, driver="linear",
+                  p=[-r, -theta[0], -theta[1], 0.0])
+
+    def payoff(t, x):
+        S1, S2 = np.exp(x[0]), np.exp(x[1])
+        itm = 0.5 * (S1 + S2) > K
+        g1, g2 = 0.5 * S1 * itm, 0.5 * S2 * itm
+        return np.maximum(0.5 * (S1 + S2) - K, 0.0), (vol[0][0] * g1 + vol[1][0] * g2,
+                                                     vol[1][1] * g2)
+
+    return Workload(f"basket2d_nx{n_x}_nt{n_t}_k{k}_L{L}", pb, payoff, (c, c))
+
+
 def quadratic_heat(n_x: int = 513, n_t: int = 32, k: int = 3, L: int = 16,
                    half_width: float = 8.0, T: float = 1.0) -> Workload:
     """f = 0, g = x^2 with X = W: y = x^2 + (T - t), z = 2x (special case)."""
