@@ -66,7 +66,7 @@ def bytes_per_point_step(pb: dict) -> float:
     return 32.0 * K + 16.0
 
 
-KERNEL_SOURCES = ["capi.hip", "sweep.hip", "device_common.h", "kernels.h", "plan_math.cpp",
+KERNEL_SOURCES = ["capi.hip", "sweep.hip", "sweep2d.hip", "sweep2d.h", "device_common.h", "kernels.h", "plan_math.cpp",
                   "plan_math.h"]
 
 
@@ -118,6 +118,75 @@ def cpu_baseline(wl, budget_s: float = 15.0) -> dict:
                       f"({nx} points), serial FP64 C oracle, {el:.1f} s"}
 
 
+def run_batch(args, B, torch, np, ms_fp64_single):
+    """Seeded batch of independent calls of uneven sizes, FP32 form, one
+    launch per time step per instance group, autotuned; checked against the
+    same batch in the FP64 form."""
+    import workloads as W
+
+    dev = "cuda:0"
+    t0 = time.perf_counter()
+    wls = W.option_batch(count=args.batch, prec="fp32_comp")
+    ios = []
+    for w in wls:
+        iy, iz = w.init_layers()
+        n = iy.shape[1]
+        ios.append((torch.as_tensor(iy, device=dev), torch.as_tensor(iz.reshape(iy.shape), device=dev),
+                    torch.empty(n, dtype=torch.float64, device=dev),
+                    torch.empty(n, dtype=torch.float64, device=dev)))
+    point_steps = sum(w.problem["n_x"] * w.problem["n_t"] for w in wls)
+    print(f"[bench] batch of {len(wls)}: {point_steps:.3e} point-steps, inputs built in "
+          f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    stream = torch.cuda.current_stream()
+
+    def timed(plan, ws, reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(reps):
+            B.bsde_solve_batched(plan, ws, ios, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    plan = B.bsde_plan([w.problem for w in wls])
+    ws = B.workspace(plan, dev)
+    tune = B.bsde_autotune(plan, ws, ios, stream=stream, reps=3)
+    rc, st = B.bsde_solve_batched(plan, ws, ios, stream=stream, stats=True)
+    print(f"[bench] batch fp32 status {B.bsde_status_string(rc)} stats {st} tune {tune}",
+          file=sys.stderr, flush=True)
+    ms = timed(plan, ws, max(1, min(args.steps, 3)))
+    y32 = [io[2].cpu().numpy() for io in ios]
+    del plan, ws
+    # the same batch in FP64 (reference for the FP32 error; also timed)
+    for w in wls:
+        w.problem["prec"] = "fp64"
+    plan = B.bsde_plan([w.problem for w in wls])
+    ws = B.workspace(plan, dev)
+    B.bsde_solve_batched(plan, ws, ios, stream=stream)
+    ms64 = timed(plan, ws, 1)
+    err_x0, err_grid = 0.0, 0.0
+    for w, io, y in zip(wls, ios, y32):
+        y64 = io[2].cpu().numpy()
+        i = w.node_index()
+        err_x0 = max(err_x0, abs(y[i] - y64[i]) / max(abs(y64[i]), 1.0))
+        err_grid = max(err_grid, float(np.max(np.abs(y - y64) / np.maximum(np.abs(y64), 1.0))))
+    del plan, ws
+    return {"instances": len(wls), "point_steps": point_steps, "prec": "fp32_comp",
+            "value": point_steps / (ms * 1e-3), "unit": "grid-point*time-step/s",
+            "ms_per_solve": ms, "fp64_ms_per_solve": ms64,
+            "speedup_vs_fp64_batch": ms64 / ms,
+            "speedup_vs_fp64_single_headline": (point_steps / (ms * 1e-3)) /
+            (262144 * 1024 / (ms_fp64_single * 1e-3)),
+            "autotune": tune, "max_rel_err_y0_vs_fp64": err_x0,
+            "max_rel_err_grid_vs_fp64": err_grid,
+            "stability_ratio_max": st["stability_ratio"],
+            "recipe": "numpy PCG64 seed 1909: K~U[80,120], sigma~U[.1,.5], r~U[0,.06], "
+                      "T~U[.1,2], n_x=round(2^U[10,16]), N in {64,128,256,512}, k=4, L=16; "
+                      "even: Black-Scholes, odd: bid-ask R=r+.05"}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -126,6 +195,8 @@ def main() -> int:
     ap.add_argument("--workload", default="bidask1d")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fp64-only", action="store_true", help="skip the FP32-form run")
+    ap.add_argument("--batch", type=int, default=4096,
+                    help="instances of the batched workload (0 skips it)")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="profiling runs: stop each solve after this many backward steps "
@@ -159,6 +230,7 @@ def main() -> int:
     pb = wl.problem
     steps_run = pb["n_t"] - wl.K + 1
     if args.profile_steps:
+        args.batch = 0
         steps_run = min(args.profile_steps, steps_run)
         pb["n_stop"] = pb["n_t"] - wl.K + 1 - steps_run
         args.no_cpu_baseline = True
@@ -216,7 +288,13 @@ def main() -> int:
         ms32, st32, kt32, y32, z32 = run("fp32_comp")
         sw32 = kt32["sweep_ms"] / kt32["sweep_launches"]
         scale = np.maximum(np.abs(y_h), 1.0)
+        x = wl.grid(0)
+        sg = wl.extra.get("sigma", 0.2)
+        core = np.abs(x - wl.x0) <= 6 * sg * math.sqrt(pb["T"])  # where the price matters
         fp32 = {
+            "max_rel_err_vs_fp64_y_core": float(np.max((np.abs(y32 - y_h) / scale)[core])),
+            "max_rel_err_vs_fp64_z_core": float(np.max(
+                (np.abs(z32 - z_h) / np.maximum(np.abs(z_h), 1.0))[core])),
             "value": nx * (pb["n_t"] if not args.profile_steps else steps_run) / (ms32 * 1e-3),
             "ms_per_step": ms32, "speedup_vs_fp64": ms / ms32, "kernel_us": sw32 * 1e3,
             "vector_alu_tflops": flops_per_point_step(pb, st32["picard_iter_mean"]) * nx
@@ -228,6 +306,10 @@ def main() -> int:
             "config": {"points_per_lane": kt32["points_per_lane"],
                        "node_groups": kt32["node_groups"], "path": kt32["path"]},
         }
+
+    batched = None
+    if args.batch:
+        batched = run_batch(args, B, torch, np, ms)
 
     out = {
         "metric": "grid-point*time-step updates/sec (k=4, L=16)",
@@ -258,6 +340,7 @@ def main() -> int:
                          "blocks": kt["blocks"], "lds_bytes": kt["lds_bytes"]},
         "accuracy": err,
         "fp32_comp": fp32,
+        "batched": batched,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget)

@@ -23,6 +23,7 @@
 #include "../../include/bsde.h"
 #include "kernels.h"
 #include "plan_math.h"
+#include "sweep2d.h"
 
 namespace {
 
@@ -86,6 +87,22 @@ struct Group {
     }
 };
 
+// A two-dimensional instance (tensor grid).
+struct Instance2 {
+    bsde_problem pb;
+    int K, n0, n1, pad0, pad0r, pad1, pad1r, npad0, npad1;
+    size_t plane;
+    double dx0, dx1, dt, h0, R;
+    std::vector<bsde::Node2Row> rows;
+    std::vector<bsde::Node2> nodes;
+    std::vector<int> m1;
+    const bsde::Node2Row *d_rows = nullptr;
+    const bsde::Node2 *d_nodes = nullptr;
+    const int *d_m1 = nullptr;
+    size_t ring_off, fin_off, stat_off;
+    int nwaves;
+};
+
 }  // namespace
 
 // A captured backward solve (hipGraph) for one set of buffers.
@@ -104,6 +121,8 @@ struct bsde_plan_s {
     size_t max_lds = 65536;
     std::vector<Instance> inst;
     std::vector<Group> groups;
+    std::vector<Instance2> inst2;       // two-dimensional plans (all instances d = 2)
+    bsde::SplineFilter filter2;
     std::vector<bsde::InstDesc> desc;       // host copy of the descriptors
     bsde::InstDesc *d_desc = nullptr;
     void *d_tables = nullptr;
@@ -149,7 +168,22 @@ bool valid_problem(const bsde_problem &p)
     for (int i = 0; i < 8; ++i)
         if (!std::isfinite(p.p[i])) return false;
     if (p.driver == BSDE_DRIVER_BIDASK && p.p[3] == 0.0) return false;
+    if (p.d == 2) {
+        if (p.n_x[1] < 4 || !(p.x_max[1] > p.x_min[1])) return false;
+        if (!std::isfinite(p.x_min[1]) || !std::isfinite(p.x_max[1])) return false;
+        if (!std::isfinite(p.drift[1]) || !(p.vol[1][1] > 0.0) || !std::isfinite(p.vol[1][1]) ||
+            !std::isfinite(p.vol[1][0]) || !std::isfinite(p.vol[0][1]))
+            return false;
+    }
     return true;
+}
+
+// What the two-dimensional path implements: vol lower triangular (any
+// correlation, written with its Cholesky factor), the linear driver, FP64.
+bool supported_2d(const bsde_problem &p)
+{
+    return p.vol[0][1] == 0.0 && p.driver == BSDE_DRIVER_LINEAR && p.prec == BSDE_FP64 &&
+           p.L <= 64;
 }
 
 // Node tables of eq (20)-(21) on the uniform grid (Section 3.2): the node
@@ -225,6 +259,126 @@ bool build_instance(const bsde_problem &p, Instance &in)
     in.drv = bsde::DriverParams{p.p[0], p.p[1], p.p[2], p.p[3], p.p[4]};
     in.nwaves = (in.nx + kBlock - 1) / kBlock * (kBlock / 64);
     return true;
+}
+
+// Two-dimensional node tables (eq (20)-(21) with tensor Gauss-Hermite nodes):
+// node (l0, l1) of layer n+j sits at x + drift j dt + vol sqrt(2 j dt) (a_l0, a_l1),
+// i.e. s0 = (drift0 j dt + vol00 dW0)/dx0 (vol lower triangular) and
+// s1 = (drift1 j dt + vol10 dW0 + vol11 dW1)/dx1 cells away, independent of
+// the grid point.  Weights fold w_l0 w_l1 / pi with Tables 1 and 2 as in 1-D,
+// z having one component per Brownian motion.
+bsde_status build_instance2(const bsde_problem &p, Instance2 &in)
+{
+    in.pb = p;
+    in.K = std::max(p.k_y, p.k_z);
+    in.n0 = p.n_x[0];
+    in.n1 = p.n_x[1];
+    in.dt = p.T / p.n_t;
+    in.dx0 = (p.x_max[0] - p.x_min[0]) / (in.n0 - 1);
+    in.dx1 = (p.x_max[1] - p.x_min[1]) / (in.n1 - 1);
+    in.R = std::max(p.vol[0][0] / in.dx0,
+                    std::sqrt(p.vol[1][0] * p.vol[1][0] + p.vol[1][1] * p.vol[1][1]) / in.dx1) *
+           std::sqrt(2.0 * in.dt);
+    double a[bsde::kMaxL], w[bsde::kMaxL], gy[8], gz[8];
+    if (!bsde::gauss_hermite(p.L, a, w)) return BSDE_EINVAL;
+    if (!bsde::spline_gamma(1, p.k_y, gy) || !bsde::spline_gamma(2, p.k_z, gz)) return BSDE_EINVAL;
+    const double inv_sqrt_pi = 0.56418958354775628695;
+    const int K = in.K, L = p.L;
+    in.rows.assign((size_t)K * L, bsde::Node2Row{});
+    in.nodes.assign((size_t)K * L * L, bsde::Node2{});
+    in.m1.assign((size_t)K * L * L, 0);
+    int m0min = 0, m0max = 0, m1min = 0, m1max = 0;
+    const double d0 = in.dx0 * in.dx0 / 6.0, d1 = in.dx1 * in.dx1 / 6.0;
+    for (int j = 1; j <= K; ++j) {
+        const double sq = std::sqrt(2.0 * j * in.dt);
+        for (int l0 = 0; l0 < L; ++l0) {
+            const double dW0 = sq * a[l0];
+            const double s0 = (p.drift[0] * j * in.dt + p.vol[0][0] * dW0) / in.dx0;
+            const double f0 = std::floor(s0);
+            if (!(std::fabs(f0) < 1e8)) return BSDE_EINVAL;
+            const double ph0 = s0 - f0, u0 = 1.0 - ph0;
+            bsde::Node2Row &row = in.rows[(size_t)(j - 1) * L + l0];
+            row.m0 = (int)f0;
+            row.B0 = ph0;
+            row.C0 = d0 * (u0 * u0 * u0 - u0);
+            row.D0 = d0 * (ph0 * ph0 * ph0 - ph0);
+            int lo = INT32_MAX, hi = INT32_MIN;
+            for (int l1 = 0; l1 < L; ++l1) {
+                const double dW1 = sq * a[l1];
+                const double s1 =
+                    (p.drift[1] * j * in.dt + p.vol[1][0] * dW0 + p.vol[1][1] * dW1) / in.dx1;
+                const double f1 = std::floor(s1);
+                if (!(std::fabs(f1) < 1e8)) return BSDE_EINVAL;
+                const double ph1 = s1 - f1, u1 = 1.0 - ph1;
+                const double wgt = w[l0] * inv_sqrt_pi * w[l1] * inv_sqrt_pi;
+                const size_t k = ((size_t)(j - 1) * L + l0) * L + l1;
+                bsde::Node2 &nd = in.nodes[k];
+                nd.B1 = ph1;
+                nd.C1 = d1 * (u1 * u1 * u1 - u1);
+                nd.D1 = d1 * (ph1 * ph1 * ph1 - ph1);
+                nd.cfy = (j <= p.k_y) ? p.k_y * in.dt * gy[j] * wgt : 0.0;
+                nd.cfz1 = (j <= p.k_z) ? gz[j] * wgt * dW0 / gz[0] : 0.0;
+                nd.cfz2 = (j <= p.k_z) ? gz[j] * wgt * dW1 / gz[0] : 0.0;
+                nd.cz = ((j == 1 ? 1.0 : 0.0) - (j <= p.k_z ? gz[j] : 0.0)) * wgt / gz[0];
+                nd.cy = (j == p.k_y) ? wgt : 0.0;
+                in.m1[k] = (int)f1;
+                lo = std::min(lo, (int)f1);
+                hi = std::max(hi, (int)f1);
+            }
+            row.m1lo = lo;
+            row.m1hi = hi;
+            if (bsde::kTile2C + hi - lo + 2 > bsde::kWin2) return BSDE_EUNSUPPORTED;
+            m0min = std::min(m0min, row.m0);
+            m0max = std::max(m0max, row.m0);
+            m1min = std::min(m1min, lo);
+            m1max = std::max(m1max, hi);
+        }
+    }
+    in.h0 = p.k_y * in.dt * gy[0];
+    // ghosts: node reach plus the overhang of the last tile (4 rows, 64 columns)
+    in.pad0 = std::max(0, -m0min) + 1;
+    in.pad0r = std::max(0, m0max) + bsde::kTile2R + 1;
+    in.pad1 = std::max(0, -m1min) + 1;
+    in.pad1r = std::max(0, m1max) + bsde::kTile2C + 3;
+    in.npad0 = in.pad0 + in.n0 + in.pad0r;
+    in.npad1 = in.pad1 + in.n1 + in.pad1r;
+    in.plane = (size_t)in.npad0 * in.npad1;
+    const int tiles = ((in.n0 + bsde::kTile2R - 1) / bsde::kTile2R) *
+                      ((in.n1 + bsde::kTile2C - 1) / bsde::kTile2C);
+    in.nwaves = tiles * bsde::kTile2R;
+    return BSDE_OK;
+}
+
+bsde::Sweep2Args sweep2_args(const Instance2 &in, char *ws, bool stats)
+{
+    bsde::Sweep2Args a{};
+    a.ring = reinterpret_cast<double *>(ws + in.ring_off);
+    a.plane = in.plane;
+    a.n0 = in.n0;
+    a.n1 = in.n1;
+    a.npad1 = in.npad1;
+    a.pad0 = in.pad0;
+    a.pad1 = in.pad1;
+    a.K = in.K;
+    a.Ky = in.pb.k_y;
+    a.L = in.pb.L;
+    a.n_stop = in.pb.n_stop;
+    a.rows = in.d_rows;
+    a.nodes = in.d_nodes;
+    a.m1 = in.d_m1;
+    a.drv = bsde::DriverParams{in.pb.p[0], in.pb.p[1], in.pb.p[2], in.pb.p[3], in.pb.p[4]};
+    a.dt = in.dt;
+    a.h0 = in.h0;
+    a.picard_max = in.pb.picard_max;
+    a.picard_tol = in.pb.picard_tol;
+    a.fin = reinterpret_cast<double *>(ws + in.fin_off);
+    if (stats) {
+        unsigned long long *sum = reinterpret_cast<unsigned long long *>(ws + in.stat_off);
+        a.st_iter_sum = sum;
+        a.st_nonconv = sum + in.nwaves;
+        a.st_iter_max = reinterpret_cast<unsigned int *>(sum + 2 * in.nwaves);
+    }
+    return a;
 }
 
 // The fused kernel with P points per lane and G node groups for every
@@ -436,11 +590,43 @@ bsde_status enqueue_gather(const bsde_plan_s &pl, char *ws, const bsde_io *io,
     return BSDE_OK;
 }
 
+// Two-dimensional plan: per instance, initial layers (values, tensor splines,
+// ghosts) -> per step the sweep and the splines of the new layer -> outputs.
+bsde_status enqueue_solve2(const bsde_plan_s &pl, char *ws, const bsde_io *io, bool stats,
+                           unsigned long long *nonfinite, hipStream_t s, KernelTimer *tm)
+{
+    for (size_t b = 0; b < pl.inst2.size(); ++b) {
+        const Instance2 &in = pl.inst2[b];
+        bsde::Sweep2Args a = sweep2_args(in, ws, stats);
+        bsde::SplineFilter f = pl.filter2;
+        f.s6[0] = 6.0 / (in.dx0 * in.dx0) * pl.pcr_base.inv_b;
+        f.s6[1] = 6.0 / (in.dx1 * in.dx1) * pl.pcr_base.inv_b;
+        const int N = in.pb.n_t, K = in.K;
+        a.n = N - K;
+        HIP_OK(bsde::launch_scatter2d(a, io[b].init_y, io[b].init_z, s));
+        for (int r = 0; r < K; ++r) HIP_OK(bsde::launch_spline2d(a, (N - K + 1 + r) % (K + 1), f, s));
+        for (int n = N - K; n >= in.pb.n_stop; --n) {
+            a.n = n;
+            if (tm) HIP_OK(tm->mark(tm->sweep, s));
+            HIP_OK(bsde::launch_sweep2d(a, s));
+            if (tm) HIP_OK(tm->mark(tm->sweep, s));
+            if (n > in.pb.n_stop) {
+                if (tm) HIP_OK(tm->mark(tm->spline, s));
+                HIP_OK(bsde::launch_spline2d(a, n % (K + 1), f, s));
+                if (tm) HIP_OK(tm->mark(tm->spline, s));
+            }
+        }
+        HIP_OK(bsde::launch_gather2d(a, io[b].y0, io[b].z0, nonfinite, s));
+    }
+    return BSDE_OK;
+}
+
 // The whole solve: initial layers -> backward loop (all groups, step by
 // step) -> outputs.
 bsde_status enqueue_solve(const bsde_plan_s &pl, char *ws, const bsde_io *io, bool stats,
                           unsigned long long *nonfinite, hipStream_t s, KernelTimer *tm = nullptr)
 {
+    if (!pl.inst2.empty()) return enqueue_solve2(pl, ws, io, stats, nonfinite, s, tm);
     bsde_status rc = enqueue_init(pl, ws, io, s);
     if (rc != BSDE_OK) return rc;
     int smax = 0;
@@ -456,7 +642,7 @@ bsde_status enqueue_solve(const bsde_plan_s &pl, char *ws, const bsde_io *io, bo
 bsde_status finish_stats(bsde_plan_t plan, char *ws, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
                          bsde_stats *st)
 {
-    const int count = (int)plan->inst.size();
+    const int count = (int)plan->desc.size();
     unsigned long long *tot = reinterpret_cast<unsigned long long *>(ws + plan->totals_off);
     HIP_OK(bsde::launch_reduce_stats(ws, plan->d_desc, count, tot, s));
     std::vector<unsigned long long> h(3 * (size_t)count + 1);
@@ -467,12 +653,18 @@ bsde_status finish_stats(bsde_plan_t plan, char *ws, hipStream_t s, hipEvent_t e
     long long point_steps = 0;
     double R = 0.0;
     for (int b = 0; b < count; ++b) {
-        const Instance &in = plan->inst[b];
         mx = std::max(mx, h[3 * b]);
         sum += h[3 * b + 1];
         nonc += h[3 * b + 2];
-        point_steps += (long long)in.nx * in.steps;
-        R = std::max(R, in.R);
+        if (plan->inst2.empty()) {
+            const Instance &in = plan->inst[b];
+            point_steps += (long long)in.nx * in.steps;
+            R = std::max(R, in.R);
+        } else {
+            const Instance2 &in = plan->inst2[b];
+            point_steps += (long long)in.n0 * in.n1 * (in.pb.n_t - in.K - in.pb.n_stop + 1);
+            R = std::max(R, in.R);
+        }
     }
     float ms = 0.0f;
     HIP_OK(hipEventElapsedTime(&ms, e0, e1));
@@ -586,6 +778,147 @@ bsde_status solve_impl(bsde_plan_t plan, void *ws, const bsde_io *io, int count,
 }  // namespace
 
 // --------------------------------------------------------------------------
+// Plans of two-dimensional problems
+// --------------------------------------------------------------------------
+namespace {
+
+void pcr_base_coefficients(bsde::PcrCoef &c)
+{
+    // PCR coefficients of the (1, 4, 1) system: round r eliminates the
+    // neighbours at distance 2^r; a' = -a^2/b, b' = b - 2a^2/b
+    double av = 1.0, bv = 4.0;
+    for (int r = 0; r < bsde::kPcrRounds; ++r) {
+        const double k = av / bv;
+        c.kappa[r] = k;
+        bv = bv - 2.0 * k * av;
+        av = -k * av;
+    }
+    c.inv_b = 1.0 / bv;
+    c.s6 = 0.0;
+}
+
+// The truncated PCR as a filter on the right-hand side: apply its rounds to
+// a unit impulse (c), and fold in the second difference (d).
+void pcr_filter(const bsde::PcrCoef &pc, bsde::SplineFilter &f)
+{
+    constexpr int T = bsde::kPcrTaps, H = T / 2;
+    double cur[T] = {0.0}, nxt[T];
+    cur[H] = 1.0;
+    int h = 1;
+    for (int r = 0; r < bsde::kPcrRounds; ++r, h <<= 1) {
+        for (int k = 0; k < T; ++k) {
+            const double lo = k - h >= 0 ? cur[k - h] : 0.0, hi = k + h < T ? cur[k + h] : 0.0;
+            nxt[k] = cur[k] - pc.kappa[r] * (lo + hi);
+        }
+        std::memcpy(cur, nxt, sizeof(cur));
+    }
+    for (int k = 0; k < T; ++k) f.c[k] = cur[k];
+    // d_m = c_{m-1} - 2 c_m + c_{m+1}, m = -32..32
+    for (int m = -H - 1; m <= H + 1; ++m) {
+        auto cc = [&](int q) { return (q >= -H && q <= H) ? cur[q + H] : 0.0; };
+        f.d[m + H + 1] = cc(m - 1) - 2.0 * cc(m) + cc(m + 1);
+    }
+    f.s6[0] = f.s6[1] = 0.0;
+}
+
+bsde_status plan_2d(const bsde_problem *pb, int batch, bsde_plan_t *out)
+{
+    for (int b = 0; b < batch; ++b)
+        if (!supported_2d(pb[b])) return BSDE_EUNSUPPORTED;
+    bsde_plan_s *pl = new (std::nothrow) bsde_plan_s;
+    if (!pl) return BSDE_ENOMEM;
+    pl->inst2.resize(batch);
+    for (int b = 0; b < batch; ++b) {
+        const bsde_status rc = build_instance2(pb[b], pl->inst2[b]);
+        if (rc != BSDE_OK) {
+            delete pl;
+            return rc;
+        }
+    }
+    pcr_base_coefficients(pl->pcr_base);
+    pcr_filter(pl->pcr_base, pl->filter2);
+    if (hipGetDevice(&pl->device) != hipSuccess) {
+        delete pl;
+        return BSDE_EDEVICE;
+    }
+    {
+        const char *g = std::getenv("BSDE_GRAPH");
+        pl->use_graphs = !(g && g[0] == '0');
+    }
+    // device tables: node rows, nodes, axis-1 offsets; descriptors (statistics)
+    size_t tbytes = 0;
+    std::vector<size_t> toff(batch);
+    for (int b = 0; b < batch; ++b) {
+        const Instance2 &in = pl->inst2[b];
+        toff[b] = tbytes;
+        tbytes += align_up(in.rows.size() * sizeof(bsde::Node2Row), 256) +
+                  align_up(in.nodes.size() * sizeof(bsde::Node2), 256) +
+                  align_up(in.m1.size() * sizeof(int), 256);
+    }
+    const size_t desc_off = tbytes;
+    tbytes += align_up((size_t)batch * sizeof(bsde::InstDesc), 256);
+    if (hipMalloc(&pl->d_tables, tbytes) != hipSuccess) {
+        delete pl;
+        return BSDE_ENOMEM;
+    }
+    char *dev = static_cast<char *>(pl->d_tables);
+    std::vector<char> host(desc_off);
+    for (int b = 0; b < batch; ++b) {
+        Instance2 &in = pl->inst2[b];
+        size_t o = toff[b];
+        auto put = [&](const void *src, size_t bytes) {
+            std::memcpy(host.data() + o, src, bytes);
+            void *d = dev + o;
+            o += align_up(bytes, 256);
+            return d;
+        };
+        in.d_rows = static_cast<const bsde::Node2Row *>(
+            put(in.rows.data(), in.rows.size() * sizeof(bsde::Node2Row)));
+        in.d_nodes =
+            static_cast<const bsde::Node2 *>(put(in.nodes.data(), in.nodes.size() * sizeof(bsde::Node2)));
+        in.d_m1 = static_cast<const int *>(put(in.m1.data(), in.m1.size() * sizeof(int)));
+    }
+    // workspace: rings (12 planes per layer), final layers, statistics
+    size_t off = 0;
+    for (Instance2 &in : pl->inst2) {
+        in.ring_off = off;
+        off += align_up((size_t)12 * (in.K + 1) * in.plane * sizeof(double), 256);
+    }
+    for (Instance2 &in : pl->inst2) {
+        in.fin_off = off;
+        off += align_up((size_t)3 * in.n0 * in.n1 * sizeof(double), 256);
+    }
+    pl->stats_off = off;
+    for (Instance2 &in : pl->inst2) {
+        in.stat_off = off;
+        off += align_up((size_t)in.nwaves * (2 * sizeof(unsigned long long) + sizeof(unsigned int)),
+                        256);
+    }
+    pl->totals_off = off;
+    off += align_up((3 * (size_t)batch + 1) * sizeof(unsigned long long), 256);
+    pl->stats_bytes = off - pl->stats_off;
+    pl->ws_bytes = off;
+    pl->desc.resize(batch);
+    for (int b = 0; b < batch; ++b) {
+        bsde::InstDesc &d = pl->desc[b];
+        std::memset(&d, 0, sizeof(d));
+        d.stat_off = pl->inst2[b].stat_off;
+        d.nwaves = pl->inst2[b].nwaves;
+    }
+    pl->d_desc = reinterpret_cast<bsde::InstDesc *>(dev + desc_off);
+    if (hipMemcpy(pl->d_tables, host.data(), desc_off, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(pl->d_desc, pl->desc.data(), batch * sizeof(bsde::InstDesc),
+                  hipMemcpyHostToDevice) != hipSuccess) {
+        bsde_plan_destroy(pl);
+        return BSDE_EDEVICE;
+    }
+    *out = pl;
+    return BSDE_OK;
+}
+
+}  // namespace
+
+// --------------------------------------------------------------------------
 // C ABI
 // --------------------------------------------------------------------------
 extern "C" {
@@ -621,8 +954,9 @@ bsde_status bsde_plan(const bsde_problem *pb, int batch, bsde_plan_t *out)
     if (!pb || !out || batch < 1) return BSDE_EINVAL;
     for (int b = 0; b < batch; ++b) {
         if (!valid_problem(pb[b])) return BSDE_EINVAL;
-        if (pb[b].d != 1) return BSDE_EUNSUPPORTED;
+        if (pb[b].d != pb[0].d) return BSDE_EINVAL;
     }
+    if (pb[0].d == 2) return plan_2d(pb, batch, out);
     bsde_plan_s *pl = new (std::nothrow) bsde_plan_s;
     if (!pl) return BSDE_ENOMEM;
     pl->inst.resize(batch);
@@ -841,7 +1175,7 @@ bsde_status bsde_solve(bsde_plan_t plan, void *ws, const double *init_y, const d
                        double *y0, double *z0, void *stream, bsde_stats *st)
 {
     if (!plan) return BSDE_EINVAL;
-    if (plan->inst.size() != 1) return BSDE_EINVAL;
+    if (plan->desc.size() != 1) return BSDE_EINVAL;
     bsde_io io{init_y, init_z, y0, z0};
     return solve_impl(plan, ws, &io, 1, stream, st);
 }
@@ -850,13 +1184,13 @@ bsde_status bsde_solve_batched(bsde_plan_t plan, void *ws, const bsde_io *io, vo
                                bsde_stats *st)
 {
     if (!plan) return BSDE_EINVAL;
-    return solve_impl(plan, ws, io, (int)plan->inst.size(), stream, st);
+    return solve_impl(plan, ws, io, (int)plan->desc.size(), stream, st);
 }
 
 bsde_status bsde_profile_kernels(bsde_plan_t plan, void *ws, const bsde_io *io, void *stream,
                                  bsde_kernel_times *kt)
 {
-    const int count = plan ? (int)plan->inst.size() : 0;
+    const int count = plan ? (int)plan->desc.size() : 0;
     if (!kt || !valid_io(plan, ws, io, count)) return BSDE_EINVAL;
     hipStream_t s = static_cast<hipStream_t>(stream);
     char *w = static_cast<char *>(ws);
@@ -879,6 +1213,15 @@ bsde_status bsde_profile_kernels(bsde_plan_t plan, void *ws, const bsde_io *io, 
     kt->sweep_launches = (int)(tm.sweep.size() / 2);
     kt->spline_ms = sp;
     kt->spline_launches = (int)(tm.spline.size() / 2);
+    if (plan->groups.empty()) {  // two-dimensional plan
+        const Instance2 &in = plan->inst2[0];
+        kt->path = 2;
+        kt->points_per_lane = 1;
+        kt->node_groups = 1;
+        kt->blocks = in.nwaves / bsde::kTile2R;
+        kt->lds_bytes = 0;
+        return BSDE_OK;
+    }
     const Group &g = plan->groups[0];
     kt->path = g.cfg.path;
     kt->points_per_lane = g.cfg.P;
@@ -891,8 +1234,12 @@ bsde_status bsde_profile_kernels(bsde_plan_t plan, void *ws, const bsde_io *io, 
 bsde_status bsde_autotune(bsde_plan_t plan, void *ws, const bsde_io *io, void *stream, int reps,
                           bsde_tune_report *rep)
 {
-    const int count = plan ? (int)plan->inst.size() : 0;
+    const int count = plan ? (int)plan->desc.size() : 0;
     if (!valid_io(plan, ws, io, count) || reps < 1) return BSDE_EINVAL;
+    if (plan->groups.empty()) {  // two-dimensional plan: one kernel shape
+        if (rep) *rep = bsde_tune_report{2, 1, 1, 0.0, 0};
+        return BSDE_OK;
+    }
     hipStream_t s = static_cast<hipStream_t>(stream);
     char *w = static_cast<char *>(ws);
     std::lock_guard<std::mutex> lock(plan->mu);

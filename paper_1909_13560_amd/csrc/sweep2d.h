@@ -1,0 +1,75 @@
+// sweep2d.h -- data layout and launchers of the two-dimensional sweep
+// (arXiv:1909.13560, eq (20)-(21) on a tensor grid, Section 5 Examples 4-5).
+//
+// A time layer is 12 planes of padded n0 x n1 doubles: for each of y, z1, z2
+// the value v and the tensor natural-spline derivatives M_xx (along axis 0),
+// M_yy (along axis 1) and M_xxyy.  Plane p of slot s starts at
+// ring + (12 s + p) * plane; point (i0, i1) sits at
+// (i0 + pad0) * npad1 + (i1 + pad1).  Ghost points outside the grid hold the
+// boundary data that makes the tensor spline evaluate at the clamped
+// coordinates: beyond an axis-0 edge {v, 0, M_yy, 0} of the edge row, beyond
+// an axis-1 edge {v, M_xx, 0, 0} of the edge column, beyond both {v, 0, 0, 0}.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "device_common.h"
+
+namespace bsde {
+
+constexpr int kTile2R = 4;    // tile rows (axis 0): one wavefront each
+constexpr int kTile2C = 64;   // tile columns (axis 1): one lane each
+constexpr int kMaxReach2d = 240;  // widest axis-1 node spread of one axis-0 node row
+constexpr int kWin2 = kTile2C + kMaxReach2d + 2;
+constexpr int kPcrTaps = 2 * (1 + 2 + 4 + 8 + 16) + 1;  // 63: reach of the truncated PCR
+
+// Per (j, l0): the axis-0 offset of the node row and its spline weights, and
+// the range of axis-1 offsets over l1.
+struct Node2Row {
+    int m0, m1lo, m1hi, pad;
+    double B0, C0, D0;
+};
+
+// Per (j, l0, l1): axis-1 spline weights and the folded quadrature weights.
+struct alignas(16) Node2 {
+    double B1, C1, D1;
+    double cfy, cfz1, cfz2, cz, cy;
+};
+
+// Natural-spline second derivatives by the truncated PCR written as a
+// filter: M_i = s6 * sum_k c[k + 31] r~_{i+k} (r~ the odd extension of the
+// second differences), or for 32 <= i <= n - 33 directly from the values:
+// M_i = s6 * sum_k d[k + 32] v_{i+k}.
+struct SplineFilter {
+    double c[kPcrTaps];
+    double d[kPcrTaps + 2];
+    double s6[2];  // 6 / dx^2 / b_5 of axis 0, axis 1
+};
+
+struct Sweep2Args {
+    double *ring;
+    size_t plane;
+    int n0, n1, npad1, pad0, pad1;
+    int K, Ky, L, n, n_stop;
+    const Node2Row *rows;   // K*L
+    const Node2 *nodes;     // K*L*L
+    const int *m1;          // K*L*L
+    DriverParams drv;
+    double dt, h0;
+    int picard_max;
+    double picard_tol;
+    double *fin;            // layer n_stop: y, z1, z2 planes of n0*n1
+    unsigned int *st_iter_max;
+    unsigned long long *st_iter_sum, *st_nonconv;
+};
+
+hipError_t launch_sweep2d(const Sweep2Args &a, hipStream_t s);
+// splines and ghosts of the layer in slot `slot`
+hipError_t launch_spline2d(const Sweep2Args &a, int slot, const SplineFilter &f, hipStream_t s);
+// layer r = 0..K-1 of init_y (K x n0 n1) and init_z (K x 2 x n0 n1) into the ring
+hipError_t launch_scatter2d(const Sweep2Args &a, const double *iy, const double *iz,
+                            hipStream_t s);
+hipError_t launch_gather2d(const Sweep2Args &a, double *y0, double *z0,
+                           unsigned long long *nonfinite, hipStream_t s);
+
+}  // namespace bsde

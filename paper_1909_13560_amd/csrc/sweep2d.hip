@@ -1,0 +1,321 @@
+// sweep2d.hip -- the backward sweep on a two-dimensional tensor grid
+// (arXiv:1909.13560, eq (20)-(21); Section 5, Examples 4 and 5).
+//
+// The expectations over the L x L tensor Gauss-Hermite nodes use the tensor
+// natural spline of each layer.  Its 16-term evaluation at a node
+// (i0 + s0, i1 + s1) is regrouped by axes:
+//   U(q) = A0 v(p, q)    + B0 v(p+1, q)    + C0 Mxx(p, q)   + D0 Mxx(p+1, q)
+//   V(q) = A0 Myy(p, q)  + B0 Myy(p+1, q)  + C0 Mxxyy(p, q) + D0 Mxxyy(p+1, q)
+//   S    = A1 U(q) + B1 U(q+1) + C1 V(q) + D1 V(q+1)      (p = i0 + m0, q = i1 + m1)
+// With X = x + drift t + vol W and vol lower triangular, the axis-0 offset
+// s0 depends on the axis-0 Gauss-Hermite index l0 only, so for one l0 the
+// block evaluates (U, V) once per (tile row, window column) into LDS and
+// every node l1 of that row costs one axis-1 evaluation per function.
+#include "sweep2d.h"
+
+namespace bsde {
+
+namespace {
+
+__device__ inline double f_linear2(const DriverParams &p, double y, double z1, double z2)
+{
+    return fma(p.p0, y, fma(p.p1, z1, fma(p.p2, z2, p.p3)));
+}
+
+__device__ inline size_t pidx(const Sweep2Args &a, int i0, int i1)
+{
+    return (size_t)(i0 + a.pad0) * a.npad1 + (size_t)(i1 + a.pad1);
+}
+
+// The L nodes l1 of one axis-0 row of layer j, for the lane's point.
+template <bool LASTY>
+__device__ inline void row_nodes(const Sweep2Args &a, const double2 (*uv)[kTile2R][kWin2],
+                                 const Node2 *ntab, const int *nm1, int r, int c, int m1lo,
+                                 double &Y, double &Z1, double &Z2)
+{
+#pragma unroll 1
+    for (int l1 = 0; l1 < a.L; ++l1) {
+        const Node2 nd = ntab[l1];
+        const int e = c + nm1[l1] - m1lo;
+        double h[3];
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            const double2 p0 = uv[f][r][e], p1 = uv[f][r][e + 1];
+            h[f] = fma(nd.B1, p1.x - p0.x, fma(nd.C1, p0.y, fma(nd.D1, p1.y, p0.x)));
+        }
+        const double fh = f_linear2(a.drv, h[0], h[1], h[2]);
+        Y = fma(nd.cfy, fh, Y);
+        if (LASTY) Y = fma(nd.cy, h[0], Y);
+        Z1 = fma(nd.cfz1, fh, fma(nd.cz, h[1], Z1));
+        Z2 = fma(nd.cfz2, fh, fma(nd.cz, h[2], Z2));
+    }
+}
+
+}  // namespace
+
+// One time step: layer n from layers n+1..n+K.  Block = 4 x 64 points.
+__global__ void __launch_bounds__(256) sweep2d(const Sweep2Args a)
+{
+    __shared__ double2 uv[3][kTile2R][kWin2];
+    __shared__ Node2 ntab[64];
+    __shared__ int nm1[64];
+    const int tiles1 = (a.n1 + kTile2C - 1) / kTile2C;
+    const int idx = xcd_tile(blockIdx.x, gridDim.x);
+    const int t0 = (idx / tiles1) * kTile2R, t1 = (idx % tiles1) * kTile2C;
+    const int tid = threadIdx.x;
+    const int r = __builtin_amdgcn_readfirstlane(tid / kTile2C), c = tid % kTile2C;
+    const int S = a.K + 1;
+    double Y = 0.0, Z1 = 0.0, Z2 = 0.0;
+    for (int j = 1; j <= a.K; ++j) {
+        const double *slot = a.ring + (size_t)(12 * ((a.n + j) % S)) * a.plane;
+        for (int l0 = 0; l0 < a.L; ++l0) {
+            const int rowi = (j - 1) * a.L + l0;
+            const Node2Row row = a.rows[rowi];
+            const int W = kTile2C + row.m1hi - row.m1lo + 2;
+            for (int l1 = tid; l1 < a.L; l1 += 256) {
+                ntab[l1] = a.nodes[(size_t)rowi * a.L + l1];
+                nm1[l1] = a.m1[(size_t)rowi * a.L + l1];
+            }
+            // axis-0 evaluation at s0 for the tile rows and the window columns
+            for (int e = tid; e < kTile2R * W; e += 256) {
+                const int rr = e / W, cc = e - rr * W;
+                const size_t o = pidx(a, t0 + rr + row.m0, t1 + row.m1lo + cc);
+                const size_t o1 = o + a.npad1;
+#pragma unroll
+                for (int f = 0; f < 3; ++f) {
+                    const double *v = slot + (size_t)(4 * f) * a.plane;
+                    const double *mxx = v + a.plane, *myy = v + 2 * a.plane, *mxy = v + 3 * a.plane;
+                    const double U = fma(row.B0, v[o1] - v[o], fma(row.C0, mxx[o], fma(row.D0, mxx[o1], v[o])));
+                    const double V =
+                        fma(row.B0, myy[o1] - myy[o], fma(row.C0, mxy[o], fma(row.D0, mxy[o1], myy[o])));
+                    uv[f][rr][cc] = make_double2(U, V);
+                }
+            }
+            __syncthreads();
+            if (j == a.Ky)
+                row_nodes<true>(a, uv, ntab, nm1, r, c, row.m1lo, Y, Z1, Z2);
+            else
+                row_nodes<false>(a, uv, ntab, nm1, r, c, row.m1lo, Y, Z1, Z2);
+            __syncthreads();
+        }
+    }
+    // implicit y equation by Picard iteration from y^{n+1}
+    const int i0 = t0 + r, i1 = t1 + c;
+    const bool valid = i0 < a.n0 && i1 < a.n1;
+    const double *prev = a.ring + (size_t)(12 * ((a.n + 1) % S)) * a.plane;
+    double *out = a.ring + (size_t)(12 * (a.n % S)) * a.plane;
+    const size_t o = pidx(a, min(i0, a.n0 - 1), min(i1, a.n1 - 1));
+    double y = prev[o];
+    int it = 0;
+    bool conv = true;
+    if (a.picard_tol > 0.0) {
+        conv = false;
+        while (it < a.picard_max) {
+            const double yn = fma(a.h0, f_linear2(a.drv, y, Z1, Z2), Y);
+            ++it;
+            const double dy = fabs(yn - y);
+            y = yn;
+            if (dy <= a.picard_tol * fmax(1.0, fabs(y))) {
+                conv = true;
+                break;
+            }
+        }
+    } else {
+        for (; it < a.picard_max; ++it) y = fma(a.h0, f_linear2(a.drv, y, Z1, Z2), Y);
+    }
+    unsigned int it_max = 0, it_sum = 0, nonconv = 0;
+    if (valid) {
+        out[o] = y;
+        out[o + 4 * a.plane] = Z1;
+        out[o + 8 * a.plane] = Z2;
+        if (a.n == a.n_stop) {
+            const size_t np = (size_t)a.n0 * a.n1, k = (size_t)i0 * a.n1 + i1;
+            a.fin[k] = y;
+            a.fin[np + k] = Z1;
+            a.fin[2 * np + k] = Z2;
+        }
+        it_max = it;
+        it_sum = it;
+        nonconv = conv ? 0u : 1u;
+    }
+    if (a.st_iter_max) {
+        it_max = wave_max_u32(it_max);
+        it_sum = wave_sum_u32(it_sum);
+        nonconv = wave_sum_u32(nonconv);
+        if (c == 0) {
+            const int w = idx * kTile2R + r;
+            a.st_iter_max[w] = max(a.st_iter_max[w], it_max);
+            a.st_iter_sum[w] += it_sum;
+            a.st_nonconv[w] += nonconv;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Tensor natural spline of a layer: M_xx and M_yy of the values, then M_xxyy
+// as the axis-1 spline of M_xx, then the ghost points.
+// ---------------------------------------------------------------------------
+namespace {
+
+// second difference of line values at k, oddly extended about 0 and n-1
+__device__ inline double rt_line(const double *v, long stride, int n, int k)
+{
+    const int per = 2 * (n - 1);
+    int kk = k % per;
+    if (kk < 0) kk += per;
+    double sign = 1.0;
+    if (kk > n - 1) {
+        kk = per - kk;
+        sign = -1.0;
+    }
+    if (kk == 0 || kk == n - 1) return 0.0;
+    const double vm = v[(long)(kk - 1) * stride], v0 = v[(long)kk * stride],
+                 vp = v[(long)(kk + 1) * stride];
+    return sign * ((vp - v0) - (v0 - vm));
+}
+
+__device__ inline double spline_line(const double *v, long stride, int n, int i,
+                                     const SplineFilter &F, double s6)
+{
+    if (i == 0 || i == n - 1) return 0.0;
+    double acc = 0.0;
+    if (i >= 32 && i <= n - 33) {
+        const double *p = v + (long)(i - 32) * stride;
+#pragma unroll
+        for (int k = 0; k < kPcrTaps + 2; ++k) acc = fma(F.d[k], p[(long)k * stride], acc);
+    } else {
+        for (int k = 0; k < kPcrTaps; ++k) acc = fma(F.c[k], rt_line(v, stride, n, i + k - 31), acc);
+    }
+    return s6 * acc;
+}
+
+}  // namespace
+
+__global__ void __launch_bounds__(256) spline2d_axes(const Sweep2Args a, int slot,
+                                                     const SplineFilter F)
+{
+    const long i = blockIdx.x * 256L + threadIdx.x;
+    if (i >= (long)a.n0 * a.n1) return;
+    const int i0 = (int)(i / a.n1), i1 = (int)(i % a.n1);
+    double *base = a.ring + (size_t)(12 * slot) * a.plane;
+    const size_t o = pidx(a, i0, i1);
+    for (int f = 0; f < 3; ++f) {
+        double *v = base + (size_t)(4 * f) * a.plane;
+        const double *col = v + pidx(a, 0, i1);   // axis-0 line through the point
+        const double *rowp = v + pidx(a, i0, 0);  // axis-1 line
+        v[a.plane + o] = spline_line(col, a.npad1, a.n0, i0, F, F.s6[0]);
+        v[2 * a.plane + o] = spline_line(rowp, 1, a.n1, i1, F, F.s6[1]);
+    }
+}
+
+__global__ void __launch_bounds__(256) spline2d_cross(const Sweep2Args a, int slot,
+                                                      const SplineFilter F)
+{
+    const long i = blockIdx.x * 256L + threadIdx.x;
+    if (i >= (long)a.n0 * a.n1) return;
+    const int i0 = (int)(i / a.n1), i1 = (int)(i % a.n1);
+    double *base = a.ring + (size_t)(12 * slot) * a.plane;
+    const size_t o = pidx(a, i0, i1);
+    for (int f = 0; f < 3; ++f) {
+        double *v = base + (size_t)(4 * f) * a.plane;
+        const double *mxx_row = v + a.plane + pidx(a, i0, 0);
+        v[3 * a.plane + o] = spline_line(mxx_row, 1, a.n1, i1, F, F.s6[1]);
+    }
+}
+
+// Ghost points: the data of the nearest grid point with the derivative
+// planes across the crossed edge set to zero (clamped evaluation).
+__global__ void __launch_bounds__(256) ghosts2d(const Sweep2Args a, int slot, int npad0)
+{
+    const long i = blockIdx.x * 256L + threadIdx.x;
+    if (i >= (long)npad0 * a.npad1) return;
+    const int g0 = (int)(i / a.npad1) - a.pad0, g1 = (int)(i % a.npad1) - a.pad1;
+    const bool in0 = g0 >= 0 && g0 < a.n0, in1 = g1 >= 0 && g1 < a.n1;
+    if (in0 && in1) return;
+    const size_t src = pidx(a, min(max(g0, 0), a.n0 - 1), min(max(g1, 0), a.n1 - 1));
+    double *base = a.ring + (size_t)(12 * slot) * a.plane;
+    for (int f = 0; f < 3; ++f) {
+        double *v = base + (size_t)(4 * f) * a.plane;
+        v[i] = v[src];
+        v[a.plane + i] = in0 ? v[a.plane + src] : 0.0;
+        v[2 * a.plane + i] = in1 ? v[2 * a.plane + src] : 0.0;
+        v[3 * a.plane + i] = 0.0;
+    }
+}
+
+__global__ void __launch_bounds__(256) scatter2d(const Sweep2Args a, const double *__restrict__ iy,
+                                                 const double *__restrict__ iz)
+{
+    const long np = (long)a.n0 * a.n1;
+    const long i = blockIdx.x * 256L + threadIdx.x;
+    const int r = blockIdx.y;
+    if (i >= np) return;
+    const int n = a.n + 1 + r;  // a.n = N - K: layers N-K+1 .. N
+    double *base = a.ring + (size_t)(12 * (n % (a.K + 1))) * a.plane;
+    const size_t o = pidx(a, (int)(i / a.n1), (int)(i % a.n1));
+    base[o] = iy[r * np + i];
+    base[4 * a.plane + o] = iz[(2L * r) * np + i];
+    base[8 * a.plane + o] = iz[(2L * r + 1) * np + i];
+}
+
+__global__ void __launch_bounds__(256) gather2d(const Sweep2Args a, double *__restrict__ y0,
+                                                double *__restrict__ z0,
+                                                unsigned long long *nonfinite)
+{
+    const long np = (long)a.n0 * a.n1;
+    unsigned int bad = 0;
+    for (long i = blockIdx.x * 256L + threadIdx.x; i < np; i += (long)gridDim.x * 256) {
+        const double y = a.fin[i], z1 = a.fin[np + i], z2 = a.fin[2 * np + i];
+        y0[i] = y;
+        z0[i] = z1;
+        z0[np + i] = z2;
+        bad += (isfinite(y) && isfinite(z1) && isfinite(z2)) ? 0u : 1u;
+    }
+    bad = wave_sum_u32(bad);
+    if (nonfinite && (threadIdx.x & 63) == 0 && bad) atomicAdd(nonfinite, (unsigned long long)bad);
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_sweep2d(const Sweep2Args &a, hipStream_t s)
+{
+    const int tiles = ((a.n0 + kTile2R - 1) / kTile2R) * ((a.n1 + kTile2C - 1) / kTile2C);
+    hipLaunchKernelGGL(sweep2d, dim3(tiles), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_spline2d(const Sweep2Args &a, int slot, const SplineFilter &f, hipStream_t s)
+{
+    const long np = (long)a.n0 * a.n1;
+    const int blocks = (int)((np + 255) / 256);
+    hipLaunchKernelGGL(spline2d_axes, dim3(blocks), dim3(256), 0, s, a, slot, f);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(spline2d_cross, dim3(blocks), dim3(256), 0, s, a, slot, f);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int npad0 = (int)(a.plane / a.npad1);
+    const int gb = (int)(((long)npad0 * a.npad1 + 255) / 256);
+    hipLaunchKernelGGL(ghosts2d, dim3(gb), dim3(256), 0, s, a, slot, npad0);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter2d(const Sweep2Args &a, const double *iy, const double *iz, hipStream_t s)
+{
+    const long np = (long)a.n0 * a.n1;
+    hipLaunchKernelGGL(scatter2d, dim3((unsigned)((np + 255) / 256), a.K), dim3(256), 0, s, a, iy,
+                       iz);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather2d(const Sweep2Args &a, double *y0, double *z0,
+                           unsigned long long *nonfinite, hipStream_t s)
+{
+    const long np = (long)a.n0 * a.n1;
+    const int blocks = (int)std::min<long>(2048, (np + 255) / 256);
+    hipLaunchKernelGGL(gather2d, dim3(blocks), dim3(256), 0, s, a, y0, z0, nonfinite);
+    return hipGetLastError();
+}
+
+}  // namespace bsde

@@ -102,3 +102,33 @@ def test_plan_rejects_empty_batch():
     arr = (B._Problem * 1)(B.problem_struct(W.sine_1d().problem))
     assert B.load().bsde_plan(arr, 0, ctypes.byref(h)) == B.BSDE_EINVAL
     assert B.load().bsde_plan(None, 1, ctypes.byref(h)) == B.BSDE_EINVAL
+
+
+@pytest.mark.parametrize("change", ["vol01", "driver", "fp32"])
+def test_plan_2d_reports_unsupported_variants(change):
+    # valid two-dimensional problems outside the implemented path are refused
+    # before any device call
+    pb = dict(W.exchange_2d(n_x=33, n_t=8).problem)
+    if change == "vol01":
+        pb["vol"] = [[0.25, 0.05], [0.0, 0.3]]
+    elif change == "driver":
+        pb["driver"] = "cubic"
+    else:
+        pb["prec"] = "fp32_comp"
+    with pytest.raises(B.BsdeError) as e:
+        B.bsde_plan(pb)
+    assert e.value.code == B.BSDE_EUNSUPPORTED
+
+
+def test_plan_rejects_mixed_dimensions():
+    with pytest.raises(B.BsdeError) as e:
+        B.bsde_plan([W.sine_1d().problem, W.sine_2d(n_x=17).problem])
+    assert e.value.code == B.BSDE_EINVAL
+
+
+def test_plan_rejects_invalid_2d_axis():
+    pb = dict(W.sine_2d(n_x=17).problem)
+    pb["n_x"] = [17, 3]
+    with pytest.raises(B.BsdeError) as e:
+        B.bsde_plan(pb)
+    assert e.value.code == B.BSDE_EINVAL

@@ -349,3 +349,72 @@ def test_autotune_keeps_results(lib, orc):
         iy, iz = w.init_layers()
         yo, zo, _ = orc.solve(w.problem, iy, iz)
         assert max(rel_err(y, yo), rel_err(z, zo[0])) <= TOL64
+
+
+# ----------------------------------------------------------------------------
+# Two space dimensions
+# ----------------------------------------------------------------------------
+
+
+def test_2d_example4_table9_row(lib, orc):
+    # Example 4, K = 3, N = 8, M = 128: the paper prints 3.94e-4 / 1.43e-3
+    wl = W.sine_2d(n_x=129, n_t=8, k=3, L=8)
+    y, z, yo, zo, *_ = run_both(lib, orc, wl)
+    assert rel_err(z[1], zo[1]) <= TOL64
+    i = wl.node_index()
+    assert abs(y[i]) == pytest.approx(3.94e-4, rel=0.01)
+    assert math.hypot(z[0, i] - 1.0, z[1, i] - 1.0) == pytest.approx(1.43e-3, rel=0.01)
+
+
+@pytest.mark.parametrize("rho", [0.0, 0.5])
+def test_2d_exchange_option(lib, orc, rho):
+    wl = W.exchange_2d(n_x=97, n_t=10, k=3, L=8, rho=rho)
+    y, z, yo, zo, *_ = run_both(lib, orc, wl)
+    assert rel_err(z[1], zo[1]) <= TOL64
+    ye, ze = wl.exact_at_t0()
+    i = wl.node_index()
+    assert abs(y[i] - ye[i]) < 1e-4
+
+
+def test_2d_ragged_grid_unequal_orders(lib, orc):
+    wl = W.exchange_2d(n_x=77, n_t=9, k=2, L=7, rho=0.3)
+    pb = wl.problem
+    pb["n_x"] = [77, 130]
+    pb["x_max"] = [pb["x_max"][0], pb["x_min"][1] + 129 * (pb["x_max"][1] - pb["x_min"][1]) / 76]
+    pb["k_y"], pb["k_z"] = 3, 2
+    wl.x0 = (pb["x_min"][0], pb["x_min"][1])
+    y, z, yo, zo, *_ = run_both(lib, orc, wl)
+    assert rel_err(z[1], zo[1]) <= TOL64
+
+
+def test_2d_basket_checkpoint(lib, orc):
+    wl = W.basket_2d(n_x=65, n_t=12, k=3, L=16)
+    y, z, yo, zo, *_ = run_both(lib, orc, wl, n_stop=4)
+    assert rel_err(z[1], zo[1]) <= TOL64
+
+
+def test_2d_picard_tolerance_and_batch(lib, orc):
+    import torch
+
+    wls = [W.sine_2d(n_x=33, n_t=6, k=2, L=8), W.exchange_2d(n_x=41, n_t=7, k=4, L=6, rho=0.5)]
+    wls[0].problem["picard_tol"] = 1e-14
+    plan = lib.bsde_plan([w.problem for w in wls])
+    ws = lib.workspace(plan)
+    ios = []
+    for w in wls:
+        iy, iz = w.init_layers()
+        n = iy.shape[1]
+        ios.append((torch.as_tensor(iy, device="cuda").contiguous(),
+                    torch.as_tensor(iz.reshape(iy.shape[0], -1), device="cuda").contiguous(),
+                    torch.empty(n, dtype=torch.float64, device="cuda"),
+                    torch.empty(2 * n, dtype=torch.float64, device="cuda")))
+    rc, st = lib.bsde_solve_batched(plan, ws, ios, stats=True)
+    torch.cuda.synchronize()
+    assert rc == lib.BSDE_OK and st["picard_nonconverged"] == 0
+    for w, io in zip(wls, ios):
+        iy, iz = w.init_layers()
+        yo, zo, _ = orc.solve(w.problem, iy, iz)
+        n = iy.shape[1]
+        assert rel_err(io[2].cpu().numpy(), yo) <= TOL64
+        zz = io[3].cpu().numpy().reshape(2, n)
+        assert max(rel_err(zz[0], zo[0]), rel_err(zz[1], zo[1])) <= TOL64
