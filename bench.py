@@ -187,6 +187,54 @@ def run_batch(args, B, torch, np, ms_fp64_single):
                       "even: Black-Scholes, odd: bid-ask R=r+.05"}
 
 
+def flops_per_point_step_2d(pb: dict, picard_mean: float) -> float:
+    """Algorithmic FP64 operations of one point and step of the 2-D sweep: per
+    tensor node (K L^2 of them) three bicubic tensor-spline evaluations of 16
+    terms (32 flops each), the linear driver (6) and the weighted
+    accumulations (y: 2, z1: 4, z2: 4); per layer j = K_y the y expectation
+    (2 per node); the z combination and each Picard iteration (8)."""
+    K, L = max(pb["k_y"], pb["k_z"]), pb["L"]
+    per_node = 3 * 32 + 6 + 10
+    return K * L * L * per_node + 2 * L * L + 2 * (3 * K + 1) + 2 * K + picard_mean * 8
+
+
+def run_2d(args, B, torch, np):
+    """A few backward steps of the basket call on the 1024 x 1024 tensor grid
+    (N = 128, k = 3, 16 x 16 Gauss-Hermite nodes, FP64)."""
+    import workloads as W
+
+    dev = "cuda:0"
+    wl = W.basket_2d(n_x=1024, n_t=128, k=3, L=16)
+    pb = wl.problem
+    steps = args.steps_2d
+    pb["n_stop"] = pb["n_t"] - wl.K + 1 - steps
+    iy, iz = wl.init_layers()
+    npts = iy.shape[1]
+    t_iy = torch.as_tensor(iy, device=dev)
+    t_iz = torch.as_tensor(iz.reshape(wl.K, -1), device=dev)
+    y0 = torch.empty(npts, dtype=torch.float64, device=dev)
+    z0 = torch.empty(2 * npts, dtype=torch.float64, device=dev)
+    plan = B.bsde_plan(pb)
+    ws = B.workspace(plan, dev)
+    stream = torch.cuda.current_stream()
+    rc, st = B.bsde_solve(plan, ws, t_iy, t_iz, y0, z0, stream=stream, stats=True)
+    kt = B.bsde_profile_kernels(plan, ws, [(t_iy, t_iz, y0, z0)], stream=stream)
+    sweep_ms = kt["sweep_ms"] / kt["sweep_launches"]
+    spline_ms = kt["spline_ms"] / max(kt["spline_launches"], 1)
+    fl = flops_per_point_step_2d(pb, st["picard_iter_mean"]) * npts
+    print(f"[bench] 2-D basket: status {B.bsde_status_string(rc)} {st} kernels {kt}",
+          file=sys.stderr, flush=True)
+    return {"workload": wl.name, "points": npts, "steps_timed": steps, "dtype": "f64",
+            "sweep_kernel_us": sweep_ms * 1e3, "spline_us_per_layer": spline_ms * 1e3,
+            "value": npts / ((sweep_ms + spline_ms) * 1e-3), "unit": "grid-point*time-step/s",
+            "roofline": {"bound": "alu", "achieved": fl / (sweep_ms * 1e-3) / 1e12,
+                         "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": fl / (sweep_ms * 1e-3) / 1e12 / FP64_VALU_PEAK_TFLOPS,
+                         "flops_per_launch": fl},
+            "full_solve_estimate_s": (pb["n_t"] - wl.K + 1) * (sweep_ms + spline_ms) * 1e-3,
+            "stability_ratio": st["stability_ratio"]}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -197,6 +245,8 @@ def main() -> int:
     ap.add_argument("--fp64-only", action="store_true", help="skip the FP32-form run")
     ap.add_argument("--batch", type=int, default=4096,
                     help="instances of the batched workload (0 skips it)")
+    ap.add_argument("--steps-2d", type=int, default=6,
+                    help="backward steps of the 2-D basket workload to time (0 skips it)")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="profiling runs: stop each solve after this many backward steps "
@@ -231,6 +281,7 @@ def main() -> int:
     steps_run = pb["n_t"] - wl.K + 1
     if args.profile_steps:
         args.batch = 0
+        args.steps_2d = 0
         steps_run = min(args.profile_steps, steps_run)
         pb["n_stop"] = pb["n_t"] - wl.K + 1 - steps_run
         args.no_cpu_baseline = True
@@ -310,6 +361,7 @@ def main() -> int:
     batched = None
     if args.batch:
         batched = run_batch(args, B, torch, np, ms)
+    two_d = run_2d(args, B, torch, np) if args.steps_2d else None
 
     out = {
         "metric": "grid-point*time-step updates/sec (k=4, L=16)",
@@ -341,6 +393,7 @@ def main() -> int:
         "accuracy": err,
         "fp32_comp": fp32,
         "batched": batched,
+        "two_d": two_d,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget)

@@ -35,6 +35,12 @@
  *   - Picard starts from y^{n+1}_i and stops after picard_max iterations, or
  *     earlier when |y_new - y| <= picard_tol * max(1, |y_new|) if tol > 0.
  *
+ * Pins (tests outside this file): Tables 4 and 5 (d = 1, Examples 1 and 2)
+ * and Table 9 (d = 2, Example 4) reproduced to the printed digits, the
+ * closed forms of Examples 3 and 5, library references for the quadrature
+ * rule and the spline, and special cases (a problem independent of x2
+ * reduces the d = 2 sweep to the d = 1 sweep).
+ *
  * Built with -O2 -ffp-contract=off and no fast-math.
  */
 #include <math.h>

@@ -288,7 +288,8 @@ def bidask_call_1d(n_x: int = 262144, n_t: int = 1024, k: int = 4, L: int = 16,
 
 def option_batch(count: int = 4096, seed: int = 1909, log2_nx: tuple = (10.0, 16.0),
                  n_ts: tuple = (64, 128, 256, 512), k: int = 4, L: int = 16,
-                 prec: str = "fp32_comp", shared_grid: int = 0) -> list:
+                 prec: str = "fp32_comp", shared_grid: int = 0,
+                 max_half_width: float = 60.0) -> list:
     """Independent European calls of uneven sizes (the batched workload).
 
     Drawn from numpy's PCG64 generator seeded with ``seed``: strike
@@ -298,7 +299,10 @@ def option_batch(count: int = 4096, seed: int = 1909, log2_nx: tuple = (10.0, 16
     the bid-ask call with R = r + 0.05 and the sign as written (s = +1).
     The log-price interval around ln S0 has half-width
     max(6 sigma sqrt(T) + |mu - sigma^2/2| T, sigma sqrt(2 dt) (n_x - 1) / 32),
-    so the stability ratio is at most 16 by construction.  The first
+    so the stability ratio is at most 16 by construction; the half-width is
+    capped at ``max_half_width`` (e^(ln 100 + 60) ~ 1e28 keeps prices within
+    single precision) and, where the cap binds, n_x is lowered to the
+    largest grid with ratio <= 16.  The first
     ``shared_grid`` instances share sigma = 0.2, mu = 0.1, T = 1, N = 256,
     n_x = 16384 and the interval (Black-Scholes; K and r still vary).
     """
@@ -318,6 +322,9 @@ def option_batch(count: int = 4096, seed: int = 1909, log2_nx: tuple = (10.0, 16
         dt = T / nt
         hw = max(6 * sg * math.sqrt(T) + abs(mu - 0.5 * sg ** 2) * T,
                  sg * math.sqrt(2 * dt) * (nx - 1) / 32)
+        if hw > max_half_width:
+            hw = max_half_width
+            nx = int(32 * hw / (sg * math.sqrt(2 * dt))) + 1
         if bid_ask:
             w = bidask_call_1d(n_x=nx, n_t=nt, k=k, L=L, half_width=hw, K=Kb, r=r, R=r + 0.05,
                                mu=mu, sigma=sg, T=T, sign=1.0)
