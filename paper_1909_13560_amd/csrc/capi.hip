@@ -402,7 +402,7 @@ SweepConfig fused_config(const std::vector<Instance> &all, const std::vector<int
         const int reach1 = in.win_hi[1] - in.win_lo[1] + 1;
         const int w1 = T + reach1;
         const size_t window = bsde::fused_window_lds(P, f32);
-        const size_t need = window + bsde::node_table_lds(in.K * in.pb.L, f32);
+        const size_t need = window + (size_t)in.K * in.pb.L * sizeof(int);
         const size_t reduce_bytes = (size_t)(G - 1) * kBlock * P * 2 * sizeof(double);
         const bool fits = reach <= bsde::kMaxReach2 && reach1 <= bsde::kMaxReach1 &&
                           wmax + bsde::kHalo <= bsde::window_elems(P) &&
@@ -423,10 +423,10 @@ SweepConfig direct_config(const std::vector<Instance> &all, const std::vector<in
     SweepConfig c;
     c.path = PATH_DIRECT;
     c.P = P;
-    size_t lds = 0;
-    for (int b : members)
-        lds = std::max(lds, bsde::node_table_lds(all[b].K * all[b].pb.L, f32));
-    c.lds = lds;
+    (void)all;
+    (void)members;
+    (void)f32;
+    c.lds = 0;  // the direct kernel uses no LDS
     return c;
 }
 
@@ -1036,8 +1036,7 @@ bsde_status bsde_plan(const bsde_problem *pb, int batch, bsde_plan_t *out)
         toff[b] = tbytes;
         const size_t kl = (size_t)in.K * in.pb.L;
         tbytes += align_up(kl * sizeof(int), 256) + align_up(kl * sizeof(bsde::NodeRec), 256) +
-                  align_up(kl * sizeof(bsde::NodeRec32), 256) + align_up(kl * sizeof(double), 256) +
-                  2 * align_up((in.K + 1) * sizeof(int), 256);
+                  align_up(kl * sizeof(bsde::NodeRec32), 256) + 2 * align_up((in.K + 1) * sizeof(int), 256);
     }
     const size_t desc_off = tbytes;
     tbytes += align_up((size_t)batch * sizeof(bsde::InstDesc), 256);
@@ -1069,20 +1068,20 @@ bsde_status bsde_plan(const bsde_problem *pb, int batch, bsde_plan_t *out)
         };
         std::vector<bsde::NodeRec> recs(kl);
         std::vector<bsde::NodeRec32> recs32(kl);
-        std::vector<double> cyk(kl, 0.0);
         for (size_t k = 0; k < kl; ++k) {
             const int l = (int)(k % in.pb.L), j = (int)(k / in.pb.L) + 1;
-            recs[k] = bsde::NodeRec{in.B[k], in.C[k], in.D[k], in.cfy[k], in.cfz[k], in.cz[k]};
+            const double cy = (j == in.pb.k_y) ? in.cy[l] : 0.0;
+            recs[k] = bsde::NodeRec{in.B[k],   in.C[k],  in.D[k], in.cfy[k],
+                                    in.cfz[k], in.cz[k], cy,      0.0};
             recs32[k] = bsde::NodeRec32{(float)in.B[k],   (float)in.C[k],   (float)in.D[k],
                                         (float)in.cfy[k], (float)in.cfz[k], (float)in.cz[k],
-                                        in.cz[k]};
-            if (j == in.pb.k_y) cyk[k] = in.cy[l];
+                                        (float)cy,        0.0f,             in.cz[k],
+                                        cy};
         }
         in.dtab.rec = static_cast<const bsde::NodeRec *>(put(recs.data(), kl * sizeof(bsde::NodeRec)));
         in.dtab.rec32 =
             static_cast<const bsde::NodeRec32 *>(put(recs32.data(), kl * sizeof(bsde::NodeRec32)));
         in.dtab.m = static_cast<const int *>(put(in.m.data(), kl * sizeof(int)));
-        in.dtab.cy = static_cast<const double *>(put(cyk.data(), kl * sizeof(double)));
         in.dtab.win_lo = static_cast<const int *>(put(in.win_lo.data(), (in.K + 1) * sizeof(int)));
         in.dtab.win_hi = static_cast<const int *>(put(in.win_hi.data(), (in.K + 1) * sizeof(int)));
     }

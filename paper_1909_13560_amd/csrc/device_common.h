@@ -30,6 +30,8 @@ constexpr int kSplineTile = 512;   // grid points per block of the standalone sp
 // Coefficients of one Gauss-Hermite node (j, l), the same for every grid
 // point.  With phi the fraction of the node's cell offset, the spline value
 // at the node is  v0 + B (v1 - v0) + C M0 + D M1  (second-derivative form).
+// 64 bytes: the kernels read a node with scalar loads (one per node, ahead
+// of use), so the coefficients never occupy the LDS pipe.
 struct alignas(16) NodeRec {
     double B;      // phi
     double C;      // dx^2/6 ((1-phi)^3 - (1-phi))
@@ -37,16 +39,20 @@ struct alignas(16) NodeRec {
     double cfy;    // weight of f-hat in the constant of the y equation
     double cfz;    // weight of f-hat in z^n
     double cz;     // weight of z-hat in z^n
+    double cy;     // weight of y-hat in the y constant (non-zero only for j = K_y)
+    double pad;
 };
 
 // The FP32 form's node coefficients: interpolation weights and the weights
-// of the small terms in single precision, the weight of the z record value
-// (which carries the magnitude of z^n) in double precision.  32 bytes.
+// of the small terms in single precision, the weights of the record values
+// (which carry the magnitude of y^n and z^n) in double precision.  48 bytes.
 struct alignas(16) NodeRec32 {
     float B, C, D;
     float cfy, cfz;
     float czf;  // cz in single precision (weight of the interpolation correction)
-    double cz;
+    float cyf;  // cy in single precision
+    float pad;
+    double cz, cy;
 };
 
 // Node table of one instance (device memory).  K*L entries, row j-1 holds the
@@ -55,7 +61,6 @@ struct NodeTable {
     const NodeRec *rec;
     const NodeRec32 *rec32;  // the same coefficients for the FP32 form
     const int *m;       // integer cell offset of the node from x_i
-    const double *cy;   // weight of y-hat in the y constant (non-zero only for j = K_y)
     const int *win_lo;  // [K+1]: lowest node offset of layer j (j = 1 also <= 0)
     const int *win_hi;  // [K+1]: highest node offset of layer j (j = 1 also >= 0)
 };
@@ -446,26 +451,40 @@ struct Prec<true> {
 __device__ inline const NodeRec *node_recs(const NodeTable &t, NodeRec *) { return t.rec; }
 __device__ inline const NodeRec32 *node_recs(const NodeTable &t, NodeRec32 *) { return t.rec32; }
 
-// Copy the node table (K*L records, offsets and y weights) of an instance
-// into LDS, where every lane of a wavefront reads the same address (a
-// broadcast).  Called by all NT threads; ends synchronised.
-template <int NT, typename Node>
-__device__ inline void load_node_table(const NodeTable &t, int nodes, Node *trec, int *tm,
-                                       double *tcy)
+// Read a node record through the constant address space: the address is the
+// same for the whole wavefront, so this compiles to scalar loads into SGPRs.
+template <typename T>
+__device__ inline T const_load(const T *p)
 {
-    const Node *src = node_recs(t, trec);
-    for (int i = threadIdx.x; i < nodes; i += NT) {
-        trec[i] = src[i];
-        tm[i] = t.m[i];
-        tcy[i] = t.cy[i];
-    }
-    __syncthreads();
+    return *(const __attribute__((address_space(4))) T *)(p);
 }
-
-template <typename Node>
-__host__ __device__ constexpr size_t node_lds_bytes(int nodes)
+__device__ inline NodeRec load_node(const NodeRec *p)
 {
-    return (size_t)nodes * (sizeof(Node) + sizeof(double)) + (size_t)((nodes + 1) & ~1) * sizeof(int);
+    NodeRec r;
+    r.B = const_load(&p->B);
+    r.C = const_load(&p->C);
+    r.D = const_load(&p->D);
+    r.cfy = const_load(&p->cfy);
+    r.cfz = const_load(&p->cfz);
+    r.cz = const_load(&p->cz);
+    r.cy = const_load(&p->cy);
+    r.pad = 0.0;
+    return r;
+}
+__device__ inline NodeRec32 load_node(const NodeRec32 *p)
+{
+    NodeRec32 r;
+    r.B = const_load(&p->B);
+    r.C = const_load(&p->C);
+    r.D = const_load(&p->D);
+    r.cfy = const_load(&p->cfy);
+    r.cfz = const_load(&p->cfz);
+    r.czf = const_load(&p->czf);
+    r.cyf = const_load(&p->cyf);
+    r.pad = 0.0f;
+    r.cz = const_load(&p->cz);
+    r.cy = const_load(&p->cy);
+    return r;
 }
 
 // Accumulators of P points: Y (constant of the y equation) and Z (= z^n) in
@@ -484,7 +503,7 @@ struct Acc {
 // the expectation of y itself (the layer j = K_y).
 // ---------------------------------------------------------------------------
 template <int P, int DRV, bool LASTY>
-__device__ inline void node_accumulate(const double2 (&r)[2][P + 1], const NodeRec &c, double cy,
+__device__ inline void node_accumulate(const double2 (&r)[2][P + 1], const NodeRec &c,
                                        const Driver<DRV, double> &f, Acc<P> &acc)
 {
 #pragma unroll
@@ -496,7 +515,7 @@ __device__ inline void node_accumulate(const double2 (&r)[2][P + 1], const NodeR
                               fma(c.C, rz[q].y, fma(c.D, rz[q + 1].y, rz[q].x)));
         const double fh = f(yh, zh);
         double y = fma(c.cfy, fh, acc.Y[q]);
-        if (LASTY) y = fma(cy, yh, y);
+        if (LASTY) y = fma(c.cy, yh, y);
         acc.Y[q] = y;
         acc.Z[q] = fma(c.cfz, fh, fma(c.cz, zh, acc.Z[q]));
     }
@@ -513,7 +532,7 @@ __device__ inline void node_accumulate(const double2 (&r)[2][P + 1], const NodeR
 // single precision.  f-hat itself is evaluated in single precision at
 // v0 + d.
 template <int P, int DRV, bool LASTY>
-__device__ inline void node_accumulate(const float4 (&r)[1][P + 1], const NodeRec32 &c, double cy,
+__device__ inline void node_accumulate(const float4 (&r)[1][P + 1], const NodeRec32 &c,
                                        const Driver<DRV, float> &f, Acc<P> &acc)
 {
 #pragma unroll
@@ -526,38 +545,52 @@ __device__ inline void node_accumulate(const float4 (&r)[1][P + 1], const NodeRe
         acc.Zf[q] = fmaf(c.cfz, fh, fmaf(c.czf, dz, acc.Zf[q]));
         acc.Z[q] = fma(c.cz, (double)r0.z, acc.Z[q]);
         if (LASTY) {
-            acc.Yf[q] = fmaf((float)cy, dy, acc.Yf[q]);
-            acc.Y[q] = fma(cy, (double)r0.x, acc.Y[q]);
+            acc.Yf[q] = fmaf(c.cyf, dy, acc.Yf[q]);
+            acc.Y[q] = fma(c.cy, (double)r0.x, acc.Y[q]);
         }
     }
 }
 
 // Nodes l = l0, l0 + LS, l0 + 2 LS, ... < L of one layer, reading P+1
-// consecutive records per lane from src at node offset m.
-// The node offsets of a layer are held one per lane (L <= 64) and moved to
-// a scalar register per node with readlane, so the records of a node are
-// addressed without waiting for an LDS read; the coefficients are read from
-// LDS together with the records.
+// consecutive records per lane from src at node offset m.  The node offsets
+// of a layer are held one per lane (L <= 64) and moved to a scalar register
+// per node with readlane, and the coefficient records come through scalar
+// loads, so the only per-node LDS traffic is the records themselves.
 template <int P, int DRV, bool LASTY, bool F32, typename Src>
-__device__ inline void layer_nodes(const Src &src, const typename Prec<F32>::Node *trec,
-                                   const int *tm, const double *tcy, int row, int l0, int LS,
-                                   int L, const Driver<DRV, typename Prec<F32>::Raw> &f,
-                                   Acc<P> &acc)
+__device__ inline void layer_nodes(const Src &src, const typename Prec<F32>::Node *nodes,
+                                   const int *m, int l0, int LS, int L,
+                                   const Driver<DRV, typename Prec<F32>::Raw> &f, Acc<P> &acc)
+// m: the layer's node offsets in LDS (a vector-memory load here would make
+// every node wait for the outstanding prefetch of the next window)
 {
     using V = typename Prec<F32>::V;
+    using Node = typename Prec<F32>::Node;
     constexpr int NA = Prec<F32>::NA;
     if (F32) {
 #pragma unroll
         for (int q = 0; q < P; ++q) acc.Yf[q] = acc.Zf[q] = 0.0f;
     }
-    const int lane = threadIdx.x & 63;
-    const int mv = tm[row + min(lane, L - 1)];
+    if (l0 < L) {
+        const int lane = threadIdx.x & 63;
+        const int mv = m[min(lane, L - 1)];
+        int l = l0;
+        // two nodes per iteration: their scalar and LDS loads are in flight
+        // together, so one wait covers both
 #pragma unroll 1
-    for (int l = l0; l < L; l += LS) {
-        const int m = __builtin_amdgcn_readlane(mv, l);
-        V r[NA][P + 1];
-        src.template fetch<P>(m, r);
-        node_accumulate<P, DRV, LASTY>(r, trec[row + l], LASTY ? tcy[row + l] : 0.0, f, acc);
+        for (; l + LS < L; l += 2 * LS) {
+            const Node c0 = load_node(nodes + l), c1 = load_node(nodes + l + LS);
+            V r0[NA][P + 1], r1[NA][P + 1];
+            src.template fetch<P>(__builtin_amdgcn_readlane(mv, l), r0);
+            src.template fetch<P>(__builtin_amdgcn_readlane(mv, l + LS), r1);
+            node_accumulate<P, DRV, LASTY>(r0, c0, f, acc);
+            node_accumulate<P, DRV, LASTY>(r1, c1, f, acc);
+        }
+        if (l < L) {
+            const Node c0 = load_node(nodes + l);
+            V r0[NA][P + 1];
+            src.template fetch<P>(__builtin_amdgcn_readlane(mv, l), r0);
+            node_accumulate<P, DRV, LASTY>(r0, c0, f, acc);
+        }
     }
     if (F32) {
 #pragma unroll

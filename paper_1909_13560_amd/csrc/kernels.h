@@ -30,7 +30,6 @@ struct GatherChunk {
 
 bool fused_supported(int P, int G);
 bool direct_p_supported(int P);
-size_t node_table_lds(int nodes, bool f32);
 size_t fused_window_lds(int P, bool f32);  // window + PCR arrays
 
 hipError_t launch_sweep_fused(int P, int G, bool f32, int driver, const StepArgs &a, int blocks,

@@ -94,16 +94,17 @@ struct GlobalWindow {
 };
 
 template <int P, int DRV, bool F32, typename Src>
-__device__ inline void layer_dispatch(const Src &src, const typename Prec<F32>::Node *trec,
-                                      const int *tm, const double *tcy, int j, int l0, int LS,
+__device__ inline void layer_dispatch(const Src &src, const int *tm, int j, int l0, int LS,
                                       const SweepArgs &a, Acc<P> &acc)
 {
+    using Node = typename Prec<F32>::Node;
     const Driver<DRV, typename Prec<F32>::Raw> f(a.drv, (a.n + j) * a.dt);
     const int row = (j - 1) * a.L;
+    const Node *nodes = node_recs(a.tab, static_cast<Node *>(nullptr)) + row;
     if (j == a.Ky)
-        layer_nodes<P, DRV, true, F32>(src, trec, tm, tcy, row, l0, LS, a.L, f, acc);
+        layer_nodes<P, DRV, true, F32>(src, nodes, tm + row, l0, LS, a.L, f, acc);
     else
-        layer_nodes<P, DRV, false, F32>(src, trec, tm, tcy, row, l0, LS, a.L, f, acc);
+        layer_nodes<P, DRV, false, F32>(src, nodes, tm + row, l0, LS, a.L, f, acc);
 }
 
 template <bool F32>
@@ -127,15 +128,14 @@ __host__ __device__ constexpr size_t window_lds_bytes(int P)
 // A block of G*kBlock threads owns a tile of kBlock*P points; thread group g
 // (kBlock threads) takes the nodes l = g, g+G, ... of every layer, and the G
 // partial sums meet in LDS before group 0 finishes the points.
-// Dynamic LDS: the window arrays, the four PCR arrays (pcr_values(P) doubles
-// each), the node table (K*L node records, K*L int, K*L double).
+// Dynamic LDS: the window arrays, the four PCR arrays (pcr_values(P)
+// doubles each) and the node offsets (K*L int).
 // ---------------------------------------------------------------------------
 template <int P, int G, int DRV, bool F32>
 __device__ inline void fused_tile(const SweepArgs &a, int tile, char *smem)
 {
     using PR = Prec<F32>;
     using Rec = typename PR::Rec;
-    using Node = typename PR::Node;
     using V = typename PR::V;
     constexpr int T = kBlock * P;
     constexpr int NT = kBlock * G;
@@ -143,9 +143,7 @@ __device__ inline void fused_tile(const SweepArgs &a, int tile, char *smem)
     V *wbase = reinterpret_cast<V *>(smem);
     const typename PR::template Win<P> win{wbase};
     double *R = reinterpret_cast<double *>(smem + window_lds_bytes<F32>(P));
-    Node *trec = reinterpret_cast<Node *>(R + 4 * CAP1);
-    int *tm = reinterpret_cast<int *>(trec + a.K * a.L);
-    double *tcy = reinterpret_cast<double *>(tm + ((a.K * a.L + 1) & ~1));
+    int *tm = reinterpret_cast<int *>(R + 4 * CAP1);
 
     const int tid = threadIdx.x;
     // kBlock is a multiple of the wavefront size: the group is wave-uniform
@@ -154,7 +152,7 @@ __device__ inline void fused_tile(const SweepArgs &a, int tile, char *smem)
     const int t0 = tile * T;
     const int S = a.K + 1;
     Rec *ring = ring_of<F32>(a);
-    load_node_table<NT>(a.tab, a.K * a.L, trec, tm, tcy);
+    for (int i = tid; i < a.K * a.L; i += NT) tm[i] = a.tab.m[i];
 
     Acc<P> acc;
 #pragma unroll
@@ -222,7 +220,7 @@ __device__ inline void fused_tile(const SweepArgs &a, int tile, char *smem)
         }
         const LdsWindow<P, F32> src{wbase, kHalo - mlo,
                                     WinLayout<P>::kPad ? lane_pt + lane_pt / P : lane_pt};
-        layer_dispatch<P, DRV, F32>(src, trec, tm, tcy, j, grp, G, a, acc);
+        layer_dispatch<P, DRV, F32>(src, tm, j, grp, G, a, acc);
         __syncthreads();  // the window is reused by the next layer
     }
     if (G > 1) {  // partial sums of groups 1..G-1 meet group 0 in LDS, in group order
@@ -264,26 +262,23 @@ __global__ void __launch_bounds__(kBlock * G) sweep_fused(const StepArgs s)
 template <int P, int DRV, bool F32>
 __global__ void __launch_bounds__(kBlock) sweep_direct(const StepArgs s)
 {
-    using Node = typename Prec<F32>::Node;
-    extern __shared__ double2 smem_direct[];
     const int idx = xcd_tile(blockIdx.x, gridDim.x);
     const InstDesc &d = s.desc[s.tile_inst[idx]];
     const SweepArgs a = bind_instance(d, s.ws, s.s, s.stats != 0);
     const int tile = idx - d.tile_base;
-    Node *trec = reinterpret_cast<Node *>(smem_direct);
-    int *tm = reinterpret_cast<int *>(trec + a.K * a.L);
-    double *tcy = reinterpret_cast<double *>(tm + ((a.K * a.L + 1) & ~1));
+    __shared__ int tm[kMaxNodes];
+    for (int i = threadIdx.x; i < a.K * a.L; i += kBlock) tm[i] = a.tab.m[i];
+    __syncthreads();
     const int first = (tile * kBlock + (int)threadIdx.x) * P;
     const int i0 = min(first, a.nx - 1);  // lanes past the end read in bounds, store nothing
     const int S = a.K + 1;
-    load_node_table<kBlock>(a.tab, a.K * a.L, trec, tm, tcy);
     Acc<P> acc;
 #pragma unroll
     for (int q = 0; q < P; ++q) acc.Y[q] = acc.Z[q] = 0.0;
     const auto *ring = ring_of<F32>(a);
     for (int j = 1; j <= a.K; ++j) {
         const GlobalWindow<F32> src{ring + (size_t)((a.n + j) % S) * a.npad + a.pad_l + i0};
-        layer_dispatch<P, DRV, F32>(src, trec, tm, tcy, j, 0, 1, a, acc);
+        layer_dispatch<P, DRV, F32>(src, tm, j, 0, 1, a, acc);
     }
     finish_points<P, DRV, F32>(a, first, acc, (tile * kBlock + (int)threadIdx.x) >> 6);
 }
@@ -500,11 +495,6 @@ hipError_t direct_by_driver(int driver, const StepArgs &a, int blocks, size_t ld
 
 bool fused_supported(int P, int G) { return (P == 1 || P == 2 || P == 4) && (G == 1 || G == 2); }
 bool direct_p_supported(int P) { return P == 1 || P == 2 || P == 4; }
-
-size_t node_table_lds(int nodes, bool f32)
-{
-    return f32 ? node_lds_bytes<NodeRec32>(nodes) : node_lds_bytes<NodeRec>(nodes);
-}
 
 size_t fused_window_lds(int P, bool f32)
 {
