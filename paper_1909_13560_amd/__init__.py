@@ -164,8 +164,10 @@ class Plan:
         self.problems = problems
 
     def __del__(self):
-        if getattr(self, "handle", None):
-            load().bsde_plan_destroy(ctypes.c_void_p(self.handle))
+        # at interpreter exit the module globals may already be gone
+        lib = _lib
+        if getattr(self, "handle", None) and lib is not None and ctypes is not None:
+            lib.bsde_plan_destroy(ctypes.c_void_p(self.handle))
             self.handle = None
 
 
