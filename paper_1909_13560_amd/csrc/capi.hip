@@ -91,6 +91,7 @@ struct Group {
 struct Instance2 {
     bsde_problem pb;
     int K, n0, n1, pad0, pad0r, pad1, pad1r, npad0, npad1;
+    int win;  // LDS window columns of the sweep kernel
     size_t plane;
     double dx0, dx1, dt, h0, R;
     std::vector<bsde::Node2Row> rows;
@@ -288,6 +289,7 @@ bsde_status build_instance2(const bsde_problem &p, Instance2 &in)
     in.nodes.assign((size_t)K * L * L, bsde::Node2{});
     in.m1.assign((size_t)K * L * L, 0);
     int m0min = 0, m0max = 0, m1min = 0, m1max = 0;
+    in.win = 0;
     const double d0 = in.dx0 * in.dx0 / 6.0, d1 = in.dx1 * in.dx1 / 6.0;
     for (int j = 1; j <= K; ++j) {
         const double sq = std::sqrt(2.0 * j * in.dt);
@@ -328,6 +330,7 @@ bsde_status build_instance2(const bsde_problem &p, Instance2 &in)
             row.m1lo = lo;
             row.m1hi = hi;
             if (bsde::kTile2C + hi - lo + 2 > bsde::kWin2) return BSDE_EUNSUPPORTED;
+            in.win = std::max(in.win, bsde::kTile2C + hi - lo + 2);
             m0min = std::min(m0min, row.m0);
             m0max = std::max(m0max, row.m0);
             m1min = std::min(m1min, lo);
@@ -363,6 +366,7 @@ bsde::Sweep2Args sweep2_args(const Instance2 &in, char *ws, bool stats)
     a.Ky = in.pb.k_y;
     a.L = in.pb.L;
     a.n_stop = in.pb.n_stop;
+    a.win = in.win;
     a.rows = in.d_rows;
     a.nodes = in.d_nodes;
     a.m1 = in.d_m1;

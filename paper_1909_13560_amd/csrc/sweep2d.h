@@ -20,7 +20,7 @@ namespace bsde {
 constexpr int kTile2R = 4;    // tile rows (axis 0): one wavefront each
 constexpr int kTile2C = 64;   // tile columns (axis 1): one lane each
 constexpr int kMaxReach2d = 240;  // widest axis-1 node spread of one axis-0 node row
-constexpr int kWin2 = kTile2C + kMaxReach2d + 2;
+constexpr int kWin2 = kTile2C + kMaxReach2d + 2;  // widest LDS window (59 KB of (U, V))
 constexpr int kPcrTaps = 2 * (1 + 2 + 4 + 8 + 16) + 1;  // 63: reach of the truncated PCR
 
 // Per (j, l0): the axis-0 offset of the node row and its spline weights, and
@@ -51,6 +51,7 @@ struct Sweep2Args {
     size_t plane;
     int n0, n1, npad1, pad0, pad1;
     int K, Ky, L, n, n_stop;
+    int win;                // LDS window columns: 64 + widest m1 spread of a row + 2
     const Node2Row *rows;   // K*L
     const Node2 *nodes;     // K*L*L
     const int *m1;          // K*L*L
@@ -63,6 +64,7 @@ struct Sweep2Args {
     unsigned long long *st_iter_sum, *st_nonconv;
 };
 
+size_t sweep2d_lds(int win);  // dynamic LDS of the sweep kernel
 hipError_t launch_sweep2d(const Sweep2Args &a, hipStream_t s);
 // splines and ghosts of the layer in slot `slot`
 hipError_t launch_spline2d(const Sweep2Args &a, int slot, const SplineFilter &f, hipStream_t s);

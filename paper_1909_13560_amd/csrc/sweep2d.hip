@@ -27,11 +27,18 @@ __device__ inline size_t pidx(const Sweep2Args &a, int i0, int i1)
     return (size_t)(i0 + a.pad0) * a.npad1 + (size_t)(i1 + a.pad1);
 }
 
+// (U, V) of function f, tile row rr, window column cc in the LDS window of
+// width a.win (dynamic: the widest axis-1 node spread of the plan).
+__device__ inline int uv_index(const Sweep2Args &a, int f, int rr, int cc)
+{
+    return (f * kTile2R + rr) * a.win + cc;
+}
+
 // The L nodes l1 of one axis-0 row of layer j, for the lane's point.
 template <bool LASTY>
-__device__ inline void row_nodes(const Sweep2Args &a, const double2 (*uv)[kTile2R][kWin2],
-                                 const Node2 *ntab, const int *nm1, int r, int c, int m1lo,
-                                 double &Y, double &Z1, double &Z2)
+__device__ inline void row_nodes(const Sweep2Args &a, const double2 *uv, const Node2 *ntab,
+                                 const int *nm1, int r, int c, int m1lo, double &Y, double &Z1,
+                                 double &Z2)
 {
 #pragma unroll 1
     for (int l1 = 0; l1 < a.L; ++l1) {
@@ -40,7 +47,7 @@ __device__ inline void row_nodes(const Sweep2Args &a, const double2 (*uv)[kTile2
         double h[3];
 #pragma unroll
         for (int f = 0; f < 3; ++f) {
-            const double2 p0 = uv[f][r][e], p1 = uv[f][r][e + 1];
+            const double2 p0 = uv[uv_index(a, f, r, e)], p1 = uv[uv_index(a, f, r, e + 1)];
             h[f] = fma(nd.B1, p1.x - p0.x, fma(nd.C1, p0.y, fma(nd.D1, p1.y, p0.x)));
         }
         const double fh = f_linear2(a.drv, h[0], h[1], h[2]);
@@ -54,9 +61,10 @@ __device__ inline void row_nodes(const Sweep2Args &a, const double2 (*uv)[kTile2
 }  // namespace
 
 // One time step: layer n from layers n+1..n+K.  Block = 4 x 64 points.
+// Dynamic LDS: (U, V) of 3 functions x 4 rows x a.win columns.
 __global__ void __launch_bounds__(256) sweep2d(const Sweep2Args a)
 {
-    __shared__ double2 uv[3][kTile2R][kWin2];
+    extern __shared__ double2 uv[];
     __shared__ Node2 ntab[64];
     __shared__ int nm1[64];
     const int tiles1 = (a.n1 + kTile2C - 1) / kTile2C;
@@ -88,7 +96,7 @@ __global__ void __launch_bounds__(256) sweep2d(const Sweep2Args a)
                     const double U = fma(row.B0, v[o1] - v[o], fma(row.C0, mxx[o], fma(row.D0, mxx[o1], v[o])));
                     const double V =
                         fma(row.B0, myy[o1] - myy[o], fma(row.C0, mxy[o], fma(row.D0, mxy[o1], myy[o])));
-                    uv[f][rr][cc] = make_double2(U, V);
+                    uv[uv_index(a, f, rr, cc)] = make_double2(U, V);
                 }
             }
             __syncthreads();
@@ -278,10 +286,12 @@ __global__ void __launch_bounds__(256) gather2d(const Sweep2Args a, double *__re
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
+size_t sweep2d_lds(int win) { return (size_t)3 * kTile2R * win * sizeof(double2); }
+
 hipError_t launch_sweep2d(const Sweep2Args &a, hipStream_t s)
 {
     const int tiles = ((a.n0 + kTile2R - 1) / kTile2R) * ((a.n1 + kTile2C - 1) / kTile2C);
-    hipLaunchKernelGGL(sweep2d, dim3(tiles), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(sweep2d, dim3(tiles), dim3(256), sweep2d_lds(a.win), s, a);
     return hipGetLastError();
 }
 
