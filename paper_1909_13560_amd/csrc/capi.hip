@@ -154,6 +154,7 @@ namespace {
 bool valid_problem(const bsde_problem &p)
 {
     if (p.d != 1 && p.d != 2) return false;
+    static_assert(bsde::kMaxK <= bsde::kMaxOrder, "descriptor window arrays hold K + 1 entries");
     if (p.k_y < 1 || p.k_y > bsde::kMaxK || p.k_z < 1 || p.k_z > bsde::kMaxK) return false;
     const int K = std::max(p.k_y, p.k_z);
     if (p.n_t < K || !(p.T > 0.0) || !std::isfinite(p.T)) return false;
@@ -515,8 +516,13 @@ bsde::StepArgs step_args(const bsde_plan_s &pl, const Group &g, char *ws, int s,
 {
     bsde::StepArgs a;
     a.ws = ws;
-    a.desc = pl.d_desc;
-    a.tile_inst = spline_map ? g.d_spline_inst : g.d_tile_inst;
+    if (g.members.size() == 1) {  // no tile map: every block is of this instance
+        a.desc = pl.d_desc + g.members[0];
+        a.tile_inst = nullptr;
+    } else {
+        a.desc = pl.d_desc;
+        a.tile_inst = spline_map ? g.d_spline_inst : g.d_tile_inst;
+    }
     a.s = s;
     a.stats = stats ? 1 : 0;
     return a;
@@ -1031,8 +1037,8 @@ bsde_status bsde_plan(const bsde_problem *pb, int batch, bsde_plan_t *out)
         });
         g.max_steps = pl->inst[g.members[0]].steps;
     }
-    // device tables: per instance node records (both forms), offsets, y
-    // weights, windows; the descriptors; per group the tile maps
+    // device tables: per instance node records (both forms) and offsets; the
+    // descriptors (with the window bounds); per group the tile maps
     size_t tbytes = 0;
     std::vector<size_t> toff(batch);
     for (int b = 0; b < batch; ++b) {
@@ -1040,7 +1046,7 @@ bsde_status bsde_plan(const bsde_problem *pb, int batch, bsde_plan_t *out)
         toff[b] = tbytes;
         const size_t kl = (size_t)in.K * in.pb.L;
         tbytes += align_up(kl * sizeof(int), 256) + align_up(kl * sizeof(bsde::NodeRec), 256) +
-                  align_up(kl * sizeof(bsde::NodeRec32), 256) + 2 * align_up((in.K + 1) * sizeof(int), 256);
+                  align_up(kl * sizeof(bsde::NodeRec32), 256);
     }
     const size_t desc_off = tbytes;
     tbytes += align_up((size_t)batch * sizeof(bsde::InstDesc), 256);
@@ -1086,8 +1092,6 @@ bsde_status bsde_plan(const bsde_problem *pb, int batch, bsde_plan_t *out)
         in.dtab.rec32 =
             static_cast<const bsde::NodeRec32 *>(put(recs32.data(), kl * sizeof(bsde::NodeRec32)));
         in.dtab.m = static_cast<const int *>(put(in.m.data(), kl * sizeof(int)));
-        in.dtab.win_lo = static_cast<const int *>(put(in.win_lo.data(), (in.K + 1) * sizeof(int)));
-        in.dtab.win_hi = static_cast<const int *>(put(in.win_hi.data(), (in.K + 1) * sizeof(int)));
     }
     if (hipMemcpy(pl->d_tables, host.data(), desc_off, hipMemcpyHostToDevice) != hipSuccess) {
         bsde_plan_destroy(pl);
@@ -1151,6 +1155,10 @@ bsde_status bsde_plan(const bsde_problem *pb, int batch, bsde_plan_t *out)
         d.nwaves = in.nwaves;
         d.n0 = in.pb.n_t - in.K;
         d.f32 = in.f32 ? 1 : 0;
+        for (int j = 0; j <= in.K; ++j) {
+            d.win_lo[j] = in.win_lo[j];
+            d.win_hi[j] = in.win_hi[j];
+        }
     }
     for (Group &g : pl->groups) {
         bsde_status rc = apply_config(*pl, g, default_config(pl->inst, g, pl->max_lds));

@@ -65,6 +65,8 @@ struct NodeTable {
     const int *win_hi;  // [K+1]: highest node offset of layer j (j = 1 also >= 0)
 };
 
+constexpr int kMaxOrder = 6;  // largest K of Tables 1-2
+
 constexpr int kMaxNodes = 6 * 64;      // K * L at most
 constexpr int kMaxReach1 = 160;        // widest node reach of layer n+1 in the fused kernel
 constexpr int kMaxReach2 = 320;        // widest node reach of layers n+2.. in the fused kernel
@@ -150,12 +152,15 @@ struct InstDesc {
     int tile_base;        // first tile of the instance in its group's sweep grid
     int spline_base;      // first tile of the instance in its group's spline grid
     int spline_tiles;     // tiles of the standalone spline kernel
+    // window bounds of the layers (NodeTable::win_lo/win_hi point here once
+    // bound, so they load together with the descriptor)
+    int win_lo[kMaxOrder + 1], win_hi[kMaxOrder + 1];
 };
 
 struct StepArgs {
     char *ws;
     const InstDesc *desc;
-    const int *tile_inst;  // grid tile -> descriptor index
+    const int *tile_inst;  // grid tile -> descriptor index; NULL: every tile is of desc[0]
     int s;                 // step: each instance computes layer n0 - s
     int stats;             // bind the statistics slots
 };
@@ -229,6 +234,8 @@ __device__ inline int xcd_tile(int b, int nb)
 __device__ inline SweepArgs bind_instance(const InstDesc &d, char *ws, int s, bool stats)
 {
     SweepArgs a = d.a;
+    a.tab.win_lo = d.win_lo;
+    a.tab.win_hi = d.win_hi;
     a.n = d.n0 - s;
     a.ring = reinterpret_cast<Rec64 *>(ws + d.ring_off);
     a.ring32 = reinterpret_cast<Rec32 *>(ws + d.ring_off);
@@ -245,6 +252,14 @@ __device__ inline SweepArgs bind_instance(const InstDesc &d, char *ws, int s, bo
         a.st_iter_max = nullptr;
     }
     return a;
+}
+
+// The descriptor of block idx of a step launch.  A group of one instance
+// launches without a tile map, so its blocks start with a single dependent
+// load (the descriptor) before the first ring read.
+__device__ inline const InstDesc &block_desc(const StepArgs &s, int idx)
+{
+    return s.tile_inst ? s.desc[s.tile_inst[idx]] : s.desc[0];
 }
 
 // ---------------------------------------------------------------------------

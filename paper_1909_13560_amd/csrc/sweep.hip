@@ -250,7 +250,7 @@ __global__ void __launch_bounds__(kBlock * G) sweep_fused(const StepArgs s)
 {
     extern __shared__ double2 smem_fused[];
     const int idx = xcd_tile(blockIdx.x, gridDim.x);
-    const InstDesc &d = s.desc[s.tile_inst[idx]];
+    const InstDesc &d = block_desc(s, idx);
     const SweepArgs a = bind_instance(d, s.ws, s.s, s.stats != 0);
     fused_tile<P, G, DRV, F32>(a, idx - d.tile_base, reinterpret_cast<char *>(smem_fused));
 }
@@ -263,7 +263,7 @@ template <int P, int DRV, bool F32>
 __global__ void __launch_bounds__(kBlock) sweep_direct(const StepArgs s)
 {
     const int idx = xcd_tile(blockIdx.x, gridDim.x);
-    const InstDesc &d = s.desc[s.tile_inst[idx]];
+    const InstDesc &d = block_desc(s, idx);
     const SweepArgs a = bind_instance(d, s.ws, s.s, s.stats != 0);
     const int tile = idx - d.tile_base;
     __shared__ int tm[kMaxNodes];
@@ -298,7 +298,7 @@ __global__ void __launch_bounds__(kBlock) spline_layer(const StepArgs s, int mod
     __shared__ V wsm[window_lds_bytes<F32>(1) / sizeof(V)];
     __shared__ double R[4 * WS];
     const int idx = xcd_tile(blockIdx.x, gridDim.x);
-    const InstDesc &d = s.desc[s.tile_inst[idx]];
+    const InstDesc &d = block_desc(s, idx);
     const SweepArgs a = bind_instance(d, s.ws, 0, false);
     const int tile = idx - d.spline_base;
     const int n = mode == 0 ? d.n0 + 1 + s.s : d.n0 - s.s;

@@ -228,6 +228,49 @@ def test_graph_replays_match_direct_launches(lib, monkeypatch):
         assert torch.equal(yd, ref_y) and torch.equal(zd, ref_z), rep
 
 
+def test_graph_cache_eviction_keeps_results(lib):
+    # a plan keeps the captured solves of its four most recently used buffer
+    # sets; cycling through six sets evicts and recaptures on every call, and
+    # each solve must still equal the first one bit for bit
+    import torch
+
+    wl = W.bidask_call_1d(n_x=2500, n_t=14, half_width=None)
+    iy, iz = wl.init_layers()
+    n = iy.shape[1]
+    plan = lib.bsde_plan(wl.problem)
+    sets = []
+    for _ in range(6):
+        sets.append((lib.workspace(plan), torch.as_tensor(iy, device="cuda").contiguous(),
+                     torch.as_tensor(iz.reshape(iy.shape), device="cuda").contiguous(),
+                     torch.empty(n, dtype=torch.float64, device="cuda"),
+                     torch.empty(n, dtype=torch.float64, device="cuda")))
+    ref = None
+    for rep in range(2):
+        for k, (ws, a, b, y, z) in enumerate(sets):
+            y.fill_(float("nan"))
+            z.fill_(float("nan"))
+            lib.bsde_solve(plan, ws, a, b, y, z)
+            torch.cuda.synchronize()
+            if ref is None:
+                ref = (y.clone(), z.clone())
+            assert torch.equal(y, ref[0]) and torch.equal(z, ref[1]), (rep, k)
+
+
+def test_single_solve_rejects_batched_plan(lib):
+    import torch
+
+    wls = [W.sine_1d(n_x=300, n_t=8), W.sine_1d(n_x=400, n_t=8)]
+    plan = lib.bsde_plan([w.problem for w in wls])
+    ws = lib.workspace(plan)
+    iy, iz = wls[0].init_layers()
+    t_iy = torch.as_tensor(iy, device="cuda").contiguous()
+    t_iz = torch.as_tensor(iz.reshape(iy.shape), device="cuda").contiguous()
+    y0 = torch.empty(iy.shape[1], dtype=torch.float64, device="cuda")
+    z0 = torch.empty_like(y0)
+    rc, _ = lib.bsde_solve(plan, ws, t_iy, t_iz, y0, z0, check=False)
+    assert rc == lib.BSDE_EINVAL
+
+
 # ----------------------------------------------------------------------------
 # FP32 form
 # ----------------------------------------------------------------------------
@@ -391,6 +434,31 @@ def test_2d_basket_checkpoint(lib, orc):
     wl = W.basket_2d(n_x=65, n_t=12, k=3, L=16)
     y, z, yo, zo, *_ = run_both(lib, orc, wl, n_stop=4)
     assert rel_err(z[1], zo[1]) <= TOL64
+
+
+def test_2d_autotune_reports_single_shape(lib, orc):
+    # a two-dimensional plan has one kernel shape: autotune reports it and the
+    # solve afterwards is unchanged
+    import torch
+
+    wl = W.exchange_2d(n_x=49, n_t=6, k=3, L=6, rho=0.5)
+    iy, iz = wl.init_layers()
+    n = iy.shape[1]
+    plan = lib.bsde_plan(wl.problem)
+    ws = lib.workspace(plan)
+    io = (torch.as_tensor(iy, device="cuda").contiguous(),
+          torch.as_tensor(iz.reshape(iy.shape[0], -1), device="cuda").contiguous(),
+          torch.empty(n, dtype=torch.float64, device="cuda"),
+          torch.empty(2 * n, dtype=torch.float64, device="cuda"))
+    rep = lib.bsde_autotune(plan, ws, [io], reps=2)
+    assert rep["path"] == 2 and rep["candidates"] == 0
+    rc, _ = lib.bsde_solve_batched(plan, ws, [io])
+    torch.cuda.synchronize()
+    assert rc == lib.BSDE_OK
+    yo, zo, _ = orc.solve(wl.problem, iy, iz)
+    zz = io[3].cpu().numpy().reshape(2, n)
+    assert rel_err(io[2].cpu().numpy(), yo) <= TOL64
+    assert max(rel_err(zz[0], zo[0]), rel_err(zz[1], zo[1])) <= TOL64
 
 
 def test_2d_picard_tolerance_and_batch(lib, orc):
