@@ -302,6 +302,10 @@ def main() -> int:
         ws = B.workspace(plan, dev)
         y0 = torch.empty(nx, dtype=torch.float64, device=dev)
         z0 = torch.empty(nx, dtype=torch.float64, device=dev)
+        # the library's own kernel-shape choice for this plan, made once (like
+        # the plan itself) before anything is timed
+        tune = B.bsde_autotune(plan, ws, [(t_iy, t_iz, y0, z0)], stream=stream, reps=20)
+        print(f"[bench] {prec}: autotune {tune}", file=sys.stderr, flush=True)
         # one checked solve: status and Picard statistics
         rc, st = B.bsde_solve(plan, ws, t_iy, t_iz, y0, z0, stream=stream, stats=True)
         print(f"[bench] workload {wl.name} {prec} status {B.bsde_status_string(rc)} stats {st}",

@@ -115,6 +115,41 @@ struct PcrCoef {
     double inv_b;                // 1 / diagonal after the last round
 };
 
+// The same five rounds as two filters, for windows clear of the domain ends
+// (constants of the (1, 4, 1) system, evaluated at compile time): rounds 1-3
+// with the second difference folded in, taps fa[|q|] on the values at offsets
+// q = -8..8; rounds 4-5, taps fb[|q|] at offsets 8q, q = -3..3 (with
+// t = s - k4 (s_{-8} + s_8) and u = t - k5 (t_{-16} + t_{16})).
+struct PcrFilters {
+    double fa[9];
+    double fb[4];
+};
+__host__ __device__ constexpr PcrFilters pcr_filters()
+{
+    PcrFilters r{};
+    double kap[kPcrRounds] = {};
+    double av = 1.0, bv = 4.0;
+    for (int k = 0; k < kPcrRounds; ++k) {  // a' = -a^2/b, b' = b - 2a^2/b
+        kap[k] = av / bv;
+        bv = bv - 2.0 * kap[k] * av;
+        av = -kap[k] * av;
+    }
+    double f[17] = {}, g[17] = {};
+    f[8] = 1.0;
+    for (int k = 0, h = 1; k < 3; ++k, h *= 2) {
+        for (int i = 0; i < 17; ++i)
+            g[i] = f[i] - kap[k] * ((i - h >= 0 ? f[i - h] : 0.0) + (i + h < 17 ? f[i + h] : 0.0));
+        for (int i = 0; i < 17; ++i) f[i] = g[i];
+    }
+    for (int q = 0; q <= 8; ++q)
+        r.fa[q] = (q + 7 >= 0 ? f[q + 7] : 0.0) - 2.0 * f[q + 8] + (q + 9 < 17 ? f[q + 9] : 0.0);
+    r.fb[0] = 1.0;
+    r.fb[1] = kap[3] * kap[4] - kap[3];
+    r.fb[2] = -kap[4];
+    r.fb[3] = kap[3] * kap[4];
+    return r;
+}
+
 struct SweepArgs {
     Rec64 *ring;      // FP64 form
     Rec32 *ring32;    // FP32 form
@@ -375,11 +410,112 @@ __device__ inline void spline_load(const Rec *__restrict__ g, int nx, int lo, in
     }
 }
 
+// spline_window for a window clear of the domain ends (every staged record
+// is a grid record and every r~ the plain second difference): the five
+// rounds as two stencils, three barriers in all.  Pass A evaluates rounds
+// 1-3 on the values for the window and 24 cells either side (three outputs
+// per thread, so neighbouring outputs share their reads); pass B applies
+// rounds 4-5 (four outputs 8 apart per thread) and writes y, z, M to the
+// window.  Same linear map as the round-by-round form up to rounding.
+template <int NT, int U, int P, typename Win, typename V>
+__device__ inline void spline_window_interior(int W, const Win &win, double *R, int cap1,
+                                              const PcrCoef &c, const SplineRaw<U, V> &raw)
+{
+    const int tid = threadIdx.x;
+    const int WS = W + 2 * kHalo + 2;
+    // D[e]: staged (y, z) of record lo - kHalo - 1 + e; A[e]: pass-A output of
+    // window element e (record lo - kHalo + e)
+    double2 *D = reinterpret_cast<double2 *>(R);
+    double2 *A = reinterpret_cast<double2 *>(R + 2 * cap1);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int e = tid + u * NT;
+        if (e < WS) D[e] = make_double2(raw.y[u], raw.z[u]);
+    }
+    __syncthreads();
+    constexpr PcrFilters F = pcr_filters();
+    constexpr int kA = 3;                            // outputs per thread in pass A
+    const int a0 = kHalo - 24, a1 = kHalo + W + 24;  // pass-A outputs [a0, a1)
+    for (int t = tid; a0 + kA * t < a1; t += NT) {
+        const int e = a0 + kA * t;
+        // output e + o takes D[e + o + 1 + q] with weight fa[|q|], q = -8..8;
+        // the staged values stream through once
+        double vy[kA], vz[kA];
+#pragma unroll
+        for (int o = 0; o < kA; ++o) vy[o] = vz[o] = 0.0;
+#pragma unroll
+        for (int i = 0; i < kA + 16; ++i) {
+            // at most four reads in flight: hoisting all of them would raise
+            // the register count of the whole sweep kernel
+            if (i % 4 == 0) __builtin_amdgcn_sched_barrier(0);
+            const double2 x = D[e - 7 + i];
+#pragma unroll
+            for (int o = 0; o < kA; ++o) {
+                const int q = i - 8 - o;
+                if (q >= -8 && q <= 8) {
+                    const double w = F.fa[q < 0 ? -q : q];
+                    vy[o] = fma(w, x.x, vy[o]);
+                    vz[o] = fma(w, x.y, vz[o]);
+                }
+            }
+        }
+        // unguarded: A has room past a1 (cap1 >= W + 2 kHalo + 2), and pass B
+        // reads A below a1 only
+#pragma unroll
+        for (int o = 0; o < kA; ++o) A[e + o] = make_double2(vy[o], vz[o]);
+    }
+    __syncthreads();
+    const double sc = c.s6 * c.inv_b;
+    for (int t = tid;; t += NT) {
+        const int e = kHalo + (t & 7) + 32 * (t >> 3);  // outputs e, e+8, e+16, e+24
+        if (e >= kHalo + W) break;
+        // output e + 8o takes A[e + 8(o + q)] with weight fb[|q|], q = -3..3
+        double wy[4], wz[4];
+#pragma unroll
+        for (int o = 0; o < 4; ++o) wy[o] = wz[o] = 0.0;
+#pragma unroll
+        for (int i = 0; i < 10; ++i) {
+            if (i % 4 == 0) __builtin_amdgcn_sched_barrier(0);
+            const int k = e + 8 * (i - 3);
+            double2 x = A[min(k, a1 - 1)];
+            if (k >= a1) x = make_double2(0.0, 0.0);
+#pragma unroll
+            for (int o = 0; o < 4; ++o) {
+                const int q = i - 3 - o;
+                if (q >= -3 && q <= 3) {
+                    const double w = F.fb[q < 0 ? -q : q];
+                    wy[o] = fma(w, x.x, wy[o]);
+                    wz[o] = fma(w, x.y, wz[o]);
+                }
+            }
+        }
+        // unguarded: outputs up to kHalo + W + 24 stay inside the window
+        // arrays and the staged range, and nothing reads the window past
+        // kHalo + W
+#pragma unroll
+        for (int o = 0; o < 4; ++o) {
+            const int eo = e + 8 * o;
+            const double2 yz = D[eo + 1];
+            win.val(WinLayout<P>::slot(eo), yz.x, yz.y);
+            win.der(WinLayout<P>::slot(eo), wy[o] * sc, wz[o] * sc);
+        }
+    }
+    __syncthreads();
+}
+
 template <int NT, int U, int P, typename Rec, typename V, typename Win>
 __device__ inline void spline_window(const Rec *__restrict__ g, int nx, int lo, int W,
                                      const Win &win, double *R, int cap1, const PcrCoef &c,
                                      const SplineRaw<U, V> &raw)
 {
+    // the FP32 form keeps the round-by-round solve: the stencil passes' extra
+    // registers would cost it occupancy, which it has to spare otherwise
+    if constexpr (sizeof(V) == sizeof(double)) {
+        if (lo >= kHalo + 1 && lo + W <= nx - kHalo - 1) {
+            spline_window_interior<NT, U, P>(W, win, R, cap1, c, raw);
+            return;
+        }
+    }
     const int tid = threadIdx.x;
     const int WE = W + 2 * kHalo, WS = WE + 2;
     double *Ay = R, *Az = R + cap1, *By = R + 2 * cap1, *Bz = R + 3 * cap1;

@@ -152,17 +152,20 @@ __device__ inline void fused_tile(const SweepArgs &a, int tile, char *smem)
     const int t0 = tile * T;
     const int S = a.K + 1;
     Rec *ring = ring_of<F32>(a);
-    for (int i = tid; i < a.K * a.L; i += NT) tm[i] = a.tab.m[i];
 
     Acc<P> acc;
 #pragma unroll
     for (int q = 0; q < P; ++q) acc.Y[q] = acc.Z[q] = 0.0;
 
-    // Layers are processed in the order 2, 3, ..., K, 1: the records of layers
-    // n+2.. are complete (their splines were built by earlier launches) and
-    // their windows are prefetched into registers one layer ahead, while the
-    // raw values of layer n+1 (written by the previous launch) are loaded at
-    // the start and only turned into its spline after the other layers.
+    // Layers are processed in the order 2, 3, ..., K, 1, rotated per tile: the
+    // records of layers n+2.. are complete (their splines were built by
+    // earlier launches) and their windows are prefetched into registers one
+    // layer ahead, while the raw values of layer n+1 (written by the previous
+    // launch) are loaded at the start and turned into its spline at its turn.
+    // The rotation key (tile / 32) differs between the blocks that share a CU
+    // (tiles 32 apart under the XCD-aware numbering), so their spline and
+    // node phases fall at different times; it depends on the tile alone, so a
+    // tile computes the same in a batch as on its own.
     constexpr int kPre = (T + kMaxReach2 + NT - 1) / NT;
     constexpr int kRaw = pcr_slots(P, NT);
     Rec pre[kPre];
@@ -176,16 +179,31 @@ __device__ inline void fused_tile(const SweepArgs &a, int tile, char *smem)
             if (e < W) pre[u] = g[lo + e];
         }
     };
+    const int rot = ((tile >> 5) & 3) % a.K;
+    auto layer_at = [&](int jj) {  // the jj-th layer of this tile's order
+        const int q = (jj + rot) % a.K;
+        return q + 1 < a.K ? q + 2 : 1;
+    };
+    auto next_window = [&](int jj) {  // first layer after position jj other than n+1
+        for (int q = jj + 1; q < a.K; ++q)
+            if (layer_at(q) != 1) return layer_at(q);
+        return 0;
+    };
     SplineRaw<kRaw, typename PR::Raw> raw1;
     {
         const Rec *__restrict__ g1 = ring + (size_t)((a.n + 1) % S) * a.npad + a.pad_l;
         const int W1 = T + (a.tab.win_hi[1] - a.tab.win_lo[1]) + 1;
-        if (a.K >= 2) prefetch(2);
+        const int j0 = layer_at(0) != 1 ? layer_at(0) : next_window(0);
+        if (j0) prefetch(j0);
         spline_load<NT, kRaw>(g1, a.nx, t0 + a.tab.win_lo[1], W1, raw1);
     }
+    // node offsets into LDS only now: their stores wait for the loads, which
+    // must not hold back the issue of the window loads above (published by
+    // the first barrier)
+    for (int i = tid; i < a.K * a.L; i += NT) tm[i] = a.tab.m[i];
 
     for (int jj = 0; jj < a.K; ++jj) {
-        const int j = (jj + 1 < a.K) ? jj + 2 : 1;
+        const int j = layer_at(jj);
         Rec *__restrict__ g = ring + (size_t)((a.n + j) % S) * a.npad + a.pad_l;
         const int mlo = a.tab.win_lo[j], mhi = a.tab.win_hi[j];
         const int W = T + (mhi - mlo) + 1;
@@ -215,7 +233,8 @@ __device__ inline void fused_tile(const SweepArgs &a, int tile, char *smem)
                 const int e = tid + u * NT;
                 if (e < W) win.put(WinLayout<P>::slot(kHalo + e), pre[u]);
             }
-            if (j + 1 <= a.K) prefetch(j + 1);
+            const int jn = next_window(jj);
+            if (jn) prefetch(jn);
             __syncthreads();
         }
         const LdsWindow<P, F32> src{wbase, kHalo - mlo,
