@@ -60,10 +60,12 @@ def flops_per_point_step(pb: dict, picard_mean: float) -> float:
 
 
 def bytes_per_point_step(pb: dict) -> float:
-    """Algorithmic HBM bytes of the sweep kernel per point-step (FP64):
-    read the K layers' records (y, M_y, z, M_z: 32 B) and write y, z (16 B)."""
+    """Algorithmic HBM bytes of the sweep kernel per point-step (FP64): read
+    layers n+2..n+K whole (y, z and M_y, M_z: 32 B each) and the values of
+    layer n+1 (16 B), write the values of layer n and the second derivatives
+    of layer n+1 (16 B each)."""
     K = max(pb["k_y"], pb["k_z"])
-    return 32.0 * K + 16.0
+    return 32.0 * (K - 1) + 16.0 + 32.0
 
 
 KERNEL_SOURCES = ["capi.hip", "sweep.hip", "sweep2d.hip", "sweep2d.h", "device_common.h", "kernels.h", "plan_math.cpp",
@@ -303,9 +305,11 @@ def main() -> int:
         y0 = torch.empty(nx, dtype=torch.float64, device=dev)
         z0 = torch.empty(nx, dtype=torch.float64, device=dev)
         # the library's own kernel-shape choice for this plan, made once (like
-        # the plan itself) before anything is timed
-        tune = B.bsde_autotune(plan, ws, [(t_iy, t_iz, y0, z0)], stream=stream, reps=20)
-        print(f"[bench] {prec}: autotune {tune}", file=sys.stderr, flush=True)
+        # the plan itself) before anything is timed; profiling runs keep the
+        # plan's default shape, since a profiler distorts the candidates' times
+        if not args.profile_steps:
+            tune = B.bsde_autotune(plan, ws, [(t_iy, t_iz, y0, z0)], stream=stream, reps=20)
+            print(f"[bench] {prec}: autotune {tune}", file=sys.stderr, flush=True)
         # one checked solve: status and Picard statistics
         rc, st = B.bsde_solve(plan, ws, t_iy, t_iz, y0, z0, stream=stream, stats=True)
         print(f"[bench] workload {wl.name} {prec} status {B.bsde_status_string(rc)} stats {st}",

@@ -3,8 +3,9 @@
 //
 // Workspace layout (caller-owned device memory):
 //   per instance: ring of K+1 slots; layer n lives in slot n mod (K+1); a slot
-//                 is pad_l ghost records, n_x grid records, pad_r ghost records
-//                 ({y, M_y, z, M_z}, 32 bytes each)
+//                 is two planes of pad_l ghost, n_x grid and pad_r ghost
+//                 elements: (y, z), then (M_y, M_z) (16 bytes each in FP64,
+//                 8 in FP32), so each launch writes whole planes
 //   per instance: per-wavefront Picard counters (statistics)
 //   totals      : 4 x u64 reduced statistics
 #include <hip/hip_runtime.h>
@@ -28,8 +29,6 @@
 namespace {
 
 using bsde::kBlock;
-using bsde::Rec32;
-using bsde::Rec64;
 
 enum SweepPath { PATH_FUSED = 0, PATH_DIRECT = 1 };
 
@@ -1110,7 +1109,8 @@ bsde_status bsde_plan(const bsde_problem *pb, int batch, bsde_plan_t *out)
     size_t off = 0;
     for (Instance &in : pl->inst) {
         in.ring_off = off;
-        off += align_up((size_t)(in.K + 1) * in.npad * (in.f32 ? sizeof(Rec32) : sizeof(Rec64)), 256);
+        // two planes of npad (y, z) and (M_y, M_z) elements per slot
+        off += align_up((size_t)(in.K + 1) * 2 * in.npad * (in.f32 ? sizeof(float2) : sizeof(double2)), 256);
     }
     for (Instance &in : pl->inst) {
         in.fin_off = off;

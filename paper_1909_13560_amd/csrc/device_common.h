@@ -4,22 +4,11 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "../../include/bsde.h"
 
 namespace bsde {
-
-// One grid point of one time layer: the value and the natural-spline second
-// derivative of y and of z.  32 bytes, so one record is two 16-byte halves
-// (y, M_y) and (z, M_z).
-struct alignas(16) Rec64 {
-    double y, My, z, Mz;
-};
-
-// The same record in single precision (the FP32 form's ring): 16 bytes, one
-// aligned vector load.
-struct alignas(16) Rec32 {
-    float y, My, z, Mz;
-};
 
 constexpr int kBlock = 256;        // threads per block of every kernel
 constexpr int kPcrRounds = 5;      // PCR strides 1, 2, 4, 8, 16
@@ -151,8 +140,7 @@ __host__ __device__ constexpr PcrFilters pcr_filters()
 }
 
 struct SweepArgs {
-    Rec64 *ring;      // FP64 form
-    Rec32 *ring32;    // FP32 form
+    void *ring;       // K+1 slots of two planes (Slot), double2 (FP64) or float2 (FP32)
     double *fin_y, *fin_z;  // layer n_stop in double precision (written when n == n_stop)
     int n_stop;
     NodeTable tab;
@@ -177,7 +165,7 @@ struct SweepArgs {
 // (same precision, driver and tile shape); the grid's tiles are numbered
 // instance after instance.
 struct InstDesc {
-    SweepArgs a;          // ring, ring32, fin_*, st_* unset; n unset
+    SweepArgs a;          // ring, fin_*, st_* unset; n unset
     size_t ring_off;      // ring of K+1 slots
     size_t fin_off;       // layer n_stop: n_x doubles of y, then of z
     size_t stat_off;      // per-wave statistics: sum (u64), unconverged (u64), max (u32)
@@ -272,8 +260,7 @@ __device__ inline SweepArgs bind_instance(const InstDesc &d, char *ws, int s, bo
     a.tab.win_lo = d.win_lo;
     a.tab.win_hi = d.win_hi;
     a.n = d.n0 - s;
-    a.ring = reinterpret_cast<Rec64 *>(ws + d.ring_off);
-    a.ring32 = reinterpret_cast<Rec32 *>(ws + d.ring_off);
+    a.ring = ws + d.ring_off;
     a.fin_y = reinterpret_cast<double *>(ws + d.fin_off);
     a.fin_z = a.fin_y + a.nx;
     if (stats) {
@@ -309,7 +296,7 @@ __device__ inline const InstDesc &block_desc(const StepArgs &s, int idx)
 // r~_k / (6/dx^2) for any integer k, from the layer in HBM (used where the
 // window does not hold the neighbours or k is outside [1, N-2]).
 template <typename Rec>
-__device__ inline double rtilde_global(const Rec *__restrict__ g, int nx, int k, bool zf)
+__device__ inline double rtilde_global(const Rec &g, int nx, int k, bool zf)
 {
     const int per = 2 * (nx - 1);
     int kk = k % per;
@@ -320,61 +307,46 @@ __device__ inline double rtilde_global(const Rec *__restrict__ g, int nx, int k,
         sign = -1.0;
     }
     if (kk == 0 || kk == nx - 1) return 0.0;
-    const double vm = zf ? g[kk - 1].z : g[kk - 1].y;
-    const double v0 = zf ? g[kk].z : g[kk].y;
-    const double vp = zf ? g[kk + 1].z : g[kk + 1].y;
+    const double vm = zf ? g.v[kk - 1].y : g.v[kk - 1].x;
+    const double v0 = zf ? g.v[kk].y : g.v[kk].x;
+    const double vp = zf ? g.v[kk + 1].y : g.v[kk + 1].x;
     return sign * ((vp - v0) - (v0 - vm));
 }
 
 // Window of one layer in LDS.  Element e (slot WinLayout<P>::slot(e)) holds
-// the record of grid point lo - kHalo + e.
-//   FP64 form: (y, M_y) in wy[slot], (z, M_z) in wy[slot + window_slots(P)].
-//   FP32 form: (y, M_y, z, M_z) in w[slot].
+// grid point lo - kHalo + e, in the ring's two fragments:
+//   FP64 form: (y, z) in wy[slot], (M_y, M_z) in wy[slot + window_slots(P)].
+//   FP32 form: (y, z, M_y, M_z) in w[slot].
 template <int P>
 struct WinStore64 {
     double2 *wy;
-    static constexpr int kZ = window_slots(P);
-    __device__ void put(int sl, const Rec64 &r) const
+    static constexpr int kM = window_slots(P);
+    __device__ void put(int sl, const double2 &v, const double2 &m) const
     {
-        wy[sl] = make_double2(r.y, r.My);
-        wy[sl + kZ] = make_double2(r.z, r.Mz);
+        wy[sl] = v;
+        wy[sl + kM] = m;
     }
-    __device__ void val(int sl, double y, double z) const
-    {
-        wy[sl].x = y;
-        wy[sl + kZ].x = z;
-    }
-    __device__ void der(int sl, double my, double mz) const
-    {
-        wy[sl].y = my;
-        wy[sl + kZ].y = mz;
-    }
-    __device__ void write_der(int sl, Rec64 &g) const
-    {
-        g.My = wy[sl].y;
-        g.Mz = wy[sl + kZ].y;
-    }
+    __device__ void val(int sl, double y, double z) const { wy[sl] = make_double2(y, z); }
+    __device__ void der(int sl, double my, double mz) const { wy[sl + kM] = make_double2(my, mz); }
+    __device__ double2 ders(int sl) const { return wy[sl + kM]; }
 };
 
 template <int P>
 struct WinStore32 {
     float4 *w;
-    __device__ void put(int sl, const Rec32 &r) const { w[sl] = make_float4(r.y, r.My, r.z, r.Mz); }
+    __device__ void put(int sl, const float2 &v, const float2 &m) const
+    {
+        w[sl] = make_float4(v.x, v.y, m.x, m.y);
+    }
     __device__ void val(int sl, double y, double z) const
     {
-        w[sl].x = (float)y;
-        w[sl].z = (float)z;
+        reinterpret_cast<float2 *>(w + sl)[0] = make_float2((float)y, (float)z);
     }
     __device__ void der(int sl, double my, double mz) const
     {
-        w[sl].y = (float)my;
-        w[sl].w = (float)mz;
+        reinterpret_cast<float2 *>(w + sl)[1] = make_float2((float)my, (float)mz);
     }
-    __device__ void write_der(int sl, Rec32 &g) const
-    {
-        g.My = w[sl].y;
-        g.Mz = w[sl].w;
-    }
+    __device__ double2 ders(int sl) const { return make_double2(w[sl].z, w[sl].w); }
 };
 
 // Natural spline of layer g on the window of records [lo, lo + W).
@@ -393,9 +365,8 @@ struct SplineRaw {
     V y[U], z[U];
 };
 
-template <int NT, int U, typename Rec, typename V>
-__device__ inline void spline_load(const Rec *__restrict__ g, int nx, int lo, int W,
-                                   SplineRaw<U, V> &raw)
+template <int NT, int U, typename Slot, typename V>
+__device__ inline void spline_load(const Slot &g, int nx, int lo, int W, SplineRaw<U, V> &raw)
 {
     const int WS = W + 2 * kHalo + 2;
 #pragma unroll
@@ -403,9 +374,9 @@ __device__ inline void spline_load(const Rec *__restrict__ g, int nx, int lo, in
         const int e = threadIdx.x + u * NT;
         if (e < WS) {
             const int k = lo - kHalo - 1 + e;
-            const Rec r = g[min(max(k, 0), nx - 1)];
-            raw.y[u] = r.y;
-            raw.z[u] = r.z;
+            const auto r = g.v[min(max(k, 0), nx - 1)];
+            raw.y[u] = r.x;
+            raw.z[u] = r.y;
         }
     }
 }
@@ -503,8 +474,8 @@ __device__ inline void spline_window_interior(int W, const Win &win, double *R, 
     __syncthreads();
 }
 
-template <int NT, int U, int P, typename Rec, typename V, typename Win>
-__device__ inline void spline_window(const Rec *__restrict__ g, int nx, int lo, int W,
+template <int NT, int U, int P, typename Slot, typename V, typename Win>
+__device__ inline void spline_window(const Slot &g, int nx, int lo, int W,
                                      const Win &win, double *R, int cap1, const PcrCoef &c,
                                      const SplineRaw<U, V> &raw)
 {
@@ -573,14 +544,15 @@ __device__ inline void spline_window(const Rec *__restrict__ g, int nx, int lo, 
 }
 
 // The two precision forms.
-//   FP64: records Rec64, window fragments (y, M_y) and (z, M_z) as double2.
-//   FP32: records Rec32, one float4 (y, M_y, z, M_z) per record; node values
-//         and f-hat in single precision, accumulators in double precision.
+//   FP64: ring planes and window fragments (y, z) and (M_y, M_z) as double2.
+//   FP32: ring planes (y, z) and (M_y, M_z) as float2, one float4
+//         (y, z, M_y, M_z) per window element; node values and f-hat in
+//         single precision, accumulators in double precision.
 template <bool F32>
 struct Prec;
 template <>
 struct Prec<false> {
-    using Rec = Rec64;
+    using E = double2;  // one ring-plane element
     using Node = NodeRec;
     using V = double2;
     using Raw = double;
@@ -590,7 +562,7 @@ struct Prec<false> {
 };
 template <>
 struct Prec<true> {
-    using Rec = Rec32;
+    using E = float2;
     using Node = NodeRec32;
     using V = float4;
     using Raw = float;
@@ -598,6 +570,28 @@ struct Prec<true> {
     template <int P>
     using Win = WinStore32<P>;
 };
+
+// One ring slot (one time layer): two planes of npad elements, the values
+// (y, z) and the spline second derivatives (M_y, M_z), each pair a double2
+// (FP64) or float2 (FP32); index k runs from -pad_l to nx + pad_r - 1.  A
+// launch writes whole planes contiguously: the values of layer n and the
+// derivatives of layer n+1.
+template <bool F32>
+struct Slot {
+    using E = typename Prec<F32>::E;
+    using T = typename std::conditional<F32, float, double>::type;
+    E *v, *m;
+    __device__ void set_val(int k, double y, double z) const { v[k] = E{(T)y, (T)z}; }
+    __device__ void set_der(int k, double my, double mz) const { m[k] = E{(T)my, (T)mz}; }
+};
+
+template <bool F32>
+__device__ inline Slot<F32> ring_slot(const SweepArgs &a, int layer)
+{
+    using E = typename Slot<F32>::E;
+    E *base = static_cast<E *>(a.ring) + (size_t)(layer % (a.K + 1)) * 2 * a.npad + a.pad_l;
+    return Slot<F32>{base, base + a.npad};
+}
 
 __device__ inline const NodeRec *node_recs(const NodeTable &t, NodeRec *) { return t.rec; }
 __device__ inline const NodeRec32 *node_recs(const NodeTable &t, NodeRec32 *) { return t.rec32; }
@@ -659,11 +653,11 @@ __device__ inline void node_accumulate(const double2 (&r)[2][P + 1], const NodeR
 {
 #pragma unroll
     for (int q = 0; q < P; ++q) {
-        const double2 *ry = r[0], *rz = r[1];
-        const double yh = fma(c.B, ry[q + 1].x - ry[q].x,
-                              fma(c.C, ry[q].y, fma(c.D, ry[q + 1].y, ry[q].x)));
-        const double zh = fma(c.B, rz[q + 1].x - rz[q].x,
-                              fma(c.C, rz[q].y, fma(c.D, rz[q + 1].y, rz[q].x)));
+        const double2 *rv = r[0], *rm = r[1];  // (y, z) and (M_y, M_z)
+        const double yh = fma(c.B, rv[q + 1].x - rv[q].x,
+                              fma(c.C, rm[q].x, fma(c.D, rm[q + 1].x, rv[q].x)));
+        const double zh = fma(c.B, rv[q + 1].y - rv[q].y,
+                              fma(c.C, rm[q].y, fma(c.D, rm[q + 1].y, rv[q].y)));
         const double fh = f(yh, zh);
         double y = fma(c.cfy, fh, acc.Y[q]);
         if (LASTY) y = fma(c.cy, yh, y);
@@ -688,13 +682,13 @@ __device__ inline void node_accumulate(const float4 (&r)[1][P + 1], const NodeRe
 {
 #pragma unroll
     for (int q = 0; q < P; ++q) {
-        const float4 r0 = r[0][q], r1 = r[0][q + 1];
-        const float dy = fmaf(c.B, r1.x - r0.x, fmaf(c.C, r0.y, c.D * r1.y));
-        const float dz = fmaf(c.B, r1.z - r0.z, fmaf(c.C, r0.w, c.D * r1.w));
-        const float fh = f(r0.x + dy, r0.z + dz);
+        const float4 r0 = r[0][q], r1 = r[0][q + 1];  // (y, z, M_y, M_z)
+        const float dy = fmaf(c.B, r1.x - r0.x, fmaf(c.C, r0.z, c.D * r1.z));
+        const float dz = fmaf(c.B, r1.y - r0.y, fmaf(c.C, r0.w, c.D * r1.w));
+        const float fh = f(r0.x + dy, r0.y + dz);
         acc.Yf[q] = fmaf(c.cfy, fh, acc.Yf[q]);
         acc.Zf[q] = fmaf(c.cfz, fh, fmaf(c.czf, dz, acc.Zf[q]));
-        acc.Z[q] = fma(c.cz, (double)r0.z, acc.Z[q]);
+        acc.Z[q] = fma(c.cz, (double)r0.y, acc.Z[q]);
         if (LASTY) {
             acc.Yf[q] = fmaf(c.cyf, dy, acc.Yf[q]);
             acc.Y[q] = fma(c.cy, (double)r0.x, acc.Y[q]);
@@ -759,23 +753,15 @@ template <int P, int DRV, bool F32>
 __device__ inline void finish_points(const SweepArgs &a, int first, const Acc<P> &acc,
                                      int wave_slot)
 {
-    using Rec = typename Prec<F32>::Rec;
-    const int S = a.K + 1;
     const Driver<DRV, double> f0(a.drv, a.n * a.dt);
-    Rec *ring = nullptr;
-    if constexpr (F32)
-        ring = a.ring32;
-    else
-        ring = a.ring;
-    const Rec *__restrict__ prev = ring + (size_t)((a.n + 1) % S) * a.npad + a.pad_l;
-    Rec *__restrict__ out = ring + (size_t)(a.n % S) * a.npad + a.pad_l;
+    const Slot<F32> prev = ring_slot<F32>(a, a.n + 1), out = ring_slot<F32>(a, a.n);
     const bool last = a.n == a.n_stop;
     unsigned int it_max = 0, it_sum = 0, nonconv = 0;
 #pragma unroll
     for (int q = 0; q < P; ++q) {
         const int i = first + q;
         const bool valid = i < a.nx;
-        double y = prev[min(i, a.nx - 1)].y;
+        double y = prev.v[min(i, a.nx - 1)].x;
         const double zq = acc.Z[q], Yq = acc.Y[q];
         int it = 0;
         bool conv = true;
@@ -795,8 +781,7 @@ __device__ inline void finish_points(const SweepArgs &a, int first, const Acc<P>
             for (; it < a.picard_max; ++it) y = fma(a.h0, f0(y, zq), Yq);
         }
         if (valid) {
-            out[i].y = y;
-            out[i].z = zq;
+            out.set_val(i, y, zq);
             if (last) {
                 a.fin_y[i] = y;
                 a.fin_z[i] = zq;

@@ -72,22 +72,21 @@ struct LdsWindow {
 // Node records read straight from the layer in HBM (direct kernel).
 template <bool F32>
 struct GlobalWindow {
-    using Rec = typename Prec<F32>::Rec;
     using V = typename Prec<F32>::V;
     static constexpr int NA = Prec<F32>::NA;
-    const Rec *lay;  // record of the lane's first point
+    Slot<F32> lay;  // the layer
+    int i0;         // the lane's first point
     template <int P>
     __device__ void fetch(int m, V (&r)[NA][P + 1]) const
     {
-        const Rec *__restrict__ s = lay + m;
 #pragma unroll
         for (int q = 0; q <= P; ++q) {
-            const Rec x = s[q];
+            const auto v = lay.v[i0 + m + q], mm = lay.m[i0 + m + q];
             if constexpr (F32) {
-                r[0][q] = make_float4(x.y, x.My, x.z, x.Mz);
+                r[0][q] = make_float4(v.x, v.y, mm.x, mm.y);
             } else {
-                r[0][q] = make_double2(x.y, x.My);
-                r[1][q] = make_double2(x.z, x.Mz);
+                r[0][q] = v;
+                r[1][q] = mm;
             }
         }
     }
@@ -105,15 +104,6 @@ __device__ inline void layer_dispatch(const Src &src, const int *tm, int j, int 
         layer_nodes<P, DRV, true, F32>(src, nodes, tm + row, l0, LS, a.L, f, acc);
     else
         layer_nodes<P, DRV, false, F32>(src, nodes, tm + row, l0, LS, a.L, f, acc);
-}
-
-template <bool F32>
-__device__ inline typename Prec<F32>::Rec *ring_of(const SweepArgs &a)
-{
-    if constexpr (F32)
-        return a.ring32;
-    else
-        return a.ring;
 }
 
 // LDS bytes of the window arrays of the fused kernel.
@@ -135,7 +125,7 @@ template <int P, int G, int DRV, bool F32>
 __device__ inline void fused_tile(const SweepArgs &a, int tile, char *smem)
 {
     using PR = Prec<F32>;
-    using Rec = typename PR::Rec;
+    using E = typename PR::E;
     using V = typename PR::V;
     constexpr int T = kBlock * P;
     constexpr int NT = kBlock * G;
@@ -150,8 +140,6 @@ __device__ inline void fused_tile(const SweepArgs &a, int tile, char *smem)
     const int grp = __builtin_amdgcn_readfirstlane(tid / kBlock);
     const int lane_pt = (tid % kBlock) * P;
     const int t0 = tile * T;
-    const int S = a.K + 1;
-    Rec *ring = ring_of<F32>(a);
 
     Acc<P> acc;
 #pragma unroll
@@ -168,15 +156,21 @@ __device__ inline void fused_tile(const SweepArgs &a, int tile, char *smem)
     // tile computes the same in a batch as on its own.
     constexpr int kPre = (T + kMaxReach2 + NT - 1) / NT;
     constexpr int kRaw = pcr_slots(P, NT);
-    Rec pre[kPre];
+    using FT = typename Slot<F32>::T;
+    struct Frag {  // plain scalars, so that the array lives in registers
+        FT y, z, My, Mz;
+    } pre[kPre];   // the next window, both fragments
     auto prefetch = [&](int j) {
-        const Rec *__restrict__ g = ring + (size_t)((a.n + j) % S) * a.npad + a.pad_l;
+        const Slot<F32> g = ring_slot<F32>(a, a.n + j);
         const int lo = t0 + a.tab.win_lo[j];
         const int W = T + (a.tab.win_hi[j] - a.tab.win_lo[j]) + 1;
 #pragma unroll
         for (int u = 0; u < kPre; ++u) {
             const int e = tid + u * NT;
-            if (e < W) pre[u] = g[lo + e];
+            if (e < W) {
+                const E v = g.v[lo + e], m = g.m[lo + e];
+                pre[u] = Frag{v.x, v.y, m.x, m.y};
+            }
         }
     };
     const int rot = ((tile >> 5) & 3) % a.K;
@@ -191,7 +185,7 @@ __device__ inline void fused_tile(const SweepArgs &a, int tile, char *smem)
     };
     SplineRaw<kRaw, typename PR::Raw> raw1;
     {
-        const Rec *__restrict__ g1 = ring + (size_t)((a.n + 1) % S) * a.npad + a.pad_l;
+        const Slot<F32> g1 = ring_slot<F32>(a, a.n + 1);
         const int W1 = T + (a.tab.win_hi[1] - a.tab.win_lo[1]) + 1;
         const int j0 = layer_at(0) != 1 ? layer_at(0) : next_window(0);
         if (j0) prefetch(j0);
@@ -204,7 +198,7 @@ __device__ inline void fused_tile(const SweepArgs &a, int tile, char *smem)
 
     for (int jj = 0; jj < a.K; ++jj) {
         const int j = layer_at(jj);
-        Rec *__restrict__ g = ring + (size_t)((a.n + j) % S) * a.npad + a.pad_l;
+        const Slot<F32> g = ring_slot<F32>(a, a.n + j);
         const int mlo = a.tab.win_lo[j], mhi = a.tab.win_hi[j];
         const int W = T + (mhi - mlo) + 1;
         const int lo = t0 + mlo;
@@ -213,25 +207,31 @@ __device__ inline void fused_tile(const SweepArgs &a, int tile, char *smem)
             // HBM for the later steps, with the ghost records
             spline_window<NT, kRaw, P>(g, a.nx, lo, W, win, R, CAP1, a.pcr, raw1);
             const int kend = min(t0 + T, a.nx);
-            for (int k = t0 + tid; k < kend; k += NT)
-                win.write_der(WinLayout<P>::slot(k - lo + kHalo), g[k]);
+            for (int k = t0 + tid; k < kend; k += NT) {
+                const double2 d = win.ders(WinLayout<P>::slot(k - lo + kHalo));
+                g.set_der(k, d.x, d.y);
+            }
             if (tile == 0) {
-                Rec gh{};
-                gh.y = g[0].y;
-                gh.z = g[0].z;
-                for (int k = tid; k < a.pad_l; k += NT) g[k - a.pad_l] = gh;
+                const auto e0 = g.v[0];
+                for (int k = tid; k < a.pad_l; k += NT) {
+                    g.v[k - a.pad_l] = e0;
+                    g.set_der(k - a.pad_l, 0.0, 0.0);
+                }
             }
             if (tile == a.ntiles - 1) {
-                Rec gh{};
-                gh.y = g[a.nx - 1].y;
-                gh.z = g[a.nx - 1].z;
-                for (int k = tid; k < a.pad_r; k += NT) g[a.nx + k] = gh;
+                const auto e1 = g.v[a.nx - 1];
+                for (int k = tid; k < a.pad_r; k += NT) {
+                    g.v[a.nx + k] = e1;
+                    g.set_der(a.nx + k, 0.0, 0.0);
+                }
             }
         } else {
 #pragma unroll
             for (int u = 0; u < kPre; ++u) {
                 const int e = tid + u * NT;
-                if (e < W) win.put(WinLayout<P>::slot(kHalo + e), pre[u]);
+                if (e < W)
+                    win.put(WinLayout<P>::slot(kHalo + e), E{pre[u].y, pre[u].z},
+                            E{pre[u].My, pre[u].Mz});
             }
             const int jn = next_window(jj);
             if (jn) prefetch(jn);
@@ -290,13 +290,11 @@ __global__ void __launch_bounds__(kBlock) sweep_direct(const StepArgs s)
     __syncthreads();
     const int first = (tile * kBlock + (int)threadIdx.x) * P;
     const int i0 = min(first, a.nx - 1);  // lanes past the end read in bounds, store nothing
-    const int S = a.K + 1;
     Acc<P> acc;
 #pragma unroll
     for (int q = 0; q < P; ++q) acc.Y[q] = acc.Z[q] = 0.0;
-    const auto *ring = ring_of<F32>(a);
     for (int j = 1; j <= a.K; ++j) {
-        const GlobalWindow<F32> src{ring + (size_t)((a.n + j) % S) * a.npad + a.pad_l + i0};
+        const GlobalWindow<F32> src{ring_slot<F32>(a, a.n + j), i0};
         layer_dispatch<P, DRV, F32>(src, tm, j, 0, 1, a, acc);
     }
     finish_points<P, DRV, F32>(a, first, acc, (tile * kBlock + (int)threadIdx.x) >> 6);
@@ -310,7 +308,6 @@ __global__ void __launch_bounds__(kBlock) sweep_direct(const StepArgs s)
 template <bool F32>
 __global__ void __launch_bounds__(kBlock) spline_layer(const StepArgs s, int mode)
 {
-    using Rec = typename Prec<F32>::Rec;
     using V = typename Prec<F32>::V;
     constexpr int WE = kSplineTile + 2 * kHalo, WS = WE + 2;
     static_assert(WE <= window_slots(1), "spline tile exceeds the window layout");
@@ -323,8 +320,7 @@ __global__ void __launch_bounds__(kBlock) spline_layer(const StepArgs s, int mod
     const int n = mode == 0 ? d.n0 + 1 + s.s : d.n0 - s.s;
     if (mode == 0 && s.s >= a.K) return;
     if (mode == 1 && n <= a.n_stop) return;
-    Rec *slot = ring_of<F32>(a) + (size_t)(n % (a.K + 1)) * a.npad;
-    Rec *__restrict__ g = slot + a.pad_l;
+    const Slot<F32> g = ring_slot<F32>(a, n);
     const typename Prec<F32>::template Win<1> win{wsm};
     const int t0 = tile * kSplineTile;
     constexpr int U = (WS + kBlock - 1) / kBlock;
@@ -332,18 +328,23 @@ __global__ void __launch_bounds__(kBlock) spline_layer(const StepArgs s, int mod
     spline_load<kBlock, U>(g, a.nx, t0, kSplineTile, raw);
     spline_window<kBlock, U, 1>(g, a.nx, t0, kSplineTile, win, R, WS, a.pcr, raw);
     const int kend = min(t0 + kSplineTile, a.nx);
-    for (int k = t0 + (int)threadIdx.x; k < kend; k += kBlock) win.write_der(k - t0 + kHalo, g[k]);
+    for (int k = t0 + (int)threadIdx.x; k < kend; k += kBlock) {
+        const double2 dd = win.ders(k - t0 + kHalo);
+        g.set_der(k, dd.x, dd.y);
+    }
     if (tile == 0) {
-        Rec gh{};
-        gh.y = g[0].y;
-        gh.z = g[0].z;
-        for (int k = threadIdx.x; k < a.pad_l; k += kBlock) slot[k] = gh;
+        const auto e0 = g.v[0];
+        for (int k = threadIdx.x; k < a.pad_l; k += kBlock) {
+            g.v[k - a.pad_l] = e0;
+            g.set_der(k - a.pad_l, 0.0, 0.0);
+        }
     }
     if (tile == d.spline_tiles - 1) {
-        Rec gh{};
-        gh.y = g[a.nx - 1].y;
-        gh.z = g[a.nx - 1].z;
-        for (int k = threadIdx.x; k < a.pad_r; k += kBlock) g[a.nx + k] = gh;
+        const auto e1 = g.v[a.nx - 1];
+        for (int k = threadIdx.x; k < a.pad_r; k += kBlock) {
+            g.v[a.nx + k] = e1;
+            g.set_der(a.nx + k, 0.0, 0.0);
+        }
     }
 }
 
@@ -362,16 +363,14 @@ __global__ void __launch_bounds__(kBlock) scatter_layers(const ScatterChunk c, c
     const double *__restrict__ iz = c.iz[b];
     for (int r = 0; r < a.K; ++r) {
         const int n = d.n0 + 1 + r;
-        const size_t off = (size_t)(n % (a.K + 1)) * a.npad + a.pad_l;
+        const Slot<false> g64 = ring_slot<false>(a, n);
+        const Slot<true> g32 = ring_slot<true>(a, n);
         for (int i = blockIdx.x * kBlock + threadIdx.x; i < a.nx; i += gridDim.x * kBlock) {
             const double y = iy[(size_t)r * a.nx + i], z = iz[(size_t)r * a.nx + i];
-            if (d.f32) {
-                a.ring32[off + i].y = (float)y;
-                a.ring32[off + i].z = (float)z;
-            } else {
-                a.ring[off + i].y = y;
-                a.ring[off + i].z = z;
-            }
+            if (d.f32)
+                g32.set_val(i, y, z);
+            else
+                g64.set_val(i, y, z);
         }
     }
 }

@@ -81,6 +81,17 @@ def test_black_scholes_all_orders(lib, orc, k):
     run_both(lib, orc, wl)
 
 
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6])
+def test_bid_ask_every_layer_order(lib, orc, k):
+    # a grid of 157 tiles: the tiles take every rotation of the layer order
+    # (tile / 32 mod 4, reduced mod K), and the windows away from the domain
+    # ends take the stencil form of the spline
+    nx, nt = 40111, 10
+    wl = W.bidask_call_1d(n_x=nx, n_t=nt, k=k, L=16, half_width=twin_half_width(0.2, 0.5, nt, nx))
+    _, _, _, _, rc, st, sto = run_both(lib, orc, wl)
+    assert rc == lib.BSDE_OK and st["picard_nonconverged"] == 0
+
+
 @pytest.mark.parametrize("sign", [1.0, -1.0])
 def test_bid_ask_ragged_grid(lib, orc, sign):
     nx, nt = 5003, 48
