@@ -174,6 +174,12 @@ __device__ inline void fused_tile(const SweepArgs &a, int tile, char *smem)
         }
     };
     const int rot = ((tile >> 5) & 3) % a.K;
+    // Issue priority: the node loops (throughput work) run at the lowest
+    // wave priority, everything else (staging waits, the spline's barriers,
+    // Picard) at the highest, so a block's latency-bound phases go ahead of
+    // the node loops of the blocks sharing its CU instead of queueing behind
+    // them.
+    __builtin_amdgcn_s_setprio(3);
     auto layer_at = [&](int jj) {  // the jj-th layer of this tile's order
         const int q = (jj + rot) % a.K;
         return q + 1 < a.K ? q + 2 : 1;
@@ -239,7 +245,9 @@ __device__ inline void fused_tile(const SweepArgs &a, int tile, char *smem)
         }
         const LdsWindow<P, F32> src{wbase, kHalo - mlo,
                                     WinLayout<P>::kPad ? lane_pt + lane_pt / P : lane_pt};
+        __builtin_amdgcn_s_setprio(0);
         layer_dispatch<P, DRV, F32>(src, tm, j, grp, G, a, acc);
+        __builtin_amdgcn_s_setprio(3);
         __syncthreads();  // the window is reused by the next layer
     }
     if (G > 1) {  // partial sums of groups 1..G-1 meet group 0 in LDS, in group order
