@@ -71,9 +71,11 @@ typedef enum {
                            262144 points, 1024 steps)                          */
 } bsde_precision;
 
-/* One BSDE.  d = 1 in this release; the d = 2 fields are reserved. */
+/* One BSDE in one (d = 1) or two (d = 2, Section 5 Examples 4-5) space
+ * dimensions on a uniform (tensor) grid.  Fields indexed [2] use entry 0
+ * only when d = 1. */
 typedef struct {
-    int d;              /* space dimension (1)                                   */
+    int d;              /* space dimension, 1 or 2                               */
     double T;           /* terminal time, > 0                                    */
     int n_t;            /* N: time steps, dt = T/N, N >= max(k_y, k_z)           */
     int k_y, k_z;       /* multistep orders K_y, K_z in [1, 6] (Tables 1-2)       */
@@ -81,7 +83,9 @@ typedef struct {
     int n_x[2];         /* grid points per axis, >= 4 (x_i = x_min + i dx)       */
     double x_min[2], x_max[2];
     double drift[2];    /* X_{t+h} = X_t + drift h + vol (W_{t+h} - W_t)          */
-    double vol[2][2];   /* row-major; d = 1 uses vol[0][0] > 0                    */
+    double vol[2][2];   /* row-major; d = 1 uses vol[0][0] > 0; d = 2 needs
+                           vol[0][0], vol[1][1] > 0 (and vol[0][1] = 0, i.e. a
+                           lower-triangular factor, for the 2-D kernels)         */
     int driver;         /* bsde_driver_kind                                      */
     double p[8];        /* driver parameters                                     */
     int picard_max;     /* Picard iterations, >= 1                               */
@@ -125,8 +129,12 @@ typedef struct {
  * grid split into an integer cell and a fraction (Section 3.2, O(1)
  * location), with the spline basis weights at that fraction.  Small constant
  * tables are copied to the current device.
- * Errors: BSDE_EINVAL for an invalid problem or batch < 1, BSDE_EUNSUPPORTED
- * for d != 1, BSDE_ENOMEM, BSDE_EDEVICE.  *out is set only on success.
+ * Errors: BSDE_EINVAL for an invalid problem, batch < 1, or problems of
+ * different d in one batch; BSDE_EUNSUPPORTED for a d = 2 problem with
+ * vol[0][1] != 0, a driver other than BSDE_DRIVER_LINEAR or the FP32 form,
+ * and for a d = 1 grid whose ring plane would reach 4 GiB (about 2.7e8 points
+ * in FP64, 5.4e8 in FP32); BSDE_ENOMEM, BSDE_EDEVICE.  *out is set only on
+ * success.
  */
 bsde_status bsde_plan(const bsde_problem *pb, int batch, bsde_plan_t *out);
 
@@ -149,9 +157,12 @@ size_t bsde_workspace_bytes(bsde_plan_t plan);
  *   ws      device workspace of at least bsde_workspace_bytes(plan) bytes,
  *           256-byte aligned; its contents on entry do not matter.
  *   init_y  device, K x n_x doubles: row r is y at t_{N-K+1+r} (row K-1 is the
- *           terminal layer g(x_i)); K = max(k_y, k_z).
- *   init_z  device, K x n_x doubles, same layout for z.
- *   y0, z0  device, n_x doubles each: receive y and z at t_0 on the grid.
+ *           terminal layer g(x_i)); K = max(k_y, k_z).  For d = 2 a row is
+ *           the n_x[0] x n_x[1] grid, point (i0, i1) at i0 n_x[1] + i1.
+ *   init_z  device, K x n_x doubles, same layout for z; for d = 2 each row r
+ *           is two grid rows, z_1 then z_2.
+ *   y0, z0  device, n_x doubles each: receive y and z at t_0 on the grid
+ *           (d = 2: y0 one grid, z0 two grids, z_1 then z_2).
  *   stream  hipStream_t or NULL.
  *   st      NULL: fully asynchronous.  Non-NULL: the call synchronises the
  *           stream, fills *st and returns BSDE_ENOCONV / BSDE_ENONFINITE when
@@ -191,7 +202,7 @@ typedef struct {
     int spline_launches;
     int path;             /* sweep kernel of group 0: 0 = LDS-staged windows with
                              the spline of the newest layer in-kernel, 1 = direct
-                             loads                                              */
+                             loads, 2 = the two-dimensional sweep                */
     int points_per_lane;  /* grid points per lane of the sweep kernel            */
     int node_groups;      /* thread groups sharing the nodes of one tile         */
     int blocks;           /* blocks of the first sweep launch of group 0         */

@@ -974,6 +974,12 @@ bsde_status bsde_plan(const bsde_problem *pb, int batch, bsde_plan_t *out)
             delete pl;
             return BSDE_EINVAL;
         }
+        // the kernels address a ring plane by 32-bit byte offsets
+        const Instance &in = pl->inst[b];
+        if ((uint64_t)in.npad * (in.f32 ? sizeof(float2) : sizeof(double2)) >= (uint64_t(1) << 32)) {
+            delete pl;
+            return BSDE_EUNSUPPORTED;
+        }
     }
     // PCR coefficients of the (1, 4, 1) system: round r eliminates the
     // neighbours at distance 2^r; a' = -a^2/b, b' = b - 2a^2/b

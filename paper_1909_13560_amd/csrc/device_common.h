@@ -307,9 +307,10 @@ __device__ inline double rtilde_global(const Rec &g, int nx, int k, bool zf)
         sign = -1.0;
     }
     if (kk == 0 || kk == nx - 1) return 0.0;
-    const double vm = zf ? g.v[kk - 1].y : g.v[kk - 1].x;
-    const double v0 = zf ? g.v[kk].y : g.v[kk].x;
-    const double vp = zf ? g.v[kk + 1].y : g.v[kk + 1].x;
+    const auto em = g.val(kk - 1), e0 = g.val(kk), ep = g.val(kk + 1);
+    const double vm = zf ? em.y : em.x;
+    const double v0 = zf ? e0.y : e0.x;
+    const double vp = zf ? ep.y : ep.x;
     return sign * ((vp - v0) - (v0 - vm));
 }
 
@@ -374,7 +375,7 @@ __device__ inline void spline_load(const Slot &g, int nx, int lo, int W, SplineR
         const int e = threadIdx.x + u * NT;
         if (e < WS) {
             const int k = lo - kHalo - 1 + e;
-            const auto r = g.v[min(max(k, 0), nx - 1)];
+            const auto r = g.val(min(max(k, 0), nx - 1));
             raw.y[u] = r.x;
             raw.z[u] = r.y;
         }
@@ -576,21 +577,32 @@ struct Prec<true> {
 // (FP64) or float2 (FP32); index k runs from -pad_l to nx + pad_r - 1.  A
 // launch writes whole planes contiguously: the values of layer n and the
 // derivatives of layer n+1.
+// Elements are addressed by a 32-bit byte offset from the plane's start
+// (the host keeps a plane below 4 GiB): both planes share the offset of a
+// point, and the loads take the form "scalar base + 32-bit vector offset".
 template <bool F32>
 struct Slot {
     using E = typename Prec<F32>::E;
     using T = typename std::conditional<F32, float, double>::type;
-    E *v, *m;
-    __device__ void set_val(int k, double y, double z) const { v[k] = E{(T)y, (T)z}; }
-    __device__ void set_der(int k, double my, double mz) const { m[k] = E{(T)my, (T)mz}; }
+    char *v0, *m0;  // plane starts (element -pad_l)
+    int pad;        // pad_l
+    __device__ unsigned off(int k) const { return (unsigned)(k + pad) * (unsigned)sizeof(E); }
+    __device__ E val(int k) const { return *reinterpret_cast<const E *>(v0 + off(k)); }
+    __device__ E der(int k) const { return *reinterpret_cast<const E *>(m0 + off(k)); }
+    __device__ void set_val(int k, const E &e) const { *reinterpret_cast<E *>(v0 + off(k)) = e; }
+    __device__ void set_val(int k, double y, double z) const { set_val(k, E{(T)y, (T)z}); }
+    __device__ void set_der(int k, double my, double mz) const
+    {
+        *reinterpret_cast<E *>(m0 + off(k)) = E{(T)my, (T)mz};
+    }
 };
 
 template <bool F32>
 __device__ inline Slot<F32> ring_slot(const SweepArgs &a, int layer)
 {
     using E = typename Slot<F32>::E;
-    E *base = static_cast<E *>(a.ring) + (size_t)(layer % (a.K + 1)) * 2 * a.npad + a.pad_l;
-    return Slot<F32>{base, base + a.npad};
+    char *base = static_cast<char *>(a.ring) + (size_t)(layer % (a.K + 1)) * 2 * a.npad * sizeof(E);
+    return Slot<F32>{base, base + (size_t)a.npad * sizeof(E), a.pad_l};
 }
 
 __device__ inline const NodeRec *node_recs(const NodeTable &t, NodeRec *) { return t.rec; }
@@ -761,7 +773,7 @@ __device__ inline void finish_points(const SweepArgs &a, int first, const Acc<P>
     for (int q = 0; q < P; ++q) {
         const int i = first + q;
         const bool valid = i < a.nx;
-        double y = prev.v[min(i, a.nx - 1)].x;
+        double y = prev.val(min(i, a.nx - 1)).x;
         const double zq = acc.Z[q], Yq = acc.Y[q];
         int it = 0;
         bool conv = true;

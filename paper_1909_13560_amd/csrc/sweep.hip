@@ -81,7 +81,7 @@ struct GlobalWindow {
     {
 #pragma unroll
         for (int q = 0; q <= P; ++q) {
-            const auto v = lay.v[i0 + m + q], mm = lay.m[i0 + m + q];
+            const auto v = lay.val(i0 + m + q), mm = lay.der(i0 + m + q);
             if constexpr (F32) {
                 r[0][q] = make_float4(v.x, v.y, mm.x, mm.y);
             } else {
@@ -168,7 +168,7 @@ __device__ inline void fused_tile(const SweepArgs &a, int tile, char *smem)
         for (int u = 0; u < kPre; ++u) {
             const int e = tid + u * NT;
             if (e < W) {
-                const E v = g.v[lo + e], m = g.m[lo + e];
+                const E v = g.val(lo + e), m = g.der(lo + e);
                 pre[u] = Frag{v.x, v.y, m.x, m.y};
             }
         }
@@ -218,16 +218,16 @@ __device__ inline void fused_tile(const SweepArgs &a, int tile, char *smem)
                 g.set_der(k, d.x, d.y);
             }
             if (tile == 0) {
-                const auto e0 = g.v[0];
+                const auto e0 = g.val(0);
                 for (int k = tid; k < a.pad_l; k += NT) {
-                    g.v[k - a.pad_l] = e0;
+                    g.set_val(k - a.pad_l, e0);
                     g.set_der(k - a.pad_l, 0.0, 0.0);
                 }
             }
             if (tile == a.ntiles - 1) {
-                const auto e1 = g.v[a.nx - 1];
+                const auto e1 = g.val(a.nx - 1);
                 for (int k = tid; k < a.pad_r; k += NT) {
-                    g.v[a.nx + k] = e1;
+                    g.set_val(a.nx + k, e1);
                     g.set_der(a.nx + k, 0.0, 0.0);
                 }
             }
@@ -341,16 +341,16 @@ __global__ void __launch_bounds__(kBlock) spline_layer(const StepArgs s, int mod
         g.set_der(k, dd.x, dd.y);
     }
     if (tile == 0) {
-        const auto e0 = g.v[0];
+        const auto e0 = g.val(0);
         for (int k = threadIdx.x; k < a.pad_l; k += kBlock) {
-            g.v[k - a.pad_l] = e0;
+            g.set_val(k - a.pad_l, e0);
             g.set_der(k - a.pad_l, 0.0, 0.0);
         }
     }
     if (tile == d.spline_tiles - 1) {
-        const auto e1 = g.v[a.nx - 1];
+        const auto e1 = g.val(a.nx - 1);
         for (int k = threadIdx.x; k < a.pad_r; k += kBlock) {
-            g.v[a.nx + k] = e1;
+            g.set_val(a.nx + k, e1);
             g.set_der(a.nx + k, 0.0, 0.0);
         }
     }

@@ -120,6 +120,26 @@ def test_plan_2d_reports_unsupported_variants(change):
     assert e.value.code == B.BSDE_EUNSUPPORTED
 
 
+@pytest.mark.parametrize("prec,n_x,limited", [
+    ("fp64", 280_000_000, True), ("fp32_comp", 280_000_000, False), ("fp32_comp", 560_000_000, True)])
+def test_plan_refuses_ring_planes_past_4gib(prec, n_x, limited):
+    # the sweep kernels address a ring plane (16-byte elements in FP64, 8 in
+    # FP32) by 32-bit byte offsets; larger grids are refused before any device
+    # call, smaller ones get past that check (and here, without a device, fail
+    # later or succeed, but not with BSDE_EUNSUPPORTED)
+    pb = dict(W.bidask_call_1d(n_x=1024, n_t=16, half_width=None).problem)
+    dx = (pb["x_max"] - pb["x_min"]) / 1023  # same cell width, so the nodes stay near
+    pb["n_x"] = n_x
+    pb["x_max"] = pb["x_min"] + (n_x - 1) * dx
+    pb["prec"] = prec
+    try:
+        B.bsde_plan(pb)
+        code = B.BSDE_OK
+    except B.BsdeError as e:
+        code = e.code
+    assert (code == B.BSDE_EUNSUPPORTED) == limited
+
+
 def test_plan_rejects_mixed_dimensions():
     with pytest.raises(B.BsdeError) as e:
         B.bsde_plan([W.sine_1d().problem, W.sine_2d(n_x=17).problem])
