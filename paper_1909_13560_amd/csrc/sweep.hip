@@ -30,7 +30,7 @@ namespace bsde {
 // the padded layout its slot is
 //   (P+1) tig + off + off/P + q + [q >= P - off % P]   (tig = lane_pt / P),
 // so the per-record offsets are one of P compile-time patterns.  The FP64
-// form reads (y, M_y) and, window_slots(P) slots further, (z, M_z).
+// form reads (y, z) and, window_slots(P) slots further, (M_y, M_z).
 template <int P, int B, bool PAD, int NA, typename V>
 __device__ inline void fetch_slots(const V *w, int base, V (&r)[NA][P + 1])
 {

@@ -186,8 +186,11 @@ def test_picard_nonconvergence_is_reported(lib):
 def test_batched_equals_single(lib):
     import torch
 
+    # the last instance has 157 tiles, so its tiles take every rotation of the
+    # layer order; in the batch they sit behind the other instances' tiles
     wls = [W.sine_1d(n_x=700, n_t=20, k=2), W.bidask_call_1d(n_x=1500, n_t=16, half_width=None),
-           W.bs_call_1d(n_x=999, n_t=12, k=5, L=16, half_width=None)]
+           W.bs_call_1d(n_x=999, n_t=12, k=5, L=16, half_width=None),
+           W.bidask_call_1d(n_x=40111, n_t=12, half_width=twin_half_width(0.2, 0.5, 12, 40111))]
     plan = lib.bsde_plan([w.problem for w in wls])
     ws = lib.workspace(plan)
     ios, outs = [], []
