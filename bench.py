@@ -97,8 +97,10 @@ def measured_traffic(workload_name: str):
     return 1024.0 * (t["fetch_kib"] * t["read_factor"] + t["write_kib"] * t["write_factor"])
 
 
-def cpu_baseline(wl, budget_s: float = 15.0) -> dict:
-    """Serial oracle on the first steps of the same workload (bounded sample)."""
+def cpu_baseline(wl, budget_s: float = 15.0):
+    """Serial oracle on the first steps of the same workload (bounded sample).
+    Returns the report and the oracle's layer at the sample's last step
+    (n_stop, y, z) for the full-size parity check."""
     import oracle
 
     oracle.build(force=False)
@@ -110,14 +112,16 @@ def cpu_baseline(wl, budget_s: float = 15.0) -> dict:
     oracle.solve(pb, iy, iz, n_stop=pb["n_t"] - K)
     one = time.perf_counter() - t0
     steps = max(1, min(pb["n_t"] - K + 1, int(budget_s / max(one, 1e-3))))
+    n_stop = pb["n_t"] - K + 1 - steps
     t0 = time.perf_counter()
-    oracle.solve(pb, iy, iz, n_stop=pb["n_t"] - K + 1 - steps)
+    yo, zo, _ = oracle.solve(pb, iy, iz, n_stop=n_stop)
     el = time.perf_counter() - t0
     nx = pb["n_x"]
-    return {"value": nx * steps / el, "unit": "grid-point*time-step/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"first {steps} of {pb['n_t'] - K + 1} backward steps at full grid "
-                      f"({nx} points), serial FP64 C oracle, {el:.1f} s"}
+    return ({"value": nx * steps / el, "unit": "grid-point*time-step/s", "cores": 1,
+             "kind": "oracle",
+             "sample": f"first {steps} of {pb['n_t'] - K + 1} backward steps at full grid "
+                       f"({nx} points), serial FP64 C oracle, {el:.1f} s"},
+            (n_stop, yo, zo[0]))
 
 
 def run_batch(args, B, torch, np, ms_fp64_single):
@@ -374,6 +378,8 @@ def main() -> int:
     out = {
         "metric": "grid-point*time-step updates/sec (k=4, L=16)",
         "value": value,
+        # the same rate counting only the layers the sweep computes, N - K + 1
+        "value_computed_steps": nx * steps_run / (ms * 1e-3),
         "unit": "grid-point*time-step/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -404,7 +410,15 @@ def main() -> int:
         "two_d": two_d,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget)
+        out["cpu_baseline"], (n_stop, yo, zo) = cpu_baseline(wl, args.cpu_budget)
+        # the library against the oracle at full size, over the same steps
+        par = {"n_stop": n_stop, "steps": pb["n_t"] - wl.K + 1 - n_stop}
+        for prec in (["fp64"] if args.fp64_only else ["fp64", "fp32_comp"]):
+            y_g, z_g, _, _ = B.solve(dict(pb, n_stop=n_stop, prec=prec), iy, iz)
+            par[f"max_rel_err_{prec}"] = float(max(
+                np.max(np.abs(y_g - yo) / np.maximum(np.abs(yo), 1.0)),
+                np.max(np.abs(z_g[0] - zo) / np.maximum(np.abs(zo), 1.0))))
+        out["oracle_parity_full_grid"] = par
     print(json.dumps(out), flush=True)
     return 0
 

@@ -230,8 +230,10 @@ typedef struct {
  * bsde_autotune -- choose the sweep kernel shape of every group of the plan
  * by measurement: the initial layers of io are loaded into ws, and for each
  * shape that fits (fused kernel with 1, 2 or 4 points per lane and 1 or 2
- * node groups; the direct kernel when none fits) the first time step of the
- * group is launched `reps` times and timed with hipEvents; the fastest shape
+ * node groups; the direct kernel when none fits) the group's first time step
+ * and three more spread over its steps (so a batch's shrinking set of active
+ * instances counts) are launched `reps` times and timed with hipEvents, in
+ * two passes over the shapes (each keeps its faster pass); the fastest shape
  * is kept in the plan.  Replaces the default shape (or BSDE_SWEEP); drops the
  * plan's captured graphs.  Synchronises the stream.  Must not run while
  * another solve uses the plan.  rep may be NULL.

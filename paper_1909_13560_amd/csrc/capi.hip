@@ -1280,27 +1280,43 @@ bsde_status bsde_autotune(bsde_plan_t plan, void *ws, const bsde_io *io, void *s
         if (cand.empty()) cand.push_back(direct_config(plan->inst, g.members, g.f32, 2));
         float best = 0.0f;
         SweepConfig best_c = g.cfg;
-        for (const SweepConfig &c : cand) {
-            rc = apply_config(*plan, g, c);
-            if (rc != BSDE_OK) break;
-            // step 0 recomputes the same layer from the initial layers on
-            // every repetition: the timed launches are idempotent
-            rc = enqueue_step(*plan, g, w, 0, false, s, nullptr);  // warm-up
-            if (rc != BSDE_OK) break;
-            if (hipEventRecord(e0, s) != hipSuccess) { rc = BSDE_EDEVICE; break; }
-            for (int r = 0; r < reps && rc == BSDE_OK; ++r)
-                rc = enqueue_step(*plan, g, w, 0, false, s, nullptr);
-            if (rc != BSDE_OK) break;
-            float ms = 0.0f;
-            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-                rc = BSDE_EDEVICE;
-                break;
+        // Timed steps: the first, and three more spread over the group's
+        // steps, so that a batch's shrinking set of active instances weighs
+        // in.  The warm-up runs steps 0 and 1, after which every plane of
+        // every ring slot holds finite data (initial layers, their splines
+        // and the warm-up's output), so any step does the work of a real one;
+        // the solve reloads the initial layers afterwards.
+        int sample[4] = {0, g.max_steps / 4, g.max_steps / 2, (3 * g.max_steps) / 4};
+        const int nsample = g.max_steps >= 8 ? 4 : 1;
+        // Two passes over the candidates, each keeping its faster pass: the
+        // first candidate timed would otherwise run while the clocks ramp up.
+        std::vector<float> t(cand.size(), 0.0f);
+        for (int pass = 0; pass < 2 && rc == BSDE_OK; ++pass) {
+            for (size_t ci = 0; ci < cand.size(); ++ci) {
+                rc = apply_config(*plan, g, cand[ci]);
+                if (rc != BSDE_OK) break;
+                rc = enqueue_step(*plan, g, w, 0, false, s, nullptr);  // warm-up
+                if (rc == BSDE_OK && nsample > 1) rc = enqueue_step(*plan, g, w, 1, false, s, nullptr);
+                if (rc != BSDE_OK) break;
+                if (hipEventRecord(e0, s) != hipSuccess) { rc = BSDE_EDEVICE; break; }
+                for (int r = 0; r < reps && rc == BSDE_OK; ++r)
+                    for (int k = 0; k < nsample && rc == BSDE_OK; ++k)
+                        rc = enqueue_step(*plan, g, w, sample[k], false, s, nullptr);
+                if (rc != BSDE_OK) break;
+                float ms = 0.0f;
+                if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                    hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                    rc = BSDE_EDEVICE;
+                    break;
+                }
+                if (pass == 0) ++tried;
+                if (t[ci] == 0.0f || ms < t[ci]) t[ci] = ms;
             }
-            ++tried;
-            if (best == 0.0f || ms < best) {
-                best = ms;
-                best_c = c;
+        }
+        for (size_t ci = 0; ci < cand.size() && rc == BSDE_OK; ++ci) {
+            if (best == 0.0f || t[ci] < best) {
+                best = t[ci];
+                best_c = cand[ci];
             }
         }
         if (rc == BSDE_OK) rc = apply_config(*plan, g, best_c);
@@ -1309,7 +1325,7 @@ bsde_status bsde_autotune(bsde_plan_t plan, void *ws, const bsde_io *io, void *s
             rep->path = best_c.path;
             rep->points_per_lane = best_c.P;
             rep->node_groups = best_c.G;
-            rep->best_ms_per_step = best / reps;
+            rep->best_ms_per_step = best / (reps * nsample);
         }
     }
     (void)hipEventDestroy(e0);
