@@ -232,9 +232,10 @@ typedef struct {
  * shape that fits (fused kernel with 1, 2 or 4 points per lane and 1 or 2
  * node groups; the direct kernel when none fits) the group's first time step
  * and three more spread over its steps (so a batch's shrinking set of active
- * instances counts) are launched `reps` times and timed with hipEvents, in
- * two passes over the shapes (each keeps its faster pass); the fastest shape
- * is kept in the plan.  Replaces the default shape (or BSDE_SWEEP); drops the
+ * instances counts) are run `reps` times, replayed from a captured graph as
+ * a solve would run them (directly when BSDE_GRAPH=0), and timed with
+ * hipEvents, in two passes over the shapes (each keeps its faster pass); the
+ * fastest shape is kept in the plan.  Replaces the default shape (or BSDE_SWEEP); drops the
  * plan's captured graphs.  Synchronises the stream.  Must not run while
  * another solve uses the plan.  rep may be NULL.
  * Errors: BSDE_EINVAL (as bsde_solve_batched, or reps < 1), BSDE_EDEVICE.

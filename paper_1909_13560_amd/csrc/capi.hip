@@ -1298,17 +1298,53 @@ bsde_status bsde_autotune(bsde_plan_t plan, void *ws, const bsde_io *io, void *s
                 rc = enqueue_step(*plan, g, w, 0, false, s, nullptr);  // warm-up
                 if (rc == BSDE_OK && nsample > 1) rc = enqueue_step(*plan, g, w, 1, false, s, nullptr);
                 if (rc != BSDE_OK) break;
-                if (hipEventRecord(e0, s) != hipSuccess) { rc = BSDE_EDEVICE; break; }
-                for (int r = 0; r < reps && rc == BSDE_OK; ++r)
-                    for (int k = 0; k < nsample && rc == BSDE_OK; ++k)
-                        rc = enqueue_step(*plan, g, w, sample[k], false, s, nullptr);
-                if (rc != BSDE_OK) break;
-                float ms = 0.0f;
-                if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                    hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-                    rc = BSDE_EDEVICE;
-                    break;
+                auto timed_steps = [&](hipStream_t q) {
+                    bsde_status r2 = BSDE_OK;
+                    for (int r = 0; r < reps && r2 == BSDE_OK; ++r)
+                        for (int k = 0; k < nsample && r2 == BSDE_OK; ++k)
+                            r2 = enqueue_step(*plan, g, w, sample[k], false, q, nullptr);
+                    return r2;
+                };
+                // the timed steps run the way a solve runs: replayed from a
+                // graph (launches from a graph and direct launches rank the
+                // shapes differently), or directly when the plan does not use
+                // graphs
+                hipGraphExec_t exec = nullptr;
+                if (plan->use_graphs) {
+                    if (!plan->capture_stream &&
+                        hipStreamCreateWithFlags(&plan->capture_stream, hipStreamNonBlocking) != hipSuccess) {
+                        rc = BSDE_EDEVICE;
+                        break;
+                    }
+                    hipStream_t cs = plan->capture_stream;
+                    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+                        rc = BSDE_EDEVICE;
+                        break;
+                    }
+                    rc = timed_steps(cs);
+                    hipGraph_t graph = nullptr;
+                    const hipError_t ec = hipStreamEndCapture(cs, &graph);
+                    if (rc == BSDE_OK && ec == hipSuccess &&
+                        hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess)
+                        rc = BSDE_EDEVICE;
+                    if (graph) (void)hipGraphDestroy(graph);
+                    if (rc == BSDE_OK && ec != hipSuccess) rc = BSDE_EDEVICE;
+                    if (rc == BSDE_OK && hipGraphLaunch(exec, s) != hipSuccess) rc = BSDE_EDEVICE;
+                    if (rc != BSDE_OK) {
+                        if (exec) (void)hipGraphExecDestroy(exec);
+                        break;
+                    }
                 }
+                float ms = 0.0f;
+                if (hipEventRecord(e0, s) != hipSuccess) rc = BSDE_EDEVICE;
+                if (rc == BSDE_OK) rc = exec ? (hipGraphLaunch(exec, s) == hipSuccess ? BSDE_OK : BSDE_EDEVICE)
+                                             : timed_steps(s);
+                if (rc == BSDE_OK &&
+                    (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                     hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                    rc = BSDE_EDEVICE;
+                if (exec) (void)hipGraphExecDestroy(exec);
+                if (rc != BSDE_OK) break;
                 if (pass == 0) ++tried;
                 if (t[ci] == 0.0f || ms < t[ci]) t[ci] = ms;
             }
