@@ -754,6 +754,17 @@ bool valid_io(bsde_plan_t plan, void *ws, const bsde_io *io, int count)
     return true;
 }
 
+// Two hipEvents released on every path out of the scope that made them.
+struct EventPair {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    bool create() { return hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess; }
+    ~EventPair()
+    {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    }
+};
+
 bsde_status solve_impl(bsde_plan_t plan, void *ws, const bsde_io *io, int count, void *stream,
                        bsde_stats *st)
 {
@@ -761,12 +772,11 @@ bsde_status solve_impl(bsde_plan_t plan, void *ws, const bsde_io *io, int count,
     hipStream_t s = static_cast<hipStream_t>(stream);
     char *w = static_cast<char *>(ws);
     const bool stats = st != nullptr;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
+    EventPair ev;
     unsigned long long *nonfinite = nullptr;
     if (stats) {
-        HIP_OK(hipEventCreate(&e0));
-        HIP_OK(hipEventCreate(&e1));
-        HIP_OK(hipEventRecord(e0, s));
+        if (!ev.create()) return BSDE_EDEVICE;
+        HIP_OK(hipEventRecord(ev.e0, s));
         // per-wave counters and the totals start at zero
         HIP_OK(bsde::launch_clear(reinterpret_cast<unsigned long long *>(w + plan->stats_off),
                                   plan->stats_bytes / 8, s));
@@ -776,12 +786,9 @@ bsde_status solve_impl(bsde_plan_t plan, void *ws, const bsde_io *io, int count,
                                       : enqueue_solve(*plan, w, io, stats, nonfinite, s);
     if (rc != BSDE_OK) return rc;
     if (!stats) return BSDE_OK;
-    HIP_OK(hipEventRecord(e1, s));
-    HIP_OK(hipEventSynchronize(e1));
-    rc = finish_stats(plan, w, s, e0, e1, st);
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    return rc;
+    HIP_OK(hipEventRecord(ev.e1, s));
+    HIP_OK(hipEventSynchronize(ev.e1));
+    return finish_stats(plan, w, s, ev.e0, ev.e1, st);
 }
 
 }  // namespace
@@ -1265,9 +1272,9 @@ bsde_status bsde_autotune(bsde_plan_t plan, void *ws, const bsde_io *io, void *s
     // the descriptors are rewritten (synchronously) for every candidate shape:
     // no kernel of the stream may still read them
     HIP_OK(hipStreamSynchronize(s));
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    HIP_OK(hipEventCreate(&e0));
-    HIP_OK(hipEventCreate(&e1));
+    EventPair ev;
+    if (!ev.create()) return BSDE_EDEVICE;
+    hipEvent_t e0 = ev.e0, e1 = ev.e1;
     int tried = 0;
     for (Group &g : plan->groups) {
         std::vector<SweepConfig> cand;
@@ -1364,8 +1371,6 @@ bsde_status bsde_autotune(bsde_plan_t plan, void *ws, const bsde_io *io, void *s
             rep->best_ms_per_step = best / (reps * nsample);
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     if (rep) rep->candidates = tried;
     return rc;
 }
