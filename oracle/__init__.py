@@ -81,6 +81,9 @@ def _load():
         lib.oracle_spline_eval.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                            dp, ctypes.c_int, dp, dp]
         lib.oracle_spline_eval.restype = ctypes.c_int
+        lib.oracle_first_step_points_2d.argtypes = [
+            ctypes.POINTER(_Problem), dp, dp, ctypes.c_int, ctypes.POINTER(ctypes.c_long), dp, dp]
+        lib.oracle_first_step_points_2d.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -140,6 +143,32 @@ def solve(pb: dict, init_y: np.ndarray, init_z: np.ndarray, n_stop: int = 0):
         raise ValueError(f"oracle_solve failed with code {rc}")
     return y, z, {"picard_iter_max": st.picard_iter_max,
                   "picard_nonconverged": st.picard_nonconverged}
+
+
+def first_step_points_2d(pb: dict, init_y: np.ndarray, init_z: np.ndarray, idx):
+    """The first backward step (layer N-K) of a d = 2 problem at the flat grid
+    indices ``idx`` (i0 * n_x[1] + i1), with the arithmetic of ``solve``.
+
+    Returns ``(y, z)`` with y of shape (m,) and z of shape (2, m).  For checks
+    at grid sizes where a whole step of the serial oracle takes minutes.
+    """
+    lib = _load()
+    if int(pb["d"]) != 2:
+        raise ValueError("first_step_points_2d needs a d = 2 problem")
+    n0, n1 = (int(v) for v in pb["n_x"])
+    K = max(int(pb["k_y"]), int(pb["k_z"]))
+    iy = np.ascontiguousarray(init_y, dtype=np.float64).reshape(K, n0 * n1)
+    iz = np.ascontiguousarray(init_z, dtype=np.float64).reshape(K, 2, n0 * n1)
+    ix = np.ascontiguousarray(idx, dtype=np.int64).ravel()
+    y = np.empty(ix.size)
+    z = np.empty((ix.size, 2))
+    s = _to_struct(pb, int(pb["n_t"]) - K)
+    rc = lib.oracle_first_step_points_2d(
+        ctypes.byref(s), _ptr(iy), _ptr(iz), int(ix.size),
+        ix.ctypes.data_as(ctypes.POINTER(ctypes.c_long)), _ptr(y), _ptr(z))
+    if rc != 0:
+        raise ValueError(f"oracle_first_step_points_2d failed with code {rc}")
+    return y, np.ascontiguousarray(z.T)
 
 
 def gauss_hermite(L: int):

@@ -405,121 +405,204 @@ static double tensor_eval(const tspline *s, int n0, int n1, double xmin0, double
     return acc;
 }
 
+/* Everything one backward step of the 2-D sweep reads: the grid, the
+ * quadrature rule, the coefficients of Tables 1-2 and the ring of K+1 layers
+ * (each with its tensor splines). */
+typedef struct {
+    int N, Ky, Kz, K, L, n0, n1;
+    double dt, xmin0, dx0, xmin1, dx1;
+    double a[ORACLE_MAX_L], w[ORACLE_MAX_L], gy[7], gz[7];
+    tspline ring[7][3]; /* per ring slot: 3 fields (y, z1, z2) x 4 arrays */
+    double *mem, *work;
+} ctx2;
+
+#define SLOT2(c, n) ((c)->ring[(n) % ((c)->K + 1)])
+
+static void ctx2_free(ctx2 *c)
+{
+    free(c->mem);
+    free(c->work);
+}
+
+/* Grid, quadrature, coefficients and the K initial layers with their tensor
+ * splines (Section 3.1 steps 1-2). */
+static int ctx2_init(const oracle_problem *pb, const double *init_y, const double *init_z,
+                     ctx2 *c)
+{
+    c->N = pb->n_t;
+    c->Ky = pb->k_y;
+    c->Kz = pb->k_z;
+    c->K = c->Ky > c->Kz ? c->Ky : c->Kz;
+    c->L = pb->L;
+    c->n0 = pb->n_x[0];
+    c->n1 = pb->n_x[1];
+    const long np = (long)c->n0 * c->n1;
+    c->dt = pb->T / c->N;
+    c->xmin0 = pb->x_min[0];
+    c->dx0 = (pb->x_max[0] - pb->x_min[0]) / (c->n0 - 1);
+    c->xmin1 = pb->x_min[1];
+    c->dx1 = (pb->x_max[1] - pb->x_min[1]) / (c->n1 - 1);
+    c->mem = NULL;
+    c->work = NULL;
+
+    int rc = oracle_gauss_hermite(c->L, c->a, c->w);
+    if (rc) return rc;
+    for (int l = 0; l < c->L; ++l) c->w[l] /= sqrt(M_PI); /* one pi^(-1/2) per axis */
+    oracle_gamma(1, c->Ky, c->gy);
+    oracle_gamma(2, c->Kz, c->gz);
+
+    c->mem = (double *)malloc(sizeof(double) * (size_t)np * 12 * (c->K + 1));
+    int nmax = c->n0 > c->n1 ? c->n0 : c->n1;
+    c->work = (double *)malloc(sizeof(double) * (size_t)2 * nmax);
+    if (!c->mem || !c->work) {
+        ctx2_free(c);
+        return ORACLE_ENOMEM;
+    }
+    for (int s = 0; s <= c->K; ++s)
+        for (int f = 0; f < 3; ++f) {
+            double *b = c->mem + (size_t)np * (12 * s + 4 * f);
+            c->ring[s][f].v = b;
+            c->ring[s][f].Mxx = b + np;
+            c->ring[s][f].Myy = b + 2 * np;
+            c->ring[s][f].Mxxyy = b + 3 * np;
+        }
+    for (int r = 0; r < c->K; ++r) {
+        int n = c->N - c->K + 1 + r;
+        memcpy(SLOT2(c, n)[0].v, init_y + (size_t)r * np, sizeof(double) * np);
+        memcpy(SLOT2(c, n)[1].v, init_z + (size_t)r * 2 * np, sizeof(double) * np);
+        memcpy(SLOT2(c, n)[2].v, init_z + (size_t)r * 2 * np + np, sizeof(double) * np);
+        for (int f = 0; f < 3; ++f)
+            tensor_spline(c->n0, c->n1, c->dx0, c->dx1, &SLOT2(c, n)[f], c->work);
+    }
+    return ORACLE_OK;
+}
+
+/* Layer n at grid point (i0, i1) from layers n+1..n+K (eq (20)-(21), Section
+ * 3.1 step 3): y to out[0], z1 and z2 to out[1], out[2]; *it receives the
+ * Picard iterations, *conv whether the tolerance was met. */
+static void point2(const oracle_problem *pb, const ctx2 *c, int n, int i0, int i1, double *out,
+                   int *it_out, int *conv_out)
+{
+    const int Ky = c->Ky, Kz = c->Kz, K = c->K, L = c->L, n0 = c->n0, n1 = c->n1;
+    const double dt = c->dt, xmin0 = c->xmin0, dx0 = c->dx0, xmin1 = c->xmin1, dx1 = c->dx1;
+    const double *a = c->a, *w = c->w, *gy = c->gy, *gz = c->gz;
+    const double tn = n * dt;
+    const double x0 = xmin0 + i0 * dx0, x1 = xmin1 + i1 * dx1;
+    double Ef[7] = {0}, EfW[7][2] = {{0}}, Ez[7][2] = {{0}}, EyK = 0.0;
+    for (int j = 1; j <= K; ++j) {
+        const tspline *lj = SLOT2(c, n + j);
+        const double tj = (n + j) * dt, sq = sqrt(2.0 * j * dt);
+        for (int l0 = 0; l0 < L; ++l0)
+            for (int l1 = 0; l1 < L; ++l1) {
+                const double dW0 = sq * a[l0], dW1 = sq * a[l1];
+                const double wt = w[l0] * w[l1];
+                const double X0 = x0 + pb->drift[0] * j * dt +
+                                  pb->vol[0][0] * dW0 + pb->vol[0][1] * dW1;
+                const double X1 = x1 + pb->drift[1] * j * dt +
+                                  pb->vol[1][0] * dW0 + pb->vol[1][1] * dW1;
+                double yh = tensor_eval(&lj[0], n0, n1, xmin0, dx0, xmin1, dx1, X0, X1);
+                double zh[2];
+                zh[0] = tensor_eval(&lj[1], n0, n1, xmin0, dx0, xmin1, dx1, X0, X1);
+                zh[1] = tensor_eval(&lj[2], n0, n1, xmin0, dx0, xmin1, dx1, X0, X1);
+                const double fh = driver(pb, tj, yh, zh);
+                Ef[j] += wt * fh;
+                EfW[j][0] += wt * fh * dW0;
+                EfW[j][1] += wt * fh * dW1;
+                Ez[j][0] += wt * zh[0];
+                Ez[j][1] += wt * zh[1];
+                if (j == Ky) EyK += wt * yh;
+            }
+    }
+    double zn[2];
+    for (int cc = 0; cc < 2; ++cc) {
+        double zs = Ez[1][cc];
+        for (int j = 1; j <= Kz; ++j) zs += gz[j] * (EfW[j][cc] - Ez[j][cc]);
+        zn[cc] = zs / gz[0];
+    }
+    double Cy = EyK;
+    for (int j = 1; j <= Ky; ++j) Cy += Ky * dt * gy[j] * Ef[j];
+    const double h0 = Ky * dt * gy[0];
+    const long k = (long)i0 * n1 + i1;
+    double y = SLOT2(c, n + 1)[0].v[k];
+    int it = 0, conv = 0;
+    while (it < pb->picard_max) {
+        double yn = Cy + h0 * driver(pb, tn, y, zn);
+        ++it;
+        double dy = fabs(yn - y);
+        y = yn;
+        if (pb->picard_tol > 0.0 && dy <= pb->picard_tol * fmax(1.0, fabs(y))) {
+            conv = 1;
+            break;
+        }
+    }
+    out[0] = y;
+    out[1] = zn[0];
+    out[2] = zn[1];
+    *it_out = it;
+    *conv_out = conv;
+}
+
 static int solve2(const oracle_problem *pb, const double *init_y, const double *init_z,
                   double *y_out, double *z_out, oracle_stats *st)
 {
-    const int N = pb->n_t, Ky = pb->k_y, Kz = pb->k_z, K = Ky > Kz ? Ky : Kz;
-    const int L = pb->L, n0 = pb->n_x[0], n1 = pb->n_x[1];
-    const long np = (long)n0 * n1;
-    const double dt = pb->T / N;
-    const double xmin0 = pb->x_min[0], dx0 = (pb->x_max[0] - pb->x_min[0]) / (n0 - 1);
-    const double xmin1 = pb->x_min[1], dx1 = (pb->x_max[1] - pb->x_min[1]) / (n1 - 1);
-
-    double a[ORACLE_MAX_L], w[ORACLE_MAX_L], gy[7], gz[7];
-    int rc = oracle_gauss_hermite(L, a, w);
+    ctx2 c;
+    int rc = ctx2_init(pb, init_y, init_z, &c);
     if (rc) return rc;
-    for (int l = 0; l < L; ++l) w[l] /= sqrt(M_PI); /* one pi^(-1/2) per axis */
-    oracle_gamma(1, Ky, gy);
-    oracle_gamma(2, Kz, gz);
-
-    /* per ring slot: 3 fields (y, z1, z2) x 4 arrays */
-    tspline ring[7][3];
-    double *mem = (double *)malloc(sizeof(double) * (size_t)np * 12 * (K + 1));
-    int nmax = n0 > n1 ? n0 : n1;
-    double *work = (double *)malloc(sizeof(double) * (size_t)2 * nmax);
-    if (!mem || !work) { free(mem); free(work); return ORACLE_ENOMEM; }
-    for (int s = 0; s <= K; ++s)
-        for (int f = 0; f < 3; ++f) {
-            double *b = mem + (size_t)np * (12 * s + 4 * f);
-            ring[s][f].v = b;
-            ring[s][f].Mxx = b + np;
-            ring[s][f].Myy = b + 2 * np;
-            ring[s][f].Mxxyy = b + 3 * np;
-        }
-#define SLOT2(n) (ring[(n) % (K + 1)])
-    for (int r = 0; r < K; ++r) {
-        int n = N - K + 1 + r;
-        memcpy(SLOT2(n)[0].v, init_y + (size_t)r * np, sizeof(double) * np);
-        memcpy(SLOT2(n)[1].v, init_z + (size_t)r * 2 * np, sizeof(double) * np);
-        memcpy(SLOT2(n)[2].v, init_z + (size_t)r * 2 * np + np, sizeof(double) * np);
-        for (int f = 0; f < 3; ++f) tensor_spline(n0, n1, dx0, dx1, &SLOT2(n)[f], work);
-    }
-
+    const long np = (long)c.n0 * c.n1;
     int it_max = 0;
     long nonconv = 0;
-    for (int n = N - K; n >= pb->n_stop; --n) {
-        tspline *out = SLOT2(n);
-        const double tn = n * dt;
-        for (int i0 = 0; i0 < n0; ++i0)
-            for (int i1 = 0; i1 < n1; ++i1) {
-                const double x0 = xmin0 + i0 * dx0, x1 = xmin1 + i1 * dx1;
-                double Ef[7] = {0}, EfW[7][2] = {{0}}, Ez[7][2] = {{0}}, EyK = 0.0;
-                for (int j = 1; j <= K; ++j) {
-                    tspline *lj = SLOT2(n + j);
-                    const double tj = (n + j) * dt, sq = sqrt(2.0 * j * dt);
-                    for (int l0 = 0; l0 < L; ++l0)
-                        for (int l1 = 0; l1 < L; ++l1) {
-                            const double dW0 = sq * a[l0], dW1 = sq * a[l1];
-                            const double wt = w[l0] * w[l1];
-                            const double X0 = x0 + pb->drift[0] * j * dt +
-                                              pb->vol[0][0] * dW0 + pb->vol[0][1] * dW1;
-                            const double X1 = x1 + pb->drift[1] * j * dt +
-                                              pb->vol[1][0] * dW0 + pb->vol[1][1] * dW1;
-                            double yh = tensor_eval(&lj[0], n0, n1, xmin0, dx0, xmin1, dx1, X0, X1);
-                            double zh[2];
-                            zh[0] = tensor_eval(&lj[1], n0, n1, xmin0, dx0, xmin1, dx1, X0, X1);
-                            zh[1] = tensor_eval(&lj[2], n0, n1, xmin0, dx0, xmin1, dx1, X0, X1);
-                            const double fh = driver(pb, tj, yh, zh);
-                            Ef[j] += wt * fh;
-                            EfW[j][0] += wt * fh * dW0;
-                            EfW[j][1] += wt * fh * dW1;
-                            Ez[j][0] += wt * zh[0];
-                            Ez[j][1] += wt * zh[1];
-                            if (j == Ky) EyK += wt * yh;
-                        }
-                }
-                double zn[2];
-                for (int c = 0; c < 2; ++c) {
-                    double zs = Ez[1][c];
-                    for (int j = 1; j <= Kz; ++j) zs += gz[j] * (EfW[j][c] - Ez[j][c]);
-                    zn[c] = zs / gz[0];
-                }
-                double Cy = EyK;
-                for (int j = 1; j <= Ky; ++j) Cy += Ky * dt * gy[j] * Ef[j];
-                const double h0 = Ky * dt * gy[0];
-                const long k = (long)i0 * n1 + i1;
-                double y = SLOT2(n + 1)[0].v[k];
-                int it = 0, conv = 0;
-                while (it < pb->picard_max) {
-                    double yn = Cy + h0 * driver(pb, tn, y, zn);
-                    ++it;
-                    double dy = fabs(yn - y);
-                    y = yn;
-                    if (pb->picard_tol > 0.0 && dy <= pb->picard_tol * fmax(1.0, fabs(y))) {
-                        conv = 1;
-                        break;
-                    }
-                }
+    for (int n = c.N - c.K; n >= pb->n_stop; --n) {
+        tspline *out = SLOT2(&c, n);
+        for (int i0 = 0; i0 < c.n0; ++i0)
+            for (int i1 = 0; i1 < c.n1; ++i1) {
+                double r[3];
+                int it, conv;
+                point2(pb, &c, n, i0, i1, r, &it, &conv);
                 if (pb->picard_tol > 0.0 && !conv) ++nonconv;
                 if (it > it_max) it_max = it;
-                out[0].v[k] = y;
-                out[1].v[k] = zn[0];
-                out[2].v[k] = zn[1];
+                const long k = (long)i0 * c.n1 + i1;
+                out[0].v[k] = r[0];
+                out[1].v[k] = r[1];
+                out[2].v[k] = r[2];
             }
-        for (int f = 0; f < 3; ++f) tensor_spline(n0, n1, dx0, dx1, &out[f], work);
+        for (int f = 0; f < 3; ++f) tensor_spline(c.n0, c.n1, c.dx0, c.dx1, &out[f], c.work);
     }
-    memcpy(y_out, SLOT2(pb->n_stop)[0].v, sizeof(double) * np);
-    memcpy(z_out, SLOT2(pb->n_stop)[1].v, sizeof(double) * np);
-    memcpy(z_out + np, SLOT2(pb->n_stop)[2].v, sizeof(double) * np);
-#undef SLOT2
+    memcpy(y_out, SLOT2(&c, pb->n_stop)[0].v, sizeof(double) * np);
+    memcpy(z_out, SLOT2(&c, pb->n_stop)[1].v, sizeof(double) * np);
+    memcpy(z_out + np, SLOT2(&c, pb->n_stop)[2].v, sizeof(double) * np);
     if (st) {
         st->picard_iter_max = it_max;
         st->picard_nonconverged = nonconv;
     }
-    free(mem);
-    free(work);
+    ctx2_free(&c);
     return ORACLE_OK;
 }
+
+int oracle_first_step_points_2d(const oracle_problem *pb, const double *init_y,
+                                const double *init_z, int m, const long *idx, double *y_out,
+                                double *z_out)
+{
+    int rc = validate(pb);
+    if (rc) return rc;
+    if (pb->d != 2 || m < 0 || (m > 0 && (!idx || !y_out || !z_out))) return ORACLE_EINVAL;
+    const long np = (long)pb->n_x[0] * pb->n_x[1];
+    for (int q = 0; q < m; ++q)
+        if (idx[q] < 0 || idx[q] >= np) return ORACLE_EINVAL;
+    ctx2 c;
+    rc = ctx2_init(pb, init_y, init_z, &c);
+    if (rc) return rc;
+    for (int q = 0; q < m; ++q) {
+        double r[3];
+        int it, conv;
+        point2(pb, &c, c.N - c.K, (int)(idx[q] / c.n1), (int)(idx[q] % c.n1), r, &it, &conv);
+        y_out[q] = r[0];
+        z_out[2 * q] = r[1];
+        z_out[2 * q + 1] = r[2];
+    }
+    ctx2_free(&c);
+    return ORACLE_OK;
+}
+#undef SLOT2
 
 int oracle_solve(const oracle_problem *pb, const double *init_y, const double *init_z,
                  double *y_out, double *z_out, oracle_stats *st)

@@ -55,6 +55,14 @@ typedef struct {
 int oracle_solve(const oracle_problem *pb, const double *init_y, const double *init_z,
                  double *y_out, double *z_out, oracle_stats *st);
 
+/* d = 2 only: the first backward step (layer N-K) at the m grid points
+ * idx[q] = i0 * n_x[1] + i1, from the K initial layers, with the same
+ * arithmetic as oracle_solve.  y_out[q]; z_out[2q], z_out[2q+1] = z1, z2.
+ * For checks at grid sizes where a whole step is too slow. */
+int oracle_first_step_points_2d(const oracle_problem *pb, const double *init_y,
+                                const double *init_z, int m, const long *idx, double *y_out,
+                                double *z_out);
+
 /* Gauss-Hermite nodes a[0..L-1] and weights w[0..L-1] for exp(-x^2). */
 int oracle_gauss_hermite(int L, double *a, double *w);
 

@@ -450,6 +450,33 @@ def test_2d_basket_checkpoint(lib, orc):
     assert rel_err(z[1], zo[1]) <= TOL64
 
 
+def test_2d_full_size_basket_sampled(lib, orc):
+    # the benchmarked 2-D shape (1024 x 1024 grid, 128 steps, k = 3, 16 x 16
+    # nodes, the same launch shape): the whole grid's first layer on the GPU
+    # against the oracle at sampled points (a whole serial step takes minutes)
+    wl = W.basket_2d()
+    pb = dict(wl.problem)
+    K = max(pb["k_y"], pb["k_z"])
+    n0, n1 = pb["n_x"]
+    pb["n_stop"] = pb["n_t"] - K
+    iy, iz = wl.init_layers()
+    print(f"[case] {wl.name} fp64 n_stop={pb['n_stop']} sampled", flush=True)
+    y, z, rc, st = lib.solve(pb, iy, iz, stats=True)
+    assert rc == lib.BSDE_OK
+    rng = np.random.default_rng(1909)
+    rows = np.concatenate([[0, 1, 2, n0 // 2, n0 - 2, n0 - 1],
+                           np.arange(3, n0 - 2, 4), rng.integers(0, n0, 400)])
+    cols = np.concatenate([[0, 1, 63, 64, 65, n1 // 2, n1 - 2, n1 - 1],
+                           rng.integers(0, n1, rows.size - 8)])
+    cols = np.resize(cols, rows.size)
+    idx = np.unique(rows.astype(np.int64) * n1 + cols)
+    ys, zs = orc.first_step_points_2d(pb, iy, iz, idx)
+    ey = rel_err(y[idx], ys)
+    ez = max(rel_err(z[0, idx], zs[0]), rel_err(z[1, idx], zs[1]))
+    print(f"  {idx.size} points: rel err y {ey:.3e} z {ez:.3e}", flush=True)
+    assert ey <= TOL64 and ez <= TOL64
+
+
 def test_2d_autotune_reports_single_shape(lib, orc):
     # a two-dimensional plan has one kernel shape: autotune reports it and the
     # solve afterwards is unchanged

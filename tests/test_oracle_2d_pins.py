@@ -72,3 +72,24 @@ def test_exchange_option_sweep_against_margrabe(oracle_lib, rho):
     i = wl.node_index()
     assert abs(y[i] - ye[i]) < 1e-5
     assert abs(z[0, i] - ze[0, i]) < 1e-4 and abs(z[1, i] - ze[1, i]) < 1e-4
+
+
+def test_sampled_first_step_equals_whole_grid_step(oracle_lib):
+    # the sampled entry (used at grid sizes where a whole serial step takes
+    # minutes) returns the whole-grid sweep's first layer bit for bit, at
+    # corners, edges, a ragged interior and points whose nodes leave the box
+    wl = W.basket_2d(n_x=41, n_t=12, k=3, L=6)
+    pb = dict(wl.problem)
+    pb["n_x"] = [41, 37]
+    pb["x_max"] = [pb["x_max"][0], pb["x_min"][1] + 36 * (pb["x_max"][1] - pb["x_min"][1]) / 40]
+    rng = np.random.default_rng(7)  # any layers: the two paths must agree exactly
+    K, n = 3, 41 * 37
+    iy = rng.standard_normal((K, n))
+    iz = rng.standard_normal((K, 2, n))
+    y, z, _ = oracle_lib.solve(pb, iy, iz, n_stop=pb["n_t"] - K)
+    idx = np.array([0, 36, 40 * 37, 41 * 37 - 1, 18, 20 * 37, 20 * 37 + 36, 777, 1000, 1234])
+    ys, zs = oracle_lib.first_step_points_2d(pb, iy, iz, idx)
+    assert np.array_equal(ys, y[idx])
+    assert np.array_equal(zs[0], z[0, idx]) and np.array_equal(zs[1], z[1, idx])
+    with pytest.raises(ValueError):
+        oracle_lib.first_step_points_2d(pb, iy, iz, np.array([41 * 37]))
