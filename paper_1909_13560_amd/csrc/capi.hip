@@ -813,27 +813,13 @@ void pcr_base_coefficients(bsde::PcrCoef &c)
     c.s6 = 0.0;
 }
 
-// The truncated PCR as a filter on the right-hand side: apply its rounds to
-// a unit impulse (c), and fold in the second difference (d).
-void pcr_filter(const bsde::PcrCoef &pc, bsde::SplineFilter &f)
+// The truncated PCR's filters (compile-time constants of the (1, 4, 1)
+// system); the per-axis scale s6 is set per instance.
+void pcr_filter(bsde::SplineFilter &f)
 {
-    constexpr int T = bsde::kPcrTaps, H = T / 2;
-    double cur[T] = {0.0}, nxt[T];
-    cur[H] = 1.0;
-    int h = 1;
-    for (int r = 0; r < bsde::kPcrRounds; ++r, h <<= 1) {
-        for (int k = 0; k < T; ++k) {
-            const double lo = k - h >= 0 ? cur[k - h] : 0.0, hi = k + h < T ? cur[k + h] : 0.0;
-            nxt[k] = cur[k] - pc.kappa[r] * (lo + hi);
-        }
-        std::memcpy(cur, nxt, sizeof(cur));
-    }
-    for (int k = 0; k < T; ++k) f.c[k] = cur[k];
-    // d_m = c_{m-1} - 2 c_m + c_{m+1}, m = -32..32
-    for (int m = -H - 1; m <= H + 1; ++m) {
-        auto cc = [&](int q) { return (q >= -H && q <= H) ? cur[q + H] : 0.0; };
-        f.d[m + H + 1] = cc(m - 1) - 2.0 * cc(m) + cc(m + 1);
-    }
+    constexpr bsde::SplineTaps t = bsde::spline_taps();
+    for (int k = 0; k < bsde::kPcrTaps; ++k) f.c[k] = t.c[k];
+    for (int k = 0; k < bsde::kPcrTaps + 2; ++k) f.d[k] = t.d[k];
     f.s6[0] = f.s6[1] = 0.0;
 }
 
@@ -852,7 +838,7 @@ bsde_status plan_2d(const bsde_problem *pb, int batch, bsde_plan_t *out)
         }
     }
     pcr_base_coefficients(pl->pcr_base);
-    pcr_filter(pl->pcr_base, pl->filter2);
+    pcr_filter(pl->filter2);
     if (hipGetDevice(&pl->device) != hipSuccess) {
         delete pl;
         return BSDE_EDEVICE;

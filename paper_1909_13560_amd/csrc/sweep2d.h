@@ -39,12 +39,53 @@ struct alignas(16) Node2 {
 // Natural-spline second derivatives by the truncated PCR written as a
 // filter: M_i = s6 * sum_k c[k + 31] r~_{i+k} (r~ the odd extension of the
 // second differences), or for 32 <= i <= n - 33 directly from the values:
-// M_i = s6 * sum_k d[k + 32] v_{i+k}.
+// M_i = s6 * sum_k d[k + 32] v_{i+k}.  c and d are spline_taps(); lines of
+// at least kMinLine points use d throughout, on values reflected through the
+// line's end points.
 struct SplineFilter {
     double c[kPcrTaps];
     double d[kPcrTaps + 2];
     double s6[2];  // 6 / dx^2 / b_5 of axis 0, axis 1
 };
+constexpr int kMinLine = kPcrTaps / 2 + 2;  // 33: one reflection covers the filter's reach
+
+// The truncated PCR of the (1, 4, 1) system as line filters, constants of
+// the system evaluated at compile time: c[k + 31] acts on the odd extension
+// of the second differences, d[k + 32] on the values (the second difference
+// folded in: d_m = c_{m-1} - 2 c_m + c_{m+1}).
+struct SplineTaps {
+    double c[kPcrTaps];
+    double d[kPcrTaps + 2];
+};
+__host__ __device__ constexpr SplineTaps spline_taps()
+{
+    SplineTaps t{};
+    double kap[kPcrRounds] = {};
+    double av = 1.0, bv = 4.0;
+    for (int r = 0; r < kPcrRounds; ++r) {  // a' = -a^2/b, b' = b - 2a^2/b
+        kap[r] = av / bv;
+        bv = bv - 2.0 * kap[r] * av;
+        av = -kap[r] * av;
+    }
+    constexpr int T = kPcrTaps, H = T / 2;
+    double cur[T] = {}, nxt[T] = {};
+    cur[H] = 1.0;
+    for (int r = 0, h = 1; r < kPcrRounds; ++r, h *= 2) {  // the rounds on a unit impulse
+        for (int k = 0; k < T; ++k) {
+            const double lo = k - h >= 0 ? cur[k - h] : 0.0, hi = k + h < T ? cur[k + h] : 0.0;
+            nxt[k] = cur[k] - kap[r] * (lo + hi);
+        }
+        for (int k = 0; k < T; ++k) cur[k] = nxt[k];
+    }
+    for (int k = 0; k < T; ++k) t.c[k] = cur[k];
+    for (int m = -H - 1; m <= H + 1; ++m) {
+        const double cm = (m - 1 >= -H && m - 1 <= H) ? cur[m - 1 + H] : 0.0;
+        const double c0 = (m >= -H && m <= H) ? cur[m + H] : 0.0;
+        const double cp = (m + 1 >= -H && m + 1 <= H) ? cur[m + 1 + H] : 0.0;
+        t.d[m + H + 1] = cm - 2.0 * c0 + cp;
+    }
+    return t;
+}
 
 struct Sweep2Args {
     double *ring;

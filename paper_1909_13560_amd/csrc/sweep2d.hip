@@ -197,38 +197,97 @@ __device__ inline double spline_line(const double *v, long stride, int n, int i,
     return s6 * acc;
 }
 
-}  // namespace
+constexpr int kRun = 16;  // consecutive outputs per thread of the line passes
 
-__global__ void __launch_bounds__(256) spline2d_axes(const Sweep2Args a, int slot,
-                                                     const SplineFilter F)
+// Outputs i0 .. i0 + kRun - 1 (those < n) of the natural spline of one line
+// of n >= kMinLine values: M_i = s6 sum_k d[k] v~_{i-32+k}.  Each value is
+// loaded once and feeds every output within the filter's reach.  Beyond the
+// line's ends the values are reflected through the end points,
+// v~_{-j} = 2 v_0 - v_j and v~_{n-1+j} = 2 v_{n-1} - v_{n-1-j}: their second
+// differences are then the odd extension the natural end conditions call
+// for, so the values form holds at every point; M_0 = M_{n-1} = 0.
+__device__ inline void line_run(const double *v, long stride, int n, int i0, double s6,
+                                double *out, long ostride)
 {
-    const long i = blockIdx.x * 256L + threadIdx.x;
-    if (i >= (long)a.n0 * a.n1) return;
-    const int i0 = (int)(i / a.n1), i1 = (int)(i % a.n1);
-    double *base = a.ring + (size_t)(12 * slot) * a.plane;
-    const size_t o = pidx(a, i0, i1);
-    for (int f = 0; f < 3; ++f) {
-        double *v = base + (size_t)(4 * f) * a.plane;
-        const double *col = v + pidx(a, 0, i1);   // axis-0 line through the point
-        const double *rowp = v + pidx(a, i0, 0);  // axis-1 line
-        v[a.plane + o] = spline_line(col, a.npad1, a.n0, i0, F, F.s6[0]);
-        v[2 * a.plane + o] = spline_line(rowp, 1, a.n1, i1, F, F.s6[1]);
+    constexpr SplineTaps T = spline_taps();
+    constexpr int H = kPcrTaps / 2 + 1;  // values on each side of an output
+    double acc[kRun];
+#pragma unroll
+    for (int r = 0; r < kRun; ++r) acc[r] = 0.0;
+    if (i0 >= H && i0 + kRun - 1 + H <= n - 1) {  // clear of both ends
+        const double *p = v + (long)(i0 - H) * stride;
+#pragma unroll
+        for (int m = 0; m < kRun + 2 * H; ++m) {
+            const double x = p[(long)m * stride];
+#pragma unroll
+            for (int r = 0; r < kRun; ++r)
+                if (m - r >= 0 && m - r <= 2 * H) acc[r] = fma(T.d[m - r], x, acc[r]);
+        }
+    } else {
+        const double v0 = v[0], vn = v[(long)(n - 1) * stride];
+#pragma unroll
+        for (int m = 0; m < kRun + 2 * H; ++m) {
+            const int k = i0 - H + m;
+            // reflected index; clamped too for the loads of outputs past the
+            // end of a partial run, which are not stored
+            const int kk = min(max(k < 0 ? -k : (k > n - 1 ? 2 * (n - 1) - k : k), 0), n - 1);
+            const double y = v[(long)kk * stride];
+            const double x = k < 0 ? 2.0 * v0 - y : (k > n - 1 ? 2.0 * vn - y : y);
+#pragma unroll
+            for (int r = 0; r < kRun; ++r)
+                if (m - r >= 0 && m - r <= 2 * H) acc[r] = fma(T.d[m - r], x, acc[r]);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < kRun; ++r) {
+        const int i = i0 + r;
+        if (i < n) out[(long)i * ostride] = (i == 0 || i == n - 1) ? 0.0 : s6 * acc[r];
     }
 }
 
-__global__ void __launch_bounds__(256) spline2d_cross(const Sweep2Args a, int slot,
-                                                      const SplineFilter F)
+// The same outputs for lines shorter than kMinLine, one at a time.
+__device__ inline void line_run_short(const double *v, long stride, int n, int i0,
+                                      const SplineFilter &F, double s6, double *out, long ostride)
 {
-    const long i = blockIdx.x * 256L + threadIdx.x;
-    if (i >= (long)a.n0 * a.n1) return;
-    const int i0 = (int)(i / a.n1), i1 = (int)(i % a.n1);
-    double *base = a.ring + (size_t)(12 * slot) * a.plane;
-    const size_t o = pidx(a, i0, i1);
-    for (int f = 0; f < 3; ++f) {
-        double *v = base + (size_t)(4 * f) * a.plane;
-        const double *mxx_row = v + a.plane + pidx(a, i0, 0);
-        v[3 * a.plane + o] = spline_line(mxx_row, 1, a.n1, i1, F, F.s6[1]);
-    }
+    for (int i = i0; i < min(i0 + kRun, n); ++i)
+        out[(long)i * ostride] = spline_line(v, stride, n, i, F, s6);
+}
+
+}  // namespace
+
+// M_xx of field blockIdx.y (y, z1, z2): lines along axis 0.  Thread t:
+// column t % n1 (adjacent lanes read adjacent columns), rows from
+// kRun * (t / n1).
+__global__ void __launch_bounds__(256) spline2d_cols(const Sweep2Args a, int slot,
+                                                     const SplineFilter F)
+{
+    const long t = blockIdx.x * 256L + threadIdx.x;
+    if (t >= (long)a.n1 * ((a.n0 + kRun - 1) / kRun)) return;
+    const int i1 = (int)(t % a.n1), i0 = (int)(t / a.n1) * kRun;
+    double *col = a.ring + (size_t)(12 * slot + 4 * blockIdx.y) * a.plane + pidx(a, 0, i1);
+    if (a.n0 >= kMinLine)
+        line_run(col, a.npad1, a.n0, i0, F.s6[0], col + a.plane, a.npad1);
+    else
+        line_run_short(col, a.npad1, a.n0, i0, F, F.s6[0], col + a.plane, a.npad1);
+}
+
+// Lines along axis 1 of field blockIdx.y / 2: the values give M_yy
+// (blockIdx.y even), M_xx gives M_xxyy (odd).  Thread t: row t % n0, columns
+// from kRun * (t / n0), so that a wavefront takes one branch of line_run.
+__global__ void __launch_bounds__(256) spline2d_rows(const Sweep2Args a, int slot,
+                                                     const SplineFilter F)
+{
+    const long t = blockIdx.x * 256L + threadIdx.x;
+    if (t >= (long)a.n0 * ((a.n1 + kRun - 1) / kRun)) return;
+    const int i0 = (int)(t % a.n0), i1 = (int)(t / a.n0) * kRun;
+    const int f = blockIdx.y >> 1, g = blockIdx.y & 1;
+    double *row = a.ring + (size_t)(12 * slot + 4 * f) * a.plane + pidx(a, i0, 0);
+    const double *src = row + (size_t)g * a.plane;
+    double *dst = row + (size_t)(2 + g) * a.plane;
+    if (a.n1 >= kMinLine)
+        line_run(src, 1, a.n1, i1, F.s6[1], dst, 1);
+    else
+        line_run_short(src, 1, a.n1, i1, F, F.s6[1], dst, 1);
 }
 
 // Ghost points: the data of the nearest grid point with the derivative
@@ -297,12 +356,14 @@ hipError_t launch_sweep2d(const Sweep2Args &a, hipStream_t s)
 
 hipError_t launch_spline2d(const Sweep2Args &a, int slot, const SplineFilter &f, hipStream_t s)
 {
-    const long np = (long)a.n0 * a.n1;
-    const int blocks = (int)((np + 255) / 256);
-    hipLaunchKernelGGL(spline2d_axes, dim3(blocks), dim3(256), 0, s, a, slot, f);
+    const long tc = (long)a.n1 * ((a.n0 + kRun - 1) / kRun);
+    hipLaunchKernelGGL(spline2d_cols, dim3((unsigned)((tc + 255) / 256), 3), dim3(256), 0, s, a,
+                       slot, f);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(spline2d_cross, dim3(blocks), dim3(256), 0, s, a, slot, f);
+    const long tr = (long)a.n0 * ((a.n1 + kRun - 1) / kRun);
+    hipLaunchKernelGGL(spline2d_rows, dim3((unsigned)((tr + 255) / 256), 6), dim3(256), 0, s, a,
+                       slot, f);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int npad0 = (int)(a.plane / a.npad1);
