@@ -348,7 +348,7 @@ bsde_status build_instance2(const bsde_problem &p, Instance2 &in)
     in.plane = (size_t)in.npad0 * in.npad1;
     const int tiles = ((in.n0 + bsde::kTile2R - 1) / bsde::kTile2R) *
                       ((in.n1 + bsde::kTile2C - 1) / bsde::kTile2C);
-    in.nwaves = tiles * bsde::kTile2R;
+    in.nwaves = tiles * bsde::kWaves2;
     return BSDE_OK;
 }
 
@@ -1228,7 +1228,7 @@ bsde_status bsde_profile_kernels(bsde_plan_t plan, void *ws, const bsde_io *io, 
         kt->path = 2;
         kt->points_per_lane = 1;
         kt->node_groups = 1;
-        kt->blocks = in.nwaves / bsde::kTile2R;
+        kt->blocks = in.nwaves / bsde::kWaves2;
         kt->lds_bytes = 0;
         return BSDE_OK;
     }

@@ -60,7 +60,7 @@ __device__ inline void row_nodes(const Sweep2Args &a, const double2 *uv, const N
 
 }  // namespace
 
-// One time step: layer n from layers n+1..n+K.  Block = 4 x 64 points.
+// One time step: layer n from layers n+1..n+K.  Block = kTile2R x kTile2C points.
 // Dynamic LDS: (U, V) of 3 functions x 4 rows x a.win columns.
 __global__ void __launch_bounds__(256) sweep2d(const Sweep2Args a)
 {
@@ -150,8 +150,8 @@ __global__ void __launch_bounds__(256) sweep2d(const Sweep2Args a)
         it_max = wave_max_u32(it_max);
         it_sum = wave_sum_u32(it_sum);
         nonconv = wave_sum_u32(nonconv);
-        if (c == 0) {
-            const int w = idx * kTile2R + r;
+        if ((tid & 63) == 0) {
+            const int w = idx * kWaves2 + tid / 64;
             a.st_iter_max[w] = max(a.st_iter_max[w], it_max);
             a.st_iter_sum[w] += it_sum;
             a.st_nonconv[w] += nonconv;
