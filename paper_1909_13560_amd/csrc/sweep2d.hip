@@ -61,8 +61,8 @@ __device__ inline void row_nodes(const Sweep2Args &a, const double2 *uv, const N
 }  // namespace
 
 // One time step: layer n from layers n+1..n+K.  Block = kTile2R x kTile2C points.
-// Dynamic LDS: (U, V) of 3 functions x 4 rows x a.win columns.
-__global__ void __launch_bounds__(256) sweep2d(const Sweep2Args a)
+// Dynamic LDS: (U, V) of 3 functions x kTile2R rows x a.win columns.
+__global__ void __launch_bounds__(kThreads2) sweep2d(const Sweep2Args a)
 {
     extern __shared__ double2 uv[];
     __shared__ Node2 ntab[64];
@@ -80,12 +80,12 @@ __global__ void __launch_bounds__(256) sweep2d(const Sweep2Args a)
             const int rowi = (j - 1) * a.L + l0;
             const Node2Row row = a.rows[rowi];
             const int W = kTile2C + row.m1hi - row.m1lo + 2;
-            for (int l1 = tid; l1 < a.L; l1 += 256) {
+            for (int l1 = tid; l1 < a.L; l1 += kThreads2) {
                 ntab[l1] = a.nodes[(size_t)rowi * a.L + l1];
                 nm1[l1] = a.m1[(size_t)rowi * a.L + l1];
             }
             // axis-0 evaluation at s0 for the tile rows and the window columns
-            for (int e = tid; e < kTile2R * W; e += 256) {
+            for (int e = tid; e < kTile2R * W; e += kThreads2) {
                 const int rr = e / W, cc = e - rr * W;
                 const size_t o = pidx(a, t0 + rr + row.m0, t1 + row.m1lo + cc);
                 const size_t o1 = o + a.npad1;
@@ -350,7 +350,7 @@ size_t sweep2d_lds(int win) { return (size_t)3 * kTile2R * win * sizeof(double2)
 hipError_t launch_sweep2d(const Sweep2Args &a, hipStream_t s)
 {
     const int tiles = ((a.n0 + kTile2R - 1) / kTile2R) * ((a.n1 + kTile2C - 1) / kTile2C);
-    hipLaunchKernelGGL(sweep2d, dim3(tiles), dim3(256), sweep2d_lds(a.win), s, a);
+    hipLaunchKernelGGL(sweep2d, dim3(tiles), dim3(kThreads2), sweep2d_lds(a.win), s, a);
     return hipGetLastError();
 }
 
