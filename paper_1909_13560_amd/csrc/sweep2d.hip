@@ -34,27 +34,63 @@ __device__ inline int uv_index(const Sweep2Args &a, int f, int rr, int cc)
     return (f * kTile2R + rr) * a.win + cc;
 }
 
-// The L nodes l1 of one axis-0 row of layer j, for the lane's point.
+// Node record through the constant address space: the address is the same
+// for the whole wavefront, so this compiles to scalar loads into SGPRs.
+__device__ inline Node2 load_node2(const Node2 *p)
+{
+    const __attribute__((address_space(4))) Node2 *q =
+        (const __attribute__((address_space(4))) Node2 *)p;
+    Node2 n;
+    n.B1 = q->B1;
+    n.C1 = q->C1;
+    n.D1 = q->D1;
+    n.cfy = q->cfy;
+    n.cfz1 = q->cfz1;
+    n.cfz2 = q->cfz2;
+    n.cz = q->cz;
+    n.cy = q->cy;
+    return n;
+}
+
+template <bool LASTY>
+__device__ inline void node2_accumulate(const Sweep2Args &a, const double2 *uv, const Node2 &nd,
+                                        int r, int e, double &Y, double &Z1, double &Z2)
+{
+    double h[3];
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+        const double2 p0 = uv[uv_index(a, f, r, e)], p1 = uv[uv_index(a, f, r, e + 1)];
+        h[f] = fma(nd.B1, p1.x - p0.x, fma(nd.C1, p0.y, fma(nd.D1, p1.y, p0.x)));
+    }
+    const double fh = f_linear2(a.drv, h[0], h[1], h[2]);
+    Y = fma(nd.cfy, fh, Y);
+    if (LASTY) Y = fma(nd.cy, h[0], Y);
+    Z1 = fma(nd.cfz1, fh, fma(nd.cz, h[1], Z1));
+    Z2 = fma(nd.cfz2, fh, fma(nd.cz, h[2], Z2));
+}
+
+// The L nodes l1 of one axis-0 row of layer j, for the lane's point.  The
+// node records come through scalar loads and the axis-1 offsets, one per
+// lane in mv, through readlane, so the only per-node LDS reads are the
+// (U, V) records; two nodes per iteration share one wait.
 template <bool LASTY>
 __device__ inline void row_nodes(const Sweep2Args &a, const double2 *uv, const Node2 *ntab,
-                                 const int *nm1, int r, int c, int m1lo, double &Y, double &Z1,
+                                 int mv, int r, int c, int m1lo, double &Y, double &Z1,
                                  double &Z2)
 {
+    int l1 = 0;
 #pragma unroll 1
-    for (int l1 = 0; l1 < a.L; ++l1) {
-        const Node2 nd = ntab[l1];
-        const int e = c + nm1[l1] - m1lo;
-        double h[3];
-#pragma unroll
-        for (int f = 0; f < 3; ++f) {
-            const double2 p0 = uv[uv_index(a, f, r, e)], p1 = uv[uv_index(a, f, r, e + 1)];
-            h[f] = fma(nd.B1, p1.x - p0.x, fma(nd.C1, p0.y, fma(nd.D1, p1.y, p0.x)));
-        }
-        const double fh = f_linear2(a.drv, h[0], h[1], h[2]);
-        Y = fma(nd.cfy, fh, Y);
-        if (LASTY) Y = fma(nd.cy, h[0], Y);
-        Z1 = fma(nd.cfz1, fh, fma(nd.cz, h[1], Z1));
-        Z2 = fma(nd.cfz2, fh, fma(nd.cz, h[2], Z2));
+    for (; l1 + 1 < a.L; l1 += 2) {
+        const Node2 n0 = load_node2(ntab + l1), n1 = load_node2(ntab + l1 + 1);
+        const int e0 = c + __builtin_amdgcn_readlane(mv, l1) - m1lo;
+        const int e1 = c + __builtin_amdgcn_readlane(mv, l1 + 1) - m1lo;
+        node2_accumulate<LASTY>(a, uv, n0, r, e0, Y, Z1, Z2);
+        node2_accumulate<LASTY>(a, uv, n1, r, e1, Y, Z1, Z2);
+    }
+    if (l1 < a.L) {
+        const Node2 n0 = load_node2(ntab + l1);
+        node2_accumulate<LASTY>(a, uv, n0, r, c + __builtin_amdgcn_readlane(mv, l1) - m1lo, Y, Z1,
+                                Z2);
     }
 }
 
@@ -65,8 +101,6 @@ __device__ inline void row_nodes(const Sweep2Args &a, const double2 *uv, const N
 __global__ void __launch_bounds__(kThreads2) sweep2d(const Sweep2Args a)
 {
     extern __shared__ double2 uv[];
-    __shared__ Node2 ntab[64];
-    __shared__ int nm1[64];
     const int tiles1 = (a.n1 + kTile2C - 1) / kTile2C;
     const int idx = xcd_tile(blockIdx.x, gridDim.x);
     const int t0 = (idx / tiles1) * kTile2R, t1 = (idx % tiles1) * kTile2C;
@@ -80,10 +114,8 @@ __global__ void __launch_bounds__(kThreads2) sweep2d(const Sweep2Args a)
             const int rowi = (j - 1) * a.L + l0;
             const Node2Row row = a.rows[rowi];
             const int W = kTile2C + row.m1hi - row.m1lo + 2;
-            for (int l1 = tid; l1 < a.L; l1 += kThreads2) {
-                ntab[l1] = a.nodes[(size_t)rowi * a.L + l1];
-                nm1[l1] = a.m1[(size_t)rowi * a.L + l1];
-            }
+            // the row's axis-1 offsets, one per lane (L <= 64)
+            const int mv = a.m1[(size_t)rowi * a.L + min(tid & 63, a.L - 1)];
             // axis-0 evaluation at s0 for the tile rows and the window columns
             for (int e = tid; e < kTile2R * W; e += kThreads2) {
                 const int rr = e / W, cc = e - rr * W;
@@ -100,10 +132,11 @@ __global__ void __launch_bounds__(kThreads2) sweep2d(const Sweep2Args a)
                 }
             }
             __syncthreads();
+            const Node2 *ntab = a.nodes + (size_t)rowi * a.L;
             if (j == a.Ky)
-                row_nodes<true>(a, uv, ntab, nm1, r, c, row.m1lo, Y, Z1, Z2);
+                row_nodes<true>(a, uv, ntab, mv, r, c, row.m1lo, Y, Z1, Z2);
             else
-                row_nodes<false>(a, uv, ntab, nm1, r, c, row.m1lo, Y, Z1, Z2);
+                row_nodes<false>(a, uv, ntab, mv, r, c, row.m1lo, Y, Z1, Z2);
             __syncthreads();
         }
     }
