@@ -444,6 +444,19 @@ def test_2d_ragged_grid_unequal_orders(lib, orc):
     assert rel_err(z[1], zo[1]) <= TOL64
 
 
+def test_2d_short_columns_wide_ragged_rows(lib, orc):
+    # 21 points along axis 0 (shorter than the spline filter's one-reflection
+    # reach: the point-by-point spline form) and 700 along axis 1 (two sweep
+    # tiles per row, the second ragged; spline runs ending in a partial run)
+    wl = W.exchange_2d(n_x=21, n_t=12, k=2, L=6, rho=0.4)
+    pb = wl.problem
+    dx1 = (pb["x_max"][0] - pb["x_min"][0]) / 20 / 8
+    pb["n_x"] = [21, 700]
+    pb["x_max"] = [pb["x_max"][0], pb["x_min"][1] + 699 * dx1]
+    y, z, yo, zo, *_ = run_both(lib, orc, wl)
+    assert rel_err(z[1], zo[1]) <= TOL64
+
+
 def test_2d_basket_checkpoint(lib, orc):
     wl = W.basket_2d(n_x=65, n_t=12, k=3, L=16)
     y, z, yo, zo, *_ = run_both(lib, orc, wl, n_stop=4)
