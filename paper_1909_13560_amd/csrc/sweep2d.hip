@@ -323,6 +323,63 @@ __global__ void __launch_bounds__(256) spline2d_rows(const Sweep2Args a, int slo
         line_run_short(src, 1, a.n1, i1, F, F.s6[1], dst, 1);
 }
 
+// Lines along axis 1 of at least kMinLine points, through LDS: a block
+// stages kRowTile rows x (kRowCols + 64) values of its source plane with
+// coalesced loads (reflected through the line ends as in line_run), then each
+// thread streams the 80 values of one run of kRun outputs from LDS.  Same
+// arithmetic, in the same order, as line_run.
+constexpr int kRowTile = 16;                   // rows per block
+constexpr int kRowCols = 256 / kRowTile * kRun;  // outputs per row per block
+constexpr int kRowIn = kRowCols + 2 * (kPcrTaps / 2 + 1);  // staged values per row
+constexpr int kRowStride = kRowIn + 1;          // LDS row pitch (odd: fewer bank conflicts)
+
+__global__ void __launch_bounds__(256) spline2d_rows_lds(const Sweep2Args a, int slot,
+                                                         const SplineFilter F)
+{
+    constexpr SplineTaps T = spline_taps();
+    constexpr int H = kPcrTaps / 2 + 1;
+    __shared__ double sm[kRowTile * kRowStride];
+    const int tiles1 = (a.n1 + kRowCols - 1) / kRowCols;
+    const int r0 = (int)(blockIdx.x / tiles1) * kRowTile, c0 = (int)(blockIdx.x % tiles1) * kRowCols;
+    const int f = blockIdx.y >> 1, g = blockIdx.y & 1;
+    const int n = a.n1;
+    double *plane0 = a.ring + (size_t)(12 * slot + 4 * f) * a.plane;
+    const double *src = plane0 + (size_t)g * a.plane;
+    double *dst = plane0 + (size_t)(2 + g) * a.plane;
+    for (int e = threadIdx.x; e < kRowTile * kRowIn; e += 256) {
+        const int rr = e / kRowIn, cc = e - rr * kRowIn;
+        const int i0 = r0 + rr;
+        if (i0 >= a.n0) continue;
+        const double *v = src + pidx(a, i0, 0);
+        const int k = c0 - H + cc;
+        const int kk = min(max(k < 0 ? -k : (k > n - 1 ? 2 * (n - 1) - k : k), 0), n - 1);
+        const double y = v[kk];
+        sm[rr * kRowStride + cc] = k < 0 ? 2.0 * v[0] - y : (k > n - 1 ? 2.0 * v[n - 1] - y : y);
+    }
+    __syncthreads();
+    const int r = threadIdx.x % kRowTile, q = threadIdx.x / kRowTile;
+    const int i0 = r0 + r, j0 = c0 + q * kRun;
+    if (i0 >= a.n0 || j0 >= n) return;
+    const double *w = sm + r * kRowStride + q * kRun;
+    double acc[kRun];
+#pragma unroll
+    for (int u = 0; u < kRun; ++u) acc[u] = 0.0;
+#pragma unroll
+    for (int m = 0; m < kRun + 2 * H; ++m) {
+        const double x = w[m];
+#pragma unroll
+        for (int u = 0; u < kRun; ++u)
+            if (m - u >= 0 && m - u <= 2 * H) acc[u] = fma(T.d[m - u], x, acc[u]);
+    }
+    double *out = dst + pidx(a, i0, 0);
+    const double s6 = F.s6[1];
+#pragma unroll
+    for (int u = 0; u < kRun; ++u) {
+        const int i = j0 + u;
+        if (i < n) out[i] = (i == 0 || i == n - 1) ? 0.0 : s6 * acc[u];
+    }
+}
+
 // Ghost points: the data of the nearest grid point with the derivative
 // planes across the crossed edge set to zero (clamped evaluation).
 __global__ void __launch_bounds__(256) ghosts2d(const Sweep2Args a, int slot, int npad0)
@@ -394,9 +451,14 @@ hipError_t launch_spline2d(const Sweep2Args &a, int slot, const SplineFilter &f,
                        slot, f);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const long tr = (long)a.n0 * ((a.n1 + kRun - 1) / kRun);
-    hipLaunchKernelGGL(spline2d_rows, dim3((unsigned)((tr + 255) / 256), 6), dim3(256), 0, s, a,
-                       slot, f);
+    if (a.n1 >= kMinLine) {
+        const long tiles = (long)((a.n0 + kRowTile - 1) / kRowTile) * ((a.n1 + kRowCols - 1) / kRowCols);
+        hipLaunchKernelGGL(spline2d_rows_lds, dim3((unsigned)tiles, 6), dim3(256), 0, s, a, slot, f);
+    } else {
+        const long tr = (long)a.n0 * ((a.n1 + kRun - 1) / kRun);
+        hipLaunchKernelGGL(spline2d_rows, dim3((unsigned)((tr + 255) / 256), 6), dim3(256), 0, s, a,
+                           slot, f);
+    }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int npad0 = (int)(a.plane / a.npad1);
