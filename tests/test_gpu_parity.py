@@ -457,6 +457,18 @@ def test_2d_short_columns_wide_ragged_rows(lib, orc):
     assert rel_err(z[1], zo[1]) <= TOL64
 
 
+def test_2d_short_rows(lib, orc):
+    # 20 points along axis 1: the axis-1 spline lines are shorter than the
+    # filter's one-reflection reach and take the point-by-point form
+    wl = W.exchange_2d(n_x=40, n_t=10, k=3, L=6, rho=0.3)
+    pb = wl.problem
+    dx1 = (pb["x_max"][1] - pb["x_min"][1]) / 39
+    pb["n_x"] = [40, 20]
+    pb["x_max"] = [pb["x_max"][0], pb["x_min"][1] + 19 * dx1]
+    y, z, yo, zo, *_ = run_both(lib, orc, wl)
+    assert rel_err(z[1], zo[1]) <= TOL64
+
+
 def test_2d_basket_checkpoint(lib, orc):
     wl = W.basket_2d(n_x=65, n_t=12, k=3, L=16)
     y, z, yo, zo, *_ = run_both(lib, orc, wl, n_stop=4)
