@@ -286,3 +286,97 @@ def test_picard_tolerance_stops_early(oracle_lib):
     iy, iz = wl.init_layers()
     _, _, st = oracle_lib.solve(wl.problem, iy, iz)
     assert 1 < st["picard_iter_max"] < 10 and st["picard_nonconverged"] == 0
+
+
+# ----------------------------------------------------------------------------
+# The lending branch of the bid-ask driver, and unequal orders K_y != K_z
+# ----------------------------------------------------------------------------
+
+
+def _twin_half_width(sigma, T, n_t, n_x, R=16.0):
+    return sigma * math.sqrt(2 * T / n_t) / R * (n_x - 1) / 2
+
+
+@pytest.mark.parametrize("sign", [1.0, -1.0])
+def test_bid_ask_put_prices_at_the_lending_rate(oracle_lib, sign):
+    # A put's hedge lends (y - z/sigma > 0), so min(y - z/sigma, 0) = 0 and the
+    # driver is -r y - theta z whatever the borrowing rate R and the sign s:
+    # the exact solution is the Black-Scholes put at the lending rate r.  At
+    # the borrowing rate R the price would differ by about 1.1, so a sign or
+    # branch error in the min term shows at once.
+    nx, nt = 2048, 64
+    wl = W.bidask_put_1d(n_x=nx, n_t=nt, sign=sign,
+                         half_width=_twin_half_width(0.2, 0.5, nt, nx))
+    iy, iz = wl.init_layers()
+    y, z, st = oracle_lib.solve(wl.problem, iy, iz)
+    ye, ze = wl.exact_at_t0()
+    i = wl.node_index()
+    assert abs(y[i] - ye[i]) < 1e-5 and abs(z[0, i] - ze[i]) < 1e-8
+    tau = wl.problem["T"] + wl.extra["tau_s"]
+    y_R, _ = W.bs_put(tau, wl.x0, 100.0, wl.extra["R"], 0.2)
+    assert abs(y[i] - y_R) > 0.5
+    # the exact solution never reaches the borrowing branch
+    assert np.min(ye - ze / 0.2) >= 0.0
+    assert st["picard_nonconverged"] == 0
+
+
+def test_bid_ask_put_does_not_reach_the_borrowing_branch(oracle_lib):
+    # min(y - z/sigma, 0) vanishes for a put, so the sign s of the borrowing
+    # term must not matter; a branch taken by mistake would move the price
+    # towards the rate R (by up to about 1.1 at x0)
+    nx, nt = 2048, 32
+    out = []
+    for sign in (1.0, -1.0):
+        wl = W.bidask_put_1d(n_x=nx, n_t=nt, sign=sign,
+                             half_width=_twin_half_width(0.2, 0.5, nt, nx))
+        iy, iz = wl.init_layers()
+        y, z, _ = oracle_lib.solve(wl.problem, iy, iz)
+        out.append((y, z[0]))
+    assert np.max(np.abs(out[0][0] - out[1][0])) < 1e-12
+    assert np.max(np.abs(out[0][1] - out[1][1])) < 1e-12
+
+
+def _sine_errors(oracle_lib, ky, kz, nt):
+    # the sine problem (f = y/2 - z depends on z) on a grid with stability
+    # ratio 16: the spatial error stays below the time error
+    dx = math.sqrt(2.0 / nt) / 16.0
+    nx = int(16.0 / dx) + 1
+    nx += 1 - nx % 2  # odd: x = 0 is a node
+    wl = W.sine_1d(n_x=nx, n_t=nt, k=ky, L=16)
+    wl.problem["k_z"] = kz
+    iy, iz = wl.init_layers()
+    y, z, _ = oracle_lib.solve(wl.problem, iy, iz)
+    ye, ze = wl.exact_at_t0()
+    i = wl.node_index()
+    return abs(y[i] - ye[i]), abs(z[0, i] - ze[i])
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("ky,kz", [(3, 1), (1, 3), (2, 4), (4, 2)])
+def test_z_order_with_unequal_orders(oracle_lib, ky, kz):
+    # Theorem 2: the z error falls like dt^min(K_y + 1, K_z, 3).  The z
+    # equation takes row K_z of Table 2 and the y equation row K_y of Table 1
+    # with E[y^{n+K_y}]; taking K = max(K_y, K_z) for either, or swapping the
+    # rows, changes the observed order (e.g. (3, 1) gives 1, not 3).
+    errs = np.array([_sine_errors(oracle_lib, ky, kz, nt)[1] for nt in (16, 32, 64)])
+    order = np.log2(errs[:-1] / errs[1:])
+    expect = min(ky + 1, kz, 3)
+    assert abs(order[-1] - expect) < 0.25, (errs, order)
+
+
+@pytest.mark.parametrize("ky,kz", [(3, 1), (1, 3)])
+def test_y_order_with_unequal_orders_space_independent(oracle_lib, ky, kz):
+    # f = -r y, g = 1: z = 0 for any K_z and y follows the row K_y of Table 1
+    # alone; the trapezoid row (K_y = 1) is of order 2, the three-eighths row
+    # (K_y = 3) of order 4 (Theorem 1: min(K_y + 1, 4)).  Using the row of
+    # K_z, or of K = max(K_y, K_z), would swap the two orders.
+    errs = []
+    for nt in (16, 32, 64, 128):
+        wl = W.discount_const(k=ky, n_t=nt, r=1.0)
+        wl.problem["k_z"] = kz
+        iy, iz = wl.init_layers()
+        y, z, _ = oracle_lib.solve(wl.problem, iy, iz)
+        assert np.max(np.abs(z)) < 1e-15
+        errs.append(abs(y[0] - wl.exact_at_t0()[0][0]))
+    order = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert abs(order[-1] - min(ky + 1, 4)) < 0.2, (errs, order)

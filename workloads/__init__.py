@@ -65,6 +65,20 @@ def bs_call(tau, x, K, r, sigma, delta=0.0):
     return y, z
 
 
+def bs_put(tau, x, K, r, sigma, delta=0.0):
+    """Black-Scholes put on S = e^x: (price, sigma S dV/dS), written with
+    N(-d1), N(-d2) so that both stay accurate far out of the money."""
+    tau = np.asarray(tau, dtype=float)
+    S = np.exp(x)
+    sq = sigma * np.sqrt(tau)
+    d1 = (x - math.log(K) + (r - delta + 0.5 * sigma * sigma) * tau) / sq
+    d2 = d1 - sq
+    disc_q = np.exp(-delta * tau)
+    y = K * np.exp(-r * tau) * ndtr(-d2) - S * disc_q * ndtr(-d1)
+    z = -sigma * S * disc_q * ndtr(-d1)
+    return y, z
+
+
 def margrabe(tau, x1, x2, sigma1, sigma2, rho):
     """Margrabe exchange option max(S1 - S2, 0), S_k = e^{x_k}; returns (V, dV/dx1, dV/dx2)."""
     s = math.sqrt(sigma1 ** 2 + sigma2 ** 2 - 2 * rho * sigma1 * sigma2)
@@ -283,6 +297,40 @@ def bidask_call_1d(n_x: int = 262144, n_t: int = 1024, k: int = 4, L: int = 16,
     w = Workload(f"bidask1d_nx{n_x}_nt{n_t}_k{k}_L{L}", pb, exact, c)
     w.extra.update(dict(K=K, S0=S0, r=r, R=R, mu=mu, sigma=sigma, sign=sign, tau_s=tau_s,
                         r_eff=r_eff))
+    return w
+
+
+def bidask_put_1d(n_x: int = 4096, n_t: int = 64, k: int = 4, L: int = 16,
+                  half_width: float | None = None, K: float = 100.0, S0: float = 100.0,
+                  r: float = 0.01, R: float = 0.06, mu: float = 0.05, sigma: float = 0.2,
+                  T: float = 0.5, sign: float = 1.0, smooth: bool = True,
+                  picard_tol: float = 1e-14, picard_max: int = 30) -> Workload:
+    """Put under the bid-ask driver of ``bidask_call_1d`` (same parameters).
+
+    A put's replicating portfolio is short the asset and always lends:
+    y - z/sigma = K e^{-r tau} N(-d2) > 0, so min(y - z/sigma, 0) = 0 and the
+    driver reduces to -r y - theta z for either sign s.  The exact solution is
+    the Black-Scholes put at the lending rate r.  The terminal layer is
+    smoothed as for the call (maturity T + dt).
+    """
+    c = math.log(S0)
+    hw = 6 * sigma * math.sqrt(T) if half_width is None else half_width
+    lo, hi = _snap_domain(c, c - hw, c + hw, n_x)
+    tau_s = T / n_t if smooth else 0.0
+    theta = (mu - r) / sigma
+    pb = _problem(T=T, n_t=n_t, k_y=k, k_z=k, L=L, n_x=n_x, x_min=lo, x_max=hi,
+                  drift=mu - 0.5 * sigma ** 2, vol=sigma, driver="bidask",
+                  p=[r, R, theta, sigma, sign], picard_tol=picard_tol, picard_max=picard_max)
+
+    def exact(t, x):
+        tau = T + tau_s - t
+        if tau <= 0:
+            return np.maximum(K - np.exp(x), 0.0), -sigma * np.exp(x) * (x < math.log(K))
+        return bs_put(tau, x, K, r, sigma)
+
+    w = Workload(f"bidaskput1d_nx{n_x}_nt{n_t}_k{k}_L{L}", pb, exact, c)
+    w.extra.update(dict(K=K, S0=S0, r=r, R=R, mu=mu, sigma=sigma, sign=sign, tau_s=tau_s,
+                        r_eff=r))
     return w
 
 
