@@ -194,14 +194,53 @@ def run_batch(args, B, torch, np, ms_fp64_single):
 
 
 def flops_per_point_step_2d(pb: dict, picard_mean: float) -> float:
-    """Algorithmic FP64 operations of one point and step of the 2-D sweep: per
-    tensor node (K L^2 of them) three bicubic tensor-spline evaluations of 16
-    terms (32 flops each), the linear driver (6) and the weighted
-    accumulations (y: 2, z1: 4, z2: 4); per layer j = K_y the y expectation
-    (2 per node); the z combination and each Picard iteration (8)."""
+    """FP64 operations of one point and step of the 2-D sweep if each tensor
+    node's three bicubic tensor-spline values were evaluated directly: per
+    tensor node (K L^2 of them) three 16-term sums (32 flops each), the linear
+    driver (6) and the weighted accumulations (y: 2, z1: 4, z2: 4); per layer
+    j = K_y the y expectation (2 per node); the z combination and each Picard
+    iteration (8).  The kernel does not evaluate this form (see the next
+    function); the count is kept as a reference."""
     K, L = max(pb["k_y"], pb["k_z"]), pb["L"]
     per_node = 3 * 32 + 6 + 10
     return K * L * L * per_node + 2 * L * L + 2 * (3 * K + 1) + 2 * K + picard_mean * 8
+
+
+def window_columns_2d(pb: dict, tile_cols: int = 512) -> float:
+    """Mean over the node rows (j, l0) of the axis-1 window width per tile
+    column of the 2-D sweep: the tile's columns plus the row's node spread
+    along axis 1, plus 2 (as the plan sizes it)."""
+    import numpy as np
+
+    K, L = max(pb["k_y"], pb["k_z"]), pb["L"]
+    a, _ = np.polynomial.hermite.hermgauss(L)
+    dt = pb["T"] / pb["n_t"]
+    dx1 = (pb["x_max"][1] - pb["x_min"][1]) / (pb["n_x"][1] - 1)
+    vol = pb["vol"]
+    widths = []
+    for j in range(1, K + 1):
+        sq = math.sqrt(2 * j * dt)
+        for l0 in range(L):
+            s1 = (pb["drift"][1] * j * dt + vol[1][0] * sq * a[l0] + vol[1][1] * sq * a) / dx1
+            m1 = np.floor(s1)
+            widths.append(tile_cols + (m1.max() - m1.min()) + 2)
+    return float(np.mean(widths)) / tile_cols
+
+
+def flops_per_point_step_2d_executed(pb: dict, picard_mean: float) -> float:
+    """FP64 operations the 2-D sweep executes per point and step (axis-split
+    evaluation).  Per node row (j, l0) and window column, the axis-0 terms
+    U = A0 v(p) + B0 v(p+1) + C0 Mxx(p) + D0 Mxx(p+1) and the same V with
+    Myy, Mxxyy for y, z1, z2 (6 sums of 7 flops), over window_columns_2d
+    columns per point; per tensor node the axis-1 combination
+    A1 U(q) + B1 U(q+1) + C1 V(q) + D1 V(q+1) for y, z1, z2 (3 x 7), the
+    driver (6) and the accumulations (10); per layer j = K_y the y expectation
+    (2 per node); the z combination and each Picard iteration (8)."""
+    K, L = max(pb["k_y"], pb["k_z"]), pb["L"]
+    per_row = 6 * 7 * window_columns_2d(pb)
+    per_node = 3 * 7 + 6 + 10
+    return (K * L * (per_row + L * per_node) + 2 * L * L + 2 * (3 * K + 1) + 2 * K
+            + picard_mean * 8)
 
 
 def run_2d(args, B, torch, np):
@@ -227,7 +266,8 @@ def run_2d(args, B, torch, np):
     kt = B.bsde_profile_kernels(plan, ws, [(t_iy, t_iz, y0, z0)], stream=stream)
     sweep_ms = kt["sweep_ms"] / kt["sweep_launches"]
     spline_ms = kt["spline_ms"] / max(kt["spline_launches"], 1)
-    fl = flops_per_point_step_2d(pb, st["picard_iter_mean"]) * npts
+    fl_direct = flops_per_point_step_2d(pb, st["picard_iter_mean"]) * npts
+    fl = flops_per_point_step_2d_executed(pb, st["picard_iter_mean"]) * npts
     print(f"[bench] 2-D basket: status {B.bsde_status_string(rc)} {st} kernels {kt}",
           file=sys.stderr, flush=True)
     # whole solves (all N - K + 1 steps), replayed between events on the stream
@@ -254,7 +294,11 @@ def run_2d(args, B, torch, np):
             "roofline": {"bound": "alu", "achieved": fl / (sweep_ms * 1e-3) / 1e12,
                          "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                          "frac": fl / (sweep_ms * 1e-3) / 1e12 / FP64_VALU_PEAK_TFLOPS,
-                         "flops_per_launch": fl},
+                         "flops_per_launch": fl,
+                         "flops_counted": "executed (axis-split evaluation)",
+                         "flops_per_launch_direct_form": fl_direct,
+                         "frac_direct_form": fl_direct / (sweep_ms * 1e-3) / 1e12
+                         / FP64_VALU_PEAK_TFLOPS},
             "full_solve_s": full_s, "full_solve_steps": steps_full,
             "full_solve_value": npts * steps_full / full_s,
             "stability_ratio": st["stability_ratio"]}
@@ -382,6 +426,12 @@ def main() -> int:
             "vector_alu_tflops": flops_per_point_step(pb, st32["picard_iter_mean"]) * nx
             / (sw32 * 1e-3) / 1e12,
             "max_rel_err_vs_fp64_y": float(np.max(np.abs(y32 - y_h) / scale)),
+            # where the largest differences sit (grid index and x, final layer)
+            "argmax_y": {"i": int(np.argmax(np.abs(y32 - y_h) / scale)),
+                         "x": float(x[int(np.argmax(np.abs(y32 - y_h) / scale))])},
+            "argmax_z": {"i": int(np.argmax(np.abs(z32 - z_h) / np.maximum(np.abs(z_h), 1.0))),
+                         "x": float(x[int(np.argmax(np.abs(z32 - z_h) /
+                                                    np.maximum(np.abs(z_h), 1.0)))])},
             "max_rel_err_vs_fp64_z": float(np.max(np.abs(z32 - z_h) / np.maximum(np.abs(z_h), 1.0))),
             "rel_err_y0_vs_closed_form": float(abs(y32[i] - ye[i]) / max(abs(ye[i]), 1.0)),
             "rel_err_z0_vs_closed_form": float(abs(z32[i] - ze[i]) / max(abs(ze[i]), 1.0)),

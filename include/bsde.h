@@ -58,6 +58,17 @@ typedef enum {
     BSDE_DRIVER_EXP = 3
 } bsde_driver_kind;
 
+/* First term of the z equation (Section 2.2).  Eq (12) holds
+ * E[y_{t_{n+1}} dW_{t_{n+1}}]; the scheme of eq (20) replaces it by
+ * dt E[z_{t_{n+1}}] (the relation stated below eq (12)).  The YDW form keeps
+ * E[y^{n+1} dW_{n+1}] / dt instead: with K_z = 1 it is second order in z
+ * (the printed form is first order there), with K_z >= 2 the multistep z
+ * recurrence built on it is unstable. */
+typedef enum {
+    BSDE_ZFORM_EZ = 0,  /* E[z^{n+1}] (eq (20))                                  */
+    BSDE_ZFORM_YDW = 1  /* E[y^{n+1} dW_{n+1}] / dt                              */
+} bsde_z_form;
+
 typedef enum {
     BSDE_FP64 = 0,      /* all arithmetic in double precision                   */
     BSDE_FP32_COMP = 1  /* the ring of time layers and the node interpolation and
@@ -83,9 +94,17 @@ typedef struct {
     int n_x[2];         /* grid points per axis, >= 4 (x_i = x_min + i dx)       */
     double x_min[2], x_max[2];
     double drift[2];    /* X_{t+h} = X_t + drift h + vol (W_{t+h} - W_t)          */
-    double vol[2][2];   /* row-major; d = 1 uses vol[0][0] > 0; d = 2 needs
+    double vol[2][2];   /* row-major; d = 1 uses vol[0][0]; d = 2 needs
                            vol[0][0], vol[1][1] > 0 (and vol[0][1] = 0, i.e. a
                            lower-triangular factor, for the 2-D kernels)         */
+    double drift_x;     /* d = 1: forward coefficients of eq (1) that depend on
+                           the state, a(x) = drift[0] + drift_x x and
+                           b(x) = vol[0][0] + vol_x x, b > 0 over the grid; the
+                           node of layer n+j is one Euler step over j dt,
+                           x + a(x) j dt + b(x) sqrt(2 j dt) a_l, located per
+                           grid point.  Both 0 (the usual case): constant
+                           coefficients, drift[0] and vol[0][0] > 0.  d = 2: 0 */
+    double vol_x;
     int driver;         /* bsde_driver_kind                                      */
     double p[8];        /* driver parameters                                     */
     int picard_max;     /* Picard iterations, >= 1                               */
@@ -96,7 +115,34 @@ typedef struct {
                            full sweep.  A larger value stops early (a checkpoint
                            of the backward loop) and y0, z0 then receive layer
                            n_stop.                                               */
+    int z_form;         /* bsde_z_form                                           */
 } bsde_problem;
+
+/* Largest stability ratio R = vol sqrt(2 dt) / dx (Gauss-Hermite spread of
+ * one step, in grid cells) at which the scheme of eq (20) with the
+ * Gauss-Hermite expectations of eq (21) and the natural spline was found
+ * linearly stable for K <= 6 and L in {16, 32} (a von Neumann analysis of
+ * the scheme for linear drivers on the uniform grid).  At larger R the
+ * quadrature aliases grid-scale modes and rounding noise can grow without
+ * bound over the steps; such problems still run (bsde_problem_info flags
+ * them). */
+#define BSDE_STABILITY_LIMIT 16.0
+
+typedef struct {
+    double stability_ratio; /* R; d = 2: the larger of the two axes'          */
+    int stable;             /* 1 when R <= BSDE_STABILITY_LIMIT               */
+    int K;                  /* max(k_y, k_z): layers kept and initial layers  */
+    int node_reach;         /* widest node offset from a grid point, in cells */
+    int supported;          /* 1 when bsde_plan implements the problem        */
+} bsde_problem_info_t;
+
+/*
+ * bsde_problem_info -- host-only check of one problem (no device call): the
+ * validation bsde_plan applies, and the plan-time quantities that decide how
+ * well the scheme behaves on it, chiefly the stability ratio and its flag.
+ * Errors: BSDE_EINVAL for an invalid problem or NULL pointer.
+ */
+bsde_status bsde_problem_info(const bsde_problem *pb, bsde_problem_info_t *info);
 
 /* Opaque, immutable after creation.  A plan may be shared by threads, but
  * solves that use one workspace must not overlap. */
@@ -107,9 +153,9 @@ typedef struct {
     double picard_iter_mean;       /* mean Picard count per point-step            */
     long long picard_nonconverged; /* point-steps that hit picard_max (tol mode)  */
     long long nonfinite;           /* non-finite y or z values in the output      */
-    double stability_ratio;        /* R = vol sqrt(2 dt) / dx: Gauss-Hermite
-                                      spread per cell; the scheme loses linear
-                                      stability for large R (about R > 16)        */
+    double stability_ratio;        /* largest R = vol sqrt(2 dt) / dx over the
+                                      instances (Gauss-Hermite spread per cell)   */
+    int unstable_instances;        /* instances with R > BSDE_STABILITY_LIMIT     */
     float elapsed_ms;              /* device time of the solve (hipEvents)        */
 } bsde_stats;
 
@@ -131,7 +177,8 @@ typedef struct {
  * tables are copied to the current device.
  * Errors: BSDE_EINVAL for an invalid problem, batch < 1, or problems of
  * different d in one batch; BSDE_EUNSUPPORTED for a d = 2 problem with
- * vol[0][1] != 0, a driver other than BSDE_DRIVER_LINEAR or the FP32 form,
+ * vol[0][1] != 0, a driver other than BSDE_DRIVER_LINEAR, the FP32 form or
+ * state-dependent coefficients,
  * and for a d = 1 grid whose ring plane would reach 4 GiB (about 2.7e8 points
  * in FP64, 5.4e8 in FP32); BSDE_ENOMEM, BSDE_EDEVICE.  *out is set only on
  * success.
@@ -186,10 +233,42 @@ bsde_status bsde_solve(bsde_plan_t plan, void *ws, const double *init_y, const d
  * group still active by one layer (instances of fewer steps finish first).
  * The whole solve is one hipGraph launch as for bsde_solve.  Stats, when
  * requested, aggregate over the batch.
+ * The graph is a chain of per-step launches, not one persistent kernel: the
+ * kernel boundary is the step's device-wide barrier, while a persistent
+ * kernel whose tiles waited on their neighbours through device-scope flags
+ * ran 2.5 times slower (each release/acquire pair writes back and
+ * invalidates the L2 caches).  It is captured on the first solve with a
+ * given set of buffers (the plan does not know them) and replayed by later
+ * solves with the same buffers.
  * Errors: as bsde_solve.
  */
 bsde_status bsde_solve_batched(bsde_plan_t plan, void *ws, const bsde_io *io, void *stream,
                                bsde_stats *st);
+
+/*
+ * bsde_initial_layers -- Section 3.1 step 2: the K - 1 initial layers that
+ * follow the terminal one (K = max(k_y, k_z)), computed on the device by the
+ * 1-step scheme (eq (20) with K_y = K_z = 1, row 1 of Tables 1 and 2) with
+ * `substeps` steps per dt = T / n_t: layer t_{N-r} is the 1-step sweep from
+ * t_{N-r+1} over substeps steps of dt / substeps, r = 1..K-1, through the
+ * same sweep kernels as bsde_solve (the driver sees the absolute times).
+ * The 1-step scheme's z is first order in its step (Theorem 2), so the
+ * initial layers' error falls like 1/substeps.
+ *   pb        the problem of the main solve (its n_stop is ignored).
+ *   substeps  >= 1.
+ *   ws        device workspace of ws_bytes bytes, 256-byte aligned; the
+ *             workspace of a plan of pb (bsde_workspace_bytes) is large
+ *             enough whenever K >= 2.
+ *   init_y, init_z  device, laid out as for bsde_solve; on entry row K-1
+ *             holds the terminal layer; on return rows 0..K-2 hold the layers
+ *             at t_{N-K+1}..t_{N-1} (row K-1 is unchanged).
+ *   stream    hipStream_t or NULL; the call synchronises it.
+ * Plans one K = 1 problem per layer (host tables and small device tables).
+ * Errors: BSDE_EINVAL (invalid problem, NULL pointer, substeps < 1, a
+ * workspace too small), the errors of bsde_plan and bsde_solve.
+ */
+bsde_status bsde_initial_layers(const bsde_problem *pb, int substeps, void *ws, size_t ws_bytes,
+                                double *init_y, double *init_z, void *stream);
 
 /* Per-kernel device time of one solve, from hipEvent pairs around launches. */
 typedef struct {
@@ -202,7 +281,8 @@ typedef struct {
     int spline_launches;
     int path;             /* sweep kernel of group 0: 0 = LDS-staged windows with
                              the spline of the newest layer in-kernel, 1 = direct
-                             loads, 2 = the two-dimensional sweep                */
+                             loads, 2 = the two-dimensional sweep, 3 = nodes
+                             located per point (state-dependent coefficients)    */
     int points_per_lane;  /* grid points per lane of the sweep kernel            */
     int node_groups;      /* thread groups sharing the nodes of one tile         */
     int blocks;           /* blocks of the first sweep launch of group 0         */

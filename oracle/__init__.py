@@ -49,11 +49,15 @@ class _Problem(ctypes.Structure):
         ("x_max", ctypes.c_double * 2),
         ("drift", ctypes.c_double * 2),
         ("vol", ctypes.c_double * 4),
+        ("drift_x", ctypes.c_double),
+        ("vol_x", ctypes.c_double),
         ("driver", ctypes.c_int),
         ("p", ctypes.c_double * 8),
         ("picard_max", ctypes.c_int),
         ("picard_tol", ctypes.c_double),
         ("n_stop", ctypes.c_int),
+        ("z_form", ctypes.c_int),
+        ("quad", ctypes.c_int),
     ]
 
 
@@ -84,6 +88,12 @@ def _load():
         lib.oracle_first_step_points_2d.argtypes = [
             ctypes.POINTER(_Problem), dp, dp, ctypes.c_int, ctypes.POINTER(ctypes.c_long), dp, dp]
         lib.oracle_first_step_points_2d.restype = ctypes.c_int
+        lib.oracle_initial_layers.argtypes = [ctypes.POINTER(_Problem), ctypes.c_int, dp, dp]
+        lib.oracle_initial_layers.restype = ctypes.c_int
+        lib.oracle_exact_expectation.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                                 dp, dp, ctypes.c_int, dp, ctypes.c_double,
+                                                 ctypes.c_double, dp]
+        lib.oracle_exact_expectation.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -113,12 +123,16 @@ def _to_struct(pb: dict, n_stop: int) -> _Problem:
     v = np.atleast_2d(np.asarray(pb.get("vol", 1.0), dtype=float))
     vol[: v.shape[0], : v.shape[1]] = v
     s.vol[:] = [float(x) for x in vol.ravel()]
+    s.drift_x = float(pb.get("drift_x", 0.0))
+    s.vol_x = float(pb.get("vol_x", 0.0))
     s.driver = DRIVERS[pb["driver"]]
     p = list(pb.get("p", [])) + [0.0] * 8
     s.p[:] = [float(x) for x in p[:8]]
     s.picard_max = int(pb.get("picard_max", 30))
     s.picard_tol = float(pb.get("picard_tol", 0.0))
     s.n_stop = int(n_stop)
+    s.z_form = {"eq20": 0, "yW": 1}[pb.get("z_form", "eq20")]
+    s.quad = {"gh": 0, "exact": 1}[pb.get("quad", "gh")]
     return s
 
 
@@ -143,6 +157,25 @@ def solve(pb: dict, init_y: np.ndarray, init_z: np.ndarray, n_stop: int = 0):
         raise ValueError(f"oracle_solve failed with code {rc}")
     return y, z, {"picard_iter_max": st.picard_iter_max,
                   "picard_nonconverged": st.picard_nonconverged}
+
+
+def initial_layers(pb: dict, terminal_y: np.ndarray, terminal_z: np.ndarray, sub: int):
+    """Section 3.1 step 2: the K initial layers t_{N-K+1} .. t_N from the
+    terminal layer, the other K - 1 by the 1-step scheme with ``sub`` steps per
+    dt.  ``terminal_y``: (points,); ``terminal_z``: (d, points).  Returns
+    (init_y, init_z) of shapes (K, points) and (K, d, points)."""
+    lib = _load()
+    d = int(pb["d"])
+    npts = int(np.prod(_pair(pb["n_x"], 1)[:d]))
+    K = max(int(pb["k_y"]), int(pb["k_z"]))
+    iy = np.zeros((K, npts))
+    iz = np.zeros((K, d, npts))
+    iy[K - 1] = np.asarray(terminal_y, dtype=np.float64).reshape(npts)
+    iz[K - 1] = np.asarray(terminal_z, dtype=np.float64).reshape(d, npts)
+    rc = lib.oracle_initial_layers(ctypes.byref(_to_struct(pb, 0)), int(sub), _ptr(iy), _ptr(iz))
+    if rc != 0:
+        raise ValueError(f"oracle_initial_layers failed with code {rc}")
+    return iy, iz
 
 
 def first_step_points_2d(pb: dict, init_y: np.ndarray, init_z: np.ndarray, idx):
@@ -189,6 +222,21 @@ def gamma(table: int, K: int):
     if lib.oracle_gamma(int(table), int(K), _ptr(g)) != 0:
         raise ValueError("bad gamma table request")
     return g
+
+
+def exact_expectation(y, z, x_min: float, x_max: float, c, sd: float, h: float):
+    """The oracle's exact Gaussian expectations of the natural splines of y and
+    z at X = c + sd xi: rows E[yhat], E[yhat h xi], E[zhat], E[zhat h xi]."""
+    lib = _load()
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    c = np.ascontiguousarray(np.atleast_1d(c), dtype=np.float64)
+    out = np.empty((c.size, 4))
+    rc = lib.oracle_exact_expectation(len(y), float(x_min), float(x_max), _ptr(y), _ptr(z),
+                                      int(c.size), _ptr(c), float(sd), float(h), _ptr(out))
+    if rc != 0:
+        raise ValueError(f"oracle_exact_expectation failed with code {rc}")
+    return out.T.copy()
 
 
 def spline_eval(y: np.ndarray, x_min: float, x_max: float, X: np.ndarray):

@@ -202,6 +202,109 @@ static double basis_d(double theta, double dx)
 }
 
 /* ------------------------------------------------------------------------- */
+/* Exact Gaussian expectation of the interpolating spline (the variant of     */
+/* eq (21) without quadrature error).  X = c + s xi with xi ~ N(0, 1), and    */
+/* dW = h xi (h = sqrt(j dt)):                                                 */
+/*   E[yhat(X)]    = int yhat(x) phi((x - c)/s)/s dx,                         */
+/*   E[yhat(X) dW] = int yhat(x) h (x - c)/s phi((x - c)/s)/s dx,             */
+/* with yhat the boundary value outside the grid (Section 3.2).  Each grid    */
+/* cell is integrated by 6-point Gauss-Legendre over sub-intervals of at most */
+/* s/8 (a cubic times a Gaussian that changes little there: the rule is exact */
+/* to degree 11, and the Gaussian's Taylor remainder over s/8 is below the    */
+/* rounding of the sum); cells more than 9 s from c carry less than 1e-18 of  */
+/* the mass and are left out; the two tails outside the grid have closed      */
+/* forms (Phi, phi).  y and z are integrated together.                         */
+/* ------------------------------------------------------------------------- */
+#define GL_N 6
+static double gl_x[GL_N], gl_w[GL_N];
+
+/* Gauss-Legendre rule on [0, 1]: Newton on the Legendre recurrence */
+static void gauss_legendre01(void)
+{
+    if (gl_w[0] != 0.0) return;
+    for (int k = 0; k < GL_N; ++k) {
+        double x = cos(M_PI * (k + 0.75) / (GL_N + 0.5)), dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = x;
+            for (int n = 2; n <= GL_N; ++n) {
+                double p2 = ((2.0 * n - 1.0) * x * p1 - (n - 1.0) * p0) / n;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = GL_N * (x * p1 - p0) / (x * x - 1.0);
+            double dx = p1 / dp;
+            x -= dx;
+            if (fabs(dx) < 1e-16) break;
+        }
+        gl_x[k] = 0.5 * (1.0 - x);
+        gl_w[k] = 1.0 / ((1.0 - x * x) * dp * dp); /* 2/((1-x^2)P'^2), halved */
+    }
+}
+
+static double normal_pdf(double u) { return exp(-0.5 * u * u) / sqrt(2.0 * M_PI); }
+static double normal_cdf(double u) { return 0.5 * erfc(-u / sqrt(2.0)); }
+
+/* E[v(X)], E[v(X) dW] for the two splines (v, M) = (y, My) and (z, Mz) on the
+ * grid: out[0] = E[yhat], out[1] = E[yhat dW], out[2] = E[zhat],
+ * out[3] = E[zhat dW] */
+static void exact_expectation(int n, double xmin, double dx, const double *y, const double *My,
+                              const double *z, const double *Mz, double c, double sd, double h,
+                              double *out)
+{
+    const double xmax = xmin + (n - 1) * dx;
+    const double u0 = (xmin - c) / sd, u1 = (xmax - c) / sd;
+    /* tails: boundary values; E[xi 1{xi < u0}] = -phi(u0), E[xi 1{xi > u1}] = phi(u1) */
+    const double P0 = normal_cdf(u0), P1 = normal_cdf(-u1);
+    const double W0 = -h * normal_pdf(u0), W1 = h * normal_pdf(u1);
+    out[0] = y[0] * P0 + y[n - 1] * P1;
+    out[1] = y[0] * W0 + y[n - 1] * W1;
+    out[2] = z[0] * P0 + z[n - 1] * P1;
+    out[3] = z[0] * W0 + z[n - 1] * W1;
+    int plo = (int)floor((c - 9.0 * sd - xmin) / dx), phi_ = (int)floor((c + 9.0 * sd - xmin) / dx);
+    if (plo < 0) plo = 0;
+    if (phi_ > n - 2) phi_ = n - 2;
+    int nsub = (int)ceil(8.0 * dx / sd);
+    if (nsub < 1) nsub = 1;
+    for (int p = plo; p <= phi_; ++p) {
+        /* integrals of the four basis functions against the density, plain
+         * and dW-weighted */
+        double I[4] = {0, 0, 0, 0}, J[4] = {0, 0, 0, 0};
+        for (int q = 0; q < nsub; ++q) {
+            for (int g = 0; g < GL_N; ++g) {
+                const double th = (q + gl_x[g]) / nsub; /* fraction within cell p */
+                const double u = (xmin + (p + th) * dx - c) / sd;
+                const double wgt = gl_w[g] / nsub * dx * normal_pdf(u) / sd;
+                const double b[4] = {1.0 - th, th, basis_c(th, dx), basis_d(th, dx)};
+                for (int k = 0; k < 4; ++k) {
+                    I[k] += wgt * b[k];
+                    J[k] += wgt * b[k] * h * u;
+                }
+            }
+        }
+        out[0] += I[0] * y[p] + I[1] * y[p + 1] + I[2] * My[p] + I[3] * My[p + 1];
+        out[1] += J[0] * y[p] + J[1] * y[p + 1] + J[2] * My[p] + J[3] * My[p + 1];
+        out[2] += I[0] * z[p] + I[1] * z[p + 1] + I[2] * Mz[p] + I[3] * Mz[p + 1];
+        out[3] += J[0] * z[p] + J[1] * z[p + 1] + J[2] * Mz[p] + J[3] * Mz[p + 1];
+    }
+}
+
+int oracle_exact_expectation(int n, double xmin, double xmax, const double *y, const double *z,
+                             int m, const double *c, double sd, double h, double *out)
+{
+    if (n < 4 || !(xmax > xmin) || !(sd > 0.0) || m < 0) return ORACLE_EINVAL;
+    const double dx = (xmax - xmin) / (n - 1);
+    double *M = (double *)malloc(sizeof(double) * (size_t)4 * n);
+    if (!M) return ORACLE_ENOMEM;
+    gauss_legendre01();
+    natural_spline(n, dx, y, 1, M, 1, M + 2 * n);
+    natural_spline(n, dx, z, 1, M + n, 1, M + 2 * n);
+    for (int k = 0; k < m; ++k)
+        exact_expectation(n, xmin, dx, y, M, z, M + n, c[k], sd, h, out + 4 * (size_t)k);
+    free(M);
+    return ORACLE_OK;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Drivers f(t, x, y, z).                                                      */
 /* ------------------------------------------------------------------------- */
 static double driver(const oracle_problem *pb, double t, double y, const double *z)
@@ -244,6 +347,12 @@ static int validate(const oracle_problem *pb)
     if (pb->d == 2 && pb->driver != ORACLE_DRIVER_LINEAR) return ORACLE_EINVAL;
     if (pb->picard_max < 1) return ORACLE_EINVAL;
     if (pb->n_stop < 0 || pb->n_stop > pb->n_t - K) return ORACLE_EINVAL;
+    if (pb->z_form != 0 && pb->z_form != 1) return ORACLE_EINVAL;
+    if (pb->d == 2 && (pb->drift_x != 0.0 || pb->vol_x != 0.0)) return ORACLE_EINVAL;
+    if (pb->quad != 0 && pb->quad != 1) return ORACLE_EINVAL;
+    if (pb->quad == 1 && (pb->d != 1 || pb->driver != ORACLE_DRIVER_LINEAR ||
+                          pb->drift_x != 0.0 || pb->vol_x != 0.0))
+        return ORACLE_EINVAL;
     return ORACLE_OK;
 }
 
@@ -262,12 +371,17 @@ static int solve1(const oracle_problem *pb, const double *init_y, const double *
     const int L = pb->L, nx = pb->n_x[0];
     const double dt = pb->T / N;
     const double xmin = pb->x_min[0], dx = (pb->x_max[0] - pb->x_min[0]) / (nx - 1);
+    /* eq (1): X_{t_{n+j}} from X_{t_n} = x_i by one Euler step over j dt,
+     * a(x) = drift + drift_x x, b(x) = vol + vol_x x (constant when both
+     * slopes are 0) */
     const double drift = pb->drift[0], vol = pb->vol[0][0];
+    const double drift_x = pb->drift_x, vol_x = pb->vol_x;
 
     double a[ORACLE_MAX_L], w[ORACLE_MAX_L], gy[7], gz[7];
     int rc = oracle_gauss_hermite(L, a, w);
     if (rc) return rc;
     for (int l = 0; l < L; ++l) w[l] /= sqrt(M_PI); /* pi^(-1/2) of eq (21) */
+    gauss_legendre01();
     oracle_gamma(1, Ky, gy);
     oracle_gamma(2, Kz, gz);
 
@@ -298,13 +412,27 @@ static int solve1(const oracle_problem *pb, const double *init_y, const double *
         const double tn = n * dt;
         for (int i = 0; i < nx; ++i) {
             const double xi = xmin + i * dx;
-            double Ef[7] = {0}, EfW[7] = {0}, Ez[7] = {0}, EyK = 0.0;
+            double Ef[7] = {0}, EfW[7] = {0}, Ez[7] = {0}, EyK = 0.0, EyW1 = 0.0;
             for (int j = 1; j <= K; ++j) {
                 layer1 lj = SLOT(n + j);
                 const double tj = (n + j) * dt, sq = sqrt(2.0 * j * dt);
+                if (pb->quad == 1) {
+                    /* linear driver f = a y + b z + c: its expectations are
+                     * those of the interpolated y and z */
+                    const double cx = xi + drift * j * dt, sd = vol * sqrt(j * dt);
+                    double e[4];
+                    exact_expectation(nx, xmin, dx, lj.y, lj.My, lj.z, lj.Mz, cx, sd, sqrt(j * dt), e);
+                    const double Ey = e[0], EyWj = e[1], Ezj = e[2], EzWj = e[3];
+                    Ef[j] = pb->p[0] * Ey + pb->p[1] * Ezj + pb->p[3];
+                    EfW[j] = pb->p[0] * EyWj + pb->p[1] * EzWj;
+                    Ez[j] = Ezj;
+                    if (j == Ky) EyK = Ey;
+                    if (j == 1) EyW1 = EyWj;
+                    continue;
+                }
                 for (int l = 0; l < L; ++l) {
                     const double dW = sq * a[l];
-                    const double X = xi + drift * j * dt + vol * dW;
+                    const double X = xi + (drift + drift_x * xi) * j * dt + (vol + vol_x * xi) * dW;
                     int p;
                     double th;
                     double yh, zh;
@@ -321,10 +449,12 @@ static int solve1(const oracle_problem *pb, const double *init_y, const double *
                     EfW[j] += w[l] * fh * dW;
                     Ez[j] += w[l] * zh;
                     if (j == Ky) EyK += w[l] * yh;
+                    if (j == 1) EyW1 += w[l] * yh * dW;
                 }
             }
-            /* z equation of eq (20), explicit */
-            double zs = Ez[1];
+            /* z equation of eq (20), explicit; its first term E[z^{n+1}], or
+             * E[y^{n+1} dW]/dt (eq (12) with l = 1) */
+            double zs = pb->z_form ? EyW1 / dt : Ez[1];
             for (int j = 1; j <= Kz; ++j) zs += gz[j] * (EfW[j] - Ez[j]);
             const double zn = zs / gz[0];
             /* y equation of eq (20), implicit: Picard iteration */
@@ -488,7 +618,7 @@ static void point2(const oracle_problem *pb, const ctx2 *c, int n, int i0, int i
     const double *a = c->a, *w = c->w, *gy = c->gy, *gz = c->gz;
     const double tn = n * dt;
     const double x0 = xmin0 + i0 * dx0, x1 = xmin1 + i1 * dx1;
-    double Ef[7] = {0}, EfW[7][2] = {{0}}, Ez[7][2] = {{0}}, EyK = 0.0;
+    double Ef[7] = {0}, EfW[7][2] = {{0}}, Ez[7][2] = {{0}}, EyK = 0.0, EyW1[2] = {0.0, 0.0};
     for (int j = 1; j <= K; ++j) {
         const tspline *lj = SLOT2(c, n + j);
         const double tj = (n + j) * dt, sq = sqrt(2.0 * j * dt);
@@ -511,11 +641,15 @@ static void point2(const oracle_problem *pb, const ctx2 *c, int n, int i0, int i
                 Ez[j][0] += wt * zh[0];
                 Ez[j][1] += wt * zh[1];
                 if (j == Ky) EyK += wt * yh;
+                if (j == 1) {
+                    EyW1[0] += wt * yh * dW0;
+                    EyW1[1] += wt * yh * dW1;
+                }
             }
     }
     double zn[2];
     for (int cc = 0; cc < 2; ++cc) {
-        double zs = Ez[1][cc];
+        double zs = pb->z_form ? EyW1[cc] / dt : Ez[1][cc];
         for (int j = 1; j <= Kz; ++j) zs += gz[j] * (EfW[j][cc] - Ez[j][cc]);
         zn[cc] = zs / gz[0];
     }
@@ -611,6 +745,41 @@ int oracle_solve(const oracle_problem *pb, const double *init_y, const double *i
     if (rc) return rc;
     return pb->d == 1 ? solve1(pb, init_y, init_z, y_out, z_out, st)
                       : solve2(pb, init_y, init_z, y_out, z_out, st);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Section 3.1 step 2: the K - 1 initial layers after the terminal one, by a  */
+/* 1-step scheme on [t_{N-K+1}, t_N] with a finer time step.  The 1-step      */
+/* scheme is eq (20) with K_y = K_z = 1 (row 1 of Tables 1 and 2); each       */
+/* coarse step dt is split into `sub` steps of dt/sub.  Layer t_{N-r} is the  */
+/* 1-step sweep from t_{N-r+1} (the previous result) over `sub` fine steps;   */
+/* the absolute times of the driver stay t = n dt/sub.                        */
+/* init_y / init_z: rows as for oracle_solve; on entry row K-1 holds the       */
+/* terminal layer, on return rows 0..K-2 hold t_{N-K+1}..t_{N-1}.              */
+/* ------------------------------------------------------------------------- */
+int oracle_initial_layers(const oracle_problem *pb, int sub, double *init_y, double *init_z)
+{
+    int rc = validate(pb);
+    if (rc) return rc;
+    if (sub < 1 || !init_y || !init_z) return ORACLE_EINVAL;
+    const int K = pb->k_y > pb->k_z ? pb->k_y : pb->k_z;
+    const long np = pb->d == 1 ? (long)pb->n_x[0] : (long)pb->n_x[0] * pb->n_x[1];
+    const double dt = pb->T / pb->n_t;
+    for (int r = 1; r < K; ++r) {
+        oracle_problem q = *pb;
+        const int n_hi = pb->n_t - r + 1; /* the segment ends at t_{N-r+1} */
+        q.k_y = q.k_z = 1;
+        q.T = n_hi * dt;
+        q.n_t = n_hi * sub;
+        q.n_stop = (n_hi - 1) * sub;
+        const double *iy = init_y + (size_t)(K - r) * np;
+        const double *iz = init_z + (size_t)(K - r) * np * pb->d;
+        double *oy = init_y + (size_t)(K - 1 - r) * np;
+        double *oz = init_z + (size_t)(K - 1 - r) * np * pb->d;
+        rc = oracle_solve(&q, iy, iz, oy, oz, NULL);
+        if (rc) return rc;
+    }
+    return ORACLE_OK;
 }
 
 /* Natural spline of one line and its evaluation: exposed so the tests can pin */

@@ -36,11 +36,20 @@ typedef struct {
     double x_min[2], x_max[2];
     double drift[2];    /* X_{t+h} = X_t + drift h + vol (W_{t+h} - W_t)            */
     double vol[2][2];   /* row-major; d = 1 uses vol[0][0]                          */
+    double drift_x;     /* d = 1: state-dependent coefficients of eq (1),           */
+    double vol_x;       /*   a(x) = drift[0] + drift_x x, b(x) = vol[0][0] + vol_x x */
+                        /*   (Euler step over each horizon j dt); 0, 0: constant    */
     int driver;         /* ORACLE_DRIVER_*                                          */
     double p[8];        /* driver parameters                                        */
     int picard_max;     /* Picard iterations (fixed count when picard_tol <= 0)     */
     double picard_tol;  /* stop when |dy| <= tol * max(1, |y|); <= 0: fixed count   */
     int n_stop;         /* last layer computed; 0 is the full backward sweep        */
+    int z_form;         /* first term of the z equation: 0 = E[z^{n+1}] as in       */
+                        /* eq (20); 1 = E[y^{n+1} dW_{n+1}] / dt, the form before   */
+                        /* the relation below eq (12) replaces it                   */
+    int quad;           /* conditional expectations: 0 = Gauss-Hermite, eq (21);     */
+                        /* 1 = exact Gaussian expectation of the interpolating      */
+                        /* spline (d = 1, linear driver, constant coefficients)     */
 } oracle_problem;
 
 typedef struct {
@@ -62,6 +71,17 @@ int oracle_solve(const oracle_problem *pb, const double *init_y, const double *i
 int oracle_first_step_points_2d(const oracle_problem *pb, const double *init_y,
                                 const double *init_z, int m, const long *idx, double *y_out,
                                 double *z_out);
+
+/* Section 3.1 step 2: rows 0..K-2 of init_y / init_z (t_{N-K+1}..t_{N-1})
+ * from row K-1 (the terminal layer) by the 1-step scheme (K_y = K_z = 1 of
+ * eq (20)) with `sub` steps per dt. */
+int oracle_initial_layers(const oracle_problem *pb, int sub, double *init_y, double *init_z);
+
+/* Exact Gaussian expectations of the natural splines of y and z (n points on
+ * [xmin, xmax], boundary values outside) at X = c[k] + sd xi, xi ~ N(0, 1):
+ * out[4k..4k+3] = E[yhat], E[yhat h xi], E[zhat], E[zhat h xi]. */
+int oracle_exact_expectation(int n, double xmin, double xmax, const double *y, const double *z,
+                             int m, const double *c, double sd, double h, double *out);
 
 /* Gauss-Hermite nodes a[0..L-1] and weights w[0..L-1] for exp(-x^2). */
 int oracle_gauss_hermite(int L, double *a, double *w);

@@ -24,10 +24,13 @@ BSDE_OK, BSDE_EINVAL, BSDE_ENOMEM, BSDE_EDEVICE, BSDE_EUNSUPPORTED, BSDE_ENOCONV
     BSDE_ENONFINITE = range(7)
 DRIVERS = {"linear": 0, "bidask": 1, "cubic": 2, "exp": 3}
 PRECISIONS = {"fp64": 0, "fp32_comp": 1}
+Z_FORMS = {"eq20": 0, "yW": 1}  # bsde_z_form: E[z^{n+1}], E[y^{n+1} dW]/dt
 
 EXPORTED = ["bsde_plan", "bsde_plan_destroy", "bsde_workspace_bytes", "bsde_solve",
             "bsde_solve_batched", "bsde_profile_kernels", "bsde_status_string",
-            "bsde_gauss_hermite", "bsde_gamma", "bsde_autotune"]
+            "bsde_gauss_hermite", "bsde_gamma", "bsde_autotune", "bsde_problem_info",
+            "bsde_initial_layers"]
+STABILITY_LIMIT = 16.0  # BSDE_STABILITY_LIMIT
 
 
 class BsdeError(RuntimeError):
@@ -49,12 +52,15 @@ class _Problem(ctypes.Structure):
         ("x_max", ctypes.c_double * 2),
         ("drift", ctypes.c_double * 2),
         ("vol", ctypes.c_double * 4),
+        ("drift_x", ctypes.c_double),
+        ("vol_x", ctypes.c_double),
         ("driver", ctypes.c_int),
         ("p", ctypes.c_double * 8),
         ("picard_max", ctypes.c_int),
         ("picard_tol", ctypes.c_double),
         ("prec", ctypes.c_int),
         ("n_stop", ctypes.c_int),
+        ("z_form", ctypes.c_int),
     ]
 
 
@@ -65,8 +71,14 @@ class _Stats(ctypes.Structure):
         ("picard_nonconverged", ctypes.c_longlong),
         ("nonfinite", ctypes.c_longlong),
         ("stability_ratio", ctypes.c_double),
+        ("unstable_instances", ctypes.c_int),
         ("elapsed_ms", ctypes.c_float),
     ]
+
+
+class _ProblemInfo(ctypes.Structure):
+    _fields_ = [("stability_ratio", ctypes.c_double), ("stable", ctypes.c_int),
+                ("K", ctypes.c_int), ("node_reach", ctypes.c_int), ("supported", ctypes.c_int)]
 
 
 class _KernelTimes(ctypes.Structure):
@@ -121,6 +133,11 @@ def load() -> ctypes.CDLL:
         lib.bsde_gauss_hermite.restype = ip
         lib.bsde_gamma.argtypes = [ip, ip, dp]
         lib.bsde_gamma.restype = ip
+        lib.bsde_problem_info.argtypes = [ctypes.POINTER(_Problem), ctypes.POINTER(_ProblemInfo)]
+        lib.bsde_problem_info.restype = ip
+        lib.bsde_initial_layers.argtypes = [ctypes.POINTER(_Problem), ip, vp, ctypes.c_size_t,
+                                            vp, vp, vp]
+        lib.bsde_initial_layers.restype = ip
         _lib = lib
     return _lib
 
@@ -146,6 +163,8 @@ def problem_struct(pb: dict) -> _Problem:
     v = np.atleast_2d(np.asarray(pb.get("vol", 1.0), dtype=float))
     vol[: v.shape[0], : v.shape[1]] = v
     s.vol[:] = [float(x) for x in vol.ravel()]
+    s.drift_x = float(pb.get("drift_x", 0.0))
+    s.vol_x = float(pb.get("vol_x", 0.0))
     s.driver = DRIVERS[pb["driver"]]
     p = list(pb.get("p", [])) + [0.0] * 8
     s.p[:] = [float(x) for x in p[:8]]
@@ -153,6 +172,7 @@ def problem_struct(pb: dict) -> _Problem:
     s.picard_tol = float(pb.get("picard_tol", 0.0))
     s.prec = PRECISIONS[pb.get("prec", "fp64")]
     s.n_stop = int(pb.get("n_stop", 0))
+    s.z_form = Z_FORMS[pb.get("z_form", "eq20")]
     return s
 
 
@@ -271,6 +291,26 @@ def bsde_autotune(plan: Plan, ws, ios, stream=None, reps: int = 5) -> dict:
     if rc != BSDE_OK:
         raise BsdeError(rc, "bsde_autotune")
     return {k: getattr(rep, k) for k, _ in _TuneReport._fields_}
+
+
+def bsde_initial_layers(pb: dict, substeps: int, ws, init_y, init_z, stream=None) -> None:
+    """bsde_initial_layers on device tensors: rows 0..K-2 of init_y / init_z from
+    row K-1 (the terminal layer) by the 1-step scheme with ``substeps`` steps per dt."""
+    rc = load().bsde_initial_layers(ctypes.byref(problem_struct(pb)), int(substeps),
+                                    ctypes.c_void_p(_dptr(ws)), ctypes.c_size_t(ws.numel()),
+                                    ctypes.c_void_p(_dptr(init_y)), ctypes.c_void_p(_dptr(init_z)),
+                                    ctypes.c_void_p(_stream_ptr(stream)))
+    if rc != BSDE_OK:
+        raise BsdeError(rc, "bsde_initial_layers")
+
+
+def bsde_problem_info(pb: dict) -> dict:
+    """bsde_problem_info: host-only validation and the stability ratio with its flag."""
+    info = _ProblemInfo()
+    rc = load().bsde_problem_info(ctypes.byref(problem_struct(pb)), ctypes.byref(info))
+    if rc != BSDE_OK:
+        raise BsdeError(rc, "bsde_problem_info")
+    return {k: getattr(info, k) for k, _ in _ProblemInfo._fields_}
 
 
 def bsde_gauss_hermite(L: int):

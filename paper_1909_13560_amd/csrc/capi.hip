@@ -5,7 +5,9 @@
 //   per instance: ring of K+1 slots; layer n lives in slot n mod (K+1); a slot
 //                 is two planes of pad_l ghost, n_x grid and pad_r ghost
 //                 elements: (y, z), then (M_y, M_z) (16 bytes each in FP64,
-//                 8 in FP32), so each launch writes whole planes
+//                 8 in FP32), so each launch writes whole planes; the FP32
+//                 form adds a third plane, the rounding residuals (e_y, e_z)
+//                 of the stored values (error feedback)
 //   per instance: per-wavefront Picard counters (statistics)
 //   totals      : 4 x u64 reduced statistics
 #include <hip/hip_runtime.h>
@@ -30,7 +32,7 @@ namespace {
 
 using bsde::kBlock;
 
-enum SweepPath { PATH_FUSED = 0, PATH_DIRECT = 1 };
+enum SweepPath { PATH_FUSED = 0, PATH_DIRECT = 1, PATH_GATHER = 3 };
 
 struct SweepConfig {
     int path = PATH_DIRECT;
@@ -50,10 +52,11 @@ struct Instance {
     int m_min, m_max;
     double R;
     bool f32;
+    bool gather;  // state-dependent forward coefficients: nodes located per point
     int steps;  // layers computed: N - K - n_stop + 1
     bsde::DriverParams drv;
     std::vector<int> m, win_lo, win_hi;
-    std::vector<double> B, C, D, cfy, cfz, cz, cy;
+    std::vector<double> B, C, D, cfy, cfz, cz, cy, cyz, dw;
     bsde::NodeTable dtab;
     size_t ring_off, fin_off, stat_off;
     int nwaves;  // per-wave statistics slots (P = 1 has the most waves)
@@ -160,12 +163,16 @@ bool valid_problem(const bsde_problem &p)
     if (p.L < 1 || p.L > bsde::kMaxL) return false;
     if (p.n_x[0] < 4 || !(p.x_max[0] > p.x_min[0])) return false;
     if (!std::isfinite(p.x_min[0]) || !std::isfinite(p.x_max[0])) return false;
-    if (!std::isfinite(p.drift[0]) || !(p.vol[0][0] > 0.0) || !std::isfinite(p.vol[0][0]))
+    if (!std::isfinite(p.drift[0]) || !std::isfinite(p.vol[0][0])) return false;
+    if (!std::isfinite(p.drift_x) || !std::isfinite(p.vol_x)) return false;
+    // the diffusion coefficient b(x) = vol + vol_x x must be positive over the grid
+    if (!(p.vol[0][0] + p.vol_x * p.x_min[0] > 0.0) || !(p.vol[0][0] + p.vol_x * p.x_max[0] > 0.0))
         return false;
     if (p.driver < BSDE_DRIVER_LINEAR || p.driver > BSDE_DRIVER_EXP) return false;
     if (p.picard_max < 1) return false;
     if (p.prec != BSDE_FP64 && p.prec != BSDE_FP32_COMP) return false;
     if (p.n_stop < 0 || p.n_stop > p.n_t - K) return false;
+    if (p.z_form != BSDE_ZFORM_EZ && p.z_form != BSDE_ZFORM_YDW) return false;
     for (int i = 0; i < 8; ++i)
         if (!std::isfinite(p.p[i])) return false;
     if (p.driver == BSDE_DRIVER_BIDASK && p.p[3] == 0.0) return false;
@@ -184,7 +191,7 @@ bool valid_problem(const bsde_problem &p)
 bool supported_2d(const bsde_problem &p)
 {
     return p.vol[0][1] == 0.0 && p.driver == BSDE_DRIVER_LINEAR && p.prec == BSDE_FP64 &&
-           p.L <= 64;
+           p.L <= 64 && p.drift_x == 0.0 && p.vol_x == 0.0;
 }
 
 // Node tables of eq (20)-(21) on the uniform grid (Section 3.2): the node
@@ -202,9 +209,12 @@ bool build_instance(const bsde_problem &p, Instance &in)
     in.dt = p.T / p.n_t;
     in.dx = (p.x_max[0] - p.x_min[0]) / (in.nx - 1);
     in.f32 = p.prec == BSDE_FP32_COMP;
+    in.gather = p.drift_x != 0.0 || p.vol_x != 0.0;
     in.steps = p.n_t - in.K - p.n_stop + 1;
     const double vol = p.vol[0][0];
-    in.R = vol * std::sqrt(2.0 * in.dt) / in.dx;
+    // largest Gauss-Hermite spread per cell over the grid (b(x) is affine)
+    in.R = std::max(vol + p.vol_x * p.x_min[0], vol + p.vol_x * p.x_max[0]) *
+           std::sqrt(2.0 * in.dt) / in.dx;
     double a[bsde::kMaxL], w[bsde::kMaxL], gy[8], gz[8];
     if (!bsde::gauss_hermite(p.L, a, w)) return false;
     if (!bsde::spline_gamma(1, p.k_y, gy) || !bsde::spline_gamma(2, p.k_z, gz)) return false;
@@ -212,7 +222,7 @@ bool build_instance(const bsde_problem &p, Instance &in)
     const int K = in.K, L = p.L;
     in.m.assign(K * L, 0);
     in.B.assign(K * L, 0.0);
-    in.C = in.D = in.cfy = in.cfz = in.cz = in.B;
+    in.C = in.D = in.cfy = in.cfz = in.cz = in.cyz = in.dw = in.B;
     in.cy.assign(L, 0.0);
     in.win_lo.assign(K + 1, 0);
     in.win_hi.assign(K + 1, 0);
@@ -233,12 +243,17 @@ bool build_instance(const bsde_problem &p, Instance &in)
             const double u = 1.0 - phi;
             const double wl = w[l] * inv_sqrt_pi;
             in.m[k] = m;
+            in.dw[k] = dW;
             in.B[k] = phi;
             in.C[k] = dx26 * (u * u * u - u);
             in.D[k] = dx26 * (phi * phi * phi - phi);
             in.cfy[k] = (j <= p.k_y) ? p.k_y * in.dt * gy[j] * wl : 0.0;
             in.cfz[k] = (j <= p.k_z) ? gz[j] * wl * dW / gz[0] : 0.0;
-            in.cz[k] = ((j == 1 ? 1.0 : 0.0) - (j <= p.k_z ? gz[j] : 0.0)) * wl / gz[0];
+            // the first term of the z equation: E[z^{n+1}] (eq (20)), or
+            // E[y^{n+1} dW]/dt (eq (12) with l = 1) for the z form YDW
+            const bool ydw = p.z_form == BSDE_ZFORM_YDW;
+            in.cz[k] = ((j == 1 && !ydw ? 1.0 : 0.0) - (j <= p.k_z ? gz[j] : 0.0)) * wl / gz[0];
+            in.cyz[k] = (j == 1 && ydw) ? wl * dW / (in.dt * gz[0]) : 0.0;
             if (j == p.k_y) in.cy[l] = wl;
             lo = std::min(lo, m);
             hi = std::max(hi, m);
@@ -321,8 +336,11 @@ bsde_status build_instance2(const bsde_problem &p, Instance2 &in)
                 nd.cfy = (j <= p.k_y) ? p.k_y * in.dt * gy[j] * wgt : 0.0;
                 nd.cfz1 = (j <= p.k_z) ? gz[j] * wgt * dW0 / gz[0] : 0.0;
                 nd.cfz2 = (j <= p.k_z) ? gz[j] * wgt * dW1 / gz[0] : 0.0;
-                nd.cz = ((j == 1 ? 1.0 : 0.0) - (j <= p.k_z ? gz[j] : 0.0)) * wgt / gz[0];
+                const bool ydw = p.z_form == BSDE_ZFORM_YDW;
+                nd.cz = ((j == 1 && !ydw ? 1.0 : 0.0) - (j <= p.k_z ? gz[j] : 0.0)) * wgt / gz[0];
                 nd.cy = (j == p.k_y) ? wgt : 0.0;
+                nd.cyz1 = (j == 1 && ydw) ? wgt * dW0 / (in.dt * gz[0]) : 0.0;
+                nd.cyz2 = (j == 1 && ydw) ? wgt * dW1 / (in.dt * gz[0]) : 0.0;
                 in.m1[k] = (int)f1;
                 lo = std::min(lo, (int)f1);
                 hi = std::max(hi, (int)f1);
@@ -375,6 +393,7 @@ bsde::Sweep2Args sweep2_args(const Instance2 &in, char *ws, bool stats)
     a.h0 = in.h0;
     a.picard_max = in.pb.picard_max;
     a.picard_tol = in.pb.picard_tol;
+    a.zform = in.pb.z_form;
     a.fin = reinterpret_cast<double *>(ws + in.fin_off);
     if (stats) {
         unsigned long long *sum = reinterpret_cast<unsigned long long *>(ws + in.stat_off);
@@ -398,6 +417,7 @@ SweepConfig fused_config(const std::vector<Instance> &all, const std::vector<int
     size_t lds = 0;
     for (int b : members) {
         const Instance &in = all[b];
+        if (in.gather) return SweepConfig{PATH_FUSED, P, G, 0};
         int wmax = 0, reach = 0;
         for (int j = 2; j <= in.K; ++j) {
             wmax = std::max(wmax, T + in.win_hi[j] - in.win_lo[j] + 1);
@@ -438,8 +458,16 @@ SweepConfig direct_config(const std::vector<Instance> &all, const std::vector<in
 // latency hiding), else the widest tile that fits; the direct kernel when no
 // window fits in LDS.  BSDE_SWEEP = "fused:P:G" or "direct:P" overrides;
 // bsde_autotune replaces the choice by the fastest measured shape.
+bool group_gathers(const std::vector<Instance> &all, const std::vector<int> &members)
+{
+    for (int b : members)
+        if (all[b].gather) return true;
+    return false;
+}
+
 SweepConfig default_config(const std::vector<Instance> &all, const Group &g, size_t max_lds)
 {
+    if (group_gathers(all, g.members)) return SweepConfig{PATH_GATHER, 1, 1, 0};
     const char *env = std::getenv("BSDE_SWEEP");
     if (env) {
         int P = 0, G = 1;
@@ -541,7 +569,10 @@ bsde_status enqueue_step(const bsde_plan_s &pl, const Group &g, char *ws, int s,
         HIP_OK(bsde::launch_sweep_fused(c.P, c.G, g.f32, g.driver, a, blocks, c.lds, st));
         if (tm) HIP_OK(tm->mark(tm->sweep, st));
     } else {
-        HIP_OK(bsde::launch_sweep_direct(c.P, g.f32, g.driver, a, blocks, c.lds, st));
+        if (c.path == PATH_GATHER)
+            HIP_OK(bsde::launch_sweep_gather(g.f32, g.driver, a, blocks, st));
+        else
+            HIP_OK(bsde::launch_sweep_direct(c.P, g.f32, g.driver, a, blocks, c.lds, st));
         if (tm) HIP_OK(tm->mark(tm->sweep, st));
         // natural spline of the new layer (the fused kernel does this in-kernel)
         if (tm) HIP_OK(tm->mark(tm->spline, st));
@@ -661,6 +692,7 @@ bsde_status finish_stats(bsde_plan_t plan, char *ws, hipStream_t s, hipEvent_t e
     unsigned long long mx = 0, sum = 0, nonc = 0;
     long long point_steps = 0;
     double R = 0.0;
+    int unstable = 0;
     for (int b = 0; b < count; ++b) {
         mx = std::max(mx, h[3 * b]);
         sum += h[3 * b + 1];
@@ -669,10 +701,12 @@ bsde_status finish_stats(bsde_plan_t plan, char *ws, hipStream_t s, hipEvent_t e
             const Instance &in = plan->inst[b];
             point_steps += (long long)in.nx * in.steps;
             R = std::max(R, in.R);
+            unstable += in.R > BSDE_STABILITY_LIMIT ? 1 : 0;
         } else {
             const Instance2 &in = plan->inst2[b];
             point_steps += (long long)in.n0 * in.n1 * (in.pb.n_t - in.K - in.pb.n_stop + 1);
             R = std::max(R, in.R);
+            unstable += in.R > BSDE_STABILITY_LIMIT ? 1 : 0;
         }
     }
     float ms = 0.0f;
@@ -682,6 +716,7 @@ bsde_status finish_stats(bsde_plan_t plan, char *ws, hipStream_t s, hipEvent_t e
     st->picard_nonconverged = (long long)nonc;
     st->nonfinite = (long long)h[3 * (size_t)count];
     st->stability_ratio = R;
+    st->unstable_instances = unstable;
     st->elapsed_ms = ms;
     if (st->nonfinite) return BSDE_ENONFINITE;
     if (st->picard_nonconverged) return BSDE_ENOCONV;
@@ -951,6 +986,81 @@ bsde_status bsde_gamma(int table, int K, double *g)
     return bsde::spline_gamma(table, K, g) ? BSDE_OK : BSDE_EINVAL;
 }
 
+bsde_status bsde_initial_layers(const bsde_problem *pb, int substeps, void *ws, size_t ws_bytes,
+                                double *init_y, double *init_z, void *stream)
+{
+    if (!pb || !ws || !init_y || !init_z || substeps < 1) return BSDE_EINVAL;
+    if (!valid_problem(*pb)) return BSDE_EINVAL;
+    const int K = std::max(pb->k_y, pb->k_z);
+    const size_t np = pb->d == 1 ? (size_t)pb->n_x[0] : (size_t)pb->n_x[0] * pb->n_x[1];
+    const double dt = pb->T / pb->n_t;
+    // every segment plan has n_t = (N - r + 1) substeps steps; the count must
+    // stay an int
+    if ((long long)pb->n_t * substeps > INT32_MAX / 2) return BSDE_EINVAL;
+    for (int r = 1; r < K; ++r) {
+        // layer t_{N-r} from t_{N-r+1}: the 1-step scheme (K_y = K_z = 1) over
+        // substeps steps of dt / substeps, absolute times kept (t = n dt')
+        bsde_problem q = *pb;
+        const int n_hi = pb->n_t - r + 1;
+        q.k_y = q.k_z = 1;
+        q.T = n_hi * dt;
+        q.n_t = n_hi * substeps;
+        q.n_stop = (n_hi - 1) * substeps;
+        bsde_plan_t plan = nullptr;
+        bsde_status rc = bsde_plan(&q, 1, &plan);
+        if (rc != BSDE_OK) return rc;
+        plan->use_graphs = false;  // solved once: launch directly, no capture
+        if (bsde_workspace_bytes(plan) > ws_bytes) {
+            bsde_plan_destroy(plan);
+            return BSDE_EINVAL;
+        }
+        const bsde_io io{init_y + (size_t)(K - r) * np, init_z + (size_t)(K - r) * np * pb->d,
+                         init_y + (size_t)(K - 1 - r) * np,
+                         init_z + (size_t)(K - 1 - r) * np * pb->d};
+        // the plan (and its device tables) must outlive the enqueued work
+        rc = bsde_solve_batched(plan, ws, &io, stream, nullptr);
+        const hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+        bsde_plan_destroy(plan);
+        if (rc != BSDE_OK) return rc;
+        if (e != hipSuccess) return BSDE_EDEVICE;
+    }
+    return BSDE_OK;
+}
+
+bsde_status bsde_problem_info(const bsde_problem *pb, bsde_problem_info_t *info)
+{
+    if (!pb || !info) return BSDE_EINVAL;
+    if (!valid_problem(*pb)) return BSDE_EINVAL;
+    bsde_problem_info_t r{};
+    r.K = std::max(pb->k_y, pb->k_z);
+    if (pb->d == 1) {
+        Instance in;
+        if (!build_instance(*pb, in)) return BSDE_EINVAL;
+        r.stability_ratio = in.R;
+        r.node_reach = std::max(-in.m_min, in.m_max + 1);
+        r.supported = 1;
+    } else {
+        Instance2 in;
+        r.supported = supported_2d(*pb) ? 1 : 0;
+        if (r.supported) {
+            const bsde_status rc = build_instance2(*pb, in);
+            if (rc == BSDE_EUNSUPPORTED) r.supported = 0;
+            else if (rc != BSDE_OK) return rc;
+        }
+        const double dx0 = (pb->x_max[0] - pb->x_min[0]) / (pb->n_x[0] - 1);
+        const double dx1 = (pb->x_max[1] - pb->x_min[1]) / (pb->n_x[1] - 1);
+        const double dt = pb->T / pb->n_t;
+        r.stability_ratio =
+            std::max(std::hypot(pb->vol[0][0], pb->vol[0][1]) / dx0,
+                     std::hypot(pb->vol[1][0], pb->vol[1][1]) / dx1) * std::sqrt(2.0 * dt);
+        r.node_reach = r.supported ? in.pad0 - 1 : 0;
+        if (r.supported) r.node_reach = std::max({r.node_reach, in.pad1 - 1, in.pad0r - bsde::kTile2R - 1});
+    }
+    r.stable = r.stability_ratio <= BSDE_STABILITY_LIMIT ? 1 : 0;
+    *info = r;
+    return BSDE_OK;
+}
+
 bsde_status bsde_plan(const bsde_problem *pb, int batch, bsde_plan_t *out)
 {
     if (!pb || !out || batch < 1) return BSDE_EINVAL;
@@ -1044,7 +1154,7 @@ bsde_status bsde_plan(const bsde_problem *pb, int batch, bsde_plan_t *out)
         toff[b] = tbytes;
         const size_t kl = (size_t)in.K * in.pb.L;
         tbytes += align_up(kl * sizeof(int), 256) + align_up(kl * sizeof(bsde::NodeRec), 256) +
-                  align_up(kl * sizeof(bsde::NodeRec32), 256);
+                  align_up(kl * sizeof(bsde::NodeRec32), 256) + align_up(kl * sizeof(double), 256);
     }
     const size_t desc_off = tbytes;
     tbytes += align_up((size_t)batch * sizeof(bsde::InstDesc), 256);
@@ -1080,16 +1190,17 @@ bsde_status bsde_plan(const bsde_problem *pb, int batch, bsde_plan_t *out)
             const int l = (int)(k % in.pb.L), j = (int)(k / in.pb.L) + 1;
             const double cy = (j == in.pb.k_y) ? in.cy[l] : 0.0;
             recs[k] = bsde::NodeRec{in.B[k],   in.C[k],  in.D[k], in.cfy[k],
-                                    in.cfz[k], in.cz[k], cy,      0.0};
+                                    in.cfz[k], in.cz[k], cy,      in.cyz[k]};
             recs32[k] = bsde::NodeRec32{(float)in.B[k],   (float)in.C[k],   (float)in.D[k],
                                         (float)in.cfy[k], (float)in.cfz[k], (float)in.cz[k],
-                                        (float)cy,        0.0f,             in.cz[k],
-                                        cy};
+                                        (float)cy,        (float)in.cyz[k], in.cz[k],
+                                        cy,               in.cyz[k],        0.0};
         }
         in.dtab.rec = static_cast<const bsde::NodeRec *>(put(recs.data(), kl * sizeof(bsde::NodeRec)));
         in.dtab.rec32 =
             static_cast<const bsde::NodeRec32 *>(put(recs32.data(), kl * sizeof(bsde::NodeRec32)));
         in.dtab.m = static_cast<const int *>(put(in.m.data(), kl * sizeof(int)));
+        in.dtab.dw = static_cast<const double *>(put(in.dw.data(), kl * sizeof(double)));
     }
     if (hipMemcpy(pl->d_tables, host.data(), desc_off, hipMemcpyHostToDevice) != hipSuccess) {
         bsde_plan_destroy(pl);
@@ -1108,8 +1219,11 @@ bsde_status bsde_plan(const bsde_problem *pb, int batch, bsde_plan_t *out)
     size_t off = 0;
     for (Instance &in : pl->inst) {
         in.ring_off = off;
-        // two planes of npad (y, z) and (M_y, M_z) elements per slot
-        off += align_up((size_t)(in.K + 1) * 2 * in.npad * (in.f32 ? sizeof(float2) : sizeof(double2)), 256);
+        // planes of npad elements per slot: (y, z) and (M_y, M_z); the FP32
+        // form adds the rounding residuals (e_y, e_z)
+        off += align_up((size_t)(in.K + 1) * (in.f32 ? 3 * sizeof(float2) : 2 * sizeof(double2)) *
+                            in.npad,
+                        256);
     }
     for (Instance &in : pl->inst) {
         in.fin_off = off;
@@ -1148,6 +1262,13 @@ bsde_status bsde_plan(const bsde_problem *pb, int batch, bsde_plan_t *out)
         a.h0 = in.h0;
         a.picard_max = in.pb.picard_max;
         a.picard_tol = in.pb.picard_tol;
+        a.zform = in.pb.z_form;
+        a.x_min = in.pb.x_min[0];
+        a.dx = in.dx;
+        a.drift0 = in.pb.drift[0];
+        a.drift_x = in.pb.drift_x;
+        a.vol0 = in.pb.vol[0][0];
+        a.vol_x = in.pb.vol_x;
         d.ring_off = in.ring_off;
         d.fin_off = in.fin_off;
         d.stat_off = in.stat_off;
@@ -1270,6 +1391,7 @@ bsde_status bsde_autotune(bsde_plan_t plan, void *ws, const bsde_io *io, void *s
                 SweepConfig c = fused_config(plan->inst, g.members, g.f32, P, G, plan->max_lds);
                 if (c.lds) cand.push_back(c);
             }
+        if (group_gathers(plan->inst, g.members)) cand.assign(1, SweepConfig{PATH_GATHER, 1, 1, 0});
         if (cand.empty()) cand.push_back(direct_config(plan->inst, g.members, g.f32, 2));
         float best = 0.0f;
         SweepConfig best_c = g.cfg;

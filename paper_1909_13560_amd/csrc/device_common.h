@@ -29,7 +29,7 @@ struct alignas(16) NodeRec {
     double cfz;    // weight of f-hat in z^n
     double cz;     // weight of z-hat in z^n
     double cy;     // weight of y-hat in the y constant (non-zero only for j = K_y)
-    double pad;
+    double cyz;    // weight of y-hat in z^n (z form E[y dW]/dt: j = 1 only)
 };
 
 // The FP32 form's node coefficients: interpolation weights and the weights
@@ -38,10 +38,10 @@ struct alignas(16) NodeRec {
 struct alignas(16) NodeRec32 {
     float B, C, D;
     float cfy, cfz;
-    float czf;  // cz in single precision (weight of the interpolation correction)
-    float cyf;  // cy in single precision
-    float pad;
-    double cz, cy;
+    float czf;   // cz in single precision (weight of the interpolation correction)
+    float cyf;   // cy in single precision
+    float cyzf;  // cyz in single precision
+    double cz, cy, cyz, pad;
 };
 
 // Node table of one instance (device memory).  K*L entries, row j-1 holds the
@@ -52,6 +52,7 @@ struct NodeTable {
     const int *m;       // integer cell offset of the node from x_i
     const int *win_lo;  // [K+1]: lowest node offset of layer j (j = 1 also <= 0)
     const int *win_hi;  // [K+1]: highest node offset of layer j (j = 1 also >= 0)
+    const double *dw;   // Brownian increment sqrt(2 j dt) a_l of node (j, l) (gather path)
 };
 
 constexpr int kMaxOrder = 6;  // largest K of Tables 1-2
@@ -154,6 +155,10 @@ struct SweepArgs {
     double h0;        // K_y dt gamma_{K_y,0}: weight of the implicit f(t_n, y^n, z^n)
     int picard_max;
     double picard_tol;
+    int zform;        // first term of the z equation: 0 E[z^{n+1}], 1 E[y^{n+1} dW]/dt
+    // forward coefficients of eq (1) (gather path): a(x) = drift0 + drift_x x,
+    // b(x) = vol0 + vol_x x on the grid x_i = x_min + i dx
+    double x_min, dx, drift0, drift_x, vol0, vol_x;
     unsigned int *st_iter_max;        // per-wave running maximum (NULL: no stats)
     unsigned long long *st_iter_sum;  // per-wave running sum
     unsigned long long *st_nonconv;   // per-wave count of unconverged point-steps
@@ -572,13 +577,23 @@ struct Prec<true> {
     using Win = WinStore32<P>;
 };
 
-// One ring slot (one time layer): two planes of npad elements, the values
+// One ring slot (one time layer): planes of npad elements, the values
 // (y, z) and the spline second derivatives (M_y, M_z), each pair a double2
 // (FP64) or float2 (FP32); index k runs from -pad_l to nx + pad_r - 1.  A
 // launch writes whole planes contiguously: the values of layer n and the
 // derivatives of layer n+1.
+// The FP32 form has a third plane, the rounding residuals (e_y, e_z) of the
+// stored values: y^n is stored as fl(y^n + e_y^{n+K_y}) and z^n as
+// fl(z^n + e_z^{n+1}) (round to nearest), and the residual of that rounding
+// is kept for the layer that follows in the same recurrence.  A layer
+// changes little from one step to the next, so plain rounding would make
+// nearly the same error at every step and the errors would add up along the
+// y and z recurrences of eq (20) (linearly in the number of steps); carried
+// forward, they cancel between consecutive steps instead (error feedback, as
+// in compensated summation) and the stored layers stay within a few units in
+// the last place of single precision of the exact ones.
 // Elements are addressed by a 32-bit byte offset from the plane's start
-// (the host keeps a plane below 4 GiB): both planes share the offset of a
+// (the host keeps a plane below 4 GiB): the planes share the offset of a
 // point, and the loads take the form "scalar base + 32-bit vector offset".
 template <bool F32>
 struct Slot {
@@ -595,14 +610,39 @@ struct Slot {
     {
         *reinterpret_cast<E *>(m0 + off(k)) = E{(T)my, (T)mz};
     }
+    // FP32 form: the residual plane follows the derivative plane
+    __device__ char *r0(int npad) const { return m0 + (size_t)npad * sizeof(E); }
 };
+
+template <bool F32>
+constexpr int kSlotPlanes = F32 ? 3 : 2;  // values, derivatives (, residuals)
 
 template <bool F32>
 __device__ inline Slot<F32> ring_slot(const SweepArgs &a, int layer)
 {
     using E = typename Slot<F32>::E;
-    char *base = static_cast<char *>(a.ring) + (size_t)(layer % (a.K + 1)) * 2 * a.npad * sizeof(E);
+    char *base = static_cast<char *>(a.ring) +
+                 (size_t)(layer % (a.K + 1)) * kSlotPlanes<F32> * a.npad * sizeof(E);
     return Slot<F32>{base, base + (size_t)a.npad * sizeof(E), a.pad_l};
+}
+
+// Store (y, z) of grid point i into a FP32-form ring slot with error
+// feedback: ey, ez are the residuals carried from the previous layers of the
+// y and z recurrences (0 for the initial layers).
+__device__ inline void store_fed_back(const Slot<true> &s, int npad, int i, double y, double z,
+                                      float ey, float ez)
+{
+    const double yv = y + (double)ey, zv = z + (double)ez;
+    const float sy = (float)yv, sz = (float)zv;
+    s.set_val(i, make_float2(sy, sz));
+    *reinterpret_cast<float2 *>(s.r0(npad) + s.off(i)) =
+        make_float2((float)(yv - (double)sy), (float)(zv - (double)sz));
+}
+
+// The residuals (e_y, e_z) stored with grid point i of a FP32-form slot.
+__device__ inline float2 fed_back_residual(const Slot<true> &s, int npad, int i)
+{
+    return *reinterpret_cast<const float2 *>(s.r0(npad) + s.off(i));
 }
 
 __device__ inline const NodeRec *node_recs(const NodeTable &t, NodeRec *) { return t.rec; }
@@ -625,7 +665,7 @@ __device__ inline NodeRec load_node(const NodeRec *p)
     r.cfz = const_load(&p->cfz);
     r.cz = const_load(&p->cz);
     r.cy = const_load(&p->cy);
-    r.pad = 0.0;
+    r.cyz = const_load(&p->cyz);
     return r;
 }
 __device__ inline NodeRec32 load_node(const NodeRec32 *p)
@@ -638,9 +678,11 @@ __device__ inline NodeRec32 load_node(const NodeRec32 *p)
     r.cfz = const_load(&p->cfz);
     r.czf = const_load(&p->czf);
     r.cyf = const_load(&p->cyf);
-    r.pad = 0.0f;
+    r.cyzf = const_load(&p->cyzf);
     r.cz = const_load(&p->cz);
     r.cy = const_load(&p->cy);
+    r.cyz = const_load(&p->cyz);
+    r.pad = 0.0;
     return r;
 }
 
@@ -656,10 +698,13 @@ struct Acc {
 // ---------------------------------------------------------------------------
 // Per-node work shared by the sweep kernels: interpolate y and z at the node
 // for P consecutive points from P+1 consecutive records, evaluate f, and
-// accumulate into the y-equation constant Y and into z^n (Z).  LASTY adds
-// the expectation of y itself (the layer j = K_y).
+// accumulate into the y-equation constant Y and into z^n (Z).  Node flags NF:
+// kNodeLastY adds the expectation of y itself (the layer j = K_y), kNodeYW
+// the y-hat term of z^n (layer j = 1 of the z form E[y^{n+1} dW]/dt).
 // ---------------------------------------------------------------------------
-template <int P, int DRV, bool LASTY>
+constexpr int kNodeLastY = 1, kNodeYW = 2;
+
+template <int P, int DRV, int NF>
 __device__ inline void node_accumulate(const double2 (&r)[2][P + 1], const NodeRec &c,
                                        const Driver<DRV, double> &f, Acc<P> &acc)
 {
@@ -672,9 +717,11 @@ __device__ inline void node_accumulate(const double2 (&r)[2][P + 1], const NodeR
                               fma(c.C, rm[q].y, fma(c.D, rm[q + 1].y, rv[q].y)));
         const double fh = f(yh, zh);
         double y = fma(c.cfy, fh, acc.Y[q]);
-        if (LASTY) y = fma(c.cy, yh, y);
+        if (NF & kNodeLastY) y = fma(c.cy, yh, y);
         acc.Y[q] = y;
-        acc.Z[q] = fma(c.cfz, fh, fma(c.cz, zh, acc.Z[q]));
+        double z = fma(c.cfz, fh, fma(c.cz, zh, acc.Z[q]));
+        if (NF & kNodeYW) z = fma(c.cyz, yh, z);
+        acc.Z[q] = z;
     }
 }
 
@@ -688,7 +735,7 @@ __device__ inline void node_accumulate(const double2 (&r)[2][P + 1], const NodeR
 // whose weights are O(dt) and O(sqrt(dt)), are summed over the layer in
 // single precision.  f-hat itself is evaluated in single precision at
 // v0 + d.
-template <int P, int DRV, bool LASTY>
+template <int P, int DRV, int NF>
 __device__ inline void node_accumulate(const float4 (&r)[1][P + 1], const NodeRec32 &c,
                                        const Driver<DRV, float> &f, Acc<P> &acc)
 {
@@ -701,9 +748,13 @@ __device__ inline void node_accumulate(const float4 (&r)[1][P + 1], const NodeRe
         acc.Yf[q] = fmaf(c.cfy, fh, acc.Yf[q]);
         acc.Zf[q] = fmaf(c.cfz, fh, fmaf(c.czf, dz, acc.Zf[q]));
         acc.Z[q] = fma(c.cz, (double)r0.y, acc.Z[q]);
-        if (LASTY) {
+        if (NF & kNodeLastY) {
             acc.Yf[q] = fmaf(c.cyf, dy, acc.Yf[q]);
             acc.Y[q] = fma(c.cy, (double)r0.x, acc.Y[q]);
+        }
+        if (NF & kNodeYW) {
+            acc.Zf[q] = fmaf(c.cyzf, dy, acc.Zf[q]);
+            acc.Z[q] = fma(c.cyz, (double)r0.x, acc.Z[q]);
         }
     }
 }
@@ -713,7 +764,7 @@ __device__ inline void node_accumulate(const float4 (&r)[1][P + 1], const NodeRe
 // of a layer are held one per lane (L <= 64) and moved to a scalar register
 // per node with readlane, and the coefficient records come through scalar
 // loads, so the only per-node LDS traffic is the records themselves.
-template <int P, int DRV, bool LASTY, bool F32, typename Src>
+template <int P, int DRV, int NF, bool F32, typename Src>
 __device__ inline void layer_nodes(const Src &src, const typename Prec<F32>::Node *nodes,
                                    const int *m, int l0, int LS, int L,
                                    const Driver<DRV, typename Prec<F32>::Raw> &f, Acc<P> &acc)
@@ -739,14 +790,14 @@ __device__ inline void layer_nodes(const Src &src, const typename Prec<F32>::Nod
             V r0[NA][P + 1], r1[NA][P + 1];
             src.template fetch<P>(__builtin_amdgcn_readlane(mv, l), r0);
             src.template fetch<P>(__builtin_amdgcn_readlane(mv, l + LS), r1);
-            node_accumulate<P, DRV, LASTY>(r0, c0, f, acc);
-            node_accumulate<P, DRV, LASTY>(r1, c1, f, acc);
+            node_accumulate<P, DRV, NF>(r0, c0, f, acc);
+            node_accumulate<P, DRV, NF>(r1, c1, f, acc);
         }
         if (l < L) {
             const Node c0 = load_node(nodes + l);
             V r0[NA][P + 1];
             src.template fetch<P>(__builtin_amdgcn_readlane(mv, l), r0);
-            node_accumulate<P, DRV, LASTY>(r0, c0, f, acc);
+            node_accumulate<P, DRV, NF>(r0, c0, f, acc);
         }
     }
     if (F32) {
@@ -793,7 +844,15 @@ __device__ inline void finish_points(const SweepArgs &a, int first, const Acc<P>
             for (; it < a.picard_max; ++it) y = fma(a.h0, f0(y, zq), Yq);
         }
         if (valid) {
-            out.set_val(i, y, zq);
+            if constexpr (F32) {
+                // error feedback: residual of y^{n+K_y} (y recurrence) and of
+                // z^{n+1} (z recurrence) at the same point
+                const float ey = fed_back_residual(ring_slot<true>(a, a.n + a.Ky), a.npad, i).x;
+                const float ez = fed_back_residual(ring_slot<true>(a, a.n + 1), a.npad, i).y;
+                store_fed_back(out, a.npad, i, y, zq, ey, ez);
+            } else {
+                out.set_val(i, y, zq);
+            }
             if (last) {
                 a.fin_y[i] = y;
                 a.fin_z[i] = zq;

@@ -37,6 +37,8 @@ hipError_t launch_sweep_fused(int P, int G, bool f32, int driver, const StepArgs
 hipError_t set_fused_lds_limit(int P, int G, bool f32, int driver, size_t lds);
 hipError_t launch_sweep_direct(int P, bool f32, int driver, const StepArgs &a, int blocks,
                                size_t lds, hipStream_t s);
+// state-dependent forward coefficients: one point per lane, nodes located per point
+hipError_t launch_sweep_gather(bool f32, int driver, const StepArgs &a, int blocks, hipStream_t s);
 // mode 0: initial layer s of every instance; mode 1: layer n0 - s (direct path)
 hipError_t launch_spline(bool f32, const StepArgs &a, int mode, int blocks, hipStream_t s);
 hipError_t launch_scatter(const ScatterChunk &c, char *ws, const InstDesc *desc, int blocks_x,

@@ -100,10 +100,20 @@ __device__ inline void layer_dispatch(const Src &src, const int *tm, int j, int 
     const Driver<DRV, typename Prec<F32>::Raw> f(a.drv, (a.n + j) * a.dt);
     const int row = (j - 1) * a.L;
     const Node *nodes = node_recs(a.tab, static_cast<Node *>(nullptr)) + row;
-    if (j == a.Ky)
-        layer_nodes<P, DRV, true, F32>(src, nodes, tm + row, l0, LS, a.L, f, acc);
-    else
-        layer_nodes<P, DRV, false, F32>(src, nodes, tm + row, l0, LS, a.L, f, acc);
+    const int nf = (j == a.Ky ? kNodeLastY : 0) | (j == 1 && a.zform ? kNodeYW : 0);
+    switch (nf) {
+    case 0: layer_nodes<P, DRV, 0, F32>(src, nodes, tm + row, l0, LS, a.L, f, acc); break;
+    case kNodeLastY:
+        layer_nodes<P, DRV, kNodeLastY, F32>(src, nodes, tm + row, l0, LS, a.L, f, acc);
+        break;
+    case kNodeYW:
+        layer_nodes<P, DRV, kNodeYW, F32>(src, nodes, tm + row, l0, LS, a.L, f, acc);
+        break;
+    default:
+        layer_nodes<P, DRV, kNodeLastY | kNodeYW, F32>(src, nodes, tm + row, l0, LS, a.L, f,
+                                                       acc);
+        break;
+    }
 }
 
 // LDS bytes of the window arrays of the fused kernel.
@@ -309,6 +319,73 @@ __global__ void __launch_bounds__(kBlock) sweep_direct(const StepArgs s)
 }
 
 // ---------------------------------------------------------------------------
+// Gather sweep: forward coefficients that depend on the state (eq (1)).  The
+// node of (j, l) for point x_i is one Euler step of X over j dt,
+//   X = x_i + a(x_i) j dt + b(x_i) sqrt(2 j dt) a_l,
+// so its cell and fraction differ from point to point: each lane locates
+// its nodes (Section 3.2: floor on the uniform grid, the boundary value
+// outside the truncated domain), forms the spline basis weights at the
+// fraction and reads the two records from HBM/L2.  One point per lane; the
+// natural spline of the new layer is a separate launch.
+// ---------------------------------------------------------------------------
+template <int DRV, bool F32>
+__global__ void __launch_bounds__(kBlock) sweep_gather(const StepArgs s)
+{
+    using PR = Prec<F32>;
+    using Node = typename PR::Node;
+    using V = typename PR::V;
+    const int idx = xcd_tile(blockIdx.x, gridDim.x);
+    const InstDesc &d = block_desc(s, idx);
+    const SweepArgs a = bind_instance(d, s.ws, s.s, s.stats != 0);
+    const int tile = idx - d.tile_base;
+    const int first = tile * kBlock + (int)threadIdx.x;
+    const int i = min(first, a.nx - 1);  // lanes past the end compute in bounds, store nothing
+    const double xi = a.x_min + i * a.dx;
+    const double ax = fma(a.drift_x, xi, a.drift0), bx = fma(a.vol_x, xi, a.vol0);
+    const double dx26 = a.dx * a.dx / 6.0;
+    Acc<1> acc;
+    acc.Y[0] = acc.Z[0] = 0.0;
+    for (int j = 1; j <= a.K; ++j) {
+        const Slot<F32> g = ring_slot<F32>(a, a.n + j);
+        const Driver<DRV, typename PR::Raw> f(a.drv, (a.n + j) * a.dt);
+        const int row = (j - 1) * a.L;
+        const Node *nodes = node_recs(a.tab, static_cast<Node *>(nullptr)) + row;
+        const int nf = (j == a.Ky ? kNodeLastY : 0) | (j == 1 && a.zform ? kNodeYW : 0);
+        if (F32) acc.Yf[0] = acc.Zf[0] = 0.0f;
+        for (int l = 0; l < a.L; ++l) {
+            const double X = xi + ax * (j * a.dt) + bx * a.tab.dw[row + l];
+            const double sx = (X - a.x_min) / a.dx;
+            int p = 0;
+            double phi = 0.0;
+            if (sx >= (double)(a.nx - 1)) {
+                p = a.nx - 1;  // the last record; its right neighbour is a ghost, weight 0
+            } else if (sx > 0.0) {
+                p = min((int)floor(sx), a.nx - 2);
+                phi = sx - p;
+            }
+            const double u = 1.0 - phi;
+            Node c = load_node(nodes + l);
+            c.B = phi;
+            c.C = dx26 * (u * u * u - u);
+            c.D = dx26 * (phi * phi * phi - phi);
+            V r[PR::NA][2];
+            GlobalWindow<F32>{g, p}.template fetch<1>(0, r);
+            switch (nf) {
+            case 0: node_accumulate<1, DRV, 0>(r, c, f, acc); break;
+            case kNodeLastY: node_accumulate<1, DRV, kNodeLastY>(r, c, f, acc); break;
+            case kNodeYW: node_accumulate<1, DRV, kNodeYW>(r, c, f, acc); break;
+            default: node_accumulate<1, DRV, kNodeLastY | kNodeYW>(r, c, f, acc); break;
+            }
+        }
+        if (F32) {
+            acc.Y[0] += (double)acc.Yf[0];
+            acc.Z[0] += (double)acc.Zf[0];
+        }
+    }
+    finish_points<1, DRV, F32>(a, first, acc, (tile * kBlock + (int)threadIdx.x) >> 6);
+}
+
+// ---------------------------------------------------------------------------
 // Standalone natural spline of one layer per instance: the initial layers
 // (mode 0: layer n0 + 1 + s) and, on the direct path, the layer just computed
 // (mode 1: layer n0 - s, skipped at n_stop, which no later step reads).
@@ -376,7 +453,7 @@ __global__ void __launch_bounds__(kBlock) scatter_layers(const ScatterChunk c, c
         for (int i = blockIdx.x * kBlock + threadIdx.x; i < a.nx; i += gridDim.x * kBlock) {
             const double y = iy[(size_t)r * a.nx + i], z = iz[(size_t)r * a.nx + i];
             if (d.f32)
-                g32.set_val(i, y, z);
+                store_fed_back(g32, a.npad, i, y, z, 0.0f, 0.0f);
             else
                 g64.set_val(i, y, z);
         }
@@ -469,6 +546,14 @@ hipError_t launch_direct_t(const StepArgs &a, int blocks, size_t lds, hipStream_
     return hipGetLastError();
 }
 
+template <int P, int DRV, bool F32>
+hipError_t launch_gather_t(const StepArgs &a, int blocks, size_t, hipStream_t s)
+{
+    static_assert(P == 1, "one point per lane");
+    hipLaunchKernelGGL((sweep_gather<DRV, F32>), dim3(blocks), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
 template <int P, int G, int DRV, bool F32>
 hipError_t allow_lds_t(size_t lds)
 {
@@ -502,6 +587,12 @@ template <int P, bool F32>
 hipError_t direct_by_driver(int driver, const StepArgs &a, int blocks, size_t lds, hipStream_t s)
 {
     BSDE_BY_DRIVER(launch_direct_t, P, a, blocks, lds, s)
+}
+
+template <bool F32>
+hipError_t gather_by_driver(int driver, const StepArgs &a, int blocks, hipStream_t s)
+{
+    BSDE_BY_DRIVER(launch_gather_t, 1, a, blocks, 0, s)
 }
 
 #undef BSDE_BY_DRIVER
@@ -551,6 +642,12 @@ hipError_t launch_sweep_direct(int P, bool F32, int driver, const StepArgs &a, i
                        : direct_by_driver<4, false>(driver, a, blocks, lds, s);
     default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_sweep_gather(bool F32, int driver, const StepArgs &a, int blocks, hipStream_t s)
+{
+    return F32 ? gather_by_driver<true>(driver, a, blocks, s)
+               : gather_by_driver<false>(driver, a, blocks, s);
 }
 
 hipError_t launch_spline(bool f32, const StepArgs &a, int mode, int blocks, hipStream_t s)

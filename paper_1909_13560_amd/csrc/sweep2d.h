@@ -37,6 +37,7 @@ struct Node2Row {
 struct alignas(16) Node2 {
     double B1, C1, D1;
     double cfy, cfz1, cfz2, cz, cy;
+    double cyz1, cyz2;  // weights of y-hat in z1^n, z2^n (z form E[y dW]/dt, j = 1)
 };
 
 // Natural-spline second derivatives by the truncated PCR written as a
@@ -95,7 +96,7 @@ struct Sweep2Args {
     size_t plane;
     int n0, n1, npad1, pad0, pad1;
     int K, Ky, L, n, n_stop;
-    int win;                // LDS window columns: 64 + widest m1 spread of a row + 2
+    int win;                // LDS window columns: kTile2C + widest m1 spread of a row + 2
     const Node2Row *rows;   // K*L
     const Node2 *nodes;     // K*L*L
     const int *m1;          // K*L*L
@@ -103,6 +104,7 @@ struct Sweep2Args {
     double dt, h0;
     int picard_max;
     double picard_tol;
+    int zform;              // first term of the z equation: 0 E[z^{n+1}], 1 E[y^{n+1} dW]/dt
     double *fin;            // layer n_stop: y, z1, z2 planes of n0*n1
     unsigned int *st_iter_max;
     unsigned long long *st_iter_sum, *st_nonconv;

@@ -49,10 +49,14 @@ __device__ inline Node2 load_node2(const Node2 *p)
     n.cfz2 = q->cfz2;
     n.cz = q->cz;
     n.cy = q->cy;
+    n.cyz1 = q->cyz1;
+    n.cyz2 = q->cyz2;
     return n;
 }
 
-template <bool LASTY>
+// Node flags: bit 0 the y expectation (layer j = K_y), bit 1 the y-hat terms
+// of z^n (layer j = 1 of the z form E[y^{n+1} dW]/dt).
+template <int NF>
 __device__ inline void node2_accumulate(const Sweep2Args &a, const double2 *uv, const Node2 &nd,
                                         int r, int e, double &Y, double &Z1, double &Z2)
 {
@@ -64,16 +68,20 @@ __device__ inline void node2_accumulate(const Sweep2Args &a, const double2 *uv, 
     }
     const double fh = f_linear2(a.drv, h[0], h[1], h[2]);
     Y = fma(nd.cfy, fh, Y);
-    if (LASTY) Y = fma(nd.cy, h[0], Y);
+    if (NF & 1) Y = fma(nd.cy, h[0], Y);
     Z1 = fma(nd.cfz1, fh, fma(nd.cz, h[1], Z1));
     Z2 = fma(nd.cfz2, fh, fma(nd.cz, h[2], Z2));
+    if (NF & 2) {
+        Z1 = fma(nd.cyz1, h[0], Z1);
+        Z2 = fma(nd.cyz2, h[0], Z2);
+    }
 }
 
 // The L nodes l1 of one axis-0 row of layer j, for the lane's point.  The
 // node records come through scalar loads and the axis-1 offsets, one per
 // lane in mv, through readlane, so the only per-node LDS reads are the
 // (U, V) records; two nodes per iteration share one wait.
-template <bool LASTY>
+template <int NF>
 __device__ inline void row_nodes(const Sweep2Args &a, const double2 *uv, const Node2 *ntab,
                                  int mv, int r, int c, int m1lo, double &Y, double &Z1,
                                  double &Z2)
@@ -84,12 +92,12 @@ __device__ inline void row_nodes(const Sweep2Args &a, const double2 *uv, const N
         const Node2 n0 = load_node2(ntab + l1), n1 = load_node2(ntab + l1 + 1);
         const int e0 = c + __builtin_amdgcn_readlane(mv, l1) - m1lo;
         const int e1 = c + __builtin_amdgcn_readlane(mv, l1 + 1) - m1lo;
-        node2_accumulate<LASTY>(a, uv, n0, r, e0, Y, Z1, Z2);
-        node2_accumulate<LASTY>(a, uv, n1, r, e1, Y, Z1, Z2);
+        node2_accumulate<NF>(a, uv, n0, r, e0, Y, Z1, Z2);
+        node2_accumulate<NF>(a, uv, n1, r, e1, Y, Z1, Z2);
     }
     if (l1 < a.L) {
         const Node2 n0 = load_node2(ntab + l1);
-        node2_accumulate<LASTY>(a, uv, n0, r, c + __builtin_amdgcn_readlane(mv, l1) - m1lo, Y, Z1,
+        node2_accumulate<NF>(a, uv, n0, r, c + __builtin_amdgcn_readlane(mv, l1) - m1lo, Y, Z1,
                                 Z2);
     }
 }
@@ -133,10 +141,15 @@ __global__ void __launch_bounds__(kThreads2) sweep2d(const Sweep2Args a)
             }
             __syncthreads();
             const Node2 *ntab = a.nodes + (size_t)rowi * a.L;
-            if (j == a.Ky)
-                row_nodes<true>(a, uv, ntab, mv, r, c, row.m1lo, Y, Z1, Z2);
+            const int nf = (j == a.Ky ? 1 : 0) | (j == 1 && a.zform ? 2 : 0);
+            if (nf == 0)
+                row_nodes<0>(a, uv, ntab, mv, r, c, row.m1lo, Y, Z1, Z2);
+            else if (nf == 1)
+                row_nodes<1>(a, uv, ntab, mv, r, c, row.m1lo, Y, Z1, Z2);
+            else if (nf == 2)
+                row_nodes<2>(a, uv, ntab, mv, r, c, row.m1lo, Y, Z1, Z2);
             else
-                row_nodes<false>(a, uv, ntab, mv, r, c, row.m1lo, Y, Z1, Z2);
+                row_nodes<3>(a, uv, ntab, mv, r, c, row.m1lo, Y, Z1, Z2);
             __syncthreads();
         }
     }

@@ -152,3 +152,26 @@ def test_plan_rejects_invalid_2d_axis():
     with pytest.raises(B.BsdeError) as e:
         B.bsde_plan(pb)
     assert e.value.code == B.BSDE_EINVAL
+
+
+def test_problem_info_flags_the_stability_ratio():
+    # host only: the plan-time stability ratio R = vol sqrt(2 dt)/dx and its
+    # flag (R <= 16), for the benchmarked grid, its literal interval and a
+    # two-dimensional grid
+    cases = [(W.bidask_call_1d(), True), (W.bidask_call_1d(half_width=None), False),
+             (W.bidask_call_1d(n_x=3001, n_t=24, half_width=None), False),
+             (W.basket_2d(), True), (W.sine_1d(), True)]
+    for wl, stable in cases:
+        info = B.bsde_problem_info(wl.problem)
+        R = W.stability_ratio(wl.problem)
+        assert info["stability_ratio"] == pytest.approx(R, rel=1e-12)
+        assert info["stable"] == (1 if stable else 0) and info["supported"] == 1
+        assert info["K"] == wl.K
+    # the literal interval of the benchmark: nodes reach about 9000 cells
+    info = B.bsde_problem_info(W.bidask_call_1d(half_width=None).problem)
+    assert info["node_reach"] > 9000
+    with pytest.raises(B.BsdeError):
+        B.bsde_problem_info(dict(W.sine_1d().problem, L=0))
+    # a 2-D problem outside the 2-D kernels: reported, not refused
+    pb = dict(W.exchange_2d().problem, driver="bidask", p=[0.01, 0.06, 0.2, 0.2, 1.0])
+    assert B.bsde_problem_info(pb)["supported"] == 0

@@ -1,0 +1,199 @@
+"""GPU parity of the steps around the sweep: the initial layers of Section 3.1
+step 2 (1-step scheme with sub-steps).
+
+Same measure and bar as test_gpu_parity: max_i |gpu_i - oracle_i| /
+max(|oracle_i|, 1) over every grid point, <= 1e-10 in FP64.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from test_gpu_parity import TOL64, rel_err, twin_half_width
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1909_13560_amd as B
+
+    B.load()
+    return B
+
+
+@pytest.fixture(scope="module")
+def orc():
+    import oracle
+
+    oracle.build(force=False)
+    return oracle
+
+
+def _initial_layers_case(lib, orc, wl, sub):
+    import torch
+
+    pb = wl.problem
+    iy_ex, iz_ex = wl.init_layers()
+    K, npts = iy_ex.shape
+    d = pb["d"]
+    print(f"[case] initial layers {wl.name} sub={sub}", flush=True)
+    # the oracle's layers from the terminal one
+    iy_o, iz_o = orc.initial_layers(pb, iy_ex[-1], iz_ex[-1], sub)
+    # the library's, on the device, from the same terminal layer
+    plan = lib.bsde_plan(pb)
+    ws = lib.workspace(plan)
+    t_iy = torch.full((K, npts), float("nan"), dtype=torch.float64, device="cuda")
+    t_iz = torch.full((K, d * npts), float("nan"), dtype=torch.float64, device="cuda")
+    t_iy[K - 1] = torch.as_tensor(iy_ex[-1], device="cuda")
+    t_iz[K - 1] = torch.as_tensor(iz_ex[-1].reshape(-1), device="cuda")
+    lib.bsde_initial_layers(pb, sub, ws, t_iy, t_iz)
+    iy_g = t_iy.cpu().numpy()
+    iz_g = t_iz.cpu().numpy().reshape(K, d, npts)
+    e = max(max(rel_err(iy_g[r], iy_o[r]), max(rel_err(iz_g[r, c], iz_o[r, c]) for c in range(d)))
+            for r in range(K))
+    print(f"  layers: rel err {e:.3e}", flush=True)
+    assert e <= TOL64
+    # the whole solve from those layers
+    y0 = torch.empty(npts, dtype=torch.float64, device="cuda")
+    z0 = torch.empty(d * npts, dtype=torch.float64, device="cuda")
+    rc, _ = lib.bsde_solve(plan, ws, t_iy, t_iz, y0, z0, stats=True)
+    import torch as _t
+
+    _t.cuda.synchronize()
+    assert rc == lib.BSDE_OK
+    yo, zo, _ = orc.solve(pb, iy_o, iz_o)
+    zg = z0.cpu().numpy().reshape(d, npts)
+    es = max(rel_err(y0.cpu().numpy(), yo), max(rel_err(zg[c], zo[c]) for c in range(d)))
+    print(f"  solve: rel err {es:.3e}", flush=True)
+    assert es <= TOL64
+    return iy_g, iz_g
+
+
+@pytest.mark.parametrize("sub", [1, 7])
+def test_initial_layers_sine(lib, orc, sub):
+    _initial_layers_case(lib, orc, W.sine_1d(n_x=1025, n_t=64, k=4), sub)
+
+
+def test_initial_layers_bid_ask_and_time_dependent_driver(lib, orc):
+    nx, nt = 3001, 24
+    _initial_layers_case(
+        lib, orc, W.bidask_call_1d(n_x=nx, n_t=nt, k=5, half_width=twin_half_width(0.2, 0.5, nt, nx)),
+        4)
+    # Example 2's driver depends on t: the sub-steps must see absolute times
+    _initial_layers_case(lib, orc, W.paper_example2(3, 16, 512), 6)
+
+
+def test_initial_layers_two_dimensional(lib, orc):
+    _initial_layers_case(lib, orc, W.exchange_2d(n_x=49, n_t=8, k=3, L=6, rho=0.5), 3)
+
+
+def test_initial_layers_reject_small_workspace(lib):
+    import torch
+
+    wl = W.sine_1d(n_x=300, n_t=16, k=3)
+    ws = torch.empty(256, dtype=torch.uint8, device="cuda")
+    iy = torch.zeros((3, 300), dtype=torch.float64, device="cuda")
+    iz = torch.zeros((3, 300), dtype=torch.float64, device="cuda")
+    with pytest.raises(lib.BsdeError) as ei:
+        lib.bsde_initial_layers(wl.problem, 2, ws, iy, iz)
+    assert ei.value.code == lib.BSDE_EINVAL
+
+
+# ----------------------------------------------------------------------------
+# The z form E[y^{n+1} dW]/dt
+# ----------------------------------------------------------------------------
+
+
+def _run(lib, orc, wl, prec="fp64", tol=TOL64):
+    pb = dict(wl.problem, prec=prec)
+    print(f"[case] {wl.name} z_form={pb.get('z_form')} {prec}", flush=True)
+    iy, iz = wl.init_layers()
+    y, z, rc, st = lib.solve(pb, iy, iz)
+    yo, zo, _ = orc.solve(pb, iy, iz)
+    e = max(rel_err(y, yo), max(rel_err(z[c], zo[c]) for c in range(pb["d"])))
+    print(f"  rel err {e:.3e}", flush=True)
+    assert rc == lib.BSDE_OK and e <= tol
+    return y, z
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", TOL64), ("fp32_comp", 1e-6)])
+def test_z_form_ydw_one_step(lib, orc, prec, tol):
+    nx, nt = 4001, 64
+    wl = W.bidask_call_1d(n_x=nx, n_t=nt, k=1, half_width=twin_half_width(0.2, 0.5, nt, nx))
+    wl.problem["z_form"] = "yW"
+    _run(lib, orc, wl, prec, tol)
+    wl = W.sine_1d(n_x=1025, n_t=64, k=1)
+    wl.problem["z_form"] = "yW"
+    y, z = _run(lib, orc, wl, prec, tol)
+    # second order: at N = 64 the z error at x = 0 is below 1e-4
+    ye, ze = wl.exact_at_t0()
+    assert abs(z[0, wl.node_index()] - ze[wl.node_index()]) < 1e-4
+
+
+def test_z_form_ydw_multistep_and_two_dimensional(lib, orc):
+    # parity of the multistep form over a short sweep (it is unstable over
+    # long ones) with unequal orders, and the two-dimensional kernels
+    wl = W.sine_1d(n_x=900, n_t=8, k=3)
+    wl.problem.update(z_form="yW", k_z=2)
+    _run(lib, orc, wl)
+    wl = W.exchange_2d(n_x=57, n_t=12, k=1, L=8, rho=0.5)
+    wl.problem["z_form"] = "yW"
+    _run(lib, orc, wl)
+    wl = W.sine_2d(n_x=65, n_t=6, k=2, L=8)
+    wl.problem["z_form"] = "yW"
+    _run(lib, orc, wl)
+
+
+# ----------------------------------------------------------------------------
+# State-dependent forward coefficients: nodes located per point (gather path)
+# ----------------------------------------------------------------------------
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", TOL64), ("fp32_comp", 1e-6)])
+def test_gather_path_price_grid_and_ou(lib, orc, prec, tol):
+    # Black-Scholes on the stock-price grid (b(S) = sigma S), ragged grid
+    y, z = _run(lib, orc, W.bs_call_price_1d(n_x=1001, n_t=48, k=3), prec, tol)
+    # Ornstein-Uhlenbeck drift with both z forms and unequal orders
+    wl = W.ou_linear_1d(n_x=1201, n_t=24, k=1)
+    wl.problem["z_form"] = "yW"
+    _run(lib, orc, wl, prec, tol)
+    wl = W.ou_linear_1d(n_x=777, n_t=20, k=4)
+    wl.problem["k_z"] = 2
+    _run(lib, orc, wl, prec, tol)
+
+
+def test_gather_path_nonlinear_driver_and_batch(lib, orc):
+    import torch
+
+    # bid-ask driver with an affine volatility (nodes leave the domain at
+    # both ends), in a batch with a constant-coefficient instance (which
+    # keeps its own LDS-staged kernel)
+    g = W.bidask_call_1d(n_x=3001, n_t=16, half_width=None)
+    g.problem.update(drift_x=0.01, vol_x=0.02, vol=0.2 - 0.02 * 4.6)
+    u = W.bidask_call_1d(n_x=5003, n_t=24, half_width=twin_half_width(0.2, 0.5, 24, 5003))
+    plan = lib.bsde_plan([g.problem, u.problem])
+    ws = lib.workspace(plan)
+    ios = []
+    for w in (g, u):
+        iy, iz = w.init_layers()
+        n = iy.shape[1]
+        ios.append((torch.as_tensor(iy, device="cuda").contiguous(),
+                    torch.as_tensor(iz.reshape(iy.shape), device="cuda").contiguous(),
+                    torch.empty(n, dtype=torch.float64, device="cuda"),
+                    torch.empty(n, dtype=torch.float64, device="cuda")))
+    print("[case] gather + fused batch", flush=True)
+    rc, st = lib.bsde_solve_batched(plan, ws, ios, stats=True)
+    torch.cuda.synchronize()
+    assert rc == lib.BSDE_OK
+    kt = lib.bsde_profile_kernels(plan, ws, ios)
+    for w, io in zip((g, u), ios):
+        iy, iz = w.init_layers()
+        yo, zo, _ = orc.solve(w.problem, iy, iz)
+        e = max(rel_err(io[2].cpu().numpy(), yo), rel_err(io[3].cpu().numpy(), zo[0]))
+        print(f"  {w.name}: {e:.3e}", flush=True)
+        assert e <= TOL64
+    assert kt["sweep_launches"] == 13 + 21 and kt["spline_launches"] == 13

@@ -380,3 +380,215 @@ def test_y_order_with_unequal_orders_space_independent(oracle_lib, ky, kz):
         errs.append(abs(y[0] - wl.exact_at_t0()[0][0]))
     order = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
     assert abs(order[-1] - min(ky + 1, 4)) < 0.2, (errs, order)
+
+
+# ----------------------------------------------------------------------------
+# Linear stability in the stability ratio R = vol sqrt(2 dt) / dx
+# ----------------------------------------------------------------------------
+
+
+def _noise_growth(oracle_lib, R, n_t=200, k=4, L=16):
+    # the sine problem (f = y/2 - z, X = W) is linear, so the difference of
+    # two sweeps whose initial layers differ by grid-scale noise of size 1e-10
+    # is that noise as the scheme propagates it (through y and z)
+    dx = math.sqrt(2.0 / n_t) / R
+    nx = int(6.0 / dx) + 1
+    wl = W.sine_1d(n_x=nx, n_t=n_t, k=k, L=L)
+    wl.problem.update(x_min=-(nx - 1) * dx / 2, x_max=(nx - 1) * dx / 2)
+    iy, iz = wl.init_layers()
+    rng = np.random.default_rng(7)
+    ny, nz = (1e-10 * rng.standard_normal(a.shape) for a in (iy, iz))
+    y0, z0, _ = oracle_lib.solve(wl.problem, iy, iz)
+    y1, z1, _ = oracle_lib.solve(wl.problem, iy + ny, iz + nz)
+    return max(float(np.max(np.abs(y1 - y0))), float(np.max(np.abs(z1 - z0)))) / 1e-10
+
+
+def test_stability_ratio_limit():
+    # bsde_problem_info flags R above 16; the oracle shows why: at R = 16
+    # grid-scale noise in the initial layers is damped, at R = 64 the
+    # Gauss-Hermite sums alias it and it grows by orders of magnitude
+    import oracle
+
+    oracle.build(force=False)
+    stable, unstable = _noise_growth(oracle, 16.0), _noise_growth(oracle, 64.0)
+    assert stable < 3.0, stable
+    assert unstable > 1e3, unstable
+
+
+# ----------------------------------------------------------------------------
+# Initial layers by the 1-step scheme (Section 3.1 step 2)
+# ----------------------------------------------------------------------------
+
+
+def test_initial_layers_trapezoid_recurrence(oracle_lib):
+    # f = -r y, g = 1 (x-independent): z = 0 and the 1-step scheme of eq (20)
+    # (K_y = 1: y^n = E[y^{n+1}] + h/2 (f^{n+1} + f^n)) is the trapezoidal
+    # rule, y^n = y^{n+1} (1 - r h/2) / (1 + r h/2) with h = dt / sub, so layer
+    # t_{N-r} is ((1 - r h/2)/(1 + r h/2))^(r sub) exactly
+    r_, sub = 0.7, 5
+    wl = W.discount_const(n_x=33, n_t=16, k=4, r=r_)
+    wl.problem.update(picard_max=60, picard_tol=1e-15)
+    iy_ex, iz_ex = wl.init_layers()
+    iy, iz = oracle_lib.initial_layers(wl.problem, iy_ex[-1], iz_ex[-1], sub)
+    h = wl.dt() / sub
+    q = (1 - r_ * h / 2) / (1 + r_ * h / 2)
+    K = wl.K
+    for row in range(K):
+        steps = (K - 1 - row) * sub
+        np.testing.assert_allclose(iy[row], q ** steps, rtol=1e-14)
+        assert np.max(np.abs(iz[row])) < 1e-15
+
+
+def test_initial_layers_one_substep_is_the_one_step_sweep(oracle_lib):
+    # with one sub-step the layers are those of the 1-step scheme on the
+    # original time grid: a sweep with K_y = K_z = 1 stopped at t_{N-K+1}
+    wl = W.bidask_call_1d(n_x=600, n_t=20, half_width=None)
+    pb = wl.problem
+    iy_ex, iz_ex = wl.init_layers()
+    iy, iz = oracle_lib.initial_layers(pb, iy_ex[-1], iz_ex[-1], 1)
+    one = dict(pb, k_y=1, k_z=1)
+    for row in range(wl.K - 1):
+        n_stop = pb["n_t"] - (wl.K - 1 - row)
+        y, z, _ = oracle_lib.solve(one, iy_ex[-1:], iz_ex[-1:], n_stop=n_stop)
+        assert np.array_equal(iy[row], y) and np.array_equal(iz[row], z)
+
+
+def test_initial_layers_converge_first_order(oracle_lib):
+    # Theorem 2 with K_z = 1: the 1-step scheme's z is first order in its step,
+    # so the initial layers approach the exact ones like 1/sub (sine problem,
+    # at x = 0, away from the truncated domain's ends)
+    wl = W.sine_1d(n_x=1025, n_t=64, k=4)
+    iy_ex, iz_ex = wl.init_layers()
+    i = wl.node_index()
+    errs = []
+    for sub in (4, 8, 16):
+        iy, iz = oracle_lib.initial_layers(wl.problem, iy_ex[-1], iz_ex[-1], sub)
+        errs.append(abs(iz[0, 0, i] - iz_ex[0, 0, i]))
+        assert abs(iy[0, i] - iy_ex[0, i]) < 2e-6
+    order = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(np.abs(order - 1.0) < 0.1), (errs, order)
+
+
+def test_table4_row_with_computed_initial_layers(oracle_lib):
+    # Table 4, K = 3, N = 128, M = 4096 (1.44e-11 / 2.77e-8): with initial
+    # layers from the 1-step scheme at 16 sub-steps the z error is the printed
+    # one to 2%, and y stays within the printed order of magnitude
+    wl = W.paper_example1(3, 128, 4096)
+    iy_ex, iz_ex = wl.init_layers()
+    iy, iz = oracle_lib.initial_layers(wl.problem, iy_ex[-1], iz_ex[-1], 16)
+    y, z, _ = oracle_lib.solve(wl.problem, iy, iz)
+    i = wl.node_index()
+    assert abs(z[0, i] - 0.25) == pytest.approx(2.77e-8, rel=0.02)
+    assert abs(y[i] - 0.5) < 1e-10
+
+
+# ----------------------------------------------------------------------------
+# The z form E[y^{n+1} dW]/dt (eq (12) before the relation below it)
+# ----------------------------------------------------------------------------
+
+
+def _sine_errors_zform(oracle_lib, k, nt, z_form):
+    dx = math.sqrt(2.0 / nt) / 16.0
+    nx = int(16.0 / dx) + 1
+    nx += 1 - nx % 2
+    wl = W.sine_1d(n_x=nx, n_t=nt, k=k, L=16)
+    wl.problem["z_form"] = z_form
+    iy, iz = wl.init_layers()
+    y, z, _ = oracle_lib.solve(wl.problem, iy, iz)
+    ye, ze = wl.exact_at_t0()
+    i = wl.node_index()
+    return abs(y[i] - ye[i]), abs(z[0, i] - ze[i])
+
+
+def test_z_form_ydw_second_order_at_one_step(oracle_lib):
+    # K = 1: with E[y^{n+1} dW]/dt the z equation is the trapezoidal rule on
+    # d/dx y, second order in dt for y and z; the printed form (E[z^{n+1}])
+    # is first order there (Theorem 2: min(K_y + 1, K_z, 3) = 1)
+    e = np.array([_sine_errors_zform(oracle_lib, 1, nt, "yW") for nt in (16, 32, 64)])
+    order = np.log2(e[:-1] / e[1:])
+    assert np.all(np.abs(order - 2.0) < 0.1), (e, order)
+    e20 = np.array([_sine_errors_zform(oracle_lib, 1, nt, "eq20") for nt in (16, 32, 64)])
+    order20 = np.log2(e20[:-1] / e20[1:])
+    assert np.all(np.abs(order20[:, 1] - 1.0) < 0.1), (e20, order20)
+
+
+def test_z_form_ydw_unstable_for_multistep(oracle_lib):
+    # K = 2: the multistep z recurrence of Table 2 built on E[y^{n+1} dW]/dt
+    # amplifies the O(1/dt) term's errors: refining dt makes the error grow,
+    # which is why eq (20) takes dt E[z^{n+1}] in its place
+    e = [_sine_errors_zform(oracle_lib, 2, nt, "yW")[1] for nt in (16, 32)]
+    assert e[1] > 100 * e[0] and e[1] > 1.0, e
+    e20 = [_sine_errors_zform(oracle_lib, 2, nt, "eq20")[1] for nt in (16, 32)]
+    assert e20[1] < e20[0] < 2e-3, e20
+
+
+# ----------------------------------------------------------------------------
+# State-dependent forward coefficients (eq (1)): Euler nodes located per point
+# ----------------------------------------------------------------------------
+
+
+@pytest.mark.parametrize("k", [1, 3])
+def test_ou_linear_terminal_exact_recurrence(oracle_lib, k):
+    # dX = kappa (theta - X) dt + sigma dW, f = 0, g = x.  The Euler node of
+    # layer n+k has mean x + kappa (theta - x) k dt; linear data are
+    # interpolated exactly (natural spline, M = 0) and Gauss-Hermite sums of
+    # linear functions are exact, so y^n = theta + (x - theta) c_n with
+    # c_n = (1 - kappa k dt) c_{n+k} from the exact initial layers, at every
+    # point whose nodes stay inside the truncated domain
+    wl = W.ou_linear_1d(k=k, n_t=32)
+    pb = wl.problem
+    iy, iz = wl.init_layers()
+    y, z, _ = oracle_lib.solve(pb, iy, iz)
+    kap, th, N, dt = wl.extra["kappa"], wl.extra["theta"], pb["n_t"], wl.dt()
+    c = {N - r: math.exp(-kap * r * dt) for r in range(k)}
+    for n in range(N - k, -1, -1):
+        c[n] = (1.0 - kap * k * dt) * c[n + k]
+    x = wl.grid()
+    inner = np.abs(x - th) < 1.5
+    np.testing.assert_allclose(y[inner], th + (x[inner] - th) * c[0], rtol=0, atol=1e-12)
+
+
+def test_ou_z_needs_the_ydw_form(oracle_lib):
+    # With a state-dependent drift, E[y^{n+1} dW] = dt E[z^{n+1}] (the relation
+    # below eq (12)) no longer holds: for f = 0 the z equation of eq (20)
+    # keeps z^n = E[z^{n+1}], so z stays at its terminal value sigma instead
+    # of decaying like sigma e^{-kappa (T - t)}; the E[y dW]/dt form (K = 1)
+    # follows the decay, first order in dt (the Euler step of X)
+    errs = []
+    for nt, nx in ((16, 401), (32, 801), (64, 1601)):
+        wl = W.ou_linear_1d(k=1, n_t=nt, n_x=nx)
+        iy, iz = wl.init_layers()
+        i = wl.node_index()
+        _, z20, _ = oracle_lib.solve(wl.problem, iy, iz)
+        assert abs(z20[0, i] - wl.extra["sigma"]) < 1e-12
+        wl.problem["z_form"] = "yW"
+        _, z, _ = oracle_lib.solve(wl.problem, iy, iz)
+        errs.append(abs(z[0, i] - wl.exact_at_t0()[1][i]))
+    order = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(np.abs(order - 1.0) < 0.15), (errs, order)
+
+
+def test_black_scholes_on_the_price_grid(oracle_lib):
+    # X = S with a(S) = mu S, b(S) = sigma S (the stock-price grid that the
+    # paper contrasts with the log-price grid): the Euler nodes give a first
+    # order scheme for the Black-Scholes price (weak order of the Euler step)
+    errs = []
+    for nt in (16, 32, 64):
+        dt = 0.33 / nt
+        nx = int(300.0 / (0.2 * 300.0 * math.sqrt(2 * dt) / 16.0)) + 1
+        wl = W.bs_call_price_1d(n_x=nx, n_t=nt, k=3)
+        iy, iz = wl.init_layers()
+        y, _, _ = oracle_lib.solve(wl.problem, iy, iz)
+        ye, _ = wl.exact_at_t0()
+        errs.append(abs(y[wl.node_index()] - ye[wl.node_index()]))
+    order = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert errs[-1] < 1e-2 and np.all(np.abs(order - 1.0) < 0.15), (errs, order)
+
+
+def test_constant_coefficients_reduce_to_the_uniform_path(oracle_lib):
+    # drift_x = vol_x = 0 is the constant-coefficient problem
+    wl = W.bidask_call_1d(n_x=700, n_t=12, half_width=None)
+    iy, iz = wl.init_layers()
+    y0, z0, _ = oracle_lib.solve(wl.problem, iy, iz)
+    y1, z1, _ = oracle_lib.solve(dict(wl.problem, drift_x=0.0, vol_x=0.0), iy, iz)
+    assert np.array_equal(y0, y1) and np.array_equal(z0, z1)

@@ -334,6 +334,54 @@ def bidask_put_1d(n_x: int = 4096, n_t: int = 64, k: int = 4, L: int = 16,
     return w
 
 
+def bs_call_price_1d(n_x: int = 800, n_t: int = 64, k: int = 3, L: int = 16,
+                     S_max: float = 300.0, S_min: float = 1.0, K: float = 100.0,
+                     S0: float = 100.0, r: float = 0.05, mu: float = 0.1, sigma: float = 0.2,
+                     T: float = 0.33, smooth: bool = True) -> Workload:
+    """Black-Scholes call on the stock-price grid (X = S, not ln S): the forward
+    coefficients of eq (1) depend on the state, a(S) = mu S and b(S) = sigma S
+    (drift_x = mu, vol_x = sigma), so the nodes lie at different cell
+    fractions for every grid point (the variant that Table 7 compares with
+    the log-price grid).  f = -r y - theta z with theta = (mu - r)/sigma and
+    z = sigma S dV/dS.  Grid S_min..S_max; S0 is moved onto a node by shifting
+    the interval.  ``smooth`` as in bs_call_1d."""
+    lo, hi = _snap_domain(S0, S_min, S_max, n_x)
+    tau_s = T / n_t if smooth else 0.0
+    theta = (mu - r) / sigma
+    pb = _problem(T=T, n_t=n_t, k_y=k, k_z=k, L=L, n_x=n_x, x_min=lo, x_max=hi, drift=0.0,
+                  vol=0.0, drift_x=mu, vol_x=sigma, driver="linear", p=[-r, -theta, 0.0, 0.0])
+
+    def exact(t, S):
+        tau = T + tau_s - t
+        x = np.log(np.maximum(S, 1e-300))
+        if tau <= 0:
+            return np.maximum(S - K, 0.0), sigma * S * (S > K)
+        return bs_call(tau, x, K, r, sigma)
+
+    w = Workload(f"bsprice1d_nx{n_x}_nt{n_t}_k{k}_L{L}", pb, exact, S0)
+    w.extra.update(dict(K=K, S0=S0, r=r, mu=mu, sigma=sigma, tau_s=tau_s))
+    return w
+
+
+def ou_linear_1d(n_x: int = 801, n_t: int = 32, k: int = 3, L: int = 16, kappa: float = 1.5,
+                 theta: float = 0.4, sigma: float = 0.3, T: float = 1.0,
+                 half_width: float = 3.0) -> Workload:
+    """Ornstein-Uhlenbeck forward process dX = kappa (theta - X) dt + sigma dW
+    (a(x) = kappa theta - kappa x: drift_x = -kappa), f = 0, g(x) = x:
+    y = theta + (x - theta) e^{-kappa (T - t)}, z = sigma e^{-kappa (T - t)}."""
+    pb = _problem(T=T, n_t=n_t, k_y=k, k_z=k, L=L, n_x=n_x, x_min=theta - half_width,
+                  x_max=theta + half_width, drift=kappa * theta, drift_x=-kappa, vol=sigma,
+                  driver="linear", p=[0.0, 0.0, 0.0, 0.0])
+
+    def exact(t, x):
+        e = math.exp(-kappa * (T - t))
+        return theta + (x - theta) * e, np.full_like(x, sigma * e)
+
+    w = Workload(f"ou1d_nx{n_x}_nt{n_t}_k{k}_L{L}", pb, exact, theta)
+    w.extra.update(dict(kappa=kappa, theta=theta, sigma=sigma))
+    return w
+
+
 def option_batch(count: int = 4096, seed: int = 1909, log2_nx: tuple = (10.0, 16.0),
                  n_ts: tuple = (64, 128, 256, 512), k: int = 4, L: int = 16,
                  prec: str = "fp32_comp", shared_grid: int = 0,
@@ -502,9 +550,12 @@ def discount_const(n_x: int = 65, n_t: int = 32, k: int = 3, L: int = 8, r: floa
 
 
 def stability_ratio(pb: dict, axis: int = 0) -> float:
-    """R = (spread of one Gauss-Hermite step, vol*sqrt(2 dt)) / dx in cells."""
+    """R = (spread of one Gauss-Hermite step, vol*sqrt(2 dt)) / dx in cells;
+    with state-dependent vol (vol + vol_x x) its largest value on the grid."""
     n = _as_list(pb["n_x"])[axis]
     dx = (_as_list(pb["x_max"])[axis] - _as_list(pb["x_min"])[axis]) / (n - 1)
     vol = np.atleast_2d(np.asarray(pb.get("vol", 1.0), dtype=float))
     v = float(np.sqrt(np.sum(vol[axis] ** 2))) if pb["d"] == 2 else float(vol[0, 0])
+    if pb["d"] == 1 and pb.get("vol_x", 0.0):
+        v = max(v + pb["vol_x"] * pb["x_min"], v + pb["vol_x"] * pb["x_max"])
     return v * math.sqrt(2.0 * pb["T"] / pb["n_t"]) / dx
