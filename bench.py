@@ -22,6 +22,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -97,8 +99,29 @@ def measured_traffic(workload_name: str):
     return 1024.0 * (t["fetch_kib"] * t["read_factor"] + t["write_kib"] * t["write_factor"])
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def omp_threads() -> int:
+    """Threads the OpenMP oracle uses: OMP_NUM_THREADS if set, else the cores
+    this process may run on."""
+    v = os.environ.get("OMP_NUM_THREADS", "")
+    if v.isdigit() and int(v) > 0:
+        return int(v)
+    return len(os.sched_getaffinity(0))
+
+
 def cpu_baseline(wl, budget_s: float = 15.0):
-    """Serial oracle on the first steps of the same workload (bounded sample).
+    """Serial oracle on the first steps of the same workload (bounded sample),
+    and the same sample on all cores (the OpenMP build of the same source).
     Returns the report and the oracle's layer at the sample's last step
     (n_stop, y, z) for the full-size parity check."""
     import oracle
@@ -116,11 +139,19 @@ def cpu_baseline(wl, budget_s: float = 15.0):
     t0 = time.perf_counter()
     yo, zo, _ = oracle.solve(pb, iy, iz, n_stop=n_stop)
     el = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    yp, zp, _ = oracle.solve(pb, iy, iz, n_stop=n_stop, threads=True)
+    el_all = time.perf_counter() - t0
+    same = bool(np.array_equal(yp, yo) and np.array_equal(zp, zo))
     nx = pb["n_x"]
+    model = cpu_model()
     return ({"value": nx * steps / el, "unit": "grid-point*time-step/s", "cores": 1,
-             "kind": "oracle",
+             "kind": "oracle", "cpu": model,
              "sample": f"first {steps} of {pb['n_t'] - K + 1} backward steps at full grid "
-                       f"({nx} points), serial FP64 C oracle, {el:.1f} s"},
+                       f"({nx} points), serial FP64 C oracle, {el:.1f} s",
+             "all_cores": {"value": nx * steps / el_all, "cores": omp_threads(),
+                           "seconds": el_all, "identical_to_serial": same,
+                           "kind": "oracle, OpenMP over the points of a layer"}},
             (n_stop, yo, zo[0]))
 
 
@@ -304,6 +335,110 @@ def run_2d(args, B, torch, np):
             "stability_ratio": st["stability_ratio"]}
 
 
+def time_solves(B, torch, wl, prec="fp64", reps=5, autotune=True, extra=None):
+    """Whole solves of one workload, replayed between events after a checked
+    solve; returns (ms per solve, stats, kernel times, y0 at x0, z0 at x0, y, z)."""
+    dev = "cuda:0"
+    pb = dict(wl.problem, prec=prec, **(extra or {}))
+    iy, iz = wl.init_layers()
+    K, n = iy.shape
+    t_iy = torch.as_tensor(iy, device=dev).contiguous()
+    t_iz = torch.as_tensor(iz.reshape(K, -1), device=dev).contiguous()
+    y0 = torch.empty(n, dtype=torch.float64, device=dev)
+    z0 = torch.empty(iz.shape[1] * n, dtype=torch.float64, device=dev)
+    plan = B.bsde_plan(pb)
+    ws = B.workspace(plan, dev)
+    stream = torch.cuda.current_stream()
+    io = [(t_iy, t_iz, y0, z0)]
+    if autotune:
+        B.bsde_autotune(plan, ws, io, stream=stream, reps=5)
+    rc, st = B.bsde_solve(plan, ws, t_iy, t_iz, y0, z0, stream=stream, stats=True)
+    B.bsde_solve(plan, ws, t_iy, t_iz, y0, z0, stream=stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        B.bsde_solve(plan, ws, t_iy, t_iz, y0, z0, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    kt = B.bsde_profile_kernels(plan, ws, io, stream=stream)
+    y, z = y0.cpu().numpy(), z0.cpu().numpy()
+    return ms, st, kt, y, z, B.bsde_status_string(rc)
+
+
+def toeplitz_flops_per_point_step(pb: dict) -> tuple:
+    """Algorithmic and executed FP64 operations of the Toeplitz sweep per point
+    and step: per layer j, 8 products per band entry (expectation and
+    dW-weighted, of y and z, from the values and the second derivatives:
+    16 flops), over the band's nb_j entries (executed: nb_j + 15, the 16 x 16
+    tiles' corners); the combination and Picard are left out (under 1%)."""
+    K = max(pb["k_y"], pb["k_z"])
+    dt = pb["T"] / pb["n_t"]
+    dx = (pb["x_max"] - pb["x_min"]) / (pb["n_x"] - 1)
+    alg = exe = 0.0
+    for j in range(1, K + 1):
+        m0 = pb["drift"] * j * dt / dx
+        rho = pb["vol"] * math.sqrt(j * dt) / dx
+        reach = 9.0 * rho + 1.0
+        nb = math.ceil(m0 + reach) - math.floor(m0 - reach) + 2
+        alg += 16.0 * nb
+        exe += 16.0 * (nb + 15)
+    return alg, exe
+
+
+def run_configs(args, B, torch, np):
+    """The other configurations: the sine problem (1025 points, N = 64, k = 2),
+    Black-Scholes (16384 points, N = 256, L = 32, k = 4) on its stable twin and
+    on the literal interval (Gauss-Hermite, and the exact Gaussian expectation
+    on matrix cores), and the bid-ask call on its literal interval (R = 965)."""
+    import workloads as W
+
+    out = {}
+    wl = W.sine_1d()
+    ms, st, kt, y, z, rc = time_solves(B, torch, wl)
+    ye, ze = wl.exact_at_t0()
+    i = wl.node_index()
+    out["sine_1025_nt64_k2"] = {"ms_per_solve": ms, "value": wl.problem["n_x"] * wl.problem["n_t"] / (ms * 1e-3),
+                                "abs_err_y0": float(abs(y[i] - ye[i])), "abs_err_z0": float(abs(z[i] - ze[i])),
+                                "status": rc, "path": kt["path"]}
+    print(f"[bench] configs: sine {out['sine_1025_nt64_k2']}", file=sys.stderr, flush=True)
+    nx, nt = 16384, 256
+    twin = W.bs_call_1d(n_x=nx, n_t=nt, k=4, L=32, half_width=0.2 * math.sqrt(2 * 0.33 / nt) / 16.0 * (nx - 1) / 2)
+    lit = W.bs_call_1d(n_x=nx, n_t=nt, k=4, L=32, half_width=None)
+    for name, wl, extra in (("bs_16384_nt256_k4_L32_twin_gh", twin, None),
+                            ("bs_16384_nt256_k4_L32_literal_gh", lit, None),
+                            ("bs_16384_nt256_k4_literal_exact", lit, {"quad": "exact"}),
+                            ("bs_16384_nt256_k4_twin_exact", twin, {"quad": "exact"})):
+        ms, st, kt, y, z, rc = time_solves(B, torch, wl, extra=extra)
+        ye, ze = wl.exact_at_t0()
+        i = wl.node_index()
+        rec = {"ms_per_solve": ms, "value": nx * nt / (ms * 1e-3), "status": rc,
+               "abs_err_y0": float(abs(y[i] - ye[i])), "abs_err_z0": float(abs(z[i] - ze[i])),
+               "stability_ratio": st["stability_ratio"], "path": kt["path"],
+               "sweep_kernel_us": 1e3 * kt["sweep_ms"] / max(kt["sweep_launches"], 1)}
+        if extra:
+            alg, exe = toeplitz_flops_per_point_step(wl.problem)
+            us = rec["sweep_kernel_us"]
+            rec["roofline"] = {"bound": "mfma", "unit": "TFLOP/s", "peak": FP64_VALU_PEAK_TFLOPS,
+                               "achieved": alg * nx / (us * 1e-6) / 1e12,
+                               "frac": alg * nx / (us * 1e-6) / 1e12 / FP64_VALU_PEAK_TFLOPS,
+                               "executed_tflops": exe * nx / (us * 1e-6) / 1e12,
+                               "flops_per_point_step": alg}
+        out[name] = rec
+        print(f"[bench] configs: {name} {rec}", file=sys.stderr, flush=True)
+    wl = W.bidask_call_1d(half_width=None)
+    ms, st, kt, y, z, rc = time_solves(B, torch, wl, reps=3)
+    out["bidask_262144_nt1024_literal_gh"] = {
+        "ms_per_solve": ms, "value": wl.problem["n_x"] * wl.problem["n_t"] / (ms * 1e-3),
+        "stability_ratio": st["stability_ratio"], "path": kt["path"], "status": rc,
+        "note": "timing only: at this stability ratio Gauss-Hermite aliasing makes the "
+                "scheme unstable, so the values are not an approximation of the price"}
+    print(f"[bench] configs: bidask literal {out['bidask_262144_nt1024_literal_gh']}",
+          file=sys.stderr, flush=True)
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -317,6 +452,11 @@ def main() -> int:
     ap.add_argument("--steps-2d", type=int, default=6,
                     help="backward steps of the 2-D basket workload to time (0 skips it)")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-kernel-events", action="store_true",
+                    help="skip the directly launched, event-timed solve (profiler runs that "
+                         "should see the graph replays only)")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the other configurations (sine, Black-Scholes, literal bid-ask)")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="profiling runs: stop each solve after this many backward steps "
                          "(same per-step kernel shape; throughput then counts those steps)")
@@ -395,14 +535,24 @@ def main() -> int:
         print(f"[bench] {prec}: {args.steps} solves, {ms:.3f} ms per solve", file=sys.stderr,
               flush=True)
         # per-kernel durations from hipEvents around every launch of one solve
-        kt = B.bsde_profile_kernels(plan, ws, [(t_iy, t_iz, y0, z0)], stream=stream)
-        print(f"[bench] {prec}: kernels {kt}", file=sys.stderr, flush=True)
+        # launched directly (skipped when a profiler should see graph
+        # replays only)
+        kt = None
+        if not args.no_kernel_events:
+            kt = B.bsde_profile_kernels(plan, ws, [(t_iy, t_iz, y0, z0)], stream=stream)
+            print(f"[bench] {prec}: kernels {kt}", file=sys.stderr, flush=True)
         return ms, st, kt, y0.cpu().numpy(), z0.cpu().numpy()
 
     ms, st, kt, y_h, z_h = run("fp64")
     value = nx * (pb["n_t"] if not args.profile_steps else steps_run) / (ms * 1e-3)
-    sweep_ms = kt["sweep_ms"] / kt["sweep_launches"]
-    spline_ms = kt["spline_ms"] / kt["spline_launches"] if kt["spline_launches"] else 0.0
+    # the sweep kernel's average launch duration in the timed region: the
+    # solve is the replayed graph of steps_run sweep launches (plus the
+    # initial-layer scatter and splines and the final gather, together well
+    # under 1% of it), timed by the events around the replays; counting the
+    # whole solve against the launches makes this an upper bound
+    sweep_ms = ms / steps_run
+    sweep_ms_direct = kt["sweep_ms"] / kt["sweep_launches"] if kt else None
+    spline_ms = kt["spline_ms"] / kt["spline_launches"] if kt and kt["spline_launches"] else 0.0
     fl = flops_per_point_step(pb, st["picard_iter_mean"]) * nx
     achieved = fl / (sweep_ms * 1e-3) / 1e12
     # error of the headline value against the closed form
@@ -412,7 +562,7 @@ def main() -> int:
     fp32 = None
     if not args.fp64_only:
         ms32, st32, kt32, y32, z32 = run("fp32_comp")
-        sw32 = kt32["sweep_ms"] / kt32["sweep_launches"]
+        sw32 = ms32 / steps_run
         scale = np.maximum(np.abs(y_h), 1.0)
         x = wl.grid(0)
         sg = wl.extra.get("sigma", 0.2)
@@ -435,14 +585,15 @@ def main() -> int:
             "max_rel_err_vs_fp64_z": float(np.max(np.abs(z32 - z_h) / np.maximum(np.abs(z_h), 1.0))),
             "rel_err_y0_vs_closed_form": float(abs(y32[i] - ye[i]) / max(abs(ye[i]), 1.0)),
             "rel_err_z0_vs_closed_form": float(abs(z32[i] - ze[i]) / max(abs(ze[i]), 1.0)),
-            "config": {"points_per_lane": kt32["points_per_lane"],
-                       "node_groups": kt32["node_groups"], "path": kt32["path"]},
+            "config": ({"points_per_lane": kt32["points_per_lane"],
+                        "node_groups": kt32["node_groups"], "path": kt32["path"]} if kt32 else None),
         }
 
     batched = None
     if args.batch:
         batched = run_batch(args, B, torch, np, ms)
     two_d = run_2d(args, B, torch, np) if args.steps_2d else None
+    configs = None if (args.no_configs or args.profile_steps) else run_configs(args, B, torch, np)
 
     out = {
         "metric": "grid-point*time-step updates/sec (k=4, L=16)",
@@ -467,16 +618,20 @@ def main() -> int:
                      "unit": "TFLOP/s", "frac": achieved / FP64_VALU_PEAK_TFLOPS,
                      "traffic": measured_traffic(wl.name), "kernel": "sweep_fused",
                      "kernel_us": sweep_ms * 1e3,
+                     "kernel_us_measured_as": "graph-replayed solves between hipEvents on "
+                                              "the launch stream, per sweep launch",
+                     "kernel_us_direct_launch": (sweep_ms_direct * 1e3 if kt else None),
                      "flops_per_launch": fl,
                      "hbm_bytes_per_launch_algorithmic": bytes_per_point_step(pb) * nx},
         "spline_kernel_us": spline_ms * 1e3,
-        "sweep_config": {"points_per_lane": kt["points_per_lane"],
-                         "node_groups": kt["node_groups"], "path": kt["path"],
-                         "blocks": kt["blocks"], "lds_bytes": kt["lds_bytes"]},
+        "sweep_config": ({"points_per_lane": kt["points_per_lane"],
+                          "node_groups": kt["node_groups"], "path": kt["path"],
+                          "blocks": kt["blocks"], "lds_bytes": kt["lds_bytes"]} if kt else None),
         "accuracy": err,
         "fp32_comp": fp32,
         "batched": batched,
         "two_d": two_d,
+        "configs": configs,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"], (n_stop, yo, zo) = cpu_baseline(wl, args.cpu_budget)

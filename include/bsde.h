@@ -66,8 +66,31 @@ typedef enum {
  * recurrence built on it is unstable. */
 typedef enum {
     BSDE_ZFORM_EZ = 0,  /* E[z^{n+1}] (eq (20))                                  */
-    BSDE_ZFORM_YDW = 1  /* E[y^{n+1} dW_{n+1}] / dt                              */
+    BSDE_ZFORM_YDW = 1  /* E[y^{n+1} dW_{n+1}] / dt; FP64 only (the weights
+                           dW/dt ~ 1/sqrt(dt) would amplify the FP32 form's
+                           rounding of the stored layers)                       */
 } bsde_z_form;
+
+/* The interpolant of the layers between grid points (Section 3.3). */
+typedef enum {
+    BSDE_INTERP_SPLINE = 0,      /* natural cubic spline (d = 2: tensor product)    */
+    BSDE_INTERP_BICUBIC_FD = 1   /* d = 2: the paper's bicubic interpolation from the
+                                    values and the first and mixed derivatives,
+                                    these by fourth-order finite differences
+                                    (central inside, one-sided at the two points
+                                    next to each end); needs n_x >= 5 per axis */
+} bsde_interp;
+
+/* How the conditional expectations of eq (20) are computed. */
+typedef enum {
+    BSDE_QUAD_GH = 0,    /* Gauss-Hermite quadrature of the spline, eq (21)     */
+    BSDE_QUAD_EXACT = 1  /* the exact Gaussian expectation of the spline: a
+                            banded Toeplitz operator on the uniform grid, applied
+                            on FP64 matrix cores; no quadrature aliasing, so it
+                            stays stable at stability ratios far above 16.
+                            Linear driver, constant coefficients, FP64, d = 1;
+                            L is not used                                        */
+} bsde_quad;
 
 typedef enum {
     BSDE_FP64 = 0,      /* all arithmetic in double precision                   */
@@ -116,6 +139,8 @@ typedef struct {
                            of the backward loop) and y0, z0 then receive layer
                            n_stop.                                               */
     int z_form;         /* bsde_z_form                                           */
+    int quad;           /* bsde_quad                                             */
+    int interp;         /* bsde_interp                                           */
 } bsde_problem;
 
 /* Largest stability ratio R = vol sqrt(2 dt) / dx (Gauss-Hermite spread of

@@ -21,18 +21,23 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "bsde_oracle.c")
 _LIB = os.path.join(_HERE, "libbsde_oracle.so")
+_LIB_OMP = os.path.join(_HERE, "libbsde_oracle_omp.so")  # the same source, points shared out
 
 DRIVERS = {"linear": 0, "bidask": 1, "cubic": 2, "exp": 3}
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (-O2, no FMA contraction, no fast-math)."""
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
-        subprocess.check_call(
-            ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11",
-             "-D_DEFAULT_SOURCE", "-fPIC", "-shared", "-Wall", "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB)
+    """Compile the oracle with gcc (-O2, no FMA contraction, no fast-math):
+    the serial library, and an OpenMP build of the same source that shares the
+    grid points of a layer out over the host's cores (same arithmetic per
+    point; used for the all-cores baseline)."""
+    flags = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-D_DEFAULT_SOURCE",
+             "-fPIC", "-shared", "-Wall"]
+    for lib, extra in ((_LIB, []), (_LIB_OMP, ["-fopenmp"])):
+        if force or not os.path.exists(lib):
+            tmp = lib + ".tmp"
+            subprocess.check_call(["gcc", *flags, *extra, "-o", tmp, _SRC, "-lm"])
+            os.replace(tmp, lib)
     return _LIB
 
 
@@ -58,6 +63,7 @@ class _Problem(ctypes.Structure):
         ("n_stop", ctypes.c_int),
         ("z_form", ctypes.c_int),
         ("quad", ctypes.c_int),
+        ("interp2", ctypes.c_int),
     ]
 
 
@@ -65,15 +71,16 @@ class _Stats(ctypes.Structure):
     _fields_ = [("picard_iter_max", ctypes.c_int), ("picard_nonconverged", ctypes.c_long)]
 
 
-_lib = None
+_libs = {}
 
 
-def _load():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_LIB):
-            build()
-        lib = ctypes.CDLL(_LIB)
+def _load(threads: bool = False):
+    """The serial oracle, or with ``threads`` its OpenMP build."""
+    if threads not in _libs:
+        path = _LIB_OMP if threads else _LIB
+        if not os.path.exists(path):
+            build(force=False)
+        lib = ctypes.CDLL(path)
         dp = ctypes.POINTER(ctypes.c_double)
         lib.oracle_solve.argtypes = [ctypes.POINTER(_Problem), dp, dp, dp, dp,
                                      ctypes.POINTER(_Stats)]
@@ -94,8 +101,8 @@ def _load():
                                                  dp, dp, ctypes.c_int, dp, ctypes.c_double,
                                                  ctypes.c_double, dp]
         lib.oracle_exact_expectation.restype = ctypes.c_int
-        _lib = lib
-    return _lib
+        _libs[threads] = lib
+    return _libs[threads]
 
 
 def _ptr(a: np.ndarray):
@@ -133,16 +140,19 @@ def _to_struct(pb: dict, n_stop: int) -> _Problem:
     s.n_stop = int(n_stop)
     s.z_form = {"eq20": 0, "yW": 1}[pb.get("z_form", "eq20")]
     s.quad = {"gh": 0, "exact": 1}[pb.get("quad", "gh")]
+    s.interp2 = {"spline": 0, "bicubic_fd": 1}[pb.get("interp", "spline")]
     return s
 
 
-def solve(pb: dict, init_y: np.ndarray, init_z: np.ndarray, n_stop: int = 0):
+def solve(pb: dict, init_y: np.ndarray, init_z: np.ndarray, n_stop: int = 0,
+          threads: bool = False):
     """Run the backward sweep down to layer ``n_stop``.
 
     ``init_y``: (K, points) layers t_{N-K+1} .. t_N;  ``init_z``: (K, d, points).
     Returns ``(y, z, stats)`` with y of shape (points,) and z of shape (d, points).
+    ``threads``: the OpenMP build (d = 1: the points of a layer on all cores).
     """
-    lib = _load()
+    lib = _load(threads)
     d = int(pb["d"])
     npts = int(np.prod(_pair(pb["n_x"], 1)[:d]))
     K = max(int(pb["k_y"]), int(pb["k_z"]))

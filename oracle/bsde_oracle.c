@@ -350,6 +350,8 @@ static int validate(const oracle_problem *pb)
     if (pb->z_form != 0 && pb->z_form != 1) return ORACLE_EINVAL;
     if (pb->d == 2 && (pb->drift_x != 0.0 || pb->vol_x != 0.0)) return ORACLE_EINVAL;
     if (pb->quad != 0 && pb->quad != 1) return ORACLE_EINVAL;
+    if (pb->interp2 != 0 && pb->interp2 != 1) return ORACLE_EINVAL;
+    if (pb->interp2 == 1 && (pb->d != 2 || pb->n_x[0] < 5 || pb->n_x[1] < 5)) return ORACLE_EINVAL;
     if (pb->quad == 1 && (pb->d != 1 || pb->driver != ORACLE_DRIVER_LINEAR ||
                           pb->drift_x != 0.0 || pb->vol_x != 0.0))
         return ORACLE_EINVAL;
@@ -410,6 +412,11 @@ static int solve1(const oracle_problem *pb, const double *init_y, const double *
     for (int n = N - K; n >= pb->n_stop; --n) {
         layer1 out = SLOT(n);
         const double tn = n * dt;
+        /* the points of a layer are independent: the all-cores build of this
+         * file (OpenMP) shares them out; the arithmetic per point is the same */
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) reduction(+ : nonconv) reduction(max : it_max)
+#endif
         for (int i = 0; i < nx; ++i) {
             const double xi = xmin + i * dx;
             double Ef[7] = {0}, EfW[7] = {0}, Ez[7] = {0}, EyK = 0.0, EyW1 = 0.0;
@@ -535,11 +542,78 @@ static double tensor_eval(const tspline *s, int n0, int n1, double xmin0, double
     return acc;
 }
 
+/* ------------------------------------------------------------------------- */
+/* The paper's own 2-D interpolation (Section 3.3): bicubic interpolation from */
+/* the values and the first and mixed derivatives at the cell corners, the   */
+/* derivatives from fourth-order finite differences (central inside, one-     */
+/* sided at the two points next to each end).  Stored in the same four arrays */
+/* as the tensor spline: v, f_x (in Mxx), f_y (in Myy), f_xy (in Mxxyy).       */
+/* ------------------------------------------------------------------------- */
+static void fd4_line(int n, double h, const double *f, long fs, double *d, long ds)
+{
+#define F(i) f[(long)(i) * fs]
+    for (int i = 0; i < n; ++i) {
+        double v;
+        if (i >= 2 && i <= n - 3)
+            v = F(i - 2) - 8.0 * F(i - 1) + 8.0 * F(i + 1) - F(i + 2);
+        else if (i == 0)
+            v = -25.0 * F(0) + 48.0 * F(1) - 36.0 * F(2) + 16.0 * F(3) - 3.0 * F(4);
+        else if (i == 1)
+            v = -3.0 * F(0) - 10.0 * F(1) + 18.0 * F(2) - 6.0 * F(3) + F(4);
+        else if (i == n - 1)
+            v = 25.0 * F(n - 1) - 48.0 * F(n - 2) + 36.0 * F(n - 3) - 16.0 * F(n - 4) + 3.0 * F(n - 5);
+        else /* i == n - 2 */
+            v = 3.0 * F(n - 1) + 10.0 * F(n - 2) - 18.0 * F(n - 3) + 6.0 * F(n - 4) - F(n - 5);
+        d[(long)i * ds] = v / (12.0 * h);
+    }
+#undef F
+}
+
+static void bicubic_fd(int n0, int n1, double dx0, double dx1, tspline *s)
+{
+    for (int i1 = 0; i1 < n1; ++i1) /* f_x along axis 0 */
+        fd4_line(n0, dx0, s->v + i1, n1, s->Mxx + i1, n1);
+    for (int i0 = 0; i0 < n0; ++i0) { /* f_y, and f_xy = (f_x)_y, along axis 1 */
+        fd4_line(n1, dx1, s->v + (long)i0 * n1, 1, s->Myy + (long)i0 * n1, 1);
+        fd4_line(n1, dx1, s->Mxx + (long)i0 * n1, 1, s->Mxxyy + (long)i0 * n1, 1);
+    }
+}
+
+/* cubic Hermite basis on [0, 1]: values at 0 and 1, slopes at 0 and 1 */
+static void hermite(double t, double hv[2], double hd[2])
+{
+    hv[0] = 2.0 * t * t * t - 3.0 * t * t + 1.0;
+    hv[1] = -2.0 * t * t * t + 3.0 * t * t;
+    hd[0] = t * t * t - 2.0 * t * t + t;
+    hd[1] = t * t * t - t * t;
+}
+
+/* the bicubic at (X0, X1) with coordinates clamped to the box */
+static double bicubic_eval(const tspline *s, int n0, int n1, double xmin0, double dx0,
+                           double xmin1, double dx1, double X0, double X1)
+{
+    int p, q;
+    double t0, t1, hv0[2], hd0[2], hv1[2], hd1[2];
+    locate(X0, xmin0, dx0, n0, &p, &t0);
+    locate(X1, xmin1, dx1, n1, &q, &t1);
+    hermite(t0, hv0, hd0);
+    hermite(t1, hv1, hd1);
+    double acc = 0.0;
+    for (int u = 0; u < 2; ++u)
+        for (int v = 0; v < 2; ++v) {
+            long k = (long)(p + u) * n1 + (q + v);
+            acc += hv0[u] * hv1[v] * s->v[k] + dx0 * hd0[u] * hv1[v] * s->Mxx[k] +
+                   dx1 * hv0[u] * hd1[v] * s->Myy[k] + dx0 * dx1 * hd0[u] * hd1[v] * s->Mxxyy[k];
+        }
+    return acc;
+}
+
 /* Everything one backward step of the 2-D sweep reads: the grid, the
  * quadrature rule, the coefficients of Tables 1-2 and the ring of K+1 layers
  * (each with its tensor splines). */
 typedef struct {
     int N, Ky, Kz, K, L, n0, n1;
+    int interp2; /* 0: tensor natural spline; 1: bicubic with finite differences */
     double dt, xmin0, dx0, xmin1, dx1;
     double a[ORACLE_MAX_L], w[ORACLE_MAX_L], gy[7], gz[7];
     tspline ring[7][3]; /* per ring slot: 3 fields (y, z1, z2) x 4 arrays */
@@ -560,6 +634,7 @@ static int ctx2_init(const oracle_problem *pb, const double *init_y, const doubl
                      ctx2 *c)
 {
     c->N = pb->n_t;
+    c->interp2 = pb->interp2;
     c->Ky = pb->k_y;
     c->Kz = pb->k_z;
     c->K = c->Ky > c->Kz ? c->Ky : c->Kz;
@@ -602,7 +677,10 @@ static int ctx2_init(const oracle_problem *pb, const double *init_y, const doubl
         memcpy(SLOT2(c, n)[1].v, init_z + (size_t)r * 2 * np, sizeof(double) * np);
         memcpy(SLOT2(c, n)[2].v, init_z + (size_t)r * 2 * np + np, sizeof(double) * np);
         for (int f = 0; f < 3; ++f)
-            tensor_spline(c->n0, c->n1, c->dx0, c->dx1, &SLOT2(c, n)[f], c->work);
+            if (c->interp2)
+                bicubic_fd(c->n0, c->n1, c->dx0, c->dx1, &SLOT2(c, n)[f]);
+            else
+                tensor_spline(c->n0, c->n1, c->dx0, c->dx1, &SLOT2(c, n)[f], c->work);
     }
     return ORACLE_OK;
 }
@@ -630,10 +708,12 @@ static void point2(const oracle_problem *pb, const ctx2 *c, int n, int i0, int i
                                   pb->vol[0][0] * dW0 + pb->vol[0][1] * dW1;
                 const double X1 = x1 + pb->drift[1] * j * dt +
                                   pb->vol[1][0] * dW0 + pb->vol[1][1] * dW1;
-                double yh = tensor_eval(&lj[0], n0, n1, xmin0, dx0, xmin1, dx1, X0, X1);
+                double (*ev)(const tspline *, int, int, double, double, double, double, double,
+                             double) = c->interp2 ? bicubic_eval : tensor_eval;
+                double yh = ev(&lj[0], n0, n1, xmin0, dx0, xmin1, dx1, X0, X1);
                 double zh[2];
-                zh[0] = tensor_eval(&lj[1], n0, n1, xmin0, dx0, xmin1, dx1, X0, X1);
-                zh[1] = tensor_eval(&lj[2], n0, n1, xmin0, dx0, xmin1, dx1, X0, X1);
+                zh[0] = ev(&lj[1], n0, n1, xmin0, dx0, xmin1, dx1, X0, X1);
+                zh[1] = ev(&lj[2], n0, n1, xmin0, dx0, xmin1, dx1, X0, X1);
                 const double fh = driver(pb, tj, yh, zh);
                 Ef[j] += wt * fh;
                 EfW[j][0] += wt * fh * dW0;
@@ -699,7 +779,12 @@ static int solve2(const oracle_problem *pb, const double *init_y, const double *
                 out[1].v[k] = r[1];
                 out[2].v[k] = r[2];
             }
-        for (int f = 0; f < 3; ++f) tensor_spline(c.n0, c.n1, c.dx0, c.dx1, &out[f], c.work);
+        for (int f = 0; f < 3; ++f) {
+            if (c.interp2)
+                bicubic_fd(c.n0, c.n1, c.dx0, c.dx1, &out[f]);
+            else
+                tensor_spline(c.n0, c.n1, c.dx0, c.dx1, &out[f], c.work);
+        }
     }
     memcpy(y_out, SLOT2(&c, pb->n_stop)[0].v, sizeof(double) * np);
     memcpy(z_out, SLOT2(&c, pb->n_stop)[1].v, sizeof(double) * np);

@@ -50,6 +50,9 @@ typedef struct {
     int quad;           /* conditional expectations: 0 = Gauss-Hermite, eq (21);     */
                         /* 1 = exact Gaussian expectation of the interpolating      */
                         /* spline (d = 1, linear driver, constant coefficients)     */
+    int interp2;        /* d = 2 interpolation: 0 = tensor natural spline; 1 =       */
+                        /* bicubic from values, first and mixed derivatives by      */
+                        /* fourth-order finite differences (Section 3.3)            */
 } oracle_problem;
 
 typedef struct {

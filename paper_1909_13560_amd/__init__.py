@@ -25,6 +25,8 @@ BSDE_OK, BSDE_EINVAL, BSDE_ENOMEM, BSDE_EDEVICE, BSDE_EUNSUPPORTED, BSDE_ENOCONV
 DRIVERS = {"linear": 0, "bidask": 1, "cubic": 2, "exp": 3}
 PRECISIONS = {"fp64": 0, "fp32_comp": 1}
 Z_FORMS = {"eq20": 0, "yW": 1}  # bsde_z_form: E[z^{n+1}], E[y^{n+1} dW]/dt
+QUADS = {"gh": 0, "exact": 1}  # bsde_quad: Gauss-Hermite (eq (21)), exact Gaussian
+INTERPS = {"spline": 0, "bicubic_fd": 1}  # bsde_interp (d = 2: the paper's bicubic)
 
 EXPORTED = ["bsde_plan", "bsde_plan_destroy", "bsde_workspace_bytes", "bsde_solve",
             "bsde_solve_batched", "bsde_profile_kernels", "bsde_status_string",
@@ -61,6 +63,8 @@ class _Problem(ctypes.Structure):
         ("prec", ctypes.c_int),
         ("n_stop", ctypes.c_int),
         ("z_form", ctypes.c_int),
+        ("quad", ctypes.c_int),
+        ("interp", ctypes.c_int),
     ]
 
 
@@ -173,6 +177,8 @@ def problem_struct(pb: dict) -> _Problem:
     s.prec = PRECISIONS[pb.get("prec", "fp64")]
     s.n_stop = int(pb.get("n_stop", 0))
     s.z_form = Z_FORMS[pb.get("z_form", "eq20")]
+    s.quad = QUADS[pb.get("quad", "gh")]
+    s.interp = INTERPS[pb.get("interp", "spline")]
     return s
 
 

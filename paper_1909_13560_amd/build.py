@@ -8,7 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbsde_hip.so")
-SOURCES = [os.path.join(CSRC, f) for f in ("capi.hip", "sweep.hip", "sweep2d.hip", "plan_math.cpp")]
+SOURCES = [os.path.join(CSRC, f)
+           for f in ("capi.hip", "sweep.hip", "sweep2d.hip", "toeplitz.hip", "plan_math.cpp")]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",

@@ -32,7 +32,7 @@ namespace {
 
 using bsde::kBlock;
 
-enum SweepPath { PATH_FUSED = 0, PATH_DIRECT = 1, PATH_GATHER = 3 };
+enum SweepPath { PATH_FUSED = 0, PATH_DIRECT = 1, PATH_GATHER = 3, PATH_TOEPLITZ = 4 };
 
 struct SweepConfig {
     int path = PATH_DIRECT;
@@ -53,6 +53,10 @@ struct Instance {
     double R;
     bool f32;
     bool gather;  // state-dependent forward coefficients: nodes located per point
+    bool exact;   // exact Gaussian expectations (banded Toeplitz operators)
+    bsde::GaussBand band[bsde::kMaxOrder + 1];  // per layer j (exact)
+    int toep_off[bsde::kMaxOrder + 1] = {};       // band j in the device table
+    const double *toep_w = nullptr;
     int steps;  // layers computed: N - K - n_stop + 1
     bsde::DriverParams drv;
     std::vector<int> m, win_lo, win_hi;
@@ -173,6 +177,9 @@ bool valid_problem(const bsde_problem &p)
     if (p.prec != BSDE_FP64 && p.prec != BSDE_FP32_COMP) return false;
     if (p.n_stop < 0 || p.n_stop > p.n_t - K) return false;
     if (p.z_form != BSDE_ZFORM_EZ && p.z_form != BSDE_ZFORM_YDW) return false;
+    if (p.quad != BSDE_QUAD_GH && p.quad != BSDE_QUAD_EXACT) return false;
+    if (p.interp != BSDE_INTERP_SPLINE && p.interp != BSDE_INTERP_BICUBIC_FD) return false;
+    if (p.interp == BSDE_INTERP_BICUBIC_FD && p.d != 2) return false;
     for (int i = 0; i < 8; ++i)
         if (!std::isfinite(p.p[i])) return false;
     if (p.driver == BSDE_DRIVER_BIDASK && p.p[3] == 0.0) return false;
@@ -191,7 +198,8 @@ bool valid_problem(const bsde_problem &p)
 bool supported_2d(const bsde_problem &p)
 {
     return p.vol[0][1] == 0.0 && p.driver == BSDE_DRIVER_LINEAR && p.prec == BSDE_FP64 &&
-           p.L <= 64 && p.drift_x == 0.0 && p.vol_x == 0.0;
+           p.L <= 64 && p.drift_x == 0.0 && p.vol_x == 0.0 && p.quad == BSDE_QUAD_GH &&
+           (p.interp == BSDE_INTERP_SPLINE || (p.n_x[0] >= 5 && p.n_x[1] >= 5));
 }
 
 // Node tables of eq (20)-(21) on the uniform grid (Section 3.2): the node
@@ -210,6 +218,7 @@ bool build_instance(const bsde_problem &p, Instance &in)
     in.dx = (p.x_max[0] - p.x_min[0]) / (in.nx - 1);
     in.f32 = p.prec == BSDE_FP32_COMP;
     in.gather = p.drift_x != 0.0 || p.vol_x != 0.0;
+    in.exact = p.quad == BSDE_QUAD_EXACT;
     in.steps = p.n_t - in.K - p.n_stop + 1;
     const double vol = p.vol[0][0];
     // largest Gauss-Hermite spread per cell over the grid (b(x) is affine)
@@ -268,9 +277,22 @@ bool build_instance(const bsde_problem &p, Instance &in)
         in.m_max = std::max(in.m_max, hi);
     }
     in.h0 = p.k_y * in.dt * gy[0];
+    if (in.exact) {
+        // exact Gaussian expectations: the band of every layer; the ghosts
+        // cover the band and the Toeplitz kernel's window overhang
+        for (int j = 1; j <= K; ++j) {
+            bsde::GaussBand &b = in.band[j];
+            if (!bsde::gaussian_spline_band(p.drift[0] * j * in.dt / in.dx,
+                                            vol * std::sqrt(j * in.dt) / in.dx,
+                                            std::sqrt(j * in.dt), in.dx, b))
+                return false;
+            in.m_min = std::min(in.m_min, b.klo);
+            in.m_max = std::max(in.m_max, b.klo + (int)b.ev.size() - 1);
+        }
+    }
     in.pad_l = std::max(0, -in.m_min) + 1;
     // right ghosts cover the overhang of the last tile of any configuration
-    in.pad_r = std::max(0, in.m_max) + kBlock * kMaxP + 2;
+    in.pad_r = std::max(0, in.m_max) + kBlock * kMaxP + 2 + (in.exact ? 64 : 0);
     in.npad = in.pad_l + in.nx + in.pad_r;
     in.drv = bsde::DriverParams{p.p[0], p.p[1], p.p[2], p.p[3], p.p[4]};
     in.nwaves = (in.nx + kBlock - 1) / kBlock * (kBlock / 64);
@@ -306,6 +328,13 @@ bsde_status build_instance2(const bsde_problem &p, Instance2 &in)
     int m0min = 0, m0max = 0, m1min = 0, m1max = 0;
     in.win = 0;
     const double d0 = in.dx0 * in.dx0 / 6.0, d1 = in.dx1 * in.dx1 / 6.0;
+    // the interpolant of the layers (Section 3.3): the tensor natural spline
+    // (second derivatives in the three derivative planes), or the paper's
+    // bicubic from the values and finite-difference first and mixed
+    // derivatives (in the same planes).  Either is v0 + B (v1 - v0) + C d0 +
+    // D d1 per axis; for the bicubic B = h01(phi) (and 1 - B = h00(phi)),
+    // C = dx h10(phi) = dx phi (1 - phi)^2, D = dx h11(phi) = -dx phi^2 (1 - phi).
+    const bool bicubic = p.interp == BSDE_INTERP_BICUBIC_FD;
     for (int j = 1; j <= K; ++j) {
         const double sq = std::sqrt(2.0 * j * in.dt);
         for (int l0 = 0; l0 < L; ++l0) {
@@ -316,9 +345,15 @@ bsde_status build_instance2(const bsde_problem &p, Instance2 &in)
             const double ph0 = s0 - f0, u0 = 1.0 - ph0;
             bsde::Node2Row &row = in.rows[(size_t)(j - 1) * L + l0];
             row.m0 = (int)f0;
-            row.B0 = ph0;
-            row.C0 = d0 * (u0 * u0 * u0 - u0);
-            row.D0 = d0 * (ph0 * ph0 * ph0 - ph0);
+            if (bicubic) {  // Hermite basis: values, then dx-scaled slopes
+                row.B0 = ph0 * ph0 * (3.0 - 2.0 * ph0);
+                row.C0 = in.dx0 * ph0 * u0 * u0;
+                row.D0 = -in.dx0 * ph0 * ph0 * u0;
+            } else {
+                row.B0 = ph0;
+                row.C0 = d0 * (u0 * u0 * u0 - u0);
+                row.D0 = d0 * (ph0 * ph0 * ph0 - ph0);
+            }
             int lo = INT32_MAX, hi = INT32_MIN;
             for (int l1 = 0; l1 < L; ++l1) {
                 const double dW1 = sq * a[l1];
@@ -330,9 +365,15 @@ bsde_status build_instance2(const bsde_problem &p, Instance2 &in)
                 const double wgt = w[l0] * inv_sqrt_pi * w[l1] * inv_sqrt_pi;
                 const size_t k = ((size_t)(j - 1) * L + l0) * L + l1;
                 bsde::Node2 &nd = in.nodes[k];
-                nd.B1 = ph1;
-                nd.C1 = d1 * (u1 * u1 * u1 - u1);
-                nd.D1 = d1 * (ph1 * ph1 * ph1 - ph1);
+                if (bicubic) {
+                    nd.B1 = ph1 * ph1 * (3.0 - 2.0 * ph1);
+                    nd.C1 = in.dx1 * ph1 * u1 * u1;
+                    nd.D1 = -in.dx1 * ph1 * ph1 * u1;
+                } else {
+                    nd.B1 = ph1;
+                    nd.C1 = d1 * (u1 * u1 * u1 - u1);
+                    nd.D1 = d1 * (ph1 * ph1 * ph1 - ph1);
+                }
                 nd.cfy = (j <= p.k_y) ? p.k_y * in.dt * gy[j] * wgt : 0.0;
                 nd.cfz1 = (j <= p.k_z) ? gz[j] * wgt * dW0 / gz[0] : 0.0;
                 nd.cfz2 = (j <= p.k_z) ? gz[j] * wgt * dW1 / gz[0] : 0.0;
@@ -394,6 +435,7 @@ bsde::Sweep2Args sweep2_args(const Instance2 &in, char *ws, bool stats)
     a.picard_max = in.pb.picard_max;
     a.picard_tol = in.pb.picard_tol;
     a.zform = in.pb.z_form;
+    a.interp = in.pb.interp;
     a.fin = reinterpret_cast<double *>(ws + in.fin_off);
     if (stats) {
         unsigned long long *sum = reinterpret_cast<unsigned long long *>(ws + in.stat_off);
@@ -417,7 +459,7 @@ SweepConfig fused_config(const std::vector<Instance> &all, const std::vector<int
     size_t lds = 0;
     for (int b : members) {
         const Instance &in = all[b];
-        if (in.gather) return SweepConfig{PATH_FUSED, P, G, 0};
+        if (in.gather || in.exact) return SweepConfig{PATH_FUSED, P, G, 0};
         int wmax = 0, reach = 0;
         for (int j = 2; j <= in.K; ++j) {
             wmax = std::max(wmax, T + in.win_hi[j] - in.win_lo[j] + 1);
@@ -465,9 +507,19 @@ bool group_gathers(const std::vector<Instance> &all, const std::vector<int> &mem
     return false;
 }
 
+bool group_exact(const std::vector<Instance> &all, const std::vector<int> &members)
+{
+    for (int b : members)
+        if (all[b].exact) return true;
+    return false;
+}
+
+SweepConfig toeplitz_config() { return SweepConfig{PATH_TOEPLITZ, 4, 1, bsde::toeplitz_lds_bytes()}; }
+
 SweepConfig default_config(const std::vector<Instance> &all, const Group &g, size_t max_lds)
 {
     if (group_gathers(all, g.members)) return SweepConfig{PATH_GATHER, 1, 1, 0};
+    if (group_exact(all, g.members)) return toeplitz_config();
     const char *env = std::getenv("BSDE_SWEEP");
     if (env) {
         int P = 0, G = 1;
@@ -494,6 +546,7 @@ bsde_status apply_config(bsde_plan_s &pl, Group &g, const SweepConfig &c)
 {
     if (c.path == PATH_FUSED && c.lds > 65536)
         HIP_OK(bsde::set_fused_lds_limit(c.P, c.G, g.f32, g.driver, c.lds));
+    if (c.path == PATH_TOEPLITZ && c.lds > 65536) HIP_OK(bsde::set_toeplitz_lds_limit());
     g.cfg = c;
     g.tile_prefix.assign(g.members.size() + 1, 0);
     g.spline_prefix.assign(g.members.size() + 1, 0);
@@ -571,6 +624,8 @@ bsde_status enqueue_step(const bsde_plan_s &pl, const Group &g, char *ws, int s,
     } else {
         if (c.path == PATH_GATHER)
             HIP_OK(bsde::launch_sweep_gather(g.f32, g.driver, a, blocks, st));
+        else if (c.path == PATH_TOEPLITZ)
+            HIP_OK(bsde::launch_sweep_toeplitz(a, blocks, st));
         else
             HIP_OK(bsde::launch_sweep_direct(c.P, g.f32, g.driver, a, blocks, c.lds, st));
         if (tm) HIP_OK(tm->mark(tm->sweep, st));
@@ -643,8 +698,14 @@ bsde_status enqueue_solve2(const bsde_plan_s &pl, char *ws, const bsde_io *io, b
         f.s6[1] = 6.0 / (in.dx1 * in.dx1) * pl.pcr_base.inv_b;
         const int N = in.pb.n_t, K = in.K;
         a.n = N - K;
+        // the derivative planes of a layer: tensor spline or finite differences
+        auto interp_layer = [&](int slot) {
+            return in.pb.interp == BSDE_INTERP_BICUBIC_FD
+                       ? bsde::launch_fd2d(a, slot, in.dx0, in.dx1, s)
+                       : bsde::launch_spline2d(a, slot, f, s);
+        };
         HIP_OK(bsde::launch_scatter2d(a, io[b].init_y, io[b].init_z, s));
-        for (int r = 0; r < K; ++r) HIP_OK(bsde::launch_spline2d(a, (N - K + 1 + r) % (K + 1), f, s));
+        for (int r = 0; r < K; ++r) HIP_OK(interp_layer((N - K + 1 + r) % (K + 1)));
         for (int n = N - K; n >= in.pb.n_stop; --n) {
             a.n = n;
             if (tm) HIP_OK(tm->mark(tm->sweep, s));
@@ -652,7 +713,7 @@ bsde_status enqueue_solve2(const bsde_plan_s &pl, char *ws, const bsde_io *io, b
             if (tm) HIP_OK(tm->mark(tm->sweep, s));
             if (n > in.pb.n_stop) {
                 if (tm) HIP_OK(tm->mark(tm->spline, s));
-                HIP_OK(bsde::launch_spline2d(a, n % (K + 1), f, s));
+                HIP_OK(interp_layer(n % (K + 1)));
                 if (tm) HIP_OK(tm->mark(tm->spline, s));
             }
         }
@@ -1073,6 +1134,20 @@ bsde_status bsde_plan(const bsde_problem *pb, int batch, bsde_plan_t *out)
     if (!pl) return BSDE_ENOMEM;
     pl->inst.resize(batch);
     for (int b = 0; b < batch; ++b) {
+        // the Toeplitz kernel: linear driver, constant coefficients, FP64
+        const bsde_problem &q = pb[b];
+        // the E[y dW]/dt z form weighs the stored y by dW/dt ~ 1/sqrt(dt): in
+        // the FP32 form the ring's rounding would enter z amplified by that
+        if (q.z_form == BSDE_ZFORM_YDW && q.prec == BSDE_FP32_COMP) {
+            delete pl;
+            return BSDE_EUNSUPPORTED;
+        }
+        if (q.quad == BSDE_QUAD_EXACT &&
+            (q.driver != BSDE_DRIVER_LINEAR || q.drift_x != 0.0 || q.vol_x != 0.0 ||
+             q.prec != BSDE_FP64)) {
+            delete pl;
+            return BSDE_EUNSUPPORTED;
+        }
         if (!build_instance(pb[b], pl->inst[b])) {
             delete pl;
             return BSDE_EINVAL;
@@ -1155,6 +1230,9 @@ bsde_status bsde_plan(const bsde_problem *pb, int batch, bsde_plan_t *out)
         const size_t kl = (size_t)in.K * in.pb.L;
         tbytes += align_up(kl * sizeof(int), 256) + align_up(kl * sizeof(bsde::NodeRec), 256) +
                   align_up(kl * sizeof(bsde::NodeRec32), 256) + align_up(kl * sizeof(double), 256);
+        size_t nbw = 0;
+        for (int j = 1; j <= in.K; ++j) nbw += 4 * in.band[j].ev.size();
+        tbytes += align_up(nbw * sizeof(double), 256);
     }
     const size_t desc_off = tbytes;
     tbytes += align_up((size_t)batch * sizeof(bsde::InstDesc), 256);
@@ -1201,6 +1279,16 @@ bsde_status bsde_plan(const bsde_problem *pb, int batch, bsde_plan_t *out)
             static_cast<const bsde::NodeRec32 *>(put(recs32.data(), kl * sizeof(bsde::NodeRec32)));
         in.dtab.m = static_cast<const int *>(put(in.m.data(), kl * sizeof(int)));
         in.dtab.dw = static_cast<const double *>(put(in.dw.data(), kl * sizeof(double)));
+        std::vector<double> bw;
+        for (int j = 1; j <= in.K; ++j) {
+            const bsde::GaussBand &bd = in.band[j];
+            in.toep_off[j] = (int)bw.size();
+            bw.insert(bw.end(), bd.ev.begin(), bd.ev.end());
+            bw.insert(bw.end(), bd.em.begin(), bd.em.end());
+            bw.insert(bw.end(), bd.wv.begin(), bd.wv.end());
+            bw.insert(bw.end(), bd.wm.begin(), bd.wm.end());
+        }
+        in.toep_w = static_cast<const double *>(put(bw.data(), bw.size() * sizeof(double)));
     }
     if (hipMemcpy(pl->d_tables, host.data(), desc_off, hipMemcpyHostToDevice) != hipSuccess) {
         bsde_plan_destroy(pl);
@@ -1269,6 +1357,31 @@ bsde_status bsde_plan(const bsde_problem *pb, int batch, bsde_plan_t *out)
         a.drift_x = in.pb.drift_x;
         a.vol0 = in.pb.vol[0][0];
         a.vol_x = in.pb.vol_x;
+        if (in.exact) {
+            // eq (20) for f = p0 y + p1 z + p3 with exact expectations:
+            //   Y = E[y^{n+K_y}] + K_y dt sum_j gamma_j E[f^{n+j}]
+            //   Z = (E[z^{n+1}] (or E[y^{n+1} dW]/dt) + sum_j gamma'_j (E[f dW] - E[z])) / gamma'_0
+            double gy[8], gz[8];
+            bsde::spline_gamma(1, in.pb.k_y, gy);
+            bsde::spline_gamma(2, in.pb.k_z, gz);
+            bsde::ToepTable &t = a.toep;
+            t.w = in.toep_w;
+            const double p0 = in.pb.p[0], p1 = in.pb.p[1], p3 = in.pb.p[3];
+            const bool ydw = in.pb.z_form == BSDE_ZFORM_YDW;
+            for (int j = 1; j <= in.K; ++j) {
+                t.off[j] = in.toep_off[j];
+                t.klo[j] = in.band[j].klo;
+                t.nb[j] = (int)in.band[j].ev.size();
+                const double fy = j <= in.pb.k_y ? in.pb.k_y * in.dt * gy[j] : 0.0;
+                const double fz = j <= in.pb.k_z ? gz[j] : 0.0;
+                t.cy_ey[j] = (j == in.pb.k_y ? 1.0 : 0.0) + fy * p0;
+                t.cy_ez[j] = fy * p1;
+                t.cy_1[j] = fy * p3;
+                t.cz_ez[j] = ((j == 1 && !ydw ? 1.0 : 0.0) - fz) / gz[0];
+                t.cz_wy[j] = (fz * p0 + (j == 1 && ydw ? 1.0 / in.dt : 0.0)) / gz[0];
+                t.cz_wz[j] = fz * p1 / gz[0];
+            }
+        }
         d.ring_off = in.ring_off;
         d.fin_off = in.fin_off;
         d.stat_off = in.stat_off;
@@ -1392,6 +1505,7 @@ bsde_status bsde_autotune(bsde_plan_t plan, void *ws, const bsde_io *io, void *s
                 if (c.lds) cand.push_back(c);
             }
         if (group_gathers(plan->inst, g.members)) cand.assign(1, SweepConfig{PATH_GATHER, 1, 1, 0});
+        if (group_exact(plan->inst, g.members)) cand.assign(1, toeplitz_config());
         if (cand.empty()) cand.push_back(direct_config(plan->inst, g.members, g.f32, 2));
         float best = 0.0f;
         SweepConfig best_c = g.cfg;

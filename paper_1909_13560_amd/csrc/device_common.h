@@ -140,6 +140,19 @@ __host__ __device__ constexpr PcrFilters pcr_filters()
     return r;
 }
 
+// Exact Gaussian expectations as banded Toeplitz operators (toeplitz.hip):
+// per layer j the band of ev, em, wv, wm (nb[j] weights each, records
+// klo[j] .. klo[j] + nb[j] - 1 relative to the point) at w + off[j], and the
+// weights of eq (20) for a linear driver folded per layer:
+//   Y += cy_ey E[y] + cy_ez E[z] + cy_1,  Z += cz_ez E[z] + cz_wy E[y dW] + cz_wz E[z dW].
+constexpr int kToepChunk = 512;  // band taps staged in LDS at a time
+struct ToepTable {
+    const double *w;
+    int off[kMaxOrder + 1], klo[kMaxOrder + 1], nb[kMaxOrder + 1];
+    double cy_ey[kMaxOrder + 1], cy_ez[kMaxOrder + 1], cy_1[kMaxOrder + 1];
+    double cz_ez[kMaxOrder + 1], cz_wy[kMaxOrder + 1], cz_wz[kMaxOrder + 1];
+};
+
 struct SweepArgs {
     void *ring;       // K+1 slots of two planes (Slot), double2 (FP64) or float2 (FP32)
     double *fin_y, *fin_z;  // layer n_stop in double precision (written when n == n_stop)
@@ -159,6 +172,7 @@ struct SweepArgs {
     // forward coefficients of eq (1) (gather path): a(x) = drift0 + drift_x x,
     // b(x) = vol0 + vol_x x on the grid x_i = x_min + i dx
     double x_min, dx, drift0, drift_x, vol0, vol_x;
+    ToepTable toep;   // exact Gaussian expectations (Toeplitz path)
     unsigned int *st_iter_max;        // per-wave running maximum (NULL: no stats)
     unsigned long long *st_iter_sum;  // per-wave running sum
     unsigned long long *st_nonconv;   // per-wave count of unconverged point-steps

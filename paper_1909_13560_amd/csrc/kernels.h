@@ -39,6 +39,11 @@ hipError_t launch_sweep_direct(int P, bool f32, int driver, const StepArgs &a, i
                                size_t lds, hipStream_t s);
 // state-dependent forward coefficients: one point per lane, nodes located per point
 hipError_t launch_sweep_gather(bool f32, int driver, const StepArgs &a, int blocks, hipStream_t s);
+// exact Gaussian expectations as banded Toeplitz products on FP64 matrix
+// cores: 1024 points per block, linear driver, FP64
+size_t toeplitz_lds_bytes();
+hipError_t launch_sweep_toeplitz(const StepArgs &a, int blocks, hipStream_t s);
+hipError_t set_toeplitz_lds_limit();
 // mode 0: initial layer s of every instance; mode 1: layer n0 - s (direct path)
 hipError_t launch_spline(bool f32, const StepArgs &a, int mode, int blocks, hipStream_t s);
 hipError_t launch_scatter(const ScatterChunk &c, char *ws, const InstDesc *desc, int blocks_x,

@@ -16,12 +16,15 @@ namespace bsde {
 // of the normalised eigenvector.  The eigenproblem is solved by implicit QL
 // sweeps with Wilkinson shifts, carrying only the first row of the
 // eigenvector matrix.
-bool gauss_hermite(int L, double *a, double *w)
+namespace {
+
+// Eigenvalues d of the symmetric tridiagonal matrix (diagonal d, off-diagonal
+// e[0..L-2]) and the first components v of its normalised eigenvectors
+// (v = e_1 on entry): implicit QL sweeps with Wilkinson shifts that rotate
+// only the first row of the eigenvector matrix.
+bool tridiag_eig_first_row(std::vector<double> &d, std::vector<double> &e, std::vector<double> &v)
 {
-    if (L < 1 || L > kMaxL) return false;
-    std::vector<double> d(L, 0.0), e(L, 0.0), v(L, 0.0);
-    for (int k = 0; k + 1 < L; ++k) e[k] = std::sqrt(0.5 * (k + 1));
-    v[0] = 1.0;
+    const int L = (int)d.size();
     const double eps = 2.220446049250313e-16;
     for (int l = 0; l < L; ++l) {
         for (int iter = 0;; ++iter) {
@@ -66,6 +69,18 @@ bool gauss_hermite(int L, double *a, double *w)
             e[m] = 0.0;
         }
     }
+    return true;
+}
+
+}  // namespace
+
+bool gauss_hermite(int L, double *a, double *w)
+{
+    if (L < 1 || L > kMaxL) return false;
+    std::vector<double> d(L, 0.0), e(L, 0.0), v(L, 0.0);
+    for (int k = 0; k + 1 < L; ++k) e[k] = std::sqrt(0.5 * (k + 1));
+    v[0] = 1.0;
+    if (!tridiag_eig_first_row(d, e, v)) return false;
     std::vector<int> idx(L);
     for (int i = 0; i < L; ++i) idx[i] = i;
     std::sort(idx.begin(), idx.end(), [&](int x, int y) { return d[x] < d[y]; });
@@ -142,6 +157,72 @@ bool spline_gamma(int table, int K, double *g)
             total += cell;
         }
         g[j] = table == 1 ? total / K : first;
+    }
+    return true;
+}
+
+// Gauss-Legendre on [-1, 1] by Golub-Welsch (monic recurrence
+// p_{k+1} = x p_k - k^2/(4k^2 - 1) p_{k-1}: zero diagonal, off-diagonal
+// k / sqrt(4k^2 - 1), weights 2 v_1^2), mapped to [0, 1].
+bool gauss_legendre01(int n, double *x, double *w)
+{
+    if (n < 1 || n > kMaxL) return false;
+    std::vector<double> d(n, 0.0), e(n, 0.0), v(n, 0.0);
+    for (int k = 1; k < n; ++k) e[k - 1] = k / std::sqrt(4.0 * k * k - 1.0);
+    v[0] = 1.0;
+    if (!tridiag_eig_first_row(d, e, v)) return false;
+    std::vector<int> idx(n);
+    for (int i = 0; i < n; ++i) idx[i] = i;
+    std::sort(idx.begin(), idx.end(), [&](int a, int b) { return d[a] < d[b]; });
+    for (int i = 0; i < n; ++i) {
+        x[i] = 0.5 * (d[idx[i]] + 1.0);
+        w[i] = v[idx[i]] * v[idx[i]];  // 2 v^2 on [-1, 1], halved
+    }
+    return true;
+}
+
+bool gaussian_spline_band(double m0, double rho, double h, double dx, GaussBand &out)
+{
+    if (!(rho > 0.0) || !std::isfinite(m0) || !std::isfinite(rho)) return false;
+    constexpr int kGl = 8;  // exact to degree 15 on each sub-interval
+    double gx[kGl], gw[kGl];
+    if (!gauss_legendre01(kGl, gx, gw)) return false;
+    const double reach = 9.0 * rho + 1.0;
+    if (!(reach < 1e7)) return false;
+    const int dlo = (int)std::floor(m0 - reach), dhi = (int)std::ceil(m0 + reach);
+    // sub-intervals of at most rho / 8 in cell units: the Gaussian changes
+    // little over each, the cubic basis times it is integrated to rounding
+    const int nsub = std::max(1, (int)std::ceil(8.0 / rho));
+    const int nb = dhi - dlo + 2;  // records dlo .. dhi + 1
+    out.klo = dlo;
+    out.ev.assign(nb, 0.0);
+    out.em.assign(nb, 0.0);
+    out.wv.assign(nb, 0.0);
+    out.wm.assign(nb, 0.0);
+    const double inv_sqrt_2pi = 0.39894228040143267794, dx26 = dx * dx / 6.0;
+    for (int dd = dlo; dd <= dhi; ++dd) {
+        double I[4] = {0, 0, 0, 0}, J[4] = {0, 0, 0, 0};
+        for (int q = 0; q < nsub; ++q)
+            for (int g = 0; g < kGl; ++g) {
+                const double th = (q + gx[g]) / nsub;
+                const double xi = (dd + th - m0) / rho;
+                const double dens = gw[g] / nsub * inv_sqrt_2pi * std::exp(-0.5 * xi * xi) / rho;
+                const double u = 1.0 - th;
+                const double b[4] = {u, th, dx26 * (u * u * u - u), dx26 * (th * th * th - th)};
+                for (int k = 0; k < 4; ++k) {
+                    I[k] += dens * b[k];
+                    J[k] += dens * b[k] * h * xi;
+                }
+            }
+        const int k0 = dd - dlo;  // left record of the cell; the right one is k0 + 1
+        out.ev[k0] += I[0];
+        out.ev[k0 + 1] += I[1];
+        out.em[k0] += I[2];
+        out.em[k0 + 1] += I[3];
+        out.wv[k0] += J[0];
+        out.wv[k0 + 1] += J[1];
+        out.wm[k0] += J[2];
+        out.wm[k0 + 1] += J[3];
     }
     return true;
 }

@@ -105,6 +105,7 @@ struct Sweep2Args {
     int picard_max;
     double picard_tol;
     int zform;              // first term of the z equation: 0 E[z^{n+1}], 1 E[y^{n+1} dW]/dt
+    int interp;             // bsde_interp: the natural spline or the bicubic
     double *fin;            // layer n_stop: y, z1, z2 planes of n0*n1
     unsigned int *st_iter_max;
     unsigned long long *st_iter_sum, *st_nonconv;
@@ -114,6 +115,9 @@ size_t sweep2d_lds(int win);  // dynamic LDS of the sweep kernel
 hipError_t launch_sweep2d(const Sweep2Args &a, hipStream_t s);
 // splines and ghosts of the layer in slot `slot`
 hipError_t launch_spline2d(const Sweep2Args &a, int slot, const SplineFilter &f, hipStream_t s);
+// the paper's bicubic interpolation: derivatives by fourth-order finite
+// differences (into the three derivative planes) and ghosts of slot `slot`
+hipError_t launch_fd2d(const Sweep2Args &a, int slot, double dx0, double dx1, hipStream_t s);
 // layer r = 0..K-1 of init_y (K x n0 n1) and init_z (K x 2 x n0 n1) into the ring
 hipError_t launch_scatter2d(const Sweep2Args &a, const double *iy, const double *iz,
                             hipStream_t s);

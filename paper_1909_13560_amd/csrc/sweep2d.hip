@@ -56,15 +56,23 @@ __device__ inline Node2 load_node2(const Node2 *p)
 
 // Node flags: bit 0 the y expectation (layer j = K_y), bit 1 the y-hat terms
 // of z^n (layer j = 1 of the z form E[y^{n+1} dW]/dt).
-template <int NF>
+// CLAMP: the node's axis-1 cell q may leave the grid, and a cell that does not
+// lie inside it evaluates to the value at its first point (the nearest grid
+// line: the ghost records hold it), i.e. the interpolant at the coordinate
+// clamped to the box.  The natural spline gets that from its ghost records
+// alone (its second derivatives vanish at the ends); the bicubic's first
+// derivatives do not, so its weights B1, C1, D1 are dropped there.
+template <int NF, bool CLAMP>
 __device__ inline void node2_accumulate(const Sweep2Args &a, const double2 *uv, const Node2 &nd,
-                                        int r, int e, double &Y, double &Z1, double &Z2)
+                                        int r, int e, int q, double &Y, double &Z1, double &Z2)
 {
+    double B1 = nd.B1, C1 = nd.C1, D1 = nd.D1;
+    if (CLAMP && !(q >= 0 && q < a.n1 - 1)) B1 = C1 = D1 = 0.0;
     double h[3];
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
         const double2 p0 = uv[uv_index(a, f, r, e)], p1 = uv[uv_index(a, f, r, e + 1)];
-        h[f] = fma(nd.B1, p1.x - p0.x, fma(nd.C1, p0.y, fma(nd.D1, p1.y, p0.x)));
+        h[f] = fma(B1, p1.x - p0.x, fma(C1, p0.y, fma(D1, p1.y, p0.x)));
     }
     const double fh = f_linear2(a.drv, h[0], h[1], h[2]);
     Y = fma(nd.cfy, fh, Y);
@@ -81,25 +89,43 @@ __device__ inline void node2_accumulate(const Sweep2Args &a, const double2 *uv, 
 // node records come through scalar loads and the axis-1 offsets, one per
 // lane in mv, through readlane, so the only per-node LDS reads are the
 // (U, V) records; two nodes per iteration share one wait.
-template <int NF>
+// i1 - m1lo: the lane's column index minus the window's first offset, so that
+// a node's axis-1 cell is q = e + i1 - m1lo - c.
+template <int NF, bool CLAMP>
 __device__ inline void row_nodes(const Sweep2Args &a, const double2 *uv, const Node2 *ntab,
-                                 int mv, int r, int c, int m1lo, double &Y, double &Z1,
+                                 int mv, int r, int c, int m1lo, int i1, double &Y, double &Z1,
                                  double &Z2)
 {
+    const int qoff = i1 - c;
     int l1 = 0;
 #pragma unroll 1
     for (; l1 + 1 < a.L; l1 += 2) {
         const Node2 n0 = load_node2(ntab + l1), n1 = load_node2(ntab + l1 + 1);
         const int e0 = c + __builtin_amdgcn_readlane(mv, l1) - m1lo;
         const int e1 = c + __builtin_amdgcn_readlane(mv, l1 + 1) - m1lo;
-        node2_accumulate<NF>(a, uv, n0, r, e0, Y, Z1, Z2);
-        node2_accumulate<NF>(a, uv, n1, r, e1, Y, Z1, Z2);
+        node2_accumulate<NF, CLAMP>(a, uv, n0, r, e0, e0 + m1lo + qoff, Y, Z1, Z2);
+        node2_accumulate<NF, CLAMP>(a, uv, n1, r, e1, e1 + m1lo + qoff, Y, Z1, Z2);
     }
     if (l1 < a.L) {
         const Node2 n0 = load_node2(ntab + l1);
-        node2_accumulate<NF>(a, uv, n0, r, c + __builtin_amdgcn_readlane(mv, l1) - m1lo, Y, Z1,
-                                Z2);
+        const int e0 = c + __builtin_amdgcn_readlane(mv, l1) - m1lo;
+        node2_accumulate<NF, CLAMP>(a, uv, n0, r, e0, e0 + m1lo + qoff, Y, Z1, Z2);
     }
+}
+
+template <bool CLAMP>
+__device__ inline void row_nodes_nf(int nf, const Sweep2Args &a, const double2 *uv,
+                                    const Node2 *ntab, int mv, int r, int c, int m1lo, int i1,
+                                    double &Y, double &Z1, double &Z2)
+{
+    if (nf == 0)
+        row_nodes<0, CLAMP>(a, uv, ntab, mv, r, c, m1lo, i1, Y, Z1, Z2);
+    else if (nf == 1)
+        row_nodes<1, CLAMP>(a, uv, ntab, mv, r, c, m1lo, i1, Y, Z1, Z2);
+    else if (nf == 2)
+        row_nodes<2, CLAMP>(a, uv, ntab, mv, r, c, m1lo, i1, Y, Z1, Z2);
+    else
+        row_nodes<3, CLAMP>(a, uv, ntab, mv, r, c, m1lo, i1, Y, Z1, Z2);
 }
 
 }  // namespace
@@ -127,29 +153,36 @@ __global__ void __launch_bounds__(kThreads2) sweep2d(const Sweep2Args a)
             // axis-0 evaluation at s0 for the tile rows and the window columns
             for (int e = tid; e < kTile2R * W; e += kThreads2) {
                 const int rr = e / W, cc = e - rr * W;
-                const size_t o = pidx(a, t0 + rr + row.m0, t1 + row.m1lo + cc);
+                const int p = t0 + rr + row.m0;  // the node's axis-0 cell
+                const size_t o = pidx(a, p, t1 + row.m1lo + cc);
                 const size_t o1 = o + a.npad1;
+                // a cell outside the grid evaluates to its first point's record
+                // (clamped coordinate; see node2_accumulate).  For the natural
+                // spline this changes nothing: there both differences and both
+                // second derivatives in such a cell are exact zeros.
+                const bool in = p >= 0 && p < a.n0 - 1;
+                const double B0 = in ? row.B0 : 0.0, C0 = in ? row.C0 : 0.0, D0 = in ? row.D0 : 0.0;
 #pragma unroll
                 for (int f = 0; f < 3; ++f) {
                     const double *v = slot + (size_t)(4 * f) * a.plane;
                     const double *mxx = v + a.plane, *myy = v + 2 * a.plane, *mxy = v + 3 * a.plane;
-                    const double U = fma(row.B0, v[o1] - v[o], fma(row.C0, mxx[o], fma(row.D0, mxx[o1], v[o])));
+                    const double U = fma(B0, v[o1] - v[o], fma(C0, mxx[o], fma(D0, mxx[o1], v[o])));
                     const double V =
-                        fma(row.B0, myy[o1] - myy[o], fma(row.C0, mxy[o], fma(row.D0, mxy[o1], myy[o])));
+                        fma(B0, myy[o1] - myy[o], fma(C0, mxy[o], fma(D0, mxy[o1], myy[o])));
                     uv[uv_index(a, f, rr, cc)] = make_double2(U, V);
                 }
             }
             __syncthreads();
             const Node2 *ntab = a.nodes + (size_t)rowi * a.L;
             const int nf = (j == a.Ky ? 1 : 0) | (j == 1 && a.zform ? 2 : 0);
-            if (nf == 0)
-                row_nodes<0>(a, uv, ntab, mv, r, c, row.m1lo, Y, Z1, Z2);
-            else if (nf == 1)
-                row_nodes<1>(a, uv, ntab, mv, r, c, row.m1lo, Y, Z1, Z2);
-            else if (nf == 2)
-                row_nodes<2>(a, uv, ntab, mv, r, c, row.m1lo, Y, Z1, Z2);
+            // the bicubic needs the per-node cell check only where the tile's
+            // node cells can leave the grid along axis 1 (block-uniform)
+            const bool clamp = a.interp == BSDE_INTERP_BICUBIC_FD &&
+                               (t1 + row.m1lo < 0 || t1 + kTile2C + row.m1hi > a.n1 - 1);
+            if (clamp)
+                row_nodes_nf<true>(nf, a, uv, ntab, mv, r, c, row.m1lo, t1 + c, Y, Z1, Z2);
             else
-                row_nodes<3>(a, uv, ntab, mv, r, c, row.m1lo, Y, Z1, Z2);
+                row_nodes_nf<false>(nf, a, uv, ntab, mv, r, c, row.m1lo, t1 + c, Y, Z1, Z2);
             __syncthreads();
         }
     }
@@ -393,6 +426,54 @@ __global__ void __launch_bounds__(256) spline2d_rows_lds(const Sweep2Args a, int
     }
 }
 
+// The paper's own 2-D interpolation (Section 3.3): bicubic from the values
+// and the first and mixed derivatives, the derivatives by fourth-order
+// finite differences (central inside, one-sided at the two points next to
+// each end).  They go into the planes of the tensor spline's second
+// derivatives: f_x in M_xx, f_y in M_yy, f_xy in M_xxyy; the sweep kernel is
+// the same, with the Hermite basis weights in the node tables.
+__device__ inline double fd4_at(const double *f, long st, int n, int i, double inv12h)
+{
+    double v;
+    if (i >= 2 && i <= n - 3)
+        v = f[(i - 2) * st] - 8.0 * f[(i - 1) * st] + 8.0 * f[(i + 1) * st] - f[(i + 2) * st];
+    else if (i == 0)
+        v = -25.0 * f[0] + 48.0 * f[st] - 36.0 * f[2 * st] + 16.0 * f[3 * st] - 3.0 * f[4 * st];
+    else if (i == 1)
+        v = -3.0 * f[0] - 10.0 * f[st] + 18.0 * f[2 * st] - 6.0 * f[3 * st] + f[4 * st];
+    else if (i == n - 1)
+        v = 25.0 * f[(n - 1) * st] - 48.0 * f[(n - 2) * st] + 36.0 * f[(n - 3) * st] -
+            16.0 * f[(n - 4) * st] + 3.0 * f[(n - 5) * st];
+    else
+        v = 3.0 * f[(n - 1) * st] + 10.0 * f[(n - 2) * st] - 18.0 * f[(n - 3) * st] +
+            6.0 * f[(n - 4) * st] - f[(n - 5) * st];
+    return v * inv12h;
+}
+
+// f_x of field blockIdx.y along axis 0 (adjacent lanes on adjacent columns)
+__global__ void __launch_bounds__(256) fd2d_cols(const Sweep2Args a, int slot, double inv12h)
+{
+    const long t = blockIdx.x * 256L + threadIdx.x;
+    if (t >= (long)a.n0 * a.n1) return;
+    const int i0 = (int)(t / a.n1), i1 = (int)(t % a.n1);
+    double *v = a.ring + (size_t)(12 * slot + 4 * blockIdx.y) * a.plane;
+    v[a.plane + pidx(a, i0, i1)] = fd4_at(v + pidx(a, 0, i1), a.npad1, a.n0, i0, inv12h);
+}
+
+// Along axis 1 of field blockIdx.y / 2: f_y from the values (blockIdx.y
+// even), f_xy from f_x (odd)
+__global__ void __launch_bounds__(256) fd2d_rows(const Sweep2Args a, int slot, double inv12h)
+{
+    const long t = blockIdx.x * 256L + threadIdx.x;
+    if (t >= (long)a.n0 * a.n1) return;
+    const int i0 = (int)(t / a.n1), i1 = (int)(t % a.n1);
+    const int f = blockIdx.y >> 1, g = blockIdx.y & 1;
+    double *v = a.ring + (size_t)(12 * slot + 4 * f) * a.plane;
+    const double *src = v + (size_t)g * a.plane;
+    v[(size_t)(2 + g) * a.plane + pidx(a, i0, i1)] =
+        fd4_at(src + pidx(a, i0, 0), 1, a.n1, i1, inv12h);
+}
+
 // Ghost points: the data of the nearest grid point with the derivative
 // planes across the crossed edge set to zero (clamped evaluation).
 __global__ void __launch_bounds__(256) ghosts2d(const Sweep2Args a, int slot, int npad0)
@@ -472,6 +553,22 @@ hipError_t launch_spline2d(const Sweep2Args &a, int slot, const SplineFilter &f,
         hipLaunchKernelGGL(spline2d_rows, dim3((unsigned)((tr + 255) / 256), 6), dim3(256), 0, s, a,
                            slot, f);
     }
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int npad0 = (int)(a.plane / a.npad1);
+    const int gb = (int)(((long)npad0 * a.npad1 + 255) / 256);
+    hipLaunchKernelGGL(ghosts2d, dim3(gb), dim3(256), 0, s, a, slot, npad0);
+    return hipGetLastError();
+}
+
+hipError_t launch_fd2d(const Sweep2Args &a, int slot, double dx0, double dx1, hipStream_t s)
+{
+    const long np = (long)a.n0 * a.n1;
+    const unsigned nb = (unsigned)((np + 255) / 256);
+    hipLaunchKernelGGL(fd2d_cols, dim3(nb, 3), dim3(256), 0, s, a, slot, 1.0 / (12.0 * dx0));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(fd2d_rows, dim3(nb, 6), dim3(256), 0, s, a, slot, 1.0 / (12.0 * dx1));
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int npad0 = (int)(a.plane / a.npad1);

@@ -93,3 +93,74 @@ def test_sampled_first_step_equals_whole_grid_step(oracle_lib):
     assert np.array_equal(zs[0], z[0, idx]) and np.array_equal(zs[1], z[1, idx])
     with pytest.raises(ValueError):
         oracle_lib.first_step_points_2d(pb, iy, iz, np.array([41 * 37]))
+
+
+# ----------------------------------------------------------------------------
+# The paper's own 2-D interpolation: bicubic with finite-difference derivatives
+# ----------------------------------------------------------------------------
+
+
+def _example4_errors(oracle_lib, K, N, M, interp):
+    wl = W.sine_2d(n_x=M + 1, n_t=N, k=K, L=8)
+    wl.problem["interp"] = interp
+    iy, iz = wl.init_layers()
+    y, z, _ = oracle_lib.solve(wl.problem, iy, iz)
+    i = wl.node_index()
+    return abs(y[i]), math.hypot(z[0, i] - 1.0, z[1, i] - 1.0)
+
+
+@pytest.mark.parametrize("row", read_golden("table9_example4_k1.txt"),
+                         ids=lambda r: "K%s_N%s_M%s" % tuple(r[:3]))
+def test_table9_k1_rows_with_the_bicubic(oracle_lib, row):
+    # K = 1: y to the printed digits, z to 1% from N = 16 on (the coarsest
+    # grid, M = 46 with dx = 0.35, differs by 11%); the tensor spline is
+    # further off in z at every N
+    K, N, M = (int(v) for v in row[:3])
+    y_ref, z_ref = float(row[3]), float(row[4])
+    ey, ez = _example4_errors(oracle_lib, K, N, M, "bicubic_fd")
+    assert ey == pytest.approx(y_ref, rel=0.01)
+    assert ez == pytest.approx(z_ref, rel=0.01 if N >= 16 else 0.15)
+    _, ez_spline = _example4_errors(oracle_lib, K, N, M, "spline")
+    assert abs(ez - z_ref) < abs(ez_spline - z_ref)
+
+
+@pytest.mark.parametrize("row", [r for r in read_golden("table9_example4.txt") if r[1] == "8"],
+                         ids=lambda r: "K%s_N%s_M%s" % tuple(r[:3]))
+def test_table9_rows_with_the_bicubic(oracle_lib, row):
+    K, N, M = (int(v) for v in row[:3])
+    ey, ez = _example4_errors(oracle_lib, K, N, M, "bicubic_fd")
+    assert ey == pytest.approx(float(row[3]), rel=0.01)
+    assert ez == pytest.approx(float(row[4]), rel=0.01)
+
+
+def test_bicubic_fd_is_exact_for_cubic_polynomials(oracle_lib):
+    # fourth-order differences are exact for cubics (one-sided ones too), and
+    # the bicubic Hermite interpolant of a cubic's values and derivatives is
+    # the cubic: f = 0, X = W, g(x) = x1^3 + x1 x2^2 gives y = E[g(X_T)] =
+    # x1^3 + x1 x2^2 + (T - t)(3 x1 + x1) = x1^3 + x1 x2^2 + 4 x1 (T - t) at
+    # points whose domain of dependence (5 steps of nodes at most 1.35 apart)
+    # stays inside the grid
+    K, N, n = 2, 6, 81
+    pb = dict(d=2, T=1.0, n_t=N, k_y=K, k_z=K, L=4, n_x=[n, n], x_min=[-20.0, -20.0],
+              x_max=[20.0, 20.0], drift=[0.0, 0.0], vol=[[1.0, 0.0], [0.0, 1.0]],
+              driver="linear", p=[0.0, 0.0, 0.0, 0.0], picard_max=30, picard_tol=0.0,
+              interp="bicubic_fd")
+    x = np.linspace(-20.0, 20.0, n)
+    X1, X2 = np.meshgrid(x, x, indexing="ij")
+    dt = 1.0 / N
+
+    def exact(t):
+        return (X1 ** 3 + X1 * X2 ** 2 + 4.0 * X1 * (1.0 - t),
+                3 * X1 ** 2 + X2 ** 2 + 4.0 * (1.0 - t), 2 * X1 * X2)
+
+    iy = np.stack([exact((N - K + 1 + r) * dt)[0].ravel() for r in range(K)])
+    iz = np.stack([np.stack([exact((N - K + 1 + r) * dt)[1].ravel(),
+                             exact((N - K + 1 + r) * dt)[2].ravel()]) for r in range(K)])
+    y, z, _ = oracle_lib.solve(pb, iy, iz)
+    ye, z1e, z2e = exact(0.0)
+    inner = (np.abs(X1) <= 5.0) & (np.abs(X2) <= 5.0)
+    scale = np.maximum(np.abs(ye), 1.0)
+    assert np.max((np.abs(y.reshape(n, n) - ye) / scale)[inner]) < 1e-12
+    assert np.max(np.abs(z[0].reshape(n, n) - z1e)[inner]) < 1e-11
+    assert np.max(np.abs(z[1].reshape(n, n) - z2e)[inner]) < 1e-11
+

@@ -592,3 +592,78 @@ def test_constant_coefficients_reduce_to_the_uniform_path(oracle_lib):
     y0, z0, _ = oracle_lib.solve(wl.problem, iy, iz)
     y1, z1, _ = oracle_lib.solve(dict(wl.problem, drift_x=0.0, vol_x=0.0), iy, iz)
     assert np.array_equal(y0, y1) and np.array_equal(z0, z1)
+
+
+# ----------------------------------------------------------------------------
+# Exact Gaussian expectations of the spline (variant of eq (21))
+# ----------------------------------------------------------------------------
+
+
+def test_exact_expectation_closed_forms(oracle_lib):
+    # E[sin(c + s xi)] = sin(c) e^{-s^2/2}, E[sin(c + s xi) h xi] = h s cos(c)
+    # e^{-s^2/2} (Gaussian integration by parts), up to the spline's
+    # interpolation error (dx^4) on a fine grid; constant data give 1 and 0
+    # also next to the domain ends (the mass outside goes to the boundary value)
+    x = np.linspace(-10.0, 10.0, 4001)
+    c = np.array([0.3, 1.0, -2.0])
+    sd, h = 0.7, 0.9
+    E = oracle_lib.exact_expectation(np.sin(x), np.cos(x), -10.0, 10.0, c, sd, h)
+    g = math.exp(-sd * sd / 2)
+    np.testing.assert_allclose(E[0], np.sin(c) * g, atol=2e-12)
+    np.testing.assert_allclose(E[1], h * sd * np.cos(c) * g, atol=2e-12)
+    np.testing.assert_allclose(E[2], np.cos(c) * g, atol=2e-12)
+    np.testing.assert_allclose(E[3], -h * sd * np.sin(c) * g, atol=2e-12)
+    E = oracle_lib.exact_expectation(np.ones(101), np.full(101, 2.0), 0.0, 1.0,
+                                     np.array([0.0, 0.5, 1.0, -3.0]), 0.3, 1.0)
+    np.testing.assert_allclose(E[0], 1.0, rtol=1e-14)
+    np.testing.assert_allclose(E[2], 2.0, rtol=1e-14)
+    assert np.max(np.abs(E[1])) < 1e-14 and np.max(np.abs(E[3])) < 1e-14
+
+
+def test_exact_expectation_of_a_cubic(oracle_lib):
+    # the natural spline of x^3 is x^3 away from the domain ends (the end
+    # conditions' influence decays by 0.268 per cell), so the expectations are
+    # the Gaussian moments: E[(c + s xi)^3] = c^3 + 3 c s^2 and
+    # E[(c + s xi)^3 h xi] = h (3 c^2 s + 3 s^3)
+    x = np.linspace(-20.0, 20.0, 4001)
+    c = np.array([-1.3, 0.0, 0.7, 2.25])
+    sd, h = 0.8, 1.7
+    E = oracle_lib.exact_expectation(x ** 3, x ** 2, -20.0, 20.0, c, sd, h)
+    np.testing.assert_allclose(E[0], c ** 3 + 3 * c * sd ** 2, rtol=0, atol=1e-10)
+    np.testing.assert_allclose(E[1], h * (3 * c ** 2 * sd + 3 * sd ** 3), rtol=0, atol=1e-10)
+    np.testing.assert_allclose(E[2], c ** 2 + sd ** 2, rtol=0, atol=1e-10)
+    np.testing.assert_allclose(E[3], h * 2 * c * sd, rtol=0, atol=1e-10)
+
+
+def _noise_growth_exact(oracle_lib, R, quad, n_t=60, k=4):
+    dx = math.sqrt(2.0 / n_t) / R
+    nx = int(1.5 / dx) + 1
+    wl = W.sine_1d(n_x=nx, n_t=n_t, k=k, L=16)
+    wl.problem.update(x_min=-(nx - 1) * dx / 2, x_max=(nx - 1) * dx / 2, quad=quad)
+    iy, iz = wl.init_layers()
+    rng = np.random.default_rng(7)
+    ny, nz = (1e-10 * rng.standard_normal(a.shape) for a in (iy, iz))
+    # the all-cores build of the oracle: the same arithmetic per point
+    y0, z0, _ = oracle_lib.solve(wl.problem, iy, iz, threads=True)
+    y1, z1, _ = oracle_lib.solve(wl.problem, iy + ny, iz + nz, threads=True)
+    return max(float(np.max(np.abs(y1 - y0))), float(np.max(np.abs(z1 - z0)))) / 1e-10
+
+
+def test_exact_expectation_stays_stable_at_large_ratio(oracle_lib):
+    # at R = 64 Gauss-Hermite (L = 16) aliases grid-scale noise and the sweep
+    # amplifies it (x12 over 56 steps here, and without bound as steps are
+    # added); the exact expectation damps it (its symbol is the Gaussian's,
+    # below 1 for every nonzero frequency)
+    gh, ex = _noise_growth_exact(oracle_lib, 64.0, "gh"), _noise_growth_exact(oracle_lib, 64.0, "exact")
+    assert gh > 5.0, gh
+    assert ex < 1.0, ex
+
+
+def test_all_cores_oracle_is_the_serial_oracle(oracle_lib):
+    # the OpenMP build shares out the points of a layer; each point's
+    # arithmetic is unchanged, so the results are identical
+    wl = W.bidask_call_1d(n_x=3000, n_t=10, half_width=None)
+    iy, iz = wl.init_layers()
+    y0, z0, s0 = oracle_lib.solve(wl.problem, iy, iz)
+    y1, z1, s1 = oracle_lib.solve(wl.problem, iy, iz, threads=True)
+    assert np.array_equal(y0, y1) and np.array_equal(z0, z1) and s0 == s1
