@@ -120,8 +120,9 @@ def test_black_scholes_full_size(lib, orc, k):
     y, z, *_ = run_both(lib, orc, wl)
     ye, ze = wl.exact_at_t0()
     i = wl.node_index()
-    # first order in dt at k = 1 (Theorems 1-2), fourth-order accurate beyond
-    tol = 1e-5 if k == 1 else 1e-6
+    # first order in dt at k = 1 (Theorems 1-2; z is off the closed form by
+    # 1.1e-4 at dt = 1.3e-3, y by 4e-6), fourth-order accurate beyond
+    tol = 0.2 * wl.problem["T"] / nt if k == 1 else 1e-6
     assert abs(y[i] - ye[i]) < tol and abs(z[0, i] - ze[i]) < tol
 
 
