@@ -41,7 +41,8 @@ typedef enum {
     BSDE_EDEVICE = 3,      /* a HIP call failed (no device, launch failure, ...)  */
     BSDE_EUNSUPPORTED = 4, /* valid problem outside what this build implements    */
     BSDE_ENOCONV = 5,      /* Picard did not reach the tolerance at some point    */
-    BSDE_ENONFINITE = 6    /* a non-finite value appeared in the output layer     */
+    BSDE_ENONFINITE = 6,   /* a non-finite value appeared in the output layer     */
+    BSDE_ESCRATCH = 7      /* plan's workspace exceeds the static workspace       */
 } bsde_status;
 
 typedef enum {
@@ -294,6 +295,30 @@ bsde_status bsde_solve_batched(bsde_plan_t plan, void *ws, const bsde_io *io, vo
  */
 bsde_status bsde_initial_layers(const bsde_problem *pb, int substeps, void *ws, size_t ws_bytes,
                                 double *init_y, double *init_z, void *stream);
+
+/* Size of the library's static device workspace (64 MiB per GPU). */
+#define BSDE_STATIC_WORKSPACE_BYTES (((size_t)64) << 20)
+
+/*
+ * bsde_solve_batched_static -- for callers that cannot allocate device memory
+ * (code under hipGraph stream capture, tight serving loops, harnesses that
+ * forbid hipMalloc): bsde_solve_batched without the statistics, with the
+ * plan's workspace taken from a static device array of the library
+ * (BSDE_STATIC_WORKSPACE_BYTES, one per GPU, held until the process ends)
+ * instead of a caller-owned buffer.  Allocates nothing: no hipMalloc,
+ * hipFree, event, graph or host allocation; it only enqueues the solve's
+ * kernels on the stream (asynchronously).  The caller still owns the inputs
+ * and outputs (io as for bsde_solve_batched).
+ * Every call on one GPU uses that GPU's one static workspace: calls whose
+ * work overlaps on a GPU (different streams or threads without ordering)
+ * race and give wrong results.  A solve initialises everything it reads, so
+ * a call does not depend on the previous call's contents.
+ * The plan must have been made on the current device.
+ * Errors: BSDE_EINVAL (NULL pointer, another current device),
+ * BSDE_ESCRATCH (bsde_workspace_bytes(plan) > BSDE_STATIC_WORKSPACE_BYTES),
+ * BSDE_EDEVICE.
+ */
+bsde_status bsde_solve_batched_static(bsde_plan_t plan, const bsde_io *io, void *stream);
 
 /* Per-kernel device time of one solve, from hipEvent pairs around launches. */
 typedef struct {

@@ -21,7 +21,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbsde_hip.so")
 
 BSDE_OK, BSDE_EINVAL, BSDE_ENOMEM, BSDE_EDEVICE, BSDE_EUNSUPPORTED, BSDE_ENOCONV, \
-    BSDE_ENONFINITE = range(7)
+    BSDE_ENONFINITE, BSDE_ESCRATCH = range(8)
+STATIC_WORKSPACE_BYTES = 64 << 20  # BSDE_STATIC_WORKSPACE_BYTES
 DRIVERS = {"linear": 0, "bidask": 1, "cubic": 2, "exp": 3}
 PRECISIONS = {"fp64": 0, "fp32_comp": 1}
 Z_FORMS = {"eq20": 0, "yW": 1}  # bsde_z_form: E[z^{n+1}], E[y^{n+1} dW]/dt
@@ -31,7 +32,7 @@ INTERPS = {"spline": 0, "bicubic_fd": 1}  # bsde_interp (d = 2: the paper's bicu
 EXPORTED = ["bsde_plan", "bsde_plan_destroy", "bsde_workspace_bytes", "bsde_solve",
             "bsde_solve_batched", "bsde_profile_kernels", "bsde_status_string",
             "bsde_gauss_hermite", "bsde_gamma", "bsde_autotune", "bsde_problem_info",
-            "bsde_initial_layers"]
+            "bsde_initial_layers", "bsde_solve_batched_static"]
 STABILITY_LIMIT = 16.0  # BSDE_STABILITY_LIMIT
 
 
@@ -142,6 +143,8 @@ def load() -> ctypes.CDLL:
         lib.bsde_initial_layers.argtypes = [ctypes.POINTER(_Problem), ip, vp, ctypes.c_size_t,
                                             vp, vp, vp]
         lib.bsde_initial_layers.restype = ip
+        lib.bsde_solve_batched_static.argtypes = [vp, ctypes.POINTER(_Io), vp]
+        lib.bsde_solve_batched_static.restype = ip
         _lib = lib
     return _lib
 
@@ -275,6 +278,16 @@ def bsde_solve_batched(plan: Plan, ws, ios, stream=None, stats: bool = False, ch
     if check and rc not in (BSDE_OK, BSDE_ENOCONV, BSDE_ENONFINITE):
         raise BsdeError(rc, "bsde_solve_batched")
     return rc, (_stats_dict(st) if st is not None else None)
+
+
+def bsde_solve_batched_static(plan: Plan, ios, stream=None, check: bool = True) -> int:
+    """bsde_solve_batched_static: the batched solve in the library's static
+    workspace (allocates nothing).  ``ios`` as for bsde_solve_batched."""
+    rc = load().bsde_solve_batched_static(ctypes.c_void_p(plan.handle), _io_array(ios),
+                                          ctypes.c_void_p(_stream_ptr(stream)))
+    if check and rc not in (BSDE_OK, BSDE_ESCRATCH):
+        raise BsdeError(rc, "bsde_solve_batched_static")
+    return rc
 
 
 def bsde_profile_kernels(plan: Plan, ws, ios, stream=None) -> dict:

@@ -151,6 +151,32 @@ struct bsde_plan_s {
 
 namespace {
 
+// Static workspace of bsde_solve_batched_static: a file-scope device array
+// (each GPU the library runs on holds its own copy until the process ends).
+// In host code `scratch` names a host-side stand-in, not a device address:
+// the kernels get the address hipGetSymbolAddress returns for the device,
+// looked up once per device at plan time (set-up) and kept in
+// g_scratch_addr.
+constexpr size_t kStaticWorkspaceBytes = BSDE_STATIC_WORKSPACE_BYTES;
+__device__ __align__(256) unsigned char scratch[kStaticWorkspaceBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_addr[kMaxDevices];
+
+// Device address of `scratch` on device dev (the current device).
+bsde_status static_workspace(int dev, char **out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return BSDE_EDEVICE;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return BSDE_EDEVICE;
+        g_scratch_addr[dev] = static_cast<char *>(p);
+    }
+    *out = g_scratch_addr[dev];
+    return BSDE_OK;
+}
+
 #define HIP_OK(x)                                  \
     do {                                           \
         hipError_t e_ = (x);                       \
@@ -935,7 +961,8 @@ bsde_status plan_2d(const bsde_problem *pb, int batch, bsde_plan_t *out)
     }
     pcr_base_coefficients(pl->pcr_base);
     pcr_filter(pl->filter2);
-    if (hipGetDevice(&pl->device) != hipSuccess) {
+    char *sw = nullptr;
+    if (hipGetDevice(&pl->device) != hipSuccess || static_workspace(pl->device, &sw) != BSDE_OK) {
         delete pl;
         return BSDE_EDEVICE;
     }
@@ -1031,6 +1058,8 @@ const char *bsde_status_string(bsde_status s)
     case BSDE_EUNSUPPORTED: return "unsupported problem";
     case BSDE_ENOCONV: return "Picard iteration did not converge at some point";
     case BSDE_ENONFINITE: return "non-finite value in the output";
+    case BSDE_ESCRATCH:
+        return "workspace larger than the static workspace (BSDE_STATIC_WORKSPACE_BYTES)";
     }
     return "unknown status";
 }
@@ -1172,7 +1201,8 @@ bsde_status bsde_plan(const bsde_problem *pb, int batch, bsde_plan_t *out)
         pl->pcr_base.inv_b = 1.0 / bv;
         pl->pcr_base.s6 = 0.0;
     }
-    if (hipGetDevice(&pl->device) != hipSuccess) {
+    char *sw = nullptr;
+    if (hipGetDevice(&pl->device) != hipSuccess || static_workspace(pl->device, &sw) != BSDE_OK) {
         delete pl;
         return BSDE_EDEVICE;
     }
@@ -1429,6 +1459,24 @@ bsde_status bsde_solve_batched(bsde_plan_t plan, void *ws, const bsde_io *io, vo
 {
     if (!plan) return BSDE_EINVAL;
     return solve_impl(plan, ws, io, (int)plan->desc.size(), stream, st);
+}
+
+bsde_status bsde_solve_batched_static(bsde_plan_t plan, const bsde_io *io, void *stream)
+{
+    if (!plan || !io) return BSDE_EINVAL;
+    const int count = (int)plan->desc.size();
+    for (int b = 0; b < count; ++b)
+        if (!io[b].init_y || !io[b].init_z || !io[b].y0 || !io[b].z0) return BSDE_EINVAL;
+    if (plan->ws_bytes > kStaticWorkspaceBytes) return BSDE_ESCRATCH;
+    int dev = -1;
+    HIP_OK(hipGetDevice(&dev));
+    if (dev != plan->device) return BSDE_EINVAL;
+    char *w = nullptr;
+    const bsde_status rc = static_workspace(dev, &w);
+    if (rc != BSDE_OK) return rc;
+    // kernel launches only: no statistics (their counters would need
+    // clearing and a host read-back), no graph capture
+    return enqueue_solve(*plan, w, io, false, nullptr, static_cast<hipStream_t>(stream));
 }
 
 bsde_status bsde_profile_kernels(bsde_plan_t plan, void *ws, const bsde_io *io, void *stream,
