@@ -332,10 +332,14 @@ typedef struct {
     int path;             /* sweep kernel of group 0: 0 = LDS-staged windows with
                              the spline of the newest layer in-kernel, 1 = direct
                              loads, 2 = the two-dimensional sweep, 3 = nodes
-                             located per point (state-dependent coefficients)    */
+                             located per point (state-dependent coefficients),
+                             4 = exact expectations as banded Toeplitz products
+                             on matrix cores (BSDE_QUAD_EXACT)                   */
     int points_per_lane;  /* grid points per lane of the sweep kernel            */
-    int node_groups;      /* thread groups sharing the nodes of one tile         */
-    int blocks;           /* blocks of the first sweep launch of group 0         */
+    int node_groups;      /* thread groups sharing the nodes of one tile; for
+                             path 4 the blocks that split one tile's band (their
+                             partial sums are added by a second launch when > 1) */
+    int blocks;           /* tiles of the first sweep launch of group 0          */
     long long lds_bytes;  /* dynamic LDS per block of the sweep kernel           */
 } bsde_kernel_times;
 

@@ -79,6 +79,7 @@ struct Group {
     int *d_tile_inst = nullptr;    // grid tile -> instance (sized for P = 1)
     int *d_spline_inst = nullptr;  // spline tile -> instance
     int max_steps = 0;
+    size_t part_off = 0;  // Toeplitz split partial sums in the workspace
     int active(int s, const std::vector<Instance> &inst) const
     {
         int lo = 0, hi = (int)members.size();  // members[0..lo) have steps > s
@@ -485,7 +486,9 @@ SweepConfig fused_config(const std::vector<Instance> &all, const std::vector<int
     size_t lds = 0;
     for (int b : members) {
         const Instance &in = all[b];
-        if (in.gather || in.exact) return SweepConfig{PATH_FUSED, P, G, 0};
+        // the fused kernel serves the E[z] form of the z equation only
+        if (in.gather || in.exact || in.pb.z_form != BSDE_ZFORM_EZ)
+            return SweepConfig{PATH_FUSED, P, G, 0};
         int wmax = 0, reach = 0;
         for (int j = 2; j <= in.K; ++j) {
             wmax = std::max(wmax, T + in.win_hi[j] - in.win_lo[j] + 1);
@@ -540,12 +543,34 @@ bool group_exact(const std::vector<Instance> &all, const std::vector<int> &membe
     return false;
 }
 
-SweepConfig toeplitz_config() { return SweepConfig{PATH_TOEPLITZ, 4, 1, bsde::toeplitz_lds_bytes()}; }
+// The Toeplitz sweep takes tiles of kToepTile points (P = 1) and splits every
+// tile's band chunks over S blocks (carried in the G field) so that a group
+// with few tiles still launches about 1024 blocks: S = ceil(1024 / tiles),
+// at most 16 and at most the largest member's chunk count.
+int toeplitz_splits(const std::vector<Instance> &all, const std::vector<int> &members)
+{
+    long tiles = 0;
+    int chunks = 1;
+    for (int b : members) {
+        const Instance &in = all[b];
+        tiles += (in.nx + bsde::kToepTile - 1) / bsde::kToepTile;
+        int c = 0;
+        for (int j = 1; j <= in.K; ++j) c += bsde::toeplitz_chunks((int)in.band[j].ev.size());
+        chunks = std::max(chunks, c);
+    }
+    const long want = (1024 + std::max(tiles, 1L) - 1) / std::max(tiles, 1L);
+    return (int)std::max(1L, std::min<long>({want, 16L, (long)chunks}));
+}
+
+SweepConfig toeplitz_config(const std::vector<Instance> &all, const std::vector<int> &members)
+{
+    return SweepConfig{PATH_TOEPLITZ, 1, toeplitz_splits(all, members), bsde::toeplitz_lds_bytes()};
+}
 
 SweepConfig default_config(const std::vector<Instance> &all, const Group &g, size_t max_lds)
 {
     if (group_gathers(all, g.members)) return SweepConfig{PATH_GATHER, 1, 1, 0};
-    if (group_exact(all, g.members)) return toeplitz_config();
+    if (group_exact(all, g.members)) return toeplitz_config(all, g.members);
     const char *env = std::getenv("BSDE_SWEEP");
     if (env) {
         int P = 0, G = 1;
@@ -631,6 +656,8 @@ bsde::StepArgs step_args(const bsde_plan_s &pl, const Group &g, char *ws, int s,
     }
     a.s = s;
     a.stats = stats ? 1 : 0;
+    a.part = g.cfg.path == PATH_TOEPLITZ && g.cfg.G > 1 ? reinterpret_cast<double *>(ws + g.part_off)
+                                                         : nullptr;
     return a;
 }
 
@@ -651,7 +678,7 @@ bsde_status enqueue_step(const bsde_plan_s &pl, const Group &g, char *ws, int s,
         if (c.path == PATH_GATHER)
             HIP_OK(bsde::launch_sweep_gather(g.f32, g.driver, a, blocks, st));
         else if (c.path == PATH_TOEPLITZ)
-            HIP_OK(bsde::launch_sweep_toeplitz(a, blocks, st));
+            HIP_OK(bsde::launch_sweep_toeplitz(a, blocks, c.G, st));
         else
             HIP_OK(bsde::launch_sweep_direct(c.P, g.f32, g.driver, a, blocks, c.lds, st));
         if (tm) HIP_OK(tm->mark(tm->sweep, st));
@@ -1232,7 +1259,7 @@ bsde_status bsde_plan(const bsde_problem *pb, int batch, bsde_plan_t *out)
             const Group &g = pl->groups[k];
             const SweepConfig &c = own[g.members[0]];
             if (g.f32 == in.f32 && g.driver == in.pb.driver && c.path == own[b].path &&
-                c.P == own[b].P && c.G == own[b].G)
+                (c.path == PATH_TOEPLITZ || (c.P == own[b].P && c.G == own[b].G)))
                 gi = (int)k;
         }
         if (gi < 0) {
@@ -1346,6 +1373,17 @@ bsde_status bsde_plan(const bsde_problem *pb, int batch, bsde_plan_t *out)
     for (Instance &in : pl->inst) {
         in.fin_off = off;
         off += align_up((size_t)2 * in.nx * sizeof(double), 256);
+    }
+    // partial sums of the split Toeplitz sweep: 2 kToepTile doubles per tile
+    // and split
+    for (Group &g : pl->groups) {
+        if (!group_exact(pl->inst, g.members)) continue;
+        const int S = toeplitz_splits(pl->inst, g.members);
+        if (S == 1) continue;
+        size_t tiles = 0;
+        for (int b : g.members) tiles += sweep_tiles(pl->inst[b], 1);
+        g.part_off = off;
+        off += align_up(tiles * S * 2 * bsde::kToepTile * sizeof(double), 256);
     }
     pl->stats_off = off;
     for (Instance &in : pl->inst) {
@@ -1553,7 +1591,7 @@ bsde_status bsde_autotune(bsde_plan_t plan, void *ws, const bsde_io *io, void *s
                 if (c.lds) cand.push_back(c);
             }
         if (group_gathers(plan->inst, g.members)) cand.assign(1, SweepConfig{PATH_GATHER, 1, 1, 0});
-        if (group_exact(plan->inst, g.members)) cand.assign(1, toeplitz_config());
+        if (group_exact(plan->inst, g.members)) cand.assign(1, toeplitz_config(plan->inst, g.members));
         if (cand.empty()) cand.push_back(direct_config(plan->inst, g.members, g.f32, 2));
         float best = 0.0f;
         SweepConfig best_c = g.cfg;

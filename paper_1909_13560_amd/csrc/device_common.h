@@ -145,7 +145,8 @@ __host__ __device__ constexpr PcrFilters pcr_filters()
 // klo[j] .. klo[j] + nb[j] - 1 relative to the point) at w + off[j], and the
 // weights of eq (20) for a linear driver folded per layer:
 //   Y += cy_ey E[y] + cy_ez E[z] + cy_1,  Z += cz_ez E[z] + cz_wy E[y dW] + cz_wz E[z dW].
-constexpr int kToepChunk = 512;  // band taps staged in LDS at a time
+constexpr int kToepChunk = 256;  // band taps staged in LDS at a time (a multiple of 4)
+constexpr int kToepTile = 256;   // points per block of the Toeplitz sweep
 struct ToepTable {
     const double *w;
     int off[kMaxOrder + 1], klo[kMaxOrder + 1], nb[kMaxOrder + 1];
@@ -205,6 +206,7 @@ struct StepArgs {
     const int *tile_inst;  // grid tile -> descriptor index; NULL: every tile is of desc[0]
     int s;                 // step: each instance computes layer n0 - s
     int stats;             // bind the statistics slots
+    double *part;          // Toeplitz sweep split over S blocks per tile: partial sums
 };
 
 // ---------------------------------------------------------------------------

@@ -40,9 +40,12 @@ hipError_t launch_sweep_direct(int P, bool f32, int driver, const StepArgs &a, i
 // state-dependent forward coefficients: one point per lane, nodes located per point
 hipError_t launch_sweep_gather(bool f32, int driver, const StepArgs &a, int blocks, hipStream_t s);
 // exact Gaussian expectations as banded Toeplitz products on FP64 matrix
-// cores: 1024 points per block, linear driver, FP64
+// cores: kToepTile points per tile, linear driver, FP64.  S > 1 splits each
+// tile's band over S blocks (partial sums in a.part: 2 kToepTile doubles per
+// tile and split) and adds a finishing launch.
 size_t toeplitz_lds_bytes();
-hipError_t launch_sweep_toeplitz(const StepArgs &a, int blocks, hipStream_t s);
+int toeplitz_chunks(int nb);  // band chunks of a layer whose band has nb taps
+hipError_t launch_sweep_toeplitz(const StepArgs &a, int tiles, int S, hipStream_t s);
 hipError_t set_toeplitz_lds_limit();
 // mode 0: initial layer s of every instance; mode 1: layer n0 - s (direct path)
 hipError_t launch_spline(bool f32, const StepArgs &a, int mode, int blocks, hipStream_t s);

@@ -92,7 +92,11 @@ struct GlobalWindow {
     }
 };
 
-template <int P, int DRV, bool F32, typename Src>
+// YW: the kernel serves the E[y^{n+1} dW]/dt form of the z equation too (the
+// direct kernel).  The fused kernel leaves it out: its two extra node-loop
+// variants cost the kernel scalar registers (more spills) for a form that the
+// plan sends to the direct kernel.
+template <int P, int DRV, bool F32, bool YW, typename Src>
 __device__ inline void layer_dispatch(const Src &src, const int *tm, int j, int l0, int LS,
                                       const SweepArgs &a, Acc<P> &acc)
 {
@@ -100,20 +104,21 @@ __device__ inline void layer_dispatch(const Src &src, const int *tm, int j, int 
     const Driver<DRV, typename Prec<F32>::Raw> f(a.drv, (a.n + j) * a.dt);
     const int row = (j - 1) * a.L;
     const Node *nodes = node_recs(a.tab, static_cast<Node *>(nullptr)) + row;
-    const int nf = (j == a.Ky ? kNodeLastY : 0) | (j == 1 && a.zform ? kNodeYW : 0);
-    switch (nf) {
-    case 0: layer_nodes<P, DRV, 0, F32>(src, nodes, tm + row, l0, LS, a.L, f, acc); break;
-    case kNodeLastY:
-        layer_nodes<P, DRV, kNodeLastY, F32>(src, nodes, tm + row, l0, LS, a.L, f, acc);
-        break;
-    case kNodeYW:
-        layer_nodes<P, DRV, kNodeYW, F32>(src, nodes, tm + row, l0, LS, a.L, f, acc);
-        break;
-    default:
-        layer_nodes<P, DRV, kNodeLastY | kNodeYW, F32>(src, nodes, tm + row, l0, LS, a.L, f,
-                                                       acc);
-        break;
+    const bool last_y = j == a.Ky;
+    if constexpr (YW) {
+        if (j == 1 && a.zform) {
+            if (last_y)
+                layer_nodes<P, DRV, kNodeLastY | kNodeYW, F32>(src, nodes, tm + row, l0, LS, a.L,
+                                                               f, acc);
+            else
+                layer_nodes<P, DRV, kNodeYW, F32>(src, nodes, tm + row, l0, LS, a.L, f, acc);
+            return;
+        }
     }
+    if (last_y)
+        layer_nodes<P, DRV, kNodeLastY, F32>(src, nodes, tm + row, l0, LS, a.L, f, acc);
+    else
+        layer_nodes<P, DRV, 0, F32>(src, nodes, tm + row, l0, LS, a.L, f, acc);
 }
 
 // LDS bytes of the window arrays of the fused kernel.
@@ -256,7 +261,7 @@ __device__ inline void fused_tile(const SweepArgs &a, int tile, char *smem)
         const LdsWindow<P, F32> src{wbase, kHalo - mlo,
                                     WinLayout<P>::kPad ? lane_pt + lane_pt / P : lane_pt};
         __builtin_amdgcn_s_setprio(0);
-        layer_dispatch<P, DRV, F32>(src, tm, j, grp, G, a, acc);
+        layer_dispatch<P, DRV, F32, false>(src, tm, j, grp, G, a, acc);
         __builtin_amdgcn_s_setprio(3);
         __syncthreads();  // the window is reused by the next layer
     }
@@ -313,7 +318,7 @@ __global__ void __launch_bounds__(kBlock) sweep_direct(const StepArgs s)
     for (int q = 0; q < P; ++q) acc.Y[q] = acc.Z[q] = 0.0;
     for (int j = 1; j <= a.K; ++j) {
         const GlobalWindow<F32> src{ring_slot<F32>(a, a.n + j), i0};
-        layer_dispatch<P, DRV, F32>(src, tm, j, 0, 1, a, acc);
+        layer_dispatch<P, DRV, F32, true>(src, tm, j, 0, 1, a, acc);
     }
     finish_points<P, DRV, F32>(a, first, acc, (tile * kBlock + (int)threadIdx.x) >> 6);
 }

@@ -13,15 +13,18 @@
 // is four banded products per layer (E and dW-weighted, of y and of z) and a
 // per-point combination.
 //
-// A wavefront computes 256 consecutive points as a 16 x 16 tile
+// A block computes the 256 consecutive points of one tile as a 16 x 16 tile
 // D[r][q] = sum_k A[r][k] B[k][q] of v_mfma_f64_16x16x4f64 products: point
 // base + 16 q + p(r), A[r][k] = w[k - p(r)] (the band, shifted by the row's
 // point offset) and B[k][q] = rec[base + 16 q + klo + k].  The row order p is
 // chosen so that the four accumulator elements of a lane are consecutive
 // points (the accumulator layout of the instruction keeps row r in lane
-// group r % 4, element r / 4).  A block of four wavefronts stages the
-// records its tiles read (1024 points plus the band) in LDS, the band in
-// chunks of kChunk taps.
+// group r % 4, element r / 4).  The band of every layer is cut into chunks of
+// kToepChunk taps; the block stages the records a chunk reads (the tile plus
+// the chunk) and the chunk's band in LDS, and its four wavefronts take every
+// fourth group of four taps.  Small grids (few tiles) also split the chunks
+// over S blocks per tile: each writes its partial sums, and toeplitz_finish
+// adds them in a fixed order (deterministic) and finishes the points.
 #include "device_common.h"
 #include "kernels.h"
 
@@ -35,56 +38,65 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 // lanes of a row (records 16 apart) spread over the banks
 __device__ inline int tslot(int e) { return e + (e >> 4); }
 
-constexpr int kTilePts = 4 * 256;  // points per block (four 16 x 16 tiles)
+constexpr int kWinRecs = kToepTile + kToepChunk + 16;  // records a chunk reads
+constexpr int kWinSlots = kWinRecs + kWinRecs / 16 + 1;
+constexpr int kBandSlots = kToepChunk + 32;
+
+// y-expectation constant of eq (20) over the layers (the driver's constant
+// term), added once per point by whichever kernel finishes it
+__device__ inline double toeplitz_constant(const ToepTable &T, int K)
+{
+    double c = 0.0;
+    for (int j = 1; j <= K; ++j) c += T.cy_1[j];
+    return c;
+}
 
 }  // namespace
 
-__host__ __device__ constexpr int toeplitz_window_slots()
-{
-    return (kTilePts + kToepChunk + 16) + (kTilePts + kToepChunk + 16) / 16 + 1;
-}
-
 size_t toeplitz_lds_bytes()
 {
-    return (size_t)4 * toeplitz_window_slots() * sizeof(double) +
-           (size_t)4 * (kToepChunk + 32) * sizeof(double);
+    const size_t win = (size_t)4 * kWinSlots * sizeof(double) + (size_t)4 * kBandSlots * sizeof(double);
+    const size_t red = (size_t)4 * kToepTile * 2 * sizeof(double);  // reuses the window
+    return std::max(win, red);
 }
 
-__global__ void __launch_bounds__(256) sweep_toeplitz(const StepArgs s)
+int toeplitz_chunks(int nb) { return (nb + 15 + kToepChunk - 1) / kToepChunk; }
+
+__global__ void __launch_bounds__(256) sweep_toeplitz(const StepArgs s, int S)
 {
     extern __shared__ double tsm[];
-    constexpr int WS = toeplitz_window_slots();
-    constexpr int WB = kToepChunk + 32;
-    double *wy = tsm, *wmy = tsm + WS, *wz = tsm + 2 * WS, *wmz = tsm + 3 * WS;
-    double *bev = tsm + 4 * WS, *bem = bev + WB, *bwv = bem + WB, *bwm = bwv + WB;
+    double *wy = tsm, *wmy = tsm + kWinSlots, *wz = tsm + 2 * kWinSlots, *wmz = tsm + 3 * kWinSlots;
+    double *bev = tsm + 4 * kWinSlots, *bem = bev + kBandSlots, *bwv = bem + kBandSlots,
+           *bwm = bwv + kBandSlots;
 
     const int idx = xcd_tile(blockIdx.x, gridDim.x);
-    const InstDesc &d = block_desc(s, idx);
+    const int tg = idx / S, sp = idx - tg * S;  // tile of the group, split of the band
+    const InstDesc &d = block_desc(s, tg);
     const SweepArgs a = bind_instance(d, s.ws, s.s, s.stats != 0);
-    const int tile = idx - d.tile_base;
-    const int t0 = tile * kTilePts;
+    const int tile = tg - d.tile_base;
+    const int t0 = tile * kToepTile;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int lr = lane & 15, lk = lane >> 4;  // A row / B column, and k row of the step
+    const int lr = lane & 15, lk = lane >> 4;   // A row / B column, and k row of the step
+    const int prow = 4 * (lr & 3) + (lr >> 2);  // point offset p(r) of A row r = lr
+    const int ebase = 16 * lr;                  // B column lr: points 16 lr .. 16 lr + 15
     // the per-layer entries are indexed by j at run time: read them from the
     // descriptor in memory (scalar loads), not from the private copy in a
     const ToepTable &T = d.a.toep;
 
-    Acc<4> acc;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) acc.Y[q] = acc.Z[q] = 0.0;
-
+    double Y[4] = {0.0, 0.0, 0.0, 0.0}, Z[4] = {0.0, 0.0, 0.0, 0.0};
+    int gi = 0;  // chunk number over all layers; this block takes gi = sp mod S
     for (int j = 1; j <= a.K; ++j) {
         const Slot<false> g = ring_slot<false>(a, a.n + j);
         const int klo = T.klo[j], nb = T.nb[j];
         const double *band = T.w + T.off[j];  // ev, em, wv, wm: nb each
-        v4d cey = {0, 0, 0, 0}, cwy = cey, cez = cey, cwz = cey;
-        const int kend = nb + 15;  // k over which A[r][k] = w[k - r] can be non-zero
-        for (int c0 = 0; c0 < kend; c0 += kToepChunk) {
+        const int kend = nb + 15;  // k over which A[r][k] = w[k - p(r)] can be non-zero
+        for (int c0 = 0; c0 < kend; c0 += kToepChunk, ++gi) {
+            if (gi % S != sp) continue;
             const int clen = min(kToepChunk, kend - c0);
             __syncthreads();  // the previous chunk's reads are done
-            // records t0 + klo + c0 + e, e < kTilePts + clen + 16 (ghosts
+            // records t0 + klo + c0 + e, e < kToepTile + clen + 16 (ghosts
             // outside the grid hold the boundary value and M = 0)
-            for (int e = tid; e < kTilePts + clen + 16; e += 256) {
+            for (int e = tid; e < kToepTile + clen + 16; e += 256) {
                 const double2 v = g.val(t0 + klo + c0 + e), m = g.der(t0 + klo + c0 + e);
                 const int sl = tslot(e);
                 wy[sl] = v.x;
@@ -102,10 +114,13 @@ __global__ void __launch_bounds__(256) sweep_toeplitz(const StepArgs s)
                 bwm[q] = in ? band[3 * nb + bi] : 0.0;
             }
             __syncthreads();
-            const int ebase = 256 * wv + 16 * lr;  // B column of this lane: its tile column
-            const int prow = 4 * (lr & 3) + (lr >> 2);  // point offset p(r) of A row r = lr
-            for (int k4 = 0; k4 < clen; k4 += 4) {
-                const int kk = k4 + lk;                // local k of this lane's row
+            v4d cey = {0, 0, 0, 0}, cwy = cey, cez = cey, cwz = cey;
+            // taps 4 q .. 4 q + 3 of the chunk, q = wv, wv + 4, ... (taps past
+            // the chunk's end meet zero band entries: kToepChunk is a multiple
+            // of 4, so only the last chunk of a layer has them)
+            const int n4 = (clen + 3) >> 2;
+            for (int q = wv; q < n4; q += 4) {
+                const int kk = 4 * q + lk;             // local k of this lane's row
                 const int ai = kk - prow + 16;         // band entry c0 + kk - p(r)
                 const double aev = bev[ai], aem = bem[ai], awv = bwv[ai], awm = bwm[ai];
                 const int sl = tslot(ebase + kk);
@@ -119,25 +134,73 @@ __global__ void __launch_bounds__(256) sweep_toeplitz(const StepArgs s)
                 cwz = __builtin_amdgcn_mfma_f64_16x16x4f64(awv, bz, cwz, 0, 0, 0);
                 cwz = __builtin_amdgcn_mfma_f64_16x16x4f64(awm, bmz, cwz, 0, 0, 0);
             }
-        }
-        // D[r][q] sits in lane q + 16 (r % 4), element r / 4, and row r is the
-        // point offset p(r) = 4 (r % 4) + r / 4: this lane holds the points
-        // base + 16 lr + 4 lk + i, i = 0..3, in order.  Linear driver: the
-        // expectations of f are those of y and z combined; the host folded
-        // the weights of eq (20) (Tables 1-2, the z form) into T.c*.
+            // D[r][q] sits in lane q + 16 (r % 4), element r / 4, and row r is
+            // the point offset p(r) = 4 (r % 4) + r / 4: this lane holds the
+            // points 16 lr + 4 lk + i, i = 0..3, in order.  Linear driver: the
+            // expectations of f are those of y and z combined; the host
+            // folded the weights of eq (20) (Tables 1-2, the z form) into T.c*.
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            acc.Y[i] += T.cy_ey[j] * cey[i] + T.cy_ez[j] * cez[i] + T.cy_1[j];
-            acc.Z[i] += T.cz_ez[j] * cez[i] + T.cz_wy[j] * cwy[i] + T.cz_wz[j] * cwz[i];
+            for (int i = 0; i < 4; ++i) {
+                Y[i] += T.cy_ey[j] * cey[i] + T.cy_ez[j] * cez[i];
+                Z[i] += T.cz_ez[j] * cez[i] + T.cz_wy[j] * cwy[i] + T.cz_wz[j] * cwz[i];
+            }
         }
     }
-    finish_points<4, BSDE_DRIVER_LINEAR, false>(a, t0 + 256 * wv + 16 * lr + 4 * lk, acc,
-                                                (tile * 256 + tid) >> 6);
+    // the four wavefronts' partial sums meet in LDS (over the window)
+    __syncthreads();
+    double *red = tsm;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int pt = 16 * lr + 4 * lk + i;
+        red[(wv * kToepTile + pt) * 2] = Y[i];
+        red[(wv * kToepTile + pt) * 2 + 1] = Z[i];
+    }
+    __syncthreads();
+    double ys = 0.0, zs = 0.0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        ys += red[(w * kToepTile + tid) * 2];
+        zs += red[(w * kToepTile + tid) * 2 + 1];
+    }
+    if (S == 1) {
+        Acc<1> acc;
+        acc.Y[0] = ys + toeplitz_constant(T, a.K);
+        acc.Z[0] = zs;
+        finish_points<1, BSDE_DRIVER_LINEAR, false>(a, t0 + tid, acc, (tile * kToepTile + tid) >> 6);
+    } else {
+        double *p = s.part + ((size_t)tg * S + sp) * 2 * kToepTile;
+        p[tid] = ys;
+        p[kToepTile + tid] = zs;
+    }
 }
 
-hipError_t launch_sweep_toeplitz(const StepArgs &a, int blocks, hipStream_t s)
+// The partial sums of the S blocks of a tile, added in split order, and the
+// implicit y equation (Picard) of its points.
+__global__ void __launch_bounds__(256) toeplitz_finish(const StepArgs s, int S)
 {
-    hipLaunchKernelGGL(sweep_toeplitz, dim3(blocks), dim3(256), toeplitz_lds_bytes(), s, a);
+    const int tg = xcd_tile(blockIdx.x, gridDim.x);
+    const InstDesc &d = block_desc(s, tg);
+    const SweepArgs a = bind_instance(d, s.ws, s.s, s.stats != 0);
+    const int tile = tg - d.tile_base, tid = threadIdx.x;
+    const double *p = s.part + (size_t)tg * S * 2 * kToepTile;
+    double ys = 0.0, zs = 0.0;
+    for (int sp = 0; sp < S; ++sp) {
+        ys += p[sp * 2 * kToepTile + tid];
+        zs += p[sp * 2 * kToepTile + kToepTile + tid];
+    }
+    Acc<1> acc;
+    acc.Y[0] = ys + toeplitz_constant(d.a.toep, a.K);
+    acc.Z[0] = zs;
+    finish_points<1, BSDE_DRIVER_LINEAR, false>(a, tile * kToepTile + tid, acc,
+                                                (tile * kToepTile + tid) >> 6);
+}
+
+hipError_t launch_sweep_toeplitz(const StepArgs &a, int tiles, int S, hipStream_t s)
+{
+    hipLaunchKernelGGL(sweep_toeplitz, dim3(tiles * S), dim3(256), toeplitz_lds_bytes(), s, a, S);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || S == 1) return e;
+    hipLaunchKernelGGL(toeplitz_finish, dim3(tiles), dim3(256), 0, s, a, S);
     return hipGetLastError();
 }
 

@@ -108,12 +108,12 @@ def test_initial_layers_reject_small_workspace(lib):
 # ----------------------------------------------------------------------------
 
 
-def _run(lib, orc, wl, prec="fp64", tol=TOL64):
+def _run(lib, orc, wl, prec="fp64", tol=TOL64, threads=False):
     pb = dict(wl.problem, prec=prec)
     print(f"[case] {wl.name} z_form={pb.get('z_form')} {prec}", flush=True)
     iy, iz = wl.init_layers()
     y, z, rc, st = lib.solve(pb, iy, iz)
-    yo, zo, _ = orc.solve(pb, iy, iz)
+    yo, zo, _ = orc.solve(pb, iy, iz, n_stop=pb.get("n_stop", 0), threads=threads)
     e = max(rel_err(y, yo), max(rel_err(z[c], zo[c]) for c in range(pb["d"])))
     print(f"  rel err {e:.3e}", flush=True)
     assert rc == lib.BSDE_OK and e <= tol
@@ -236,7 +236,63 @@ def test_exact_quadrature_toeplitz(lib, orc):
           torch.as_tensor(iz.reshape(iy.shape), device="cuda").contiguous(),
           torch.empty(n, dtype=torch.float64, device="cuda"),
           torch.empty(n, dtype=torch.float64, device="cuda"))
-    assert lib.bsde_profile_kernels(plan, ws, [io])["path"] == 4
+    kt = lib.bsde_profile_kernels(plan, ws, [io])
+    assert kt["path"] == 4 and kt["node_groups"] > 1
+
+
+def _toeplitz_splits(lib, pbs):
+    import torch
+
+    plan = lib.bsde_plan(pbs)
+    ws = lib.workspace(plan)
+    ios = []
+    for pb in pbs:
+        n = pb["n_x"]
+        K = max(pb["k_y"], pb["k_z"])
+        ios.append((torch.zeros(K * n, dtype=torch.float64, device="cuda"),
+                    torch.zeros(K * n, dtype=torch.float64, device="cuda"),
+                    torch.empty(n, dtype=torch.float64, device="cuda"),
+                    torch.empty(n, dtype=torch.float64, device="cuda")))
+    kt = lib.bsde_profile_kernels(plan, ws, ios)
+    assert kt["path"] == 4
+    return kt["node_groups"]
+
+
+def test_exact_quadrature_toeplitz_splits_and_batch(lib, orc):
+    from test_gpu_parity import batched_solve
+
+    # one band chunk (K = 1 at stability ratio 16: about 220 taps): no
+    # split, the sweep kernel finishes the points itself
+    nx, nt = 3001, 40
+    wl = W.bs_call_1d(n_x=nx, n_t=nt, k=1, L=16, half_width=twin_half_width(0.2, 0.33, nt, nx))
+    wl.problem["quad"] = "exact"
+    assert _toeplitz_splits(lib, [wl.problem]) == 1
+    _run(lib, orc, wl)
+    # a batch of exact instances of different sizes and lengths in one group
+    # (tile map, splits over several blocks per tile, prefix-active launches)
+    wls = [W.sine_1d(n_x=700, n_t=20, k=2), W.sine_1d(n_x=3001, n_t=9, k=3),
+           W.bs_call_1d(n_x=1999, n_t=12, k=4, L=16,
+                        half_width=twin_half_width(0.2, 0.33, 12, 1999, 30.0))]
+    for w in wls:
+        w.problem["quad"] = "exact"
+    assert _toeplitz_splits(lib, [w.problem for w in wls]) > 1
+    rc, st, outs, _ = batched_solve(lib, wls)
+    assert rc == lib.BSDE_OK
+    for w, (y, z) in zip(wls, outs):
+        iy, iz = w.init_layers()
+        yo, zo, _ = orc.solve(dict(w.problem, prec="fp64"), iy, iz)
+        e = max(rel_err(y, yo), rel_err(z, zo[0]))
+        print(f"  {w.name}: rel err {e:.3e}", flush=True)
+        assert e <= TOL64
+
+
+def test_exact_quadrature_black_scholes_full_size_first_steps(lib, orc):
+    # 16384 points, N = 256, k = 4 on the stable twin interval, its first
+    # eight backward steps against the oracle over the whole grid
+    nx, nt = 16384, 256
+    wl = W.bs_call_1d(n_x=nx, n_t=nt, k=4, L=32, half_width=twin_half_width(0.2, 0.33, nt, nx))
+    wl.problem.update(quad="exact", n_stop=nt - 4 + 1 - 8)
+    _run(lib, orc, wl, threads=True)
 
 
 def test_exact_quadrature_refuses_unsupported(lib):
