@@ -43,6 +43,16 @@ def workload(name: str):
                                 picard_tol=1e-14, picard_max=30)
     if name == "sine1d":
         return W.sine_1d()
+    if name in ("bs1d_exact", "bs1d_literal_exact"):
+        # Black-Scholes call, 16384 points, N = 256, k = 4, exact Gaussian
+        # expectations (the Toeplitz sweep on matrix cores); the stable twin
+        # interval (stability ratio 16) or the literal ln S0 +- 6 sigma sqrt(T)
+        nx, nt = 16384, 256
+        hw = 0.2 * math.sqrt(2 * 0.33 / nt) / 16.0 * (nx - 1) / 2 if name == "bs1d_exact" else None
+        wl = W.bs_call_1d(n_x=nx, n_t=nt, k=4, L=32, half_width=hw)
+        wl.problem["quad"] = "exact"
+        wl.name += "_exact"
+        return wl
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -444,7 +454,9 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="bidask1d")
+    ap.add_argument("--workload", default="bidask1d",
+                    help="bidask1d (the headline), bidask1d_literal, sine1d, bs1d_exact, "
+                         "bs1d_literal_exact, or basket2d (the 2-D basket alone)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fp64-only", action="store_true", help="skip the FP32-form run")
     ap.add_argument("--batch", type=int, default=4096,
@@ -485,6 +497,15 @@ def main() -> int:
 
     import paper_1909_13560_amd as B
 
+    if args.workload == "basket2d":
+        # the 2-D basket alone (profiling runs of its kernels)
+        import torch
+
+        import paper_1909_13560_amd as B
+
+        torch.cuda.set_device(0)
+        print(json.dumps({"two_d": run_2d(args, B, torch, np)}), flush=True)
+        return 0
     wl = workload(args.workload)
     pb = wl.problem
     steps_run = pb["n_t"] - wl.K + 1
@@ -553,7 +574,11 @@ def main() -> int:
     sweep_ms = ms / steps_run
     sweep_ms_direct = kt["sweep_ms"] / kt["sweep_launches"] if kt else None
     spline_ms = kt["spline_ms"] / kt["spline_launches"] if kt and kt["spline_launches"] else 0.0
-    fl = flops_per_point_step(pb, st["picard_iter_mean"]) * nx
+    exact = pb.get("quad") == "exact"
+    if exact:  # the Toeplitz sweep: matrix-core products of the bands
+        fl = toeplitz_flops_per_point_step(pb)[0] * nx
+    else:
+        fl = flops_per_point_step(pb, st["picard_iter_mean"]) * nx
     achieved = fl / (sweep_ms * 1e-3) / 1e12
     # error of the headline value against the closed form
     err = {"y0": float(y_h[i]), "z0": float(z_h[i]),
@@ -614,9 +639,11 @@ def main() -> int:
                    "L": pb["L"], "driver": pb["driver"], "x_min": pb["x_min"],
                    "x_max": pb["x_max"], "picard_tol": pb["picard_tol"],
                    "stability_ratio": st["stability_ratio"]},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS,
+        "roofline": {"bound": "mfma" if exact else "alu", "achieved": achieved,
+                     "peak": FP64_VALU_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_VALU_PEAK_TFLOPS,
-                     "traffic": measured_traffic(wl.name), "kernel": "sweep_fused",
+                     "traffic": None if exact else measured_traffic(wl.name),
+                     "kernel": "sweep_toeplitz" if exact else "sweep_fused",
                      "kernel_us": sweep_ms * 1e3,
                      "kernel_us_measured_as": "graph-replayed solves between hipEvents on "
                                               "the launch stream, per sweep launch",
