@@ -397,6 +397,54 @@ def toeplitz_flops_per_point_step(pb: dict) -> tuple:
     return alg, exe
 
 
+def smoothing_study(B, torch, twin, substeps: int = 8):
+    """The Black-Scholes call of ``twin`` (16384 points, N = 256, k = 4) from
+    its payoff at T: raw, Kreiss-smoothed (orders 2 and 4) and time-shifted
+    terminal layers, the K - 1 initial layers by the method's 1-step scheme on
+    the device (``substeps`` per dt), Gauss-Hermite and exact expectations;
+    the errors at the money against the closed form, and the time of a solve."""
+    import workloads as W
+
+    dev = "cuda:0"
+    p0, nx = twin.problem, twin.problem["n_x"]
+    out = {}
+    for term in ("raw", "kreiss2", "kreiss4", "shift"):
+        wl = W.bs_call_1d(n_x=nx, n_t=p0["n_t"], k=p0["k_y"], L=p0["L"],
+                          half_width=(p0["x_max"] - p0["x_min"]) / 2, terminal=term)
+        ty, tz = W.terminal_layer(wl)
+        ye, ze = wl.exact_at_t0()
+        i = wl.node_index()
+        for q in ("gh", "exact"):
+            pb = dict(wl.problem, quad=q)
+            plan = B.bsde_plan(pb)
+            ws = B.workspace(plan, dev)
+            K = wl.K
+            t_iy = torch.zeros((K, nx), dtype=torch.float64, device=dev)
+            t_iz = torch.zeros((K, nx), dtype=torch.float64, device=dev)
+            t_iy[K - 1] = torch.as_tensor(ty, device=dev)
+            t_iz[K - 1] = torch.as_tensor(tz.reshape(-1), device=dev)
+            stream = torch.cuda.current_stream()
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            e[0].record(stream)
+            B.bsde_initial_layers(pb, substeps, ws, t_iy, t_iz, stream=stream)
+            e[1].record(stream)
+            y0 = torch.empty(nx, dtype=torch.float64, device=dev)
+            z0 = torch.empty(nx, dtype=torch.float64, device=dev)
+            rc, _ = B.bsde_solve(plan, ws, t_iy, t_iz, y0, z0, stream=stream)  # captures
+            e[2].record(stream)
+            B.bsde_solve(plan, ws, t_iy, t_iz, y0, z0, stream=stream)
+            e.append(torch.cuda.Event(enable_timing=True))
+            e[3].record(stream)
+            torch.cuda.synchronize()
+            out[f"{term}_{q}"] = {"abs_err_y0": abs(float(y0[i]) - float(ye[i])),
+                                  "abs_err_z0": abs(float(z0[i]) - float(ze[i])),
+                                  "initial_layers_ms": e[0].elapsed_time(e[1]),
+                                  "solve_ms": e[2].elapsed_time(e[3]),
+                                  "status": B.bsde_status_string(rc)}
+    print(f"[bench] configs: smoothing study {out}", file=sys.stderr, flush=True)
+    return out
+
+
 def run_configs(args, B, torch, np):
     """The other configurations: the sine problem (1025 points, N = 64, k = 2),
     Black-Scholes (16384 points, N = 256, L = 32, k = 4) on its stable twin and
@@ -437,6 +485,7 @@ def run_configs(args, B, torch, np):
                                "flops_per_point_step": alg}
         out[name] = rec
         print(f"[bench] configs: {name} {rec}", file=sys.stderr, flush=True)
+    out["smoothing_study"] = smoothing_study(B, torch, twin)
     wl = W.bidask_call_1d(half_width=None)
     ms, st, kt, y, z, rc = time_solves(B, torch, wl, reps=3)
     out["bidask_262144_nt1024_literal_gh"] = {

@@ -33,11 +33,13 @@ def orc():
     return oracle
 
 
-def _initial_layers_case(lib, orc, wl, sub):
+def _initial_layers_case(lib, orc, wl, sub, terminal=None):
     import torch
 
     pb = wl.problem
     iy_ex, iz_ex = wl.init_layers()
+    if terminal is not None:  # another terminal layer (y of (n,), z of (d, n))
+        iy_ex[-1], iz_ex[-1] = terminal
     K, npts = iy_ex.shape
     d = pb["d"]
     print(f"[case] initial layers {wl.name} sub={sub}", flush=True)
@@ -65,7 +67,7 @@ def _initial_layers_case(lib, orc, wl, sub):
 
     _t.cuda.synchronize()
     assert rc == lib.BSDE_OK
-    yo, zo, _ = orc.solve(pb, iy_o, iz_o)
+    yo, zo, _ = orc.solve(pb, iy_o, iz_o, threads=True)
     zg = z0.cpu().numpy().reshape(d, npts)
     es = max(rel_err(y0.cpu().numpy(), yo), max(rel_err(zg[c], zo[c]) for c in range(d)))
     print(f"  solve: rel err {es:.3e}", flush=True)
@@ -89,6 +91,55 @@ def test_initial_layers_bid_ask_and_time_dependent_driver(lib, orc):
 
 def test_initial_layers_two_dimensional(lib, orc):
     _initial_layers_case(lib, orc, W.exchange_2d(n_x=49, n_t=8, k=3, L=6, rho=0.5), 3)
+
+
+def test_initial_layers_from_smoothed_payoffs(lib, orc):
+    # Black-Scholes call from its payoff at T (no time shift): raw, and
+    # smoothed by the Kreiss-type operator of order 4, with Gauss-Hermite and
+    # with exact expectations (the Toeplitz kernel, in the initial layers'
+    # 1-step segments too)
+    nx, nt = 2049, 32
+    for term, q in (("raw", "gh"), ("kreiss4", "gh"), ("kreiss4", "exact")):
+        wl = W.bs_call_1d(n_x=nx, n_t=nt, k=4, L=32,
+                          half_width=twin_half_width(0.2, 0.33, nt, nx), terminal=term)
+        wl.problem["quad"] = q
+        _initial_layers_case(lib, orc, wl, 8, terminal=W.terminal_layer(wl))
+
+
+def test_smoothing_study_full_size(lib):
+    # 16384 points, N = 256, k = 4, L = 32 on the stable interval; the method's
+    # own initial layers (8 sub-steps) from the terminal layer; errors at the
+    # money against the closed form
+    import torch
+
+    nx, nt = 16384, 256
+    err = {}
+    for term, q in (("raw", "gh"), ("kreiss4", "gh"), ("kreiss4", "exact"), ("shift", "gh")):
+        wl = W.bs_call_1d(n_x=nx, n_t=nt, k=4, L=32,
+                          half_width=twin_half_width(0.2, 0.33, nt, nx), terminal=term)
+        pb = dict(wl.problem, quad=q)
+        print(f"[case] smoothing study {wl.name} {q}", flush=True)
+        ty, tz = W.terminal_layer(wl)
+        plan = lib.bsde_plan(pb)
+        ws = lib.workspace(plan)
+        t_iy = torch.zeros((4, nx), dtype=torch.float64, device="cuda")
+        t_iz = torch.zeros((4, nx), dtype=torch.float64, device="cuda")
+        t_iy[3] = torch.as_tensor(ty, device="cuda")
+        t_iz[3] = torch.as_tensor(tz.reshape(-1), device="cuda")
+        lib.bsde_initial_layers(pb, 8, ws, t_iy, t_iz)
+        y0 = torch.empty(nx, dtype=torch.float64, device="cuda")
+        z0 = torch.empty(nx, dtype=torch.float64, device="cuda")
+        rc, _ = lib.bsde_solve(plan, ws, t_iy, t_iz, y0, z0, stats=True)
+        torch.cuda.synchronize()
+        assert rc == lib.BSDE_OK
+        ye, ze = wl.exact_at_t0()
+        i = wl.node_index()
+        err[term, q] = (abs(float(y0[i]) - ye[i]), abs(float(z0[i]) - ze[i]))
+        print("  y0 err %.3e z0 err %.3e" % err[term, q], flush=True)
+    assert err["raw", "gh"][1] > 1e-3
+    assert err["kreiss4", "gh"][1] < 1e-5 and err["kreiss4", "gh"][0] > 1e-4
+    assert err["kreiss4", "exact"][0] < 1e-6 and err["kreiss4", "exact"][1] < 1e-5
+    assert err["shift", "gh"][0] < 1e-6 and err["shift", "gh"][1] < 1e-5
 
 
 def test_initial_layers_reject_small_workspace(lib):

@@ -226,20 +226,83 @@ def _snap_domain(c: float, lo: float, hi: float, n_x: int):
     return lo, lo + (n_x - 1) * dx
 
 
+# ----------------------------------------------------------------------------
+# Smoothing of non-smooth terminal data (Section 5, Example 3: the paper smooths
+# the initial condition of the call after Kreiss, Thomee and Widlund (1970)
+# without stating the operator).  The operators of that family:
+#   (M_h v)(x) = int Phi(t) v(x - h t) dt,
+# order 2: Phi the hat function on [-1, 1] (Fourier transform (sin(w/2)/(w/2))^2);
+# order 4: Phi = (4/3) B(t) - (1/6) (B(t - 1) + B(t + 1)) with B the cubic
+# B-spline on [-2, 2], whose transform is (sin(w/2)/(w/2))^4 (1 + (2/3) sin^2(w/2)):
+# it integrates to 1 and has vanishing second moment, so it changes smooth data
+# by O(h^4).  With h the grid spacing they act on a cell's scale.
+# ----------------------------------------------------------------------------
+_GL8 = np.polynomial.legendre.leggauss(8)
+
+
+def _cubic_bspline(t):
+    a = np.abs(t)
+    return np.where(a <= 1.0, (4.0 - 6.0 * a * a + 3.0 * a ** 3) / 6.0,
+                    np.where(a <= 2.0, (2.0 - a) ** 3 / 6.0, 0.0))
+
+
+def kreiss_kernel(t, order: int):
+    """The smoothing kernel Phi of the given order (2 or 4)."""
+    t = np.asarray(t, dtype=float)
+    if order == 2:
+        return np.maximum(1.0 - np.abs(t), 0.0)
+    if order == 4:
+        return 4.0 / 3.0 * _cubic_bspline(t) - (_cubic_bspline(t - 1.0) + _cubic_bspline(t + 1.0)) / 6.0
+    raise ValueError("order must be 2 or 4")
+
+
+def kreiss_smooth(v: Callable, x, h: float, order: int, kinks=()):
+    """(M_h v)(x) for a vectorised v that is smooth except at the points
+    ``kinks``: Gauss-Legendre (8 points) on every unit interval of the kernel's
+    support, split where x - h t crosses a kink, so every piece is smooth."""
+    x = np.asarray(x, dtype=float)
+    s = 1 if order == 2 else 3
+    gx, gw = _GL8
+    out = np.zeros_like(x)
+    for a in range(-s, s):
+        cuts = [np.full_like(x, float(a))]
+        for xk in kinks:
+            cuts.append(np.clip((x - xk) / h, a, a + 1.0))
+        cuts.append(np.full_like(x, a + 1.0))
+        cuts = np.sort(np.stack(cuts), axis=0)
+        for lo, hi in zip(cuts[:-1], cuts[1:]):
+            half, mid = 0.5 * (hi - lo), 0.5 * (hi + lo)
+            for xg, wg in zip(gx, gw):
+                t = mid + half * xg
+                out += wg * half * kreiss_kernel(t, order) * v(x - h * t)
+    return out
+
+
 def bs_call_1d(n_x: int = 16384, n_t: int = 256, k: int = 4, L: int = 32,
                half_width: float | None = 5.2, K: float = 100.0, S0: float = 100.0,
                r: float = 0.05, mu: float = 0.1, sigma: float = 0.2, T: float = 0.33,
-               delta: float = 0.0, smooth: bool = True) -> Workload:
+               delta: float = 0.0, smooth: bool = True, terminal: str | None = None) -> Workload:
     """Black-Scholes call as a linear BSDE on the log-price grid.
 
     f = -r y - ((mu - r + delta)/sigma) z (eq (29)-(30)), X = ln S (eq (33)).
     With ``smooth`` the terminal layer is the closed-form price with dt left
     to expiry, so the solved problem has maturity T + dt and a smooth terminal
     condition; the exact solution is the price at that maturity.
+    ``terminal`` overrides ``smooth``: "shift" (the same), "raw" (the payoff
+    and z = sigma S 1{S > K} at T), "kreiss2" or "kreiss4" (those smoothed by
+    the Kreiss-type operator of that order over one cell); for the last three
+    the exact solution is the price at maturity T and ``terminal_layer()``
+    gives the layer at t_N (the other K - 1 initial layers are then the
+    method's own, Section 3.1 step 2).
     ``half_width=None`` gives the interval [ln S0 - 6 sigma sqrt(T) - |mu - sigma^2/2| T,
     ln S0 + 6 sigma sqrt(T)]; a number gives ln S0 +- half_width.  The interval
     is shifted by less than one cell so that ln S0 is a grid node.
     """
+    if terminal is None:
+        terminal = "shift" if smooth else "raw"
+    if terminal not in ("shift", "raw", "kreiss2", "kreiss4"):
+        raise ValueError(f"unknown terminal condition {terminal}")
+    smooth = terminal == "shift"
     c = math.log(S0)
     if half_width is None:
         lo = c - 6 * sigma * math.sqrt(T) - abs(mu - 0.5 * sigma ** 2) * T
@@ -259,9 +322,31 @@ def bs_call_1d(n_x: int = 16384, n_t: int = 256, k: int = 4, L: int = 32,
             return np.maximum(np.exp(x) - K, 0.0), sigma * np.exp(x) * (x > math.log(K))
         return bs_call(tau, x, K, r, sigma, delta)
 
-    w = Workload(f"bs1d_nx{n_x}_nt{n_t}_k{k}_L{L}", pb, exact, math.log(S0))
-    w.extra.update(dict(K=K, S0=S0, r=r, mu=mu, sigma=sigma, delta=delta, tau_s=tau_s))
+    w = Workload(f"bs1d_nx{n_x}_nt{n_t}_k{k}_L{L}" + ("" if smooth else "_" + terminal), pb, exact,
+                 math.log(S0))
+    w.extra.update(dict(K=K, S0=S0, r=r, mu=mu, sigma=sigma, delta=delta, tau_s=tau_s,
+                        terminal=terminal))
     return w
+
+
+def terminal_layer(w: Workload):
+    """The layer at t_N of a Black-Scholes workload: (y, z) of shapes (n,)
+    and (1, n), smoothed as its ``terminal`` setting says."""
+    x = w.grid(0)
+    e = w.extra
+    mode = e.get("terminal", "shift")
+    if mode == "shift":
+        y, z = w.exact(w.problem["T"], x)
+        return y, z[None, :]
+    K, sigma = e["K"], e["sigma"]
+    pay = lambda u: np.maximum(np.exp(u) - K, 0.0)
+    dpay = lambda u: sigma * np.exp(u) * (u > math.log(K))
+    if mode == "raw":
+        return pay(x), dpay(x)[None, :]
+    order = int(mode[-1])
+    h = x[1] - x[0]
+    return (kreiss_smooth(pay, x, h, order, (math.log(K),)),
+            kreiss_smooth(dpay, x, h, order, (math.log(K),))[None, :])
 
 
 def bidask_call_1d(n_x: int = 262144, n_t: int = 1024, k: int = 4, L: int = 16,
