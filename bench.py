@@ -329,6 +329,31 @@ def run_2d(args, B, torch, np):
     steps_full = pb["n_t"] - wl.K + 1
     print(f"[bench] 2-D basket full solve: {full_s * 1e3:.1f} ms, status "
           f"{B.bsde_status_string(rc_f)}", file=sys.stderr, flush=True)
+    # the FP32 form (float ring with error feedback): kernel times of the same
+    # steps, whole solves, and the whole grid against the FP64 solve
+    y64, z64 = y0.cpu().numpy(), z0.cpu().numpy()
+    p32 = dict(pb, prec="fp32_comp")
+    plan32 = B.bsde_plan(p32)
+    ws32 = B.workspace(plan32, dev)
+    kt32 = B.bsde_profile_kernels(plan32, ws32, [(t_iy, t_iz, y0, z0)], stream=stream)
+    plan32f = B.bsde_plan(dict(p32, n_stop=0))
+    ws32f = B.workspace(plan32f, dev)
+    rc32, _ = B.bsde_solve(plan32f, ws32f, t_iy, t_iz, y0, z0, stream=stream, stats=False)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        B.bsde_solve(plan32f, ws32f, t_iy, t_iz, y0, z0, stream=stream, stats=False)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    full32 = e0.elapsed_time(e1) / reps * 1e-3
+    y32, z32 = y0.cpu().numpy(), z0.cpu().numpy()
+    err32 = float(max(np.max(np.abs(y32 - y64) / np.maximum(np.abs(y64), 1.0)),
+                      np.max(np.abs(z32 - z64) / np.maximum(np.abs(z64), 1.0))))
+    fp32 = {"sweep_kernel_us": 1e3 * kt32["sweep_ms"] / kt32["sweep_launches"],
+            "spline_us_per_layer": 1e3 * kt32["spline_ms"] / max(kt32["spline_launches"], 1),
+            "full_solve_s": full32, "speedup_vs_fp64": full_s / full32,
+            "max_rel_err_vs_fp64": err32, "status": B.bsde_status_string(rc32)}
+    print(f"[bench] 2-D basket FP32: {fp32}", file=sys.stderr, flush=True)
     return {"workload": wl.name, "points": npts, "steps_timed": steps, "dtype": "f64",
             "sweep_kernel_us": sweep_ms * 1e3, "spline_us_per_layer": spline_ms * 1e3,
             "value": npts / ((sweep_ms + spline_ms) * 1e-3), "unit": "grid-point*time-step/s",
@@ -342,7 +367,7 @@ def run_2d(args, B, torch, np):
                          / FP64_VALU_PEAK_TFLOPS},
             "full_solve_s": full_s, "full_solve_steps": steps_full,
             "full_solve_value": npts * steps_full / full_s,
-            "stability_ratio": st["stability_ratio"]}
+            "stability_ratio": st["stability_ratio"], "fp32_comp": fp32}
 
 
 def time_solves(B, torch, wl, prec="fp64", reps=5, autotune=True, extra=None):

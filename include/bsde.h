@@ -95,15 +95,20 @@ typedef enum {
 
 typedef enum {
     BSDE_FP64 = 0,      /* all arithmetic in double precision                   */
-    BSDE_FP32_COMP = 1  /* the ring of time layers and the node interpolation and
-                           driver evaluations in single precision; the terms
-                           that carry the size of the solution (the y-hat and
-                           z-hat expectations) summed in double precision, the
-                           small f-hat terms per layer in single precision and
-                           then added in double; spline solve, z combination
-                           and Picard in double precision.  Error against the
-                           FP64 form: a few 1e-7 relative (bid-ask call,
-                           262144 points, 1024 steps)                          */
+    BSDE_FP32_COMP = 1  /* d = 1: the ring of time layers and the node
+                           interpolation and driver evaluations in single
+                           precision; the terms that carry the size of the
+                           solution (the y-hat and z-hat expectations) summed
+                           in double precision, the small f-hat terms per
+                           layer in single precision and then added in double;
+                           spline solve, z combination and Picard in double
+                           precision.  d = 2: the ring in single precision,
+                           all arithmetic in double.  Both store each new
+                           value with the rounding residual of the layer it
+                           came from added (error feedback) and keep the new
+                           residual in the ring.  Error against the FP64
+                           form: 2.8e-7 relative over the whole grid (bid-ask
+                           call, 262144 points, 1024 steps)                    */
 } bsde_precision;
 
 /* One BSDE in one (d = 1) or two (d = 2, Section 5 Examples 4-5) space
@@ -203,8 +208,8 @@ typedef struct {
  * tables are copied to the current device.
  * Errors: BSDE_EINVAL for an invalid problem, batch < 1, or problems of
  * different d in one batch; BSDE_EUNSUPPORTED for a d = 2 problem with
- * vol[0][1] != 0, a driver other than BSDE_DRIVER_LINEAR, the FP32 form or
- * state-dependent coefficients,
+ * vol[0][1] != 0, a driver other than BSDE_DRIVER_LINEAR, the FP32 form
+ * with BSDE_ZFORM_YDW, exact expectations or state-dependent coefficients,
  * and for a d = 1 grid whose ring plane would reach 4 GiB (about 2.7e8 points
  * in FP64, 5.4e8 in FP32); BSDE_ENOMEM, BSDE_EDEVICE.  *out is set only on
  * success.

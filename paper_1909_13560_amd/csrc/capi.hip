@@ -97,6 +97,7 @@ struct Group {
 // A two-dimensional instance (tensor grid).
 struct Instance2 {
     bsde_problem pb;
+    bool f32 = false;  // FP32 form: float ring planes with residual planes
     int K, n0, n1, pad0, pad0r, pad1, pad1r, npad0, npad1;
     int win;  // LDS window columns of the sweep kernel
     size_t plane;
@@ -224,7 +225,11 @@ bool valid_problem(const bsde_problem &p)
 // correlation, written with its Cholesky factor), the linear driver, FP64.
 bool supported_2d(const bsde_problem &p)
 {
-    return p.vol[0][1] == 0.0 && p.driver == BSDE_DRIVER_LINEAR && p.prec == BSDE_FP64 &&
+    // the FP32 form stores the ring in single precision; with the E[y dW]/dt
+    // z form its rounding would enter z amplified by dW/dt (as in 1-D)
+    const bool prec_ok = p.prec == BSDE_FP64 ||
+                         (p.prec == BSDE_FP32_COMP && p.z_form == BSDE_ZFORM_EZ);
+    return p.vol[0][1] == 0.0 && p.driver == BSDE_DRIVER_LINEAR && prec_ok &&
            p.L <= 64 && p.drift_x == 0.0 && p.vol_x == 0.0 && p.quad == BSDE_QUAD_GH &&
            (p.interp == BSDE_INTERP_SPLINE || (p.n_x[0] >= 5 && p.n_x[1] >= 5));
 }
@@ -335,6 +340,7 @@ bool build_instance(const bsde_problem &p, Instance &in)
 bsde_status build_instance2(const bsde_problem &p, Instance2 &in)
 {
     in.pb = p;
+    in.f32 = p.prec == BSDE_FP32_COMP;
     in.K = std::max(p.k_y, p.k_z);
     in.n0 = p.n_x[0];
     in.n1 = p.n_x[1];
@@ -441,7 +447,7 @@ bsde_status build_instance2(const bsde_problem &p, Instance2 &in)
 bsde::Sweep2Args sweep2_args(const Instance2 &in, char *ws, bool stats)
 {
     bsde::Sweep2Args a{};
-    a.ring = reinterpret_cast<double *>(ws + in.ring_off);
+    a.ring = ws + in.ring_off;
     a.plane = in.plane;
     a.n0 = in.n0;
     a.n1 = in.n1;
@@ -754,15 +760,15 @@ bsde_status enqueue_solve2(const bsde_plan_s &pl, char *ws, const bsde_io *io, b
         // the derivative planes of a layer: tensor spline or finite differences
         auto interp_layer = [&](int slot) {
             return in.pb.interp == BSDE_INTERP_BICUBIC_FD
-                       ? bsde::launch_fd2d(a, slot, in.dx0, in.dx1, s)
-                       : bsde::launch_spline2d(a, slot, f, s);
+                       ? bsde::launch_fd2d(in.f32, a, slot, in.dx0, in.dx1, s)
+                       : bsde::launch_spline2d(in.f32, a, slot, f, s);
         };
-        HIP_OK(bsde::launch_scatter2d(a, io[b].init_y, io[b].init_z, s));
+        HIP_OK(bsde::launch_scatter2d(in.f32, a, io[b].init_y, io[b].init_z, s));
         for (int r = 0; r < K; ++r) HIP_OK(interp_layer((N - K + 1 + r) % (K + 1)));
         for (int n = N - K; n >= in.pb.n_stop; --n) {
             a.n = n;
             if (tm) HIP_OK(tm->mark(tm->sweep, s));
-            HIP_OK(bsde::launch_sweep2d(a, s));
+            HIP_OK(bsde::launch_sweep2d(in.f32, a, s));
             if (tm) HIP_OK(tm->mark(tm->sweep, s));
             if (n > in.pb.n_stop) {
                 if (tm) HIP_OK(tm->mark(tm->spline, s));
@@ -1030,11 +1036,14 @@ bsde_status plan_2d(const bsde_problem *pb, int batch, bsde_plan_t *out)
             static_cast<const bsde::Node2 *>(put(in.nodes.data(), in.nodes.size() * sizeof(bsde::Node2)));
         in.d_m1 = static_cast<const int *>(put(in.m1.data(), in.m1.size() * sizeof(int)));
     }
-    // workspace: rings (12 planes per layer), final layers, statistics
+    // workspace: rings (12 planes of doubles per layer, or 15 of floats in the
+    // FP32 form), final layers, statistics
     size_t off = 0;
     for (Instance2 &in : pl->inst2) {
         in.ring_off = off;
-        off += align_up((size_t)12 * (in.K + 1) * in.plane * sizeof(double), 256);
+        off += align_up((in.f32 ? (size_t)15 * sizeof(float) : (size_t)12 * sizeof(double)) *
+                            (in.K + 1) * in.plane,
+                        256);
     }
     for (Instance2 &in : pl->inst2) {
         in.fin_off = off;

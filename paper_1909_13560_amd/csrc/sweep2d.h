@@ -1,10 +1,13 @@
 // sweep2d.h -- data layout and launchers of the two-dimensional sweep
 // (arXiv:1909.13560, eq (20)-(21) on a tensor grid, Section 5 Examples 4-5).
 //
-// A time layer is 12 planes of padded n0 x n1 doubles: for each of y, z1, z2
+// A time layer is 12 planes of padded n0 x n1 elements: for each of y, z1, z2
 // the value v and the tensor natural-spline derivatives M_xx (along axis 0),
-// M_yy (along axis 1) and M_xxyy.  Plane p of slot s starts at
-// ring + (12 s + p) * plane; point (i0, i1) sits at
+// M_yy (along axis 1) and M_xxyy.  The elements are doubles, or floats in the
+// FP32 form, whose layers add three planes (12, 13, 14) of the rounding
+// residuals of y, z1 and z2 (error feedback, as in the 1-D form).  Plane p
+// of slot s starts at element (P s + p) * plane of the ring (P = 12 or 15);
+// point (i0, i1) sits at
 // (i0 + pad0) * npad1 + (i1 + pad1).  Ghost points outside the grid hold the
 // boundary data that makes the tensor spline evaluate at the clamped
 // coordinates: beyond an axis-0 edge {v, 0, M_yy, 0} of the edge row, beyond
@@ -92,7 +95,7 @@ __host__ __device__ constexpr SplineTaps spline_taps()
 }
 
 struct Sweep2Args {
-    double *ring;
+    char *ring;             // K+1 slots of kPlanes2<E> planes of E (double or float)
     size_t plane;
     int n0, n1, npad1, pad0, pad1;
     int K, Ky, L, n, n_stop;
@@ -111,15 +114,28 @@ struct Sweep2Args {
     unsigned long long *st_iter_sum, *st_nonconv;
 };
 
+// Planes of a ring slot and the typed address of plane p of slot `slot`.
+template <typename E>
+constexpr int kPlanes2 = std::is_same<E, float>::value ? 15 : 12;
+template <typename E>
+__host__ __device__ inline E *plane2(const Sweep2Args &a, int slot, int p)
+{
+    return reinterpret_cast<E *>(a.ring) + (size_t)(kPlanes2<E> * slot + p) * a.plane;
+}
+
+// The launchers take the element type of the ring planes: f32 = the FP32
+// form (float planes, residual planes), else double.
 size_t sweep2d_lds(int win);  // dynamic LDS of the sweep kernel
-hipError_t launch_sweep2d(const Sweep2Args &a, hipStream_t s);
+hipError_t launch_sweep2d(bool f32, const Sweep2Args &a, hipStream_t s);
 // splines and ghosts of the layer in slot `slot`
-hipError_t launch_spline2d(const Sweep2Args &a, int slot, const SplineFilter &f, hipStream_t s);
+hipError_t launch_spline2d(bool f32, const Sweep2Args &a, int slot, const SplineFilter &f,
+                           hipStream_t s);
 // the paper's bicubic interpolation: derivatives by fourth-order finite
 // differences (into the three derivative planes) and ghosts of slot `slot`
-hipError_t launch_fd2d(const Sweep2Args &a, int slot, double dx0, double dx1, hipStream_t s);
+hipError_t launch_fd2d(bool f32, const Sweep2Args &a, int slot, double dx0, double dx1,
+                       hipStream_t s);
 // layer r = 0..K-1 of init_y (K x n0 n1) and init_z (K x 2 x n0 n1) into the ring
-hipError_t launch_scatter2d(const Sweep2Args &a, const double *iy, const double *iz,
+hipError_t launch_scatter2d(bool f32, const Sweep2Args &a, const double *iy, const double *iz,
                             hipStream_t s);
 hipError_t launch_gather2d(const Sweep2Args &a, double *y0, double *z0,
                            unsigned long long *nonfinite, hipStream_t s);

@@ -130,8 +130,20 @@ __device__ inline void row_nodes_nf(int nf, const Sweep2Args &a, const double2 *
 
 }  // namespace
 
+// The FP32 form stores a value as fl(v + e) with e the residual carried from
+// the layer it was computed from, and keeps the new residual (as in 1-D).
+__device__ inline void store_fed_back2(float *val, float *res, size_t o, double v, float e)
+{
+    const double t = v + (double)e;
+    const float q = (float)t;
+    val[o] = q;
+    res[o] = (float)(t - (double)q);
+}
+
 // One time step: layer n from layers n+1..n+K.  Block = kTile2R x kTile2C points.
-// Dynamic LDS: (U, V) of 3 functions x kTile2R rows x a.win columns.
+// Dynamic LDS: (U, V) of 3 functions x kTile2R rows x a.win columns.  E: the
+// element type of the ring planes; the arithmetic is double in both forms.
+template <typename E>
 __global__ void __launch_bounds__(kThreads2) sweep2d(const Sweep2Args a)
 {
     extern __shared__ double2 uv[];
@@ -143,7 +155,7 @@ __global__ void __launch_bounds__(kThreads2) sweep2d(const Sweep2Args a)
     const int S = a.K + 1;
     double Y = 0.0, Z1 = 0.0, Z2 = 0.0;
     for (int j = 1; j <= a.K; ++j) {
-        const double *slot = a.ring + (size_t)(12 * ((a.n + j) % S)) * a.plane;
+        const E *slot = plane2<E>(a, (a.n + j) % S, 0);
         for (int l0 = 0; l0 < a.L; ++l0) {
             const int rowi = (j - 1) * a.L + l0;
             const Node2Row row = a.rows[rowi];
@@ -164,11 +176,13 @@ __global__ void __launch_bounds__(kThreads2) sweep2d(const Sweep2Args a)
                 const double B0 = in ? row.B0 : 0.0, C0 = in ? row.C0 : 0.0, D0 = in ? row.D0 : 0.0;
 #pragma unroll
                 for (int f = 0; f < 3; ++f) {
-                    const double *v = slot + (size_t)(4 * f) * a.plane;
-                    const double *mxx = v + a.plane, *myy = v + 2 * a.plane, *mxy = v + 3 * a.plane;
-                    const double U = fma(B0, v[o1] - v[o], fma(C0, mxx[o], fma(D0, mxx[o1], v[o])));
-                    const double V =
-                        fma(B0, myy[o1] - myy[o], fma(C0, mxy[o], fma(D0, mxy[o1], myy[o])));
+                    const E *v = slot + (size_t)(4 * f) * a.plane;
+                    const E *mxx = v + a.plane, *myy = v + 2 * a.plane, *mxy = v + 3 * a.plane;
+                    const double v0 = v[o], y0 = myy[o];
+                    const double U = fma(B0, (double)v[o1] - v0,
+                                         fma(C0, (double)mxx[o], fma(D0, (double)mxx[o1], v0)));
+                    const double V = fma(B0, (double)myy[o1] - y0,
+                                         fma(C0, (double)mxy[o], fma(D0, (double)mxy[o1], y0)));
                     uv[uv_index(a, f, rr, cc)] = make_double2(U, V);
                 }
             }
@@ -189,8 +203,8 @@ __global__ void __launch_bounds__(kThreads2) sweep2d(const Sweep2Args a)
     // implicit y equation by Picard iteration from y^{n+1}
     const int i0 = t0 + r, i1 = t1 + c;
     const bool valid = i0 < a.n0 && i1 < a.n1;
-    const double *prev = a.ring + (size_t)(12 * ((a.n + 1) % S)) * a.plane;
-    double *out = a.ring + (size_t)(12 * (a.n % S)) * a.plane;
+    const E *prev = plane2<E>(a, (a.n + 1) % S, 0);
+    E *out = plane2<E>(a, a.n % S, 0);
     const size_t o = pidx(a, min(i0, a.n0 - 1), min(i1, a.n1 - 1));
     double y = prev[o];
     int it = 0;
@@ -212,9 +226,19 @@ __global__ void __launch_bounds__(kThreads2) sweep2d(const Sweep2Args a)
     }
     unsigned int it_max = 0, it_sum = 0, nonconv = 0;
     if (valid) {
-        out[o] = y;
-        out[o + 4 * a.plane] = Z1;
-        out[o + 8 * a.plane] = Z2;
+        if constexpr (std::is_same<E, float>::value) {
+            // residuals of y^{n+K_y} (y recurrence) and of z^{n+1} (z recurrence)
+            const float *ry = plane2<float>(a, (a.n + a.Ky) % S, 12);
+            const float *rz = plane2<float>(a, (a.n + 1) % S, 13);
+            float *res = plane2<float>(a, a.n % S, 12);
+            store_fed_back2(out, res, o, y, ry[o]);
+            store_fed_back2(out + 4 * a.plane, res + a.plane, o, Z1, rz[o]);
+            store_fed_back2(out + 8 * a.plane, res + 2 * a.plane, o, Z2, rz[o + a.plane]);
+        } else {
+            out[o] = y;
+            out[o + 4 * a.plane] = Z1;
+            out[o + 8 * a.plane] = Z2;
+        }
         if (a.n == a.n_stop) {
             const size_t np = (size_t)a.n0 * a.n1, k = (size_t)i0 * a.n1 + i1;
             a.fin[k] = y;
@@ -245,7 +269,8 @@ __global__ void __launch_bounds__(kThreads2) sweep2d(const Sweep2Args a)
 namespace {
 
 // second difference of line values at k, oddly extended about 0 and n-1
-__device__ inline double rt_line(const double *v, long stride, int n, int k)
+template <typename E>
+__device__ inline double rt_line(const E *v, long stride, int n, int k)
 {
     const int per = 2 * (n - 1);
     int kk = k % per;
@@ -257,19 +282,20 @@ __device__ inline double rt_line(const double *v, long stride, int n, int k)
     }
     if (kk == 0 || kk == n - 1) return 0.0;
     const double vm = v[(long)(kk - 1) * stride], v0 = v[(long)kk * stride],
-                 vp = v[(long)(kk + 1) * stride];
+                 vp = v[(long)(kk + 1) * stride];  // the arithmetic is double
     return sign * ((vp - v0) - (v0 - vm));
 }
 
-__device__ inline double spline_line(const double *v, long stride, int n, int i,
+template <typename E>
+__device__ inline double spline_line(const E *v, long stride, int n, int i,
                                      const SplineFilter &F, double s6)
 {
     if (i == 0 || i == n - 1) return 0.0;
     double acc = 0.0;
     if (i >= 32 && i <= n - 33) {
-        const double *p = v + (long)(i - 32) * stride;
+        const E *p = v + (long)(i - 32) * stride;
 #pragma unroll
-        for (int k = 0; k < kPcrTaps + 2; ++k) acc = fma(F.d[k], p[(long)k * stride], acc);
+        for (int k = 0; k < kPcrTaps + 2; ++k) acc = fma(F.d[k], (double)p[(long)k * stride], acc);
     } else {
         for (int k = 0; k < kPcrTaps; ++k) acc = fma(F.c[k], rt_line(v, stride, n, i + k - 31), acc);
     }
@@ -285,8 +311,9 @@ constexpr int kRun = 16;  // consecutive outputs per thread of the line passes
 // v~_{-j} = 2 v_0 - v_j and v~_{n-1+j} = 2 v_{n-1} - v_{n-1-j}: their second
 // differences are then the odd extension the natural end conditions call
 // for, so the values form holds at every point; M_0 = M_{n-1} = 0.
-__device__ inline void line_run(const double *v, long stride, int n, int i0, double s6,
-                                double *out, long ostride)
+template <typename E>
+__device__ inline void line_run(const E *v, long stride, int n, int i0, double s6, E *out,
+                                long ostride)
 {
     constexpr SplineTaps T = spline_taps();
     constexpr int H = kPcrTaps / 2 + 1;  // values on each side of an output
@@ -294,7 +321,7 @@ __device__ inline void line_run(const double *v, long stride, int n, int i0, dou
 #pragma unroll
     for (int r = 0; r < kRun; ++r) acc[r] = 0.0;
     if (i0 >= H && i0 + kRun - 1 + H <= n - 1) {  // clear of both ends
-        const double *p = v + (long)(i0 - H) * stride;
+        const E *p = v + (long)(i0 - H) * stride;
 #pragma unroll
         for (int m = 0; m < kRun + 2 * H; ++m) {
             const double x = p[(long)m * stride];
@@ -303,7 +330,7 @@ __device__ inline void line_run(const double *v, long stride, int n, int i0, dou
                 if (m - r >= 0 && m - r <= 2 * H) acc[r] = fma(T.d[m - r], x, acc[r]);
         }
     } else {
-        const double v0 = v[0], vn = v[(long)(n - 1) * stride];
+        const double v0 = v[0], vn = v[(long)(n - 1) * stride];  // double arithmetic
 #pragma unroll
         for (int m = 0; m < kRun + 2 * H; ++m) {
             const int k = i0 - H + m;
@@ -320,16 +347,17 @@ __device__ inline void line_run(const double *v, long stride, int n, int i0, dou
 #pragma unroll
     for (int r = 0; r < kRun; ++r) {
         const int i = i0 + r;
-        if (i < n) out[(long)i * ostride] = (i == 0 || i == n - 1) ? 0.0 : s6 * acc[r];
+        if (i < n) out[(long)i * ostride] = (E)((i == 0 || i == n - 1) ? 0.0 : s6 * acc[r]);
     }
 }
 
 // The same outputs for lines shorter than kMinLine, one at a time.
-__device__ inline void line_run_short(const double *v, long stride, int n, int i0,
-                                      const SplineFilter &F, double s6, double *out, long ostride)
+template <typename E>
+__device__ inline void line_run_short(const E *v, long stride, int n, int i0,
+                                      const SplineFilter &F, double s6, E *out, long ostride)
 {
     for (int i = i0; i < min(i0 + kRun, n); ++i)
-        out[(long)i * ostride] = spline_line(v, stride, n, i, F, s6);
+        out[(long)i * ostride] = (E)spline_line(v, stride, n, i, F, s6);
 }
 
 }  // namespace
@@ -337,13 +365,14 @@ __device__ inline void line_run_short(const double *v, long stride, int n, int i
 // M_xx of field blockIdx.y (y, z1, z2): lines along axis 0.  Thread t:
 // column t % n1 (adjacent lanes read adjacent columns), rows from
 // kRun * (t / n1).
+template <typename E>
 __global__ void __launch_bounds__(256) spline2d_cols(const Sweep2Args a, int slot,
                                                      const SplineFilter F)
 {
     const long t = blockIdx.x * 256L + threadIdx.x;
     if (t >= (long)a.n1 * ((a.n0 + kRun - 1) / kRun)) return;
     const int i1 = (int)(t % a.n1), i0 = (int)(t / a.n1) * kRun;
-    double *col = a.ring + (size_t)(12 * slot + 4 * blockIdx.y) * a.plane + pidx(a, 0, i1);
+    E *col = plane2<E>(a, slot, 4 * blockIdx.y) + pidx(a, 0, i1);
     if (a.n0 >= kMinLine)
         line_run(col, a.npad1, a.n0, i0, F.s6[0], col + a.plane, a.npad1);
     else
@@ -353,6 +382,7 @@ __global__ void __launch_bounds__(256) spline2d_cols(const Sweep2Args a, int slo
 // Lines along axis 1 of field blockIdx.y / 2: the values give M_yy
 // (blockIdx.y even), M_xx gives M_xxyy (odd).  Thread t: row t % n0, columns
 // from kRun * (t / n0), so that a wavefront takes one branch of line_run.
+template <typename E>
 __global__ void __launch_bounds__(256) spline2d_rows(const Sweep2Args a, int slot,
                                                      const SplineFilter F)
 {
@@ -360,9 +390,9 @@ __global__ void __launch_bounds__(256) spline2d_rows(const Sweep2Args a, int slo
     if (t >= (long)a.n0 * ((a.n1 + kRun - 1) / kRun)) return;
     const int i0 = (int)(t % a.n0), i1 = (int)(t / a.n0) * kRun;
     const int f = blockIdx.y >> 1, g = blockIdx.y & 1;
-    double *row = a.ring + (size_t)(12 * slot + 4 * f) * a.plane + pidx(a, i0, 0);
-    const double *src = row + (size_t)g * a.plane;
-    double *dst = row + (size_t)(2 + g) * a.plane;
+    E *row = plane2<E>(a, slot, 4 * f) + pidx(a, i0, 0);
+    const E *src = row + (size_t)g * a.plane;
+    E *dst = row + (size_t)(2 + g) * a.plane;
     if (a.n1 >= kMinLine)
         line_run(src, 1, a.n1, i1, F.s6[1], dst, 1);
     else
@@ -379,6 +409,7 @@ constexpr int kRowCols = 256 / kRowTile * kRun;  // outputs per row per block
 constexpr int kRowIn = kRowCols + 2 * (kPcrTaps / 2 + 1);  // staged values per row
 constexpr int kRowStride = kRowIn + 1;          // LDS row pitch (odd: fewer bank conflicts)
 
+template <typename E>
 __global__ void __launch_bounds__(256) spline2d_rows_lds(const Sweep2Args a, int slot,
                                                          const SplineFilter F)
 {
@@ -389,18 +420,19 @@ __global__ void __launch_bounds__(256) spline2d_rows_lds(const Sweep2Args a, int
     const int r0 = (int)(blockIdx.x / tiles1) * kRowTile, c0 = (int)(blockIdx.x % tiles1) * kRowCols;
     const int f = blockIdx.y >> 1, g = blockIdx.y & 1;
     const int n = a.n1;
-    double *plane0 = a.ring + (size_t)(12 * slot + 4 * f) * a.plane;
-    const double *src = plane0 + (size_t)g * a.plane;
-    double *dst = plane0 + (size_t)(2 + g) * a.plane;
+    E *plane0 = plane2<E>(a, slot, 4 * f);
+    const E *src = plane0 + (size_t)g * a.plane;
+    E *dst = plane0 + (size_t)(2 + g) * a.plane;
     for (int e = threadIdx.x; e < kRowTile * kRowIn; e += 256) {
         const int rr = e / kRowIn, cc = e - rr * kRowIn;
         const int i0 = r0 + rr;
         if (i0 >= a.n0) continue;
-        const double *v = src + pidx(a, i0, 0);
+        const E *v = src + pidx(a, i0, 0);
         const int k = c0 - H + cc;
         const int kk = min(max(k < 0 ? -k : (k > n - 1 ? 2 * (n - 1) - k : k), 0), n - 1);
         const double y = v[kk];
-        sm[rr * kRowStride + cc] = k < 0 ? 2.0 * v[0] - y : (k > n - 1 ? 2.0 * v[n - 1] - y : y);
+        sm[rr * kRowStride + cc] =
+            k < 0 ? 2.0 * (double)v[0] - y : (k > n - 1 ? 2.0 * (double)v[n - 1] - y : y);
     }
     __syncthreads();
     const int r = threadIdx.x % kRowTile, q = threadIdx.x / kRowTile;
@@ -417,12 +449,12 @@ __global__ void __launch_bounds__(256) spline2d_rows_lds(const Sweep2Args a, int
         for (int u = 0; u < kRun; ++u)
             if (m - u >= 0 && m - u <= 2 * H) acc[u] = fma(T.d[m - u], x, acc[u]);
     }
-    double *out = dst + pidx(a, i0, 0);
+    E *out = dst + pidx(a, i0, 0);
     const double s6 = F.s6[1];
 #pragma unroll
     for (int u = 0; u < kRun; ++u) {
         const int i = j0 + u;
-        if (i < n) out[i] = (i == 0 || i == n - 1) ? 0.0 : s6 * acc[u];
+        if (i < n) out[i] = (E)((i == 0 || i == n - 1) ? 0.0 : s6 * acc[u]);
     }
 }
 
@@ -432,11 +464,12 @@ __global__ void __launch_bounds__(256) spline2d_rows_lds(const Sweep2Args a, int
 // each end).  They go into the planes of the tensor spline's second
 // derivatives: f_x in M_xx, f_y in M_yy, f_xy in M_xxyy; the sweep kernel is
 // the same, with the Hermite basis weights in the node tables.
-__device__ inline double fd4_at(const double *f, long st, int n, int i, double inv12h)
+template <typename E>
+__device__ inline double fd4_at(const E *f, long st, int n, int i, double inv12h)
 {
-    double v;
+    double v;  // double arithmetic on the (possibly float) values
     if (i >= 2 && i <= n - 3)
-        v = f[(i - 2) * st] - 8.0 * f[(i - 1) * st] + 8.0 * f[(i + 1) * st] - f[(i + 2) * st];
+        v = (double)f[(i - 2) * st] - 8.0 * f[(i - 1) * st] + 8.0 * f[(i + 1) * st] - f[(i + 2) * st];
     else if (i == 0)
         v = -25.0 * f[0] + 48.0 * f[st] - 36.0 * f[2 * st] + 16.0 * f[3 * st] - 3.0 * f[4 * st];
     else if (i == 1)
@@ -451,31 +484,34 @@ __device__ inline double fd4_at(const double *f, long st, int n, int i, double i
 }
 
 // f_x of field blockIdx.y along axis 0 (adjacent lanes on adjacent columns)
+template <typename E>
 __global__ void __launch_bounds__(256) fd2d_cols(const Sweep2Args a, int slot, double inv12h)
 {
     const long t = blockIdx.x * 256L + threadIdx.x;
     if (t >= (long)a.n0 * a.n1) return;
     const int i0 = (int)(t / a.n1), i1 = (int)(t % a.n1);
-    double *v = a.ring + (size_t)(12 * slot + 4 * blockIdx.y) * a.plane;
-    v[a.plane + pidx(a, i0, i1)] = fd4_at(v + pidx(a, 0, i1), a.npad1, a.n0, i0, inv12h);
+    E *v = plane2<E>(a, slot, 4 * blockIdx.y);
+    v[a.plane + pidx(a, i0, i1)] = (E)fd4_at(v + pidx(a, 0, i1), a.npad1, a.n0, i0, inv12h);
 }
 
 // Along axis 1 of field blockIdx.y / 2: f_y from the values (blockIdx.y
 // even), f_xy from f_x (odd)
+template <typename E>
 __global__ void __launch_bounds__(256) fd2d_rows(const Sweep2Args a, int slot, double inv12h)
 {
     const long t = blockIdx.x * 256L + threadIdx.x;
     if (t >= (long)a.n0 * a.n1) return;
     const int i0 = (int)(t / a.n1), i1 = (int)(t % a.n1);
     const int f = blockIdx.y >> 1, g = blockIdx.y & 1;
-    double *v = a.ring + (size_t)(12 * slot + 4 * f) * a.plane;
-    const double *src = v + (size_t)g * a.plane;
+    E *v = plane2<E>(a, slot, 4 * f);
+    const E *src = v + (size_t)g * a.plane;
     v[(size_t)(2 + g) * a.plane + pidx(a, i0, i1)] =
-        fd4_at(src + pidx(a, i0, 0), 1, a.n1, i1, inv12h);
+        (E)fd4_at(src + pidx(a, i0, 0), 1, a.n1, i1, inv12h);
 }
 
 // Ghost points: the data of the nearest grid point with the derivative
 // planes across the crossed edge set to zero (clamped evaluation).
+template <typename E>
 __global__ void __launch_bounds__(256) ghosts2d(const Sweep2Args a, int slot, int npad0)
 {
     const long i = blockIdx.x * 256L + threadIdx.x;
@@ -484,16 +520,17 @@ __global__ void __launch_bounds__(256) ghosts2d(const Sweep2Args a, int slot, in
     const bool in0 = g0 >= 0 && g0 < a.n0, in1 = g1 >= 0 && g1 < a.n1;
     if (in0 && in1) return;
     const size_t src = pidx(a, min(max(g0, 0), a.n0 - 1), min(max(g1, 0), a.n1 - 1));
-    double *base = a.ring + (size_t)(12 * slot) * a.plane;
+    E *base = plane2<E>(a, slot, 0);
     for (int f = 0; f < 3; ++f) {
-        double *v = base + (size_t)(4 * f) * a.plane;
+        E *v = base + (size_t)(4 * f) * a.plane;
         v[i] = v[src];
-        v[a.plane + i] = in0 ? v[a.plane + src] : 0.0;
-        v[2 * a.plane + i] = in1 ? v[2 * a.plane + src] : 0.0;
-        v[3 * a.plane + i] = 0.0;
+        v[a.plane + i] = in0 ? v[a.plane + src] : (E)0;
+        v[2 * a.plane + i] = in1 ? v[2 * a.plane + src] : (E)0;
+        v[3 * a.plane + i] = (E)0;
     }
 }
 
+template <typename E>
 __global__ void __launch_bounds__(256) scatter2d(const Sweep2Args a, const double *__restrict__ iy,
                                                  const double *__restrict__ iz)
 {
@@ -502,11 +539,16 @@ __global__ void __launch_bounds__(256) scatter2d(const Sweep2Args a, const doubl
     const int r = blockIdx.y;
     if (i >= np) return;
     const int n = a.n + 1 + r;  // a.n = N - K: layers N-K+1 .. N
-    double *base = a.ring + (size_t)(12 * (n % (a.K + 1))) * a.plane;
+    E *base = plane2<E>(a, n % (a.K + 1), 0);
     const size_t o = pidx(a, (int)(i / a.n1), (int)(i % a.n1));
-    base[o] = iy[r * np + i];
-    base[4 * a.plane + o] = iz[(2L * r) * np + i];
-    base[8 * a.plane + o] = iz[(2L * r + 1) * np + i];
+    const double v[3] = {iy[r * np + i], iz[(2L * r) * np + i], iz[(2L * r + 1) * np + i]};
+    for (int f = 0; f < 3; ++f) {
+        if constexpr (std::is_same<E, float>::value) {  // value and its rounding residual
+            store_fed_back2(base + 4 * f * a.plane, base + (12 + f) * a.plane, o, v[f], 0.0f);
+        } else {
+            base[4 * f * a.plane + o] = v[f];
+        }
+    }
 }
 
 __global__ void __launch_bounds__(256) gather2d(const Sweep2Args a, double *__restrict__ y0,
@@ -531,58 +573,95 @@ __global__ void __launch_bounds__(256) gather2d(const Sweep2Args a, double *__re
 // ---------------------------------------------------------------------------
 size_t sweep2d_lds(int win) { return (size_t)3 * kTile2R * win * sizeof(double2); }
 
-hipError_t launch_sweep2d(const Sweep2Args &a, hipStream_t s)
+namespace {
+
+template <typename E>
+hipError_t launch_sweep2d_t(const Sweep2Args &a, hipStream_t s)
 {
     const int tiles = ((a.n0 + kTile2R - 1) / kTile2R) * ((a.n1 + kTile2C - 1) / kTile2C);
-    hipLaunchKernelGGL(sweep2d, dim3(tiles), dim3(kThreads2), sweep2d_lds(a.win), s, a);
+    hipLaunchKernelGGL(sweep2d<E>, dim3(tiles), dim3(kThreads2), sweep2d_lds(a.win), s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_spline2d(const Sweep2Args &a, int slot, const SplineFilter &f, hipStream_t s)
+template <typename E>
+hipError_t launch_ghosts2d_t(const Sweep2Args &a, int slot, hipStream_t s)
+{
+    const int npad0 = (int)(a.plane / a.npad1);
+    const int gb = (int)(((long)npad0 * a.npad1 + 255) / 256);
+    hipLaunchKernelGGL(ghosts2d<E>, dim3(gb), dim3(256), 0, s, a, slot, npad0);
+    return hipGetLastError();
+}
+
+template <typename E>
+hipError_t launch_spline2d_t(const Sweep2Args &a, int slot, const SplineFilter &f, hipStream_t s)
 {
     const long tc = (long)a.n1 * ((a.n0 + kRun - 1) / kRun);
-    hipLaunchKernelGGL(spline2d_cols, dim3((unsigned)((tc + 255) / 256), 3), dim3(256), 0, s, a,
+    hipLaunchKernelGGL(spline2d_cols<E>, dim3((unsigned)((tc + 255) / 256), 3), dim3(256), 0, s, a,
                        slot, f);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (a.n1 >= kMinLine) {
         const long tiles = (long)((a.n0 + kRowTile - 1) / kRowTile) * ((a.n1 + kRowCols - 1) / kRowCols);
-        hipLaunchKernelGGL(spline2d_rows_lds, dim3((unsigned)tiles, 6), dim3(256), 0, s, a, slot, f);
+        hipLaunchKernelGGL(spline2d_rows_lds<E>, dim3((unsigned)tiles, 6), dim3(256), 0, s, a, slot,
+                           f);
     } else {
         const long tr = (long)a.n0 * ((a.n1 + kRun - 1) / kRun);
-        hipLaunchKernelGGL(spline2d_rows, dim3((unsigned)((tr + 255) / 256), 6), dim3(256), 0, s, a,
-                           slot, f);
+        hipLaunchKernelGGL(spline2d_rows<E>, dim3((unsigned)((tr + 255) / 256), 6), dim3(256), 0, s,
+                           a, slot, f);
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int npad0 = (int)(a.plane / a.npad1);
-    const int gb = (int)(((long)npad0 * a.npad1 + 255) / 256);
-    hipLaunchKernelGGL(ghosts2d, dim3(gb), dim3(256), 0, s, a, slot, npad0);
-    return hipGetLastError();
+    return launch_ghosts2d_t<E>(a, slot, s);
 }
 
-hipError_t launch_fd2d(const Sweep2Args &a, int slot, double dx0, double dx1, hipStream_t s)
+template <typename E>
+hipError_t launch_fd2d_t(const Sweep2Args &a, int slot, double dx0, double dx1, hipStream_t s)
 {
     const long np = (long)a.n0 * a.n1;
     const unsigned nb = (unsigned)((np + 255) / 256);
-    hipLaunchKernelGGL(fd2d_cols, dim3(nb, 3), dim3(256), 0, s, a, slot, 1.0 / (12.0 * dx0));
+    hipLaunchKernelGGL(fd2d_cols<E>, dim3(nb, 3), dim3(256), 0, s, a, slot, 1.0 / (12.0 * dx0));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(fd2d_rows, dim3(nb, 6), dim3(256), 0, s, a, slot, 1.0 / (12.0 * dx1));
+    hipLaunchKernelGGL(fd2d_rows<E>, dim3(nb, 6), dim3(256), 0, s, a, slot, 1.0 / (12.0 * dx1));
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int npad0 = (int)(a.plane / a.npad1);
-    const int gb = (int)(((long)npad0 * a.npad1 + 255) / 256);
-    hipLaunchKernelGGL(ghosts2d, dim3(gb), dim3(256), 0, s, a, slot, npad0);
+    return launch_ghosts2d_t<E>(a, slot, s);
+}
+
+template <typename E>
+hipError_t launch_scatter2d_t(const Sweep2Args &a, const double *iy, const double *iz,
+                              hipStream_t s)
+{
+    const long np = (long)a.n0 * a.n1;
+    hipLaunchKernelGGL(scatter2d<E>, dim3((unsigned)((np + 255) / 256), a.K), dim3(256), 0, s, a,
+                       iy, iz);
     return hipGetLastError();
 }
 
-hipError_t launch_scatter2d(const Sweep2Args &a, const double *iy, const double *iz, hipStream_t s)
+}  // namespace
+
+hipError_t launch_sweep2d(bool f32, const Sweep2Args &a, hipStream_t s)
 {
-    const long np = (long)a.n0 * a.n1;
-    hipLaunchKernelGGL(scatter2d, dim3((unsigned)((np + 255) / 256), a.K), dim3(256), 0, s, a, iy,
-                       iz);
-    return hipGetLastError();
+    return f32 ? launch_sweep2d_t<float>(a, s) : launch_sweep2d_t<double>(a, s);
+}
+
+hipError_t launch_spline2d(bool f32, const Sweep2Args &a, int slot, const SplineFilter &f,
+                           hipStream_t s)
+{
+    return f32 ? launch_spline2d_t<float>(a, slot, f, s) : launch_spline2d_t<double>(a, slot, f, s);
+}
+
+hipError_t launch_fd2d(bool f32, const Sweep2Args &a, int slot, double dx0, double dx1,
+                       hipStream_t s)
+{
+    return f32 ? launch_fd2d_t<float>(a, slot, dx0, dx1, s)
+               : launch_fd2d_t<double>(a, slot, dx0, dx1, s);
+}
+
+hipError_t launch_scatter2d(bool f32, const Sweep2Args &a, const double *iy, const double *iz,
+                            hipStream_t s)
+{
+    return f32 ? launch_scatter2d_t<float>(a, iy, iz, s) : launch_scatter2d_t<double>(a, iy, iz, s);
 }
 
 hipError_t launch_gather2d(const Sweep2Args &a, double *y0, double *z0,

@@ -104,7 +104,7 @@ def test_plan_rejects_empty_batch():
     assert B.load().bsde_plan(None, 1, ctypes.byref(h)) == B.BSDE_EINVAL
 
 
-@pytest.mark.parametrize("change", ["vol01", "driver", "fp32"])
+@pytest.mark.parametrize("change", ["vol01", "driver", "fp32_ydw", "exact"])
 def test_plan_2d_reports_unsupported_variants(change):
     # valid two-dimensional problems outside the implemented path are refused
     # before any device call
@@ -113,8 +113,10 @@ def test_plan_2d_reports_unsupported_variants(change):
         pb["vol"] = [[0.25, 0.05], [0.0, 0.3]]
     elif change == "driver":
         pb["driver"] = "cubic"
+    elif change == "fp32_ydw":
+        pb.update(prec="fp32_comp", z_form="yW", k_y=1, k_z=1)
     else:
-        pb["prec"] = "fp32_comp"
+        pb["quad"] = "exact"
     with pytest.raises(B.BsdeError) as e:
         B.bsde_plan(pb)
     assert e.value.code == B.BSDE_EUNSUPPORTED

@@ -373,3 +373,74 @@ def test_bicubic_fd_two_dimensional(lib, orc):
     wl.x0 = (pb["x_min"][0], pb["x_min"][1])
     _run(lib, orc, wl)
     y, z = _run(lib, orc, W.sine_2d(n_x=65, n_t=16, k=1, L=8))  # the spline beside it
+
+
+# ----------------------------------------------------------------------------
+# The FP32 form in 2-D: float ring planes with error feedback, FP64 arithmetic
+# ----------------------------------------------------------------------------
+
+
+def _fp32_2d_cases():
+    cases = [W.sine_2d(n_x=129, n_t=8, k=3, L=8), W.exchange_2d(n_x=97, n_t=10, k=3, L=8, rho=0.5)]
+    wl = W.exchange_2d(n_x=77, n_t=9, k=2, L=7, rho=0.3)  # ragged, unequal orders
+    pb = wl.problem
+    pb["n_x"] = [77, 130]
+    pb["x_max"] = [pb["x_max"][0], pb["x_min"][1] + 129 * (pb["x_max"][1] - pb["x_min"][1]) / 76]
+    pb["k_y"], pb["k_z"] = 3, 2
+    cases.append(wl)
+    wl = W.exchange_2d(n_x=21, n_t=12, k=2, L=6, rho=0.4)  # short columns, two tiles per row
+    pb = wl.problem
+    dx1 = (pb["x_max"][0] - pb["x_min"][0]) / 20 / 8
+    pb["n_x"] = [21, 700]
+    pb["x_max"] = [pb["x_max"][0], pb["x_min"][1] + 699 * dx1]
+    cases.append(wl)
+    wl = W.exchange_2d(n_x=77, n_t=9, k=3, L=7, rho=0.4)  # the paper's bicubic
+    wl.problem["interp"] = "bicubic_fd"
+    cases.append(wl)
+    return cases
+
+
+def test_fp32_two_dimensional(lib, orc):
+    from test_gpu_parity import TOL32
+
+    for wl in _fp32_2d_cases():
+        y, z = _run(lib, orc, wl, prec="fp32_comp", tol=TOL32)
+        assert np.all(np.isfinite(y)) and np.all(np.isfinite(z))
+    # a checkpoint of the basket (raw payoff layers)
+    wl = W.basket_2d(n_x=65, n_t=12, k=3, L=16)
+    wl.problem["n_stop"] = 4
+    _run(lib, orc, wl, prec="fp32_comp", tol=TOL32)
+    # the E[y dW]/dt z form stays refused in the FP32 form
+    wl = W.exchange_2d(n_x=33, n_t=6, k=1, L=6, rho=0.2)
+    with pytest.raises(lib.BsdeError) as ei:
+        lib.bsde_plan(dict(wl.problem, prec="fp32_comp", z_form="yW"))
+    assert ei.value.code == lib.BSDE_EUNSUPPORTED
+
+
+def test_fp32_two_dimensional_full_size(lib, orc):
+    # the benchmarked 2-D shape (1024 x 1024, 128 steps, k = 3, 16 x 16 nodes):
+    # the first layer against the oracle at sampled points, and the whole
+    # solve against the FP64 form over the whole grid
+    from test_gpu_parity import TOL32
+
+    wl = W.basket_2d()
+    pb = dict(wl.problem)
+    K = max(pb["k_y"], pb["k_z"])
+    n0, n1 = pb["n_x"]
+    iy, iz = wl.init_layers()
+    print(f"[case] {wl.name} fp32 first step sampled, whole solve", flush=True)
+    y, z, rc, _ = lib.solve(dict(pb, prec="fp32_comp", n_stop=pb["n_t"] - K), iy, iz)
+    assert rc == lib.BSDE_OK
+    rng = np.random.default_rng(2909)
+    rows = np.concatenate([[0, 1, 2, n0 // 2, n0 - 2, n0 - 1], rng.integers(0, n0, 300)])
+    cols = np.resize(np.concatenate([[0, 1, 511, 512, n1 - 2, n1 - 1], rng.integers(0, n1, 300)]),
+                     rows.size)
+    idx = np.unique(rows.astype(np.int64) * n1 + cols)
+    ys, zs = orc.first_step_points_2d(dict(pb, n_stop=pb["n_t"] - K), iy, iz, idx)
+    e1 = max(rel_err(y[idx], ys), rel_err(z[0, idx], zs[0]), rel_err(z[1, idx], zs[1]))
+    y32, z32, rc32, _ = lib.solve(dict(pb, prec="fp32_comp"), iy, iz)
+    y64, z64, rc64, _ = lib.solve(dict(pb, prec="fp64"), iy, iz)
+    assert rc32 == lib.BSDE_OK and rc64 == lib.BSDE_OK
+    e2 = max(rel_err(y32, y64), rel_err(z32[0], z64[0]), rel_err(z32[1], z64[1]))
+    print(f"  first step vs oracle {e1:.3e}, whole solve vs FP64 {e2:.3e}", flush=True)
+    assert e1 <= TOL32 and e2 <= TOL32
