@@ -136,6 +136,20 @@ __host__ __device__ constexpr size_t window_lds_bytes(int P)
 // Dynamic LDS: the window arrays, the four PCR arrays (pcr_values(P)
 // doubles each) and the node offsets (K*L int).
 // ---------------------------------------------------------------------------
+// Wave priority of a node loop with `left` more node loops to go in this
+// block: a block that is behind gets the higher priority (up to 3), so the
+// blocks sharing a CU, which start together, also end close together (the
+// launch ends with its last block).
+__device__ inline void node_loop_priority(int left)
+{
+    switch (left) {
+    case 0: __builtin_amdgcn_s_setprio(0); break;
+    case 1: __builtin_amdgcn_s_setprio(1); break;
+    case 2: __builtin_amdgcn_s_setprio(2); break;
+    default: __builtin_amdgcn_s_setprio(3); break;
+    }
+}
+
 template <int P, int G, int DRV, bool F32>
 __device__ inline void fused_tile(const SweepArgs &a, int tile, char *smem)
 {
@@ -189,11 +203,12 @@ __device__ inline void fused_tile(const SweepArgs &a, int tile, char *smem)
         }
     };
     const int rot = ((tile >> 5) & 3) % a.K;
-    // Issue priority: the node loops (throughput work) run at the lowest
-    // wave priority, everything else (staging waits, the spline's barriers,
-    // Picard) at the highest, so a block's latency-bound phases go ahead of
-    // the node loops of the blocks sharing its CU instead of queueing behind
-    // them.
+    // Issue priority: everything but the node loops (staging waits, the
+    // spline's barriers, Picard) runs at the highest wave priority, so a
+    // block's latency-bound phases go ahead of the node loops of the blocks
+    // sharing its CU instead of queueing behind them; the node loops
+    // (throughput work) run lower, the lower the further the block has got
+    // (node_loop_priority).
     __builtin_amdgcn_s_setprio(3);
     auto layer_at = [&](int jj) {  // the jj-th layer of this tile's order
         const int q = (jj + rot) % a.K;
@@ -260,7 +275,7 @@ __device__ inline void fused_tile(const SweepArgs &a, int tile, char *smem)
         }
         const LdsWindow<P, F32> src{wbase, kHalo - mlo,
                                     WinLayout<P>::kPad ? lane_pt + lane_pt / P : lane_pt};
-        __builtin_amdgcn_s_setprio(0);
+        node_loop_priority(a.K - 1 - jj);
         layer_dispatch<P, DRV, F32, false>(src, tm, j, grp, G, a, acc);
         __builtin_amdgcn_s_setprio(3);
         __syncthreads();  // the window is reused by the next layer
