@@ -147,6 +147,19 @@ typedef struct {
     int z_form;         /* bsde_z_form                                           */
     int quad;           /* bsde_quad                                             */
     int interp;         /* bsde_interp                                           */
+    const double *coef_tab; /* d = 1, optional: forward coefficients of eq (1)
+                           of any form, tabulated on the grid (host memory,
+                           copied by bsde_plan, read nowhere else):
+                           2 * tab_steps * n_x[0] doubles, row s holding
+                           a(t, x_i) at [2 s n_x + i] and b(t, x_i) > 0 at
+                           [(2 s + 1) n_x + i].  The node of layer n+j from
+                           x_i is the Euler step x_i + a j dt + b sqrt(2 j dt)
+                           a_l with the row s = n (tab_steps = n_t: a and b
+                           at t_n) or s = 0 (tab_steps = 1: time-homogeneous).
+                           drift[0], vol[0][0], drift_x and vol_x are then
+                           not used (the slopes must be 0).  NULL with
+                           tab_steps = 0: the coefficients above.            */
+    int tab_steps;      /* 0, 1 or n_t                                           */
 } bsde_problem;
 
 /* Largest stability ratio R = vol sqrt(2 dt) / dx (Gauss-Hermite spread of

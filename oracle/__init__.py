@@ -64,6 +64,8 @@ class _Problem(ctypes.Structure):
         ("z_form", ctypes.c_int),
         ("quad", ctypes.c_int),
         ("interp2", ctypes.c_int),
+        ("coef_tab", ctypes.POINTER(ctypes.c_double)),
+        ("tab_steps", ctypes.c_int),
     ]
 
 
@@ -141,6 +143,14 @@ def _to_struct(pb: dict, n_stop: int) -> _Problem:
     s.z_form = {"eq20": 0, "yW": 1}[pb.get("z_form", "eq20")]
     s.quad = {"gh": 0, "exact": 1}[pb.get("quad", "gh")]
     s.interp2 = {"spline": 0, "bicubic_fd": 1}[pb.get("interp", "spline")]
+    tab = pb.get("coef_tab")
+    if tab is not None:  # (tab_steps, 2, n_x), kept alive by the struct
+        t = np.ascontiguousarray(tab, dtype=np.float64)
+        if t.ndim != 3 or t.shape[1] != 2:
+            raise ValueError("coef_tab must have shape (tab_steps, 2, n_x)")
+        s.coef_tab = t.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        s.tab_steps = int(t.shape[0])
+        s._keep = t
     return s
 
 

@@ -28,8 +28,11 @@
  *     second-derivative form (d = 2: the tensor-product natural spline);
  *   - the forward process is X_{t+h} = X_t + drift*h + vol*(W_{t+h} - W_t)
  *     with constant drift and vol (X = W is drift 0, vol 1; the log-price of
- *     eq (33) is drift mu - sigma^2/2, vol sigma); the z equation uses the
- *     Brownian increment dW, as in eq (12)-(13);
+ *     eq (33) is drift mu - sigma^2/2, vol sigma); with coefficients that
+ *     depend on the state (affine, or tabulated on the grid and per step) it
+ *     is one Euler step X = x + a(t_n, x) j dt + b(t_n, x) dW over j dt from
+ *     (t_n, x_i), eq (1); the z equation uses the Brownian increment dW, as in
+ *     eq (12)-(13);
  *   - the driver is evaluated as f(t_{n+j}, X_node, y_hat, z_hat) inside the
  *     expectations and as f(t_n, x_i, y, z^n_i) in the implicit term;
  *   - Picard starts from y^{n+1}_i and stops after picard_max iterations, or
@@ -353,8 +356,21 @@ static int validate(const oracle_problem *pb)
     if (pb->interp2 != 0 && pb->interp2 != 1) return ORACLE_EINVAL;
     if (pb->interp2 == 1 && (pb->d != 2 || pb->n_x[0] < 5 || pb->n_x[1] < 5)) return ORACLE_EINVAL;
     if (pb->quad == 1 && (pb->d != 1 || pb->driver != ORACLE_DRIVER_LINEAR ||
-                          pb->drift_x != 0.0 || pb->vol_x != 0.0))
+                          pb->drift_x != 0.0 || pb->vol_x != 0.0 || pb->tab_steps != 0))
         return ORACLE_EINVAL;
+    if (pb->tab_steps != 0) { /* tabulated coefficients */
+        if (pb->d != 1 || !pb->coef_tab || (pb->tab_steps != 1 && pb->tab_steps != pb->n_t))
+            return ORACLE_EINVAL;
+        if (pb->drift_x != 0.0 || pb->vol_x != 0.0) return ORACLE_EINVAL;
+        const long nx = pb->n_x[0];
+        for (long k = 0; k < 2L * pb->tab_steps * nx; ++k)
+            if (!isfinite(pb->coef_tab[k])) return ORACLE_EINVAL;
+        for (int r = 0; r < pb->tab_steps; ++r)
+            for (long i = 0; i < nx; ++i)
+                if (!(pb->coef_tab[(2L * r + 1) * nx + i] > 0.0)) return ORACLE_EINVAL;
+    } else if (pb->coef_tab) {
+        return ORACLE_EINVAL;
+    }
     return ORACLE_OK;
 }
 
@@ -419,6 +435,13 @@ static int solve1(const oracle_problem *pb, const double *init_y, const double *
 #endif
         for (int i = 0; i < nx; ++i) {
             const double xi = xmin + i * dx;
+            /* eq (1)'s coefficients at (t_n, x_i): affine, or from the table */
+            double ai = drift + drift_x * xi, bi = vol + vol_x * xi;
+            if (pb->tab_steps > 0) {
+                const double *row = pb->coef_tab + 2L * (pb->tab_steps > 1 ? n : 0) * nx;
+                ai = row[i];
+                bi = row[nx + i];
+            }
             double Ef[7] = {0}, EfW[7] = {0}, Ez[7] = {0}, EyK = 0.0, EyW1 = 0.0;
             for (int j = 1; j <= K; ++j) {
                 layer1 lj = SLOT(n + j);
@@ -439,7 +462,7 @@ static int solve1(const oracle_problem *pb, const double *init_y, const double *
                 }
                 for (int l = 0; l < L; ++l) {
                     const double dW = sq * a[l];
-                    const double X = xi + (drift + drift_x * xi) * j * dt + (vol + vol_x * xi) * dW;
+                    const double X = xi + ai * j * dt + bi * dW;
                     int p;
                     double th;
                     double yh, zh;
@@ -857,6 +880,10 @@ int oracle_initial_layers(const oracle_problem *pb, int sub, double *init_y, dou
         q.T = n_hi * dt;
         q.n_t = n_hi * sub;
         q.n_stop = (n_hi - 1) * sub;
+        if (pb->tab_steps > 1) { /* per-step table: the row of t_{N-r} over the segment */
+            q.tab_steps = 1;
+            q.coef_tab = pb->coef_tab + 2L * (pb->n_t - r) * pb->n_x[0];
+        }
         const double *iy = init_y + (size_t)(K - r) * np;
         const double *iz = init_z + (size_t)(K - r) * np * pb->d;
         double *oy = init_y + (size_t)(K - 1 - r) * np;

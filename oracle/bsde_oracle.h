@@ -53,6 +53,13 @@ typedef struct {
     int interp2;        /* d = 2 interpolation: 0 = tensor natural spline; 1 =       */
                         /* bicubic from values, first and mixed derivatives by      */
                         /* fourth-order finite differences (Section 3.3)            */
+    const double *coef_tab; /* d = 1, optional: a(t, x_i) and b(t, x_i) tabulated  */
+                        /* on the grid, 2 * tab_steps * n_x[0] doubles; row s has  */
+                        /* a at [2 s n_x + i], b > 0 at [(2 s + 1) n_x + i]; the   */
+                        /* Euler step from t_n uses row n (tab_steps = n_t) or    */
+                        /* row 0 (tab_steps = 1); drift[0], vol[0][0] unused and  */
+                        /* drift_x = vol_x = 0.  NULL with tab_steps = 0.          */
+    int tab_steps;
 } oracle_problem;
 
 typedef struct {

@@ -66,6 +66,8 @@ class _Problem(ctypes.Structure):
         ("z_form", ctypes.c_int),
         ("quad", ctypes.c_int),
         ("interp", ctypes.c_int),
+        ("coef_tab", ctypes.POINTER(ctypes.c_double)),
+        ("tab_steps", ctypes.c_int),
     ]
 
 
@@ -182,6 +184,16 @@ def problem_struct(pb: dict) -> _Problem:
     s.z_form = Z_FORMS[pb.get("z_form", "eq20")]
     s.quad = QUADS[pb.get("quad", "gh")]
     s.interp = INTERPS[pb.get("interp", "spline")]
+    tab = pb.get("coef_tab")
+    if tab is not None:
+        # (tab_steps, 2, n_x): rows of a(t, x_i) and b(t, x_i); the struct keeps
+        # the array alive while the call that reads it runs
+        t = np.ascontiguousarray(tab, dtype=np.float64)
+        if t.ndim != 3 or t.shape[1] != 2:
+            raise ValueError("coef_tab must have shape (tab_steps, 2, n_x)")
+        s.coef_tab = t.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        s.tab_steps = int(t.shape[0])
+        s._keep = t
     return s
 
 
@@ -213,9 +225,11 @@ def bsde_plan(problems) -> Plan:
     """bsde_plan(pb, batch, &out) for a problem dict or a list of them."""
     if isinstance(problems, dict):
         problems = [problems]
-    arr = (_Problem * len(problems))(*[problem_struct(p) for p in problems])
+    structs = [problem_struct(p) for p in problems]  # they keep any coefficient tables alive
+    arr = (_Problem * len(problems))(*structs)
     h = ctypes.c_void_p()
     rc = load().bsde_plan(arr, len(problems), ctypes.byref(h))
+    del structs
     if rc != BSDE_OK:
         raise BsdeError(rc, "bsde_plan")
     return Plan(h.value, list(problems))

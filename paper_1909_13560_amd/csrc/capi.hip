@@ -54,6 +54,8 @@ struct Instance {
     bool f32;
     bool gather;  // state-dependent forward coefficients: nodes located per point
     bool exact;   // exact Gaussian expectations (banded Toeplitz operators)
+    std::vector<double> ctab;          // tabulated forward coefficients (host copy)
+    const double *d_ctab = nullptr;    // and on the device
     bsde::GaussBand band[bsde::kMaxOrder + 1];  // per layer j (exact)
     int toep_off[bsde::kMaxOrder + 1] = {};       // band j in the device table
     const double *toep_w = nullptr;
@@ -195,11 +197,26 @@ bool valid_problem(const bsde_problem &p)
     if (p.L < 1 || p.L > bsde::kMaxL) return false;
     if (p.n_x[0] < 4 || !(p.x_max[0] > p.x_min[0])) return false;
     if (!std::isfinite(p.x_min[0]) || !std::isfinite(p.x_max[0])) return false;
-    if (!std::isfinite(p.drift[0]) || !std::isfinite(p.vol[0][0])) return false;
-    if (!std::isfinite(p.drift_x) || !std::isfinite(p.vol_x)) return false;
-    // the diffusion coefficient b(x) = vol + vol_x x must be positive over the grid
-    if (!(p.vol[0][0] + p.vol_x * p.x_min[0] > 0.0) || !(p.vol[0][0] + p.vol_x * p.x_max[0] > 0.0))
-        return false;
+    if (p.tab_steps == 0) {
+        if (p.coef_tab) return false;
+        if (!std::isfinite(p.drift[0]) || !std::isfinite(p.vol[0][0])) return false;
+        if (!std::isfinite(p.drift_x) || !std::isfinite(p.vol_x)) return false;
+        // the diffusion coefficient b(x) = vol + vol_x x must be positive over the grid
+        if (!(p.vol[0][0] + p.vol_x * p.x_min[0] > 0.0) ||
+            !(p.vol[0][0] + p.vol_x * p.x_max[0] > 0.0))
+            return false;
+    } else {
+        // tabulated coefficients: d = 1, one row or one per step, a finite,
+        // b finite and positive, the affine slopes unused (0)
+        if (p.d != 1 || !p.coef_tab || (p.tab_steps != 1 && p.tab_steps != p.n_t)) return false;
+        if (p.drift_x != 0.0 || p.vol_x != 0.0) return false;
+        const size_t nx = (size_t)p.n_x[0];
+        for (int r = 0; r < p.tab_steps; ++r) {
+            const double *ta = p.coef_tab + (size_t)2 * r * nx, *tb = ta + nx;
+            for (size_t i = 0; i < nx; ++i)
+                if (!std::isfinite(ta[i]) || !std::isfinite(tb[i]) || !(tb[i] > 0.0)) return false;
+        }
+    }
     if (p.driver < BSDE_DRIVER_LINEAR || p.driver > BSDE_DRIVER_EXP) return false;
     if (p.picard_max < 1) return false;
     if (p.prec != BSDE_FP64 && p.prec != BSDE_FP32_COMP) return false;
@@ -221,6 +238,21 @@ bool valid_problem(const bsde_problem &p)
     return true;
 }
 
+// What the one-dimensional path implements: every valid problem except the
+// E[y dW]/dt z form in the FP32 form (it weighs the stored y by dW/dt ~
+// 1/sqrt(dt), so the ring's rounding would enter z amplified by that) and
+// exact expectations beyond the Toeplitz kernel's reach (linear driver,
+// constant coefficients, FP64).
+bool supported_1d(const bsde_problem &q)
+{
+    if (q.z_form == BSDE_ZFORM_YDW && q.prec == BSDE_FP32_COMP) return false;
+    if (q.quad == BSDE_QUAD_EXACT &&
+        (q.driver != BSDE_DRIVER_LINEAR || q.drift_x != 0.0 || q.vol_x != 0.0 ||
+         q.tab_steps != 0 || q.prec != BSDE_FP64))
+        return false;
+    return true;
+}
+
 // What the two-dimensional path implements: vol lower triangular (any
 // correlation, written with its Cholesky factor), the linear driver, FP64.
 bool supported_2d(const bsde_problem &p)
@@ -230,7 +262,8 @@ bool supported_2d(const bsde_problem &p)
     const bool prec_ok = p.prec == BSDE_FP64 ||
                          (p.prec == BSDE_FP32_COMP && p.z_form == BSDE_ZFORM_EZ);
     return p.vol[0][1] == 0.0 && p.driver == BSDE_DRIVER_LINEAR && prec_ok &&
-           p.L <= 64 && p.drift_x == 0.0 && p.vol_x == 0.0 && p.quad == BSDE_QUAD_GH &&
+           p.L <= 64 && p.drift_x == 0.0 && p.vol_x == 0.0 && p.tab_steps == 0 &&
+           p.quad == BSDE_QUAD_GH &&
            (p.interp == BSDE_INTERP_SPLINE || (p.n_x[0] >= 5 && p.n_x[1] >= 5));
 }
 
@@ -249,13 +282,28 @@ bool build_instance(const bsde_problem &p, Instance &in)
     in.dt = p.T / p.n_t;
     in.dx = (p.x_max[0] - p.x_min[0]) / (in.nx - 1);
     in.f32 = p.prec == BSDE_FP32_COMP;
-    in.gather = p.drift_x != 0.0 || p.vol_x != 0.0;
+    in.gather = p.drift_x != 0.0 || p.vol_x != 0.0 || p.tab_steps > 0;
     in.exact = p.quad == BSDE_QUAD_EXACT;
     in.steps = p.n_t - in.K - p.n_stop + 1;
     const double vol = p.vol[0][0];
-    // largest Gauss-Hermite spread per cell over the grid (b(x) is affine)
-    in.R = std::max(vol + p.vol_x * p.x_min[0], vol + p.vol_x * p.x_max[0]) *
-           std::sqrt(2.0 * in.dt) / in.dx;
+    // largest Gauss-Hermite spread per cell over the grid (b(x) is affine, or
+    // tabulated)
+    double bmax = std::max(vol + p.vol_x * p.x_min[0], vol + p.vol_x * p.x_max[0]);
+    if (p.tab_steps > 0) {
+        bmax = 0.0;
+        for (int r = 0; r < p.tab_steps; ++r)
+            for (int i = 0; i < in.nx; ++i)
+                bmax = std::max(bmax, p.coef_tab[(size_t)(2 * r + 1) * in.nx + i]);
+        // the plan keeps its own copy of the table
+        in.ctab.assign(p.coef_tab, p.coef_tab + (size_t)2 * p.tab_steps * in.nx);
+        in.pb.coef_tab = nullptr;
+    }
+    in.R = bmax * std::sqrt(2.0 * in.dt) / in.dx;
+    // the constant-coefficient node offsets (the kernels' windows; the gather
+    // kernel locates its nodes per point); with a table, drift and vol are
+    // not used and the offsets take b's largest value
+    const double drift_n = p.tab_steps > 0 ? 0.0 : p.drift[0];
+    const double vol_n = p.tab_steps > 0 ? bmax : vol;
     double a[bsde::kMaxL], w[bsde::kMaxL], gy[8], gz[8];
     if (!bsde::gauss_hermite(p.L, a, w)) return false;
     if (!bsde::spline_gamma(1, p.k_y, gy) || !bsde::spline_gamma(2, p.k_z, gz)) return false;
@@ -276,7 +324,7 @@ bool build_instance(const bsde_problem &p, Instance &in)
         for (int l = 0; l < L; ++l) {
             const int k = (j - 1) * L + l;
             const double dW = sq * a[l];
-            const double s = (p.drift[0] * j * in.dt + vol * dW) / in.dx;
+            const double s = (drift_n * j * in.dt + vol_n * dW) / in.dx;
             const double fl = std::floor(s);
             if (!(std::fabs(fl) < 1e8)) return false;
             const int m = (int)fl;
@@ -1132,6 +1180,12 @@ bsde_status bsde_initial_layers(const bsde_problem *pb, int substeps, void *ws, 
         q.T = n_hi * dt;
         q.n_t = n_hi * substeps;
         q.n_stop = (n_hi - 1) * substeps;
+        // coefficients tabulated per step: the row of t_{N-r}, held over the
+        // segment's sub-steps
+        if (pb->tab_steps > 1) {
+            q.tab_steps = 1;
+            q.coef_tab = pb->coef_tab + (size_t)2 * (pb->n_t - r) * pb->n_x[0];
+        }
         bsde_plan_t plan = nullptr;
         bsde_status rc = bsde_plan(&q, 1, &plan);
         if (rc != BSDE_OK) return rc;
@@ -1164,7 +1218,7 @@ bsde_status bsde_problem_info(const bsde_problem *pb, bsde_problem_info_t *info)
         if (!build_instance(*pb, in)) return BSDE_EINVAL;
         r.stability_ratio = in.R;
         r.node_reach = std::max(-in.m_min, in.m_max + 1);
-        r.supported = 1;
+        r.supported = supported_1d(*pb) ? 1 : 0;
     } else {
         Instance2 in;
         r.supported = supported_2d(*pb) ? 1 : 0;
@@ -1199,17 +1253,7 @@ bsde_status bsde_plan(const bsde_problem *pb, int batch, bsde_plan_t *out)
     if (!pl) return BSDE_ENOMEM;
     pl->inst.resize(batch);
     for (int b = 0; b < batch; ++b) {
-        // the Toeplitz kernel: linear driver, constant coefficients, FP64
-        const bsde_problem &q = pb[b];
-        // the E[y dW]/dt z form weighs the stored y by dW/dt ~ 1/sqrt(dt): in
-        // the FP32 form the ring's rounding would enter z amplified by that
-        if (q.z_form == BSDE_ZFORM_YDW && q.prec == BSDE_FP32_COMP) {
-            delete pl;
-            return BSDE_EUNSUPPORTED;
-        }
-        if (q.quad == BSDE_QUAD_EXACT &&
-            (q.driver != BSDE_DRIVER_LINEAR || q.drift_x != 0.0 || q.vol_x != 0.0 ||
-             q.prec != BSDE_FP64)) {
+        if (!supported_1d(pb[b])) {
             delete pl;
             return BSDE_EUNSUPPORTED;
         }
@@ -1299,6 +1343,7 @@ bsde_status bsde_plan(const bsde_problem *pb, int batch, bsde_plan_t *out)
         size_t nbw = 0;
         for (int j = 1; j <= in.K; ++j) nbw += 4 * in.band[j].ev.size();
         tbytes += align_up(nbw * sizeof(double), 256);
+        tbytes += align_up(in.ctab.size() * sizeof(double), 256);
     }
     const size_t desc_off = tbytes;
     tbytes += align_up((size_t)batch * sizeof(bsde::InstDesc), 256);
@@ -1355,6 +1400,8 @@ bsde_status bsde_plan(const bsde_problem *pb, int batch, bsde_plan_t *out)
             bw.insert(bw.end(), bd.wm.begin(), bd.wm.end());
         }
         in.toep_w = static_cast<const double *>(put(bw.data(), bw.size() * sizeof(double)));
+        if (!in.ctab.empty())
+            in.d_ctab = static_cast<const double *>(put(in.ctab.data(), in.ctab.size() * sizeof(double)));
     }
     if (hipMemcpy(pl->d_tables, host.data(), desc_off, hipMemcpyHostToDevice) != hipSuccess) {
         bsde_plan_destroy(pl);
@@ -1434,6 +1481,8 @@ bsde_status bsde_plan(const bsde_problem *pb, int batch, bsde_plan_t *out)
         a.drift_x = in.pb.drift_x;
         a.vol0 = in.pb.vol[0][0];
         a.vol_x = in.pb.vol_x;
+        a.ctab = in.d_ctab;
+        a.tab_steps = in.pb.tab_steps;
         if (in.exact) {
             // eq (20) for f = p0 y + p1 z + p3 with exact expectations:
             //   Y = E[y^{n+K_y}] + K_y dt sum_j gamma_j E[f^{n+j}]

@@ -171,8 +171,12 @@ struct SweepArgs {
     double picard_tol;
     int zform;        // first term of the z equation: 0 E[z^{n+1}], 1 E[y^{n+1} dW]/dt
     // forward coefficients of eq (1) (gather path): a(x) = drift0 + drift_x x,
-    // b(x) = vol0 + vol_x x on the grid x_i = x_min + i dx
+    // b(x) = vol0 + vol_x x on the grid x_i = x_min + i dx, or tabulated:
+    // ctab row s = (tab_steps > 1 ? n : 0) holds a(t_n, x_i) at [2 s nx + i]
+    // and b at [(2 s + 1) nx + i]
     double x_min, dx, drift0, drift_x, vol0, vol_x;
+    const double *ctab;
+    int tab_steps;
     ToepTable toep;   // exact Gaussian expectations (Toeplitz path)
     unsigned int *st_iter_max;        // per-wave running maximum (NULL: no stats)
     unsigned long long *st_iter_sum;  // per-wave running sum

@@ -339,9 +339,10 @@ __global__ void __launch_bounds__(kBlock) sweep_direct(const StepArgs s)
 }
 
 // ---------------------------------------------------------------------------
-// Gather sweep: forward coefficients that depend on the state (eq (1)).  The
-// node of (j, l) for point x_i is one Euler step of X over j dt,
-//   X = x_i + a(x_i) j dt + b(x_i) sqrt(2 j dt) a_l,
+// Gather sweep: forward coefficients that depend on the state (eq (1)),
+// affine in x or tabulated on the grid (and then also per time step).  The
+// node of (j, l) for point x_i is one Euler step of X over j dt from t_n,
+//   X = x_i + a(t_n, x_i) j dt + b(t_n, x_i) sqrt(2 j dt) a_l,
 // so its cell and fraction differ from point to point: each lane locates
 // its nodes (Section 3.2: floor on the uniform grid, the boundary value
 // outside the truncated domain), forms the spline basis weights at the
@@ -361,7 +362,15 @@ __global__ void __launch_bounds__(kBlock) sweep_gather(const StepArgs s)
     const int first = tile * kBlock + (int)threadIdx.x;
     const int i = min(first, a.nx - 1);  // lanes past the end compute in bounds, store nothing
     const double xi = a.x_min + i * a.dx;
-    const double ax = fma(a.drift_x, xi, a.drift0), bx = fma(a.vol_x, xi, a.vol0);
+    double ax, bx;
+    if (a.ctab) {  // tabulated a(t_n, x_i), b(t_n, x_i)
+        const double *row = a.ctab + (size_t)2 * (a.tab_steps > 1 ? a.n : 0) * a.nx;
+        ax = row[i];
+        bx = row[a.nx + i];
+    } else {
+        ax = fma(a.drift_x, xi, a.drift0);
+        bx = fma(a.vol_x, xi, a.vol0);
+    }
     const double dx26 = a.dx * a.dx / 6.0;
     Acc<1> acc;
     acc.Y[0] = acc.Z[0] = 0.0;

@@ -177,3 +177,29 @@ def test_problem_info_flags_the_stability_ratio():
     # a 2-D problem outside the 2-D kernels: reported, not refused
     pb = dict(W.exchange_2d().problem, driver="bidask", p=[0.01, 0.06, 0.2, 0.2, 1.0])
     assert B.bsde_problem_info(pb)["supported"] == 0
+
+
+def test_problem_info_takes_tabulated_coefficients():
+    # the stability ratio follows the table's largest b; invalid tables are
+    # refused before any device call
+    import numpy as np
+
+    w = W.ou_linear_1d(n_x=401, n_t=16)
+    t = W.tabulated(w, time_dependent=True)
+    info = B.bsde_problem_info(t.problem)
+    dx = (t.problem["x_max"] - t.problem["x_min"]) / 400
+    bmax = float(np.max(t.problem["coef_tab"][:, 1]))
+    assert info["stability_ratio"] == pytest.approx(bmax * (2 * t.problem["T"] / 16) ** 0.5 / dx,
+                                                    rel=1e-12)
+    bad = dict(t.problem, coef_tab=t.problem["coef_tab"].copy())
+    bad["coef_tab"][3, 1, 7] = -0.1
+    with pytest.raises(B.BsdeError) as e:
+        B.bsde_problem_info(bad)
+    assert e.value.code == B.BSDE_EINVAL
+    with pytest.raises(B.BsdeError) as e:  # slopes must be 0 with a table
+        B.bsde_problem_info(dict(t.problem, drift_x=0.5))
+    assert e.value.code == B.BSDE_EINVAL
+    with pytest.raises(B.BsdeError) as e:  # neither 1 nor n_t rows
+        B.bsde_problem_info(dict(t.problem, coef_tab=t.problem["coef_tab"][:5]))
+    assert e.value.code == B.BSDE_EINVAL
+    assert B.bsde_problem_info(dict(t.problem, quad="exact"))["supported"] == 0

@@ -444,3 +444,44 @@ def test_fp32_two_dimensional_full_size(lib, orc):
     e2 = max(rel_err(y32, y64), rel_err(z32[0], z64[0]), rel_err(z32[1], z64[1]))
     print(f"  first step vs oracle {e1:.3e}, whole solve vs FP64 {e2:.3e}", flush=True)
     assert e1 <= TOL32 and e2 <= TOL32
+
+
+# ----------------------------------------------------------------------------
+# Forward coefficients tabulated on the grid and per step (eq (1))
+# ----------------------------------------------------------------------------
+
+
+def test_tabulated_coefficients(lib, orc):
+    from test_gpu_parity import TOL32, batched_solve
+
+    # the affine Ornstein-Uhlenbeck drift as a table (one row, and one per step)
+    for td in (False, True):
+        _run(lib, orc, W.tabulated(W.ou_linear_1d(n_x=801, n_t=32), td))
+    # a local volatility with skew and term structure, both drivers, both forms
+    for drv in ("linear", "bidask"):
+        wl = W.local_vol_call_1d(driver=drv)
+        _run(lib, orc, wl)
+        _run(lib, orc, wl, prec="fp32_comp", tol=TOL32)
+    # time-varying vol on x^2: the left Riemann sum of sigma^2 at the interior
+    wl = W.quadratic_time_varying_vol()
+    y, _ = _run(lib, orc, wl)
+    x = wl.grid(0)
+    mid = np.abs(x) < 3.0
+    assert np.max(np.abs(y[mid] - (x[mid] ** 2 + wl.extra["y0_scheme_offset"]))) < 1e-7
+    # a batch mixing tabulated, affine and constant coefficients (one group on
+    # the gather kernel)
+    wls = [W.local_vol_call_1d(n_x=1500, n_t=20), W.ou_linear_1d(n_x=700, n_t=24),
+           W.tabulated(W.bs_call_price_1d(n_x=900, n_t=16)), W.sine_1d(n_x=600, n_t=12, k=2)]
+    rc, st, outs, _ = batched_solve(lib, wls)
+    assert rc == lib.BSDE_OK
+    for w, (y, z) in zip(wls, outs):
+        iy, iz = w.init_layers()
+        yo, zo, _ = orc.solve(w.problem, iy, iz)
+        e = max(rel_err(y, yo), rel_err(z, zo[0]))
+        print(f"  batch {w.name}: rel err {e:.3e}", flush=True)
+        assert e <= TOL64
+
+
+def test_tabulated_coefficients_initial_layers(lib, orc):
+    # per-step table: each 1-step segment holds the row of its start time
+    _initial_layers_case(lib, orc, W.local_vol_call_1d(n_x=1201, n_t=24, k=4), 5)

@@ -667,3 +667,58 @@ def test_all_cores_oracle_is_the_serial_oracle(oracle_lib):
     y0, z0, s0 = oracle_lib.solve(wl.problem, iy, iz)
     y1, z1, s1 = oracle_lib.solve(wl.problem, iy, iz, threads=True)
     assert np.array_equal(y0, y1) and np.array_equal(z0, z1) and s0 == s1
+
+
+# ----------------------------------------------------------------------------
+# Forward coefficients tabulated on the grid (eq (1) with any a(t, x), b(t, x))
+# ----------------------------------------------------------------------------
+
+
+@pytest.mark.parametrize("time_dependent", [False, True])
+def test_tabulated_coefficients_equal_the_affine_ones(oracle_lib, time_dependent):
+    # the Ornstein-Uhlenbeck drift and the stock-price grid's b(S) = sigma S
+    # (both pinned above in their affine form) given as tables: the same sweep
+    for base in (W.ou_linear_1d(n_x=401, n_t=16), W.bs_call_price_1d(n_x=400, n_t=24)):
+        iy, iz = base.init_layers()
+        y1, z1, _ = oracle_lib.solve(base.problem, iy, iz)
+        t = W.tabulated(base, time_dependent)
+        y2, z2, _ = oracle_lib.solve(t.problem, iy, iz)
+        assert np.array_equal(y1, y2) and np.array_equal(z1, z2)
+
+
+def test_tabulated_time_dependent_vol_uses_the_left_point(oracle_lib):
+    # dX = sigma(t) dW, g = x^2, f = 0, K = 1: each step adds sigma(t_n)^2 dt at
+    # the interior points, so y0 = x^2 + the left Riemann sum of sigma^2; the
+    # right sum (coefficients of t_{n+1}) differs by dt (sigma(T)^2 - sigma(0)^2)
+    w = W.quadratic_time_varying_vol()
+    iy, iz = w.init_layers()
+    y, z, _ = oracle_lib.solve(w.problem, iy, iz)
+    x = w.grid(0)
+    mid = np.abs(x) < 3.0
+    left = w.extra["y0_scheme_offset"]
+    assert np.max(np.abs(y[mid] - (x[mid] ** 2 + left))) < 1e-7
+    dt = w.dt()
+    assert dt * (0.75 ** 2 - 0.3 ** 2) > 1e-2
+    # and converges at first order in dt to the exact variance integral
+    ye, _ = w.exact_at_t0()
+    e1 = np.max(np.abs(y[mid] - ye[mid]))
+    w2 = W.quadratic_time_varying_vol(n_t=80)
+    iy2, iz2 = w2.init_layers()
+    y2, _, _ = oracle_lib.solve(w2.problem, iy2, iz2)
+    ye2, _ = w2.exact_at_t0()
+    e2 = np.max(np.abs(y2[mid] - ye2[mid]))
+    assert 1.8 < e1 / e2 < 2.2
+
+
+def test_tabulated_coefficients_validation(oracle_lib):
+    w = W.ou_linear_1d(n_x=101, n_t=8)
+    iy, iz = w.init_layers()
+    bad = W.tabulated(w)
+    bad.problem["coef_tab"] = bad.problem["coef_tab"].copy()
+    bad.problem["coef_tab"][0, 1, 50] = 0.0  # b must be positive
+    with pytest.raises(ValueError):
+        oracle_lib.solve(bad.problem, iy, iz)
+    two = W.tabulated(w)
+    two.problem["coef_tab"] = np.repeat(two.problem["coef_tab"], 2, axis=0)  # neither 1 nor N rows
+    with pytest.raises(ValueError):
+        oracle_lib.solve(two.problem, iy, iz)

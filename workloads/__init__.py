@@ -467,6 +467,93 @@ def ou_linear_1d(n_x: int = 801, n_t: int = 32, k: int = 3, L: int = 16, kappa: 
     return w
 
 
+# ----------------------------------------------------------------------------
+# Forward coefficients tabulated on the grid (eq (1) with any a(t, x), b(t, x))
+# ----------------------------------------------------------------------------
+
+
+def coef_table(pb: dict, a_fn: Callable, b_fn: Callable, time_dependent: bool) -> np.ndarray:
+    """(tab_steps, 2, n_x) rows of a(t_n, x_i) and b(t_n, x_i): one row (t = 0)
+    or one per step n = 0..N-1."""
+    n = pb["n_x"]
+    x = pb["x_min"] + np.arange(n) * ((pb["x_max"] - pb["x_min"]) / (n - 1))
+    steps = pb["n_t"] if time_dependent else 1
+    dt = pb["T"] / pb["n_t"]
+    tab = np.empty((steps, 2, n))
+    for r in range(steps):
+        t = r * dt
+        tab[r, 0] = a_fn(t, x)
+        tab[r, 1] = b_fn(t, x)
+    return tab
+
+
+def tabulated(w: Workload, time_dependent: bool = False) -> Workload:
+    """The same problem with its affine (or constant) coefficients given as a
+    table (rows repeated when time_dependent): the same arithmetic, tabulated."""
+    pb = dict(w.problem)
+    a0, a1 = pb.get("drift", 0.0), pb.get("drift_x", 0.0)
+    b0, b1 = pb.get("vol", 1.0), pb.get("vol_x", 0.0)
+    pb["coef_tab"] = coef_table(pb, lambda t, x: a0 + a1 * x, lambda t, x: b0 + b1 * x,
+                                time_dependent)
+    pb["drift_x"] = pb["vol_x"] = 0.0
+    return Workload(w.name + ("_tabt" if time_dependent else "_tab"), pb, w.exact, w.x0,
+                    extra=dict(w.extra))
+
+
+def quadratic_time_varying_vol(n_x: int = 801, n_t: int = 40, L: int = 16, T: float = 1.0,
+                               sigma0: float = 0.3, growth: float = 1.5,
+                               half_width: float = 6.0) -> Workload:
+    """dX = sigma(t) dW with sigma(t) = sigma0 (1 + growth t), f = 0, g(x) = x^2,
+    K = 1, tabulated per step: y(t, x) = x^2 + int_t^T sigma^2 ds.  The 1-step
+    scheme with the Euler node of step n at sigma(t_n) adds sigma(t_n)^2 dt per
+    step (the spline holds x^2 away from the ends), so the computed y0 is
+    x^2 + dt sum_{n<N} sigma(t_n)^2, the left Riemann sum (extra["y0_scheme"])."""
+    pb = _problem(T=T, n_t=n_t, k_y=1, k_z=1, L=L, n_x=n_x, x_min=-half_width,
+                  x_max=half_width, driver="linear", p=[0.0, 0.0, 0.0, 0.0])
+    sig = lambda t: sigma0 * (1.0 + growth * t)
+    pb["coef_tab"] = coef_table(pb, lambda t, x: np.zeros_like(x),
+                                lambda t, x: np.full_like(x, sig(t)), True)
+    dt = T / n_t
+    left = dt * sum(sig(n * dt) ** 2 for n in range(n_t))
+
+    def exact(t, x):
+        # int_t^T sigma0^2 (1 + g s)^2 ds
+        F = lambda s: sigma0 ** 2 * ((1.0 + growth * s) ** 3) / (3.0 * growth)
+        return x * x + (F(T) - F(t)), 2.0 * sig(t) * x
+
+    w = Workload(f"quadvol_nx{n_x}_nt{n_t}_L{L}", pb, exact, 0.0)
+    w.extra.update(dict(y0_scheme_offset=left))
+    return w
+
+
+def local_vol_call_1d(n_x: int = 2001, n_t: int = 48, k: int = 3, L: int = 16, K: float = 100.0,
+                      S0: float = 100.0, r: float = 0.03, mu: float = 0.06, T: float = 0.5,
+                      half_width: float = 1.2, time_dependent: bool = True,
+                      driver: str = "linear") -> Workload:
+    """A call under a local volatility with skew and a term structure,
+    sigma(t, x) = (0.2 - 0.08 tanh(x - ln K)) (1 + 0.3 t / T), on the
+    log-price grid: a = mu - sigma^2 / 2, b = sigma, tabulated per step.
+    Driver linear (f = -r y - ((mu - r)/sigma(x)) z is not linear in the table;
+    the linear driver takes theta at the money) or bid-ask.  No closed form:
+    the terminal layers are the Black-Scholes prices at the money volatility
+    (a smooth input for parity)."""
+    c = math.log(S0)
+    lo, hi = _snap_domain(c, c - half_width, c + half_width, n_x)
+    sig = lambda t, x: (0.2 - 0.08 * np.tanh(x - math.log(K))) * (1.0 + 0.3 * t / T)
+    s_atm = 0.2
+    theta = (mu - r) / s_atm
+    p = [-r, -theta, 0.0, 0.0] if driver == "linear" else [r, r + 0.05, theta, s_atm, 1.0]
+    pb = _problem(T=T, n_t=n_t, k_y=k, k_z=k, L=L, n_x=n_x, x_min=lo, x_max=hi,
+                  driver=driver, p=p)
+    pb["coef_tab"] = coef_table(pb, lambda t, x: mu - 0.5 * sig(t, x) ** 2, sig, time_dependent)
+
+    def exact(t, x):
+        return bs_call(T + T / n_t - t, x, K, r, s_atm)
+
+    w = Workload(f"lv1d_nx{n_x}_nt{n_t}_k{k}_L{L}_{driver}", pb, exact, c)
+    return w
+
+
 def option_batch(count: int = 4096, seed: int = 1909, log2_nx: tuple = (10.0, 16.0),
                  n_ts: tuple = (64, 128, 256, 512), k: int = 4, L: int = 16,
                  prec: str = "fp32_comp", shared_grid: int = 0,
