@@ -174,7 +174,8 @@ typedef struct {
 
 typedef struct {
     double stability_ratio; /* R; d = 2: the larger of the two axes'          */
-    int stable;             /* 1 when R <= BSDE_STABILITY_LIMIT               */
+    int stable;             /* 1 when R <= BSDE_STABILITY_LIMIT (to a relative
+                               1e-12, the rounding of R itself)               */
     int K;                  /* max(k_y, k_z): layers kept and initial layers  */
     int node_reach;         /* widest node offset from a grid point, in cells */
     int supported;          /* 1 when bsde_plan implements the problem        */

@@ -238,6 +238,10 @@ bool valid_problem(const bsde_problem &p)
     return true;
 }
 
+// R above BSDE_STABILITY_LIMIT by more than its own rounding (a grid built
+// for R = 16 computes R = 16 to within a few ulps)
+bool beyond_stability_limit(double R) { return R > BSDE_STABILITY_LIMIT * (1.0 + 1e-12); }
+
 // What the one-dimensional path implements: every valid problem except the
 // E[y dW]/dt z form in the FP32 form (it weighs the stored y by dW/dt ~
 // 1/sqrt(dt), so the ring's rounding would enter z amplified by that) and
@@ -869,12 +873,12 @@ bsde_status finish_stats(bsde_plan_t plan, char *ws, hipStream_t s, hipEvent_t e
             const Instance &in = plan->inst[b];
             point_steps += (long long)in.nx * in.steps;
             R = std::max(R, in.R);
-            unstable += in.R > BSDE_STABILITY_LIMIT ? 1 : 0;
+            unstable += beyond_stability_limit(in.R) ? 1 : 0;
         } else {
             const Instance2 &in = plan->inst2[b];
             point_steps += (long long)in.n0 * in.n1 * (in.pb.n_t - in.K - in.pb.n_stop + 1);
             R = std::max(R, in.R);
-            unstable += in.R > BSDE_STABILITY_LIMIT ? 1 : 0;
+            unstable += beyond_stability_limit(in.R) ? 1 : 0;
         }
     }
     float ms = 0.0f;
@@ -1236,7 +1240,7 @@ bsde_status bsde_problem_info(const bsde_problem *pb, bsde_problem_info_t *info)
         r.node_reach = r.supported ? in.pad0 - 1 : 0;
         if (r.supported) r.node_reach = std::max({r.node_reach, in.pad1 - 1, in.pad0r - bsde::kTile2R - 1});
     }
-    r.stable = r.stability_ratio <= BSDE_STABILITY_LIMIT ? 1 : 0;
+    r.stable = beyond_stability_limit(r.stability_ratio) ? 0 : 1;
     *info = r;
     return BSDE_OK;
 }

@@ -203,3 +203,14 @@ def test_problem_info_takes_tabulated_coefficients():
         B.bsde_problem_info(dict(t.problem, coef_tab=t.problem["coef_tab"][:5]))
     assert e.value.code == B.BSDE_EINVAL
     assert B.bsde_problem_info(dict(t.problem, quad="exact"))["supported"] == 0
+
+
+def test_stability_flag_tolerates_rounding_of_the_ratio():
+    # a grid built for R = 16 computes R = 16 to within a few ulps; it is
+    # stable, and R = 16.01 is not
+    nx, nt = 3001, 24
+    hw = 0.2 * (2 * 0.5 / nt) ** 0.5 / 16.0 * (nx - 1) / 2
+    info = B.bsde_problem_info(W.bidask_call_1d(n_x=nx, n_t=nt, half_width=hw).problem)
+    assert abs(info["stability_ratio"] - 16.0) < 1e-12 and info["stable"] == 1
+    info = B.bsde_problem_info(W.bidask_call_1d(n_x=nx, n_t=nt, half_width=hw / 1.000625).problem)
+    assert info["stability_ratio"] > 16.009 and info["stable"] == 0
