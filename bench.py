@@ -470,6 +470,59 @@ def smoothing_study(B, torch, twin, substeps: int = 8):
     return out
 
 
+def shared_grid_batch(B, torch, np, count: int = 256):
+    """The batched workload's shared-grid subset (Black-Scholes calls on one
+    16384-point interval, N = 256, k = 4, K and r varying), FP64: Gauss-Hermite
+    (L = 16) on the vector ALUs against exact expectations on the matrix cores
+    (Toeplitz sweep), whole batched solves timed, errors at the money against
+    the closed form."""
+    import workloads as W
+
+    dev = "cuda:0"
+    stream = torch.cuda.current_stream()
+    out = {"instances": count}
+    for quad in ("gh", "exact"):
+        wls = W.option_batch(count=count, shared_grid=count, prec="fp64")
+        ios = []
+        for w in wls:
+            w.problem["quad"] = quad
+            iy, iz = w.init_layers()
+            n = iy.shape[1]
+            ios.append((torch.as_tensor(iy, device=dev), torch.as_tensor(iz.reshape(iy.shape), device=dev),
+                        torch.empty(n, dtype=torch.float64, device=dev),
+                        torch.empty(n, dtype=torch.float64, device=dev)))
+        plan = B.bsde_plan([w.problem for w in wls])
+        ws = B.workspace(plan, dev)
+        if quad == "gh":
+            B.bsde_autotune(plan, ws, ios, stream=stream, reps=2)
+        rc, st = B.bsde_solve_batched(plan, ws, ios, stream=stream, stats=True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        reps = 2
+        for _ in range(reps):
+            B.bsde_solve_batched(plan, ws, ios, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        err = 0.0
+        for w, io in zip(wls, ios):
+            ye, _ = w.exact_at_t0()
+            i = w.node_index()
+            err = max(err, abs(float(io[2][i]) - ye[i]) / max(abs(ye[i]), 1.0))
+        point_steps = sum(w.problem["n_x"] * w.problem["n_t"] for w in wls)
+        rec = {"ms_per_solve": ms, "value": point_steps / (ms * 1e-3), "status": B.bsde_status_string(rc),
+               "max_rel_err_y0_vs_closed_form": err}
+        if quad == "exact":
+            steps = wls[0].problem["n_t"] - wls[0].K + 1
+            fl = toeplitz_flops_per_point_step(wls[0].problem)[0] * sum(w.problem["n_x"] for w in wls)
+            rec["matrix_core_tflops"] = fl * steps / (ms * 1e-3) / 1e12
+        out[quad] = rec
+        del plan, ws, ios
+    print(f"[bench] configs: shared-grid batch {out}", file=sys.stderr, flush=True)
+    return out
+
+
 def run_configs(args, B, torch, np):
     """The other configurations: the sine problem (1025 points, N = 64, k = 2),
     Black-Scholes (16384 points, N = 256, L = 32, k = 4) on its stable twin and
@@ -511,6 +564,7 @@ def run_configs(args, B, torch, np):
         out[name] = rec
         print(f"[bench] configs: {name} {rec}", file=sys.stderr, flush=True)
     out["smoothing_study"] = smoothing_study(B, torch, twin)
+    out["shared_grid_batch"] = shared_grid_batch(B, torch, np)
     wl = W.bidask_call_1d(half_width=None)
     ms, st, kt, y, z, rc = time_solves(B, torch, wl, reps=3)
     out["bidask_262144_nt1024_literal_gh"] = {
