@@ -1138,7 +1138,11 @@ extern "C" {
 
 const char *bsde_status_string(bsde_status s)
 {
-    switch (s) {
+    // a C caller may pass any int: read it as one (a value outside the
+    // enumeration would be undefined as a C++ enum value)
+    int v;
+    std::memcpy(&v, &s, sizeof(v));
+    switch (v) {
     case BSDE_OK: return "ok";
     case BSDE_EINVAL: return "invalid argument";
     case BSDE_ENOMEM: return "out of memory";
