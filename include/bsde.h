@@ -315,6 +315,24 @@ bsde_status bsde_solve_batched(bsde_plan_t plan, void *ws, const bsde_io *io, vo
 bsde_status bsde_initial_layers(const bsde_problem *pb, int substeps, void *ws, size_t ws_bytes,
                                 double *init_y, double *init_z, void *stream);
 
+/*
+ * bsde_checkpoint_layers -- resume data of a solve stopped at a checkpoint
+ * (Section 3.1 step 3's backward loop cut at layer n_stop): after
+ * bsde_solve / bsde_solve_batched of `plan` with workspace `ws` has finished
+ * (and before ws is used again), writes layers n_stop .. n_stop + K - 1 of
+ * instance b (K = max(k_y, k_z)) to layers_y and layers_z in the layout of
+ * init_y / init_z: row r = layer n_stop + r (d = 1: K x n_x and K x n_x;
+ * d = 2: K x n_x[0] n_x[1] and K x 2 x n_x[0] n_x[1]), caller-owned device
+ * buffers.  A problem with n_t' = n_stop + K - 1 and T' = n_t' T / n_t (same
+ * dt, same absolute times) started from them continues the sweep: it gives
+ * the layers of the uninterrupted solve (the FP32 form exports each stored
+ * value plus its rounding residual, which the resumed solve splits back into
+ * the same pair).  Asynchronous on the stream.
+ * Errors: BSDE_EINVAL (NULL pointer, b outside the batch), BSDE_EDEVICE.
+ */
+bsde_status bsde_checkpoint_layers(bsde_plan_t plan, void *ws, int b, double *layers_y,
+                                   double *layers_z, void *stream);
+
 /* Size of the library's static device workspace (64 MiB per GPU). */
 #define BSDE_STATIC_WORKSPACE_BYTES (((size_t)64) << 20)
 

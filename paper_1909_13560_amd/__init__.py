@@ -32,7 +32,7 @@ INTERPS = {"spline": 0, "bicubic_fd": 1}  # bsde_interp (d = 2: the paper's bicu
 EXPORTED = ["bsde_plan", "bsde_plan_destroy", "bsde_workspace_bytes", "bsde_solve",
             "bsde_solve_batched", "bsde_profile_kernels", "bsde_status_string",
             "bsde_gauss_hermite", "bsde_gamma", "bsde_autotune", "bsde_problem_info",
-            "bsde_initial_layers", "bsde_solve_batched_static"]
+            "bsde_initial_layers", "bsde_solve_batched_static", "bsde_checkpoint_layers"]
 STABILITY_LIMIT = 16.0  # BSDE_STABILITY_LIMIT
 
 
@@ -147,6 +147,8 @@ def load() -> ctypes.CDLL:
         lib.bsde_initial_layers.restype = ip
         lib.bsde_solve_batched_static.argtypes = [vp, ctypes.POINTER(_Io), vp]
         lib.bsde_solve_batched_static.restype = ip
+        lib.bsde_checkpoint_layers.argtypes = [vp, vp, ctypes.c_int, vp, vp, vp]
+        lib.bsde_checkpoint_layers.restype = ip
         _lib = lib
     return _lib
 
@@ -302,6 +304,17 @@ def bsde_solve_batched_static(plan: Plan, ios, stream=None, check: bool = True) 
     if check and rc not in (BSDE_OK, BSDE_ESCRATCH):
         raise BsdeError(rc, "bsde_solve_batched_static")
     return rc
+
+
+def bsde_checkpoint_layers(plan: Plan, ws, b: int, layers_y, layers_z, stream=None) -> None:
+    """bsde_checkpoint_layers: layers n_stop .. n_stop + K - 1 of instance b into
+    device tensors in the initial-layer layout (after a solve with ws)."""
+    rc = load().bsde_checkpoint_layers(ctypes.c_void_p(plan.handle), ctypes.c_void_p(_dptr(ws)),
+                                       int(b), ctypes.c_void_p(_dptr(layers_y)),
+                                       ctypes.c_void_p(_dptr(layers_z)),
+                                       ctypes.c_void_p(_stream_ptr(stream)))
+    if rc != BSDE_OK:
+        raise BsdeError(rc, "bsde_checkpoint_layers")
 
 
 def bsde_profile_kernels(plan: Plan, ws, ios, stream=None) -> dict:

@@ -1565,6 +1565,26 @@ bsde_status bsde_solve_batched(bsde_plan_t plan, void *ws, const bsde_io *io, vo
     return solve_impl(plan, ws, io, (int)plan->desc.size(), stream, st);
 }
 
+bsde_status bsde_checkpoint_layers(bsde_plan_t plan, void *ws, int b, double *layers_y,
+                                   double *layers_z, void *stream)
+{
+    if (!plan || !ws || !layers_y || !layers_z || b < 0) return BSDE_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char *w = static_cast<char *>(ws);
+    if (!plan->inst2.empty()) {
+        if (b >= (int)plan->inst2.size()) return BSDE_EINVAL;
+        const Instance2 &in = plan->inst2[b];
+        bsde::Sweep2Args a = sweep2_args(in, w, false);
+        HIP_OK(bsde::launch_export2d(in.f32, a, layers_y, layers_z, s));
+        return BSDE_OK;
+    }
+    if (b >= (int)plan->inst.size()) return BSDE_EINVAL;
+    const Instance &in = plan->inst[b];
+    HIP_OK(bsde::launch_export_layers(in.f32, plan->d_desc + b, in.K, in.nx, w, layers_y, layers_z,
+                                      s));
+    return BSDE_OK;
+}
+
 bsde_status bsde_solve_batched_static(bsde_plan_t plan, const bsde_io *io, void *stream)
 {
     if (!plan || !io) return BSDE_EINVAL;

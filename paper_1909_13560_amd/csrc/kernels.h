@@ -54,6 +54,10 @@ hipError_t launch_scatter(const ScatterChunk &c, char *ws, const InstDesc *desc,
 hipError_t launch_gather(const GatherChunk &c, char *ws, const InstDesc *desc, int blocks_x,
                          unsigned long long *nonfinite, hipStream_t s);
 hipError_t launch_clear(unsigned long long *p, size_t n, hipStream_t s);
+// layers n_stop .. n_stop + K - 1 of the instance of `desc` from its ring in
+// ws into ly, lz (K x nx each, row r = layer n_stop + r)
+hipError_t launch_export_layers(bool f32, const InstDesc *desc, int K, int nx, char *ws,
+                                double *ly, double *lz, hipStream_t s);
 // totals[3 b + {0, 1, 2}] = max, sum, unconverged of descriptor b
 hipError_t launch_reduce_stats(char *ws, const InstDesc *desc, int count,
                                unsigned long long *totals, hipStream_t s);

@@ -513,6 +513,44 @@ __global__ void __launch_bounds__(kBlock) gather_layers(const GatherChunk c, cha
     if (nonfinite && (threadIdx.x & 63) == 0 && bad) atomicAdd(nonfinite, (unsigned long long)bad);
 }
 
+// Checkpoint export: layers n_stop .. n_stop + K - 1 of one instance (still in
+// its ring after a solve stopped at n_stop) into the initial-layer layout, row
+// r = layer n_stop + r.  The FP32 form exports the stored value plus its
+// residual, which a later scatter splits back into the same pair.
+template <bool F32>
+__global__ void __launch_bounds__(kBlock) export_layers(const InstDesc *desc, char *ws,
+                                                        double *__restrict__ ly,
+                                                        double *__restrict__ lz)
+{
+    const InstDesc &d = *desc;
+    SweepArgs a = d.a;
+    a.ring = ws + d.ring_off;
+    const int r = blockIdx.y, nx = a.nx;
+    const Slot<F32> g = ring_slot<F32>(a, a.n_stop + r);
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < nx; i += gridDim.x * kBlock) {
+        const auto v = g.val(i);
+        double y = v.x, z = v.y;
+        if constexpr (F32) {
+            const float2 e = fed_back_residual(g, a.npad, i);
+            y += (double)e.x;
+            z += (double)e.y;
+        }
+        ly[(size_t)r * nx + i] = y;
+        lz[(size_t)r * nx + i] = z;
+    }
+}
+
+hipError_t launch_export_layers(bool f32, const InstDesc *desc, int K, int nx, char *ws,
+                                double *ly, double *lz, hipStream_t s)
+{
+    const dim3 grid((unsigned)std::min(1024, (nx + kBlock - 1) / kBlock), (unsigned)K);
+    if (f32)
+        hipLaunchKernelGGL(export_layers<true>, grid, dim3(kBlock), 0, s, desc, ws, ly, lz);
+    else
+        hipLaunchKernelGGL(export_layers<false>, grid, dim3(kBlock), 0, s, desc, ws, ly, lz);
+    return hipGetLastError();
+}
+
 __global__ void __launch_bounds__(kBlock) clear_u64(unsigned long long *p, size_t n)
 {
     for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n;

@@ -137,6 +137,8 @@ hipError_t launch_fd2d(bool f32, const Sweep2Args &a, int slot, double dx0, doub
 // layer r = 0..K-1 of init_y (K x n0 n1) and init_z (K x 2 x n0 n1) into the ring
 hipError_t launch_scatter2d(bool f32, const Sweep2Args &a, const double *iy, const double *iz,
                             hipStream_t s);
+// layers n_stop .. n_stop + K - 1 into the initial-layer layout
+hipError_t launch_export2d(bool f32, const Sweep2Args &a, double *ly, double *lz, hipStream_t s);
 hipError_t launch_gather2d(const Sweep2Args &a, double *y0, double *z0,
                            unsigned long long *nonfinite, hipStream_t s);
 

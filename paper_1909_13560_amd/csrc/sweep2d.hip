@@ -573,6 +573,29 @@ __global__ void __launch_bounds__(256) gather2d(const Sweep2Args a, double *__re
 // ---------------------------------------------------------------------------
 size_t sweep2d_lds(int win) { return (size_t)3 * kTile2R * win * sizeof(double2); }
 
+// Checkpoint export: layers n_stop .. n_stop + K - 1 into the initial-layer
+// layout (y: K x n0 n1; z: K x 2 x n0 n1), the FP32 form as value plus residual.
+template <typename E>
+__global__ void __launch_bounds__(256) export2d(const Sweep2Args a, double *__restrict__ ly,
+                                                double *__restrict__ lz)
+{
+    const long np = (long)a.n0 * a.n1;
+    const long i = blockIdx.x * 256L + threadIdx.x;
+    const int r = blockIdx.y;
+    if (i >= np) return;
+    const int slot = (a.n_stop + r) % (a.K + 1);
+    const E *base = plane2<E>(a, slot, 0);
+    const size_t o = pidx(a, (int)(i / a.n1), (int)(i % a.n1));
+    double v[3];
+    for (int f = 0; f < 3; ++f) {
+        v[f] = base[(size_t)(4 * f) * a.plane + o];
+        if constexpr (std::is_same<E, float>::value) v[f] += (double)base[(size_t)(12 + f) * a.plane + o];
+    }
+    ly[r * np + i] = v[0];
+    lz[(2L * r) * np + i] = v[1];
+    lz[(2L * r + 1) * np + i] = v[2];
+}
+
 namespace {
 
 template <typename E>
@@ -656,6 +679,17 @@ hipError_t launch_fd2d(bool f32, const Sweep2Args &a, int slot, double dx0, doub
 {
     return f32 ? launch_fd2d_t<float>(a, slot, dx0, dx1, s)
                : launch_fd2d_t<double>(a, slot, dx0, dx1, s);
+}
+
+hipError_t launch_export2d(bool f32, const Sweep2Args &a, double *ly, double *lz, hipStream_t s)
+{
+    const long np = (long)a.n0 * a.n1;
+    const dim3 grid((unsigned)((np + 255) / 256), (unsigned)a.K);
+    if (f32)
+        hipLaunchKernelGGL(export2d<float>, grid, dim3(256), 0, s, a, ly, lz);
+    else
+        hipLaunchKernelGGL(export2d<double>, grid, dim3(256), 0, s, a, ly, lz);
+    return hipGetLastError();
 }
 
 hipError_t launch_scatter2d(bool f32, const Sweep2Args &a, const double *iy, const double *iz,

@@ -485,3 +485,72 @@ def test_tabulated_coefficients(lib, orc):
 def test_tabulated_coefficients_initial_layers(lib, orc):
     # per-step table: each 1-step segment holds the row of its start time
     _initial_layers_case(lib, orc, W.local_vol_call_1d(n_x=1201, n_t=24, k=4), 5)
+
+
+# ----------------------------------------------------------------------------
+# Checkpoint and resume: the layers of a solve stopped at n_stop, exported and
+# used as the initial layers of the remaining sweep
+# ----------------------------------------------------------------------------
+
+
+def _resume_case(lib, orc, wl, n_stop, prec, tol, batch_with=None):
+    import torch
+
+    pb = dict(wl.problem, prec=prec)
+    K, N, d = max(pb["k_y"], pb["k_z"]), pb["n_t"], pb["d"]
+    print(f"[case] resume {wl.name} {prec} at n_stop={n_stop}", flush=True)
+    iy, iz = wl.init_layers()
+    npts = iy.shape[1]
+    y_full, z_full, rc, _ = lib.solve(pb, iy, iz)
+    assert rc == lib.BSDE_OK
+    # the solve stopped at n_stop, as instance b of a batch when batch_with is given
+    probs = [dict(pb, n_stop=n_stop)]
+    others = []
+    if batch_with is not None:
+        probs.insert(0, dict(batch_with.problem, prec=prec))
+        others = [batch_with]
+    plan = lib.bsde_plan(probs)
+    ws = lib.workspace(plan)
+    ios = []
+    for w, p in zip(others + [wl], probs):
+        jy, jz = w.init_layers()
+        n = jy.shape[1]
+        ios.append((torch.as_tensor(jy, device="cuda").contiguous(),
+                    torch.as_tensor(jz.reshape(jy.shape[0], -1), device="cuda").contiguous(),
+                    torch.empty(n, dtype=torch.float64, device="cuda"),
+                    torch.empty(p["d"] * n, dtype=torch.float64, device="cuda")))
+    rc, _ = lib.bsde_solve_batched(plan, ws, ios)
+    assert rc == lib.BSDE_OK
+    b = len(probs) - 1
+    ly = torch.full((K, npts), float("nan"), dtype=torch.float64, device="cuda")
+    lz = torch.full((K, d * npts), float("nan"), dtype=torch.float64, device="cuda")
+    lib.bsde_checkpoint_layers(plan, ws, b, ly, lz)
+    torch.cuda.synchronize()
+    ly, lz = ly.cpu().numpy(), lz.cpu().numpy().reshape(K, d, npts)
+    # row 0 is layer n_stop, the solve's own output
+    assert rel_err(ly[0], ios[b][2].cpu().numpy()) <= (0.0 if prec == "fp64" else 1e-7)
+    n2 = n_stop + K - 1
+    pb2 = dict(pb, n_t=n2, T=pb["T"] * n2 / N, n_stop=0)
+    y_r, z_r, rc2, _ = lib.solve(pb2, ly, lz)
+    assert rc2 == lib.BSDE_OK
+    e = max(rel_err(y_r, y_full), max(rel_err(z_r[c], z_full[c]) for c in range(d)))
+    print(f"  resumed vs uninterrupted: rel err {e:.3e}", flush=True)
+    assert e <= tol
+
+
+def test_checkpoint_resume(lib, orc):
+    from test_gpu_parity import TOL32
+
+    nx, nt = 3001, 40
+    bid = W.bidask_call_1d(n_x=nx, n_t=nt, half_width=twin_half_width(0.2, 0.5, nt, nx))
+    _resume_case(lib, orc, bid, 17, "fp64", 1e-12)
+    _resume_case(lib, orc, bid, 17, "fp32_comp", TOL32)
+    ex = W.bs_call_1d(n_x=2049, n_t=24, k=3, L=16, half_width=twin_half_width(0.2, 0.33, 24, 2049))
+    ex.problem["quad"] = "exact"
+    _resume_case(lib, orc, ex, 9, "fp64", 1e-12)
+    _resume_case(lib, orc, W.local_vol_call_1d(n_x=1201, n_t=24), 8, "fp64", 1e-12)
+    _resume_case(lib, orc, W.sine_1d(n_x=900, n_t=30, k=3), 11, "fp64", 1e-12,
+                 batch_with=W.sine_1d(n_x=500, n_t=20, k=2))
+    two = W.exchange_2d(n_x=49, n_t=12, k=3, L=6, rho=0.4)
+    _resume_case(lib, orc, two, 5, "fp64", 1e-12)
+    _resume_case(lib, orc, two, 5, "fp32_comp", TOL32)
