@@ -324,7 +324,8 @@ bsde_status bsde_initial_layers(const bsde_problem *pb, int substeps, void *ws, 
  * init_y / init_z: row r = layer n_stop + r (d = 1: K x n_x and K x n_x;
  * d = 2: K x n_x[0] n_x[1] and K x 2 x n_x[0] n_x[1]), caller-owned device
  * buffers.  A problem with n_t' = n_stop + K - 1 and T' = n_t' T / n_t (same
- * dt, same absolute times) started from them continues the sweep: it gives
+ * dt, same absolute times; a per-step coefficient table keeps its first n_t'
+ * rows) started from them continues the sweep: it gives
  * the layers of the uninterrupted solve (the FP32 form exports each stored
  * value plus its rounding residual, which the resumed solve splits back into
  * the same pair).  Asynchronous on the stream.

@@ -531,6 +531,8 @@ def _resume_case(lib, orc, wl, n_stop, prec, tol, batch_with=None):
     assert rel_err(ly[0], ios[b][2].cpu().numpy()) <= (0.0 if prec == "fp64" else 1e-7)
     n2 = n_stop + K - 1
     pb2 = dict(pb, n_t=n2, T=pb["T"] * n2 / N, n_stop=0)
+    if pb.get("coef_tab") is not None and len(pb["coef_tab"]) > 1:
+        pb2["coef_tab"] = pb["coef_tab"][:n2]  # a per-step table: the remaining steps' rows
     y_r, z_r, rc2, _ = lib.solve(pb2, ly, lz)
     assert rc2 == lib.BSDE_OK
     e = max(rel_err(y_r, y_full), max(rel_err(z_r[c], z_full[c]) for c in range(d)))
