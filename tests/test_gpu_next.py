@@ -556,3 +556,25 @@ def test_checkpoint_resume(lib, orc):
     two = W.exchange_2d(n_x=49, n_t=12, k=3, L=6, rho=0.4)
     _resume_case(lib, orc, two, 5, "fp64", 1e-12)
     _resume_case(lib, orc, two, 5, "fp32_comp", TOL32)
+
+
+def test_edge_cases_of_the_newer_paths(lib, orc):
+    from test_gpu_parity import TOL32
+
+    # exact expectations (Toeplitz sweep) on the smallest grids, a ragged last
+    # tile, and a single backward step (N = K)
+    for nx, nt, k in ((4, 12, 3), (5, 10, 2), (257, 9, 3), (300, 4, 4)):
+        wl = W.sine_1d(n_x=nx, n_t=nt, k=k)
+        wl.problem["quad"] = "exact"
+        _run(lib, orc, wl)
+    # tabulated coefficients (gather sweep) on the smallest grid and one step
+    for nx, nt in ((4, 8), (65, 3)):
+        wl = W.tabulated(W.ou_linear_1d(n_x=nx, n_t=nt, k=3), True)
+        _run(lib, orc, wl)
+    # the FP32 form in 2-D on the smallest grids of each interpolant and one step
+    for interp, n in (("spline", 4), ("bicubic_fd", 5)):
+        wl = W.exchange_2d(n_x=n, n_t=6, k=2, L=4, rho=0.3)
+        wl.problem["interp"] = interp
+        _run(lib, orc, wl, prec="fp32_comp", tol=TOL32)
+    wl = W.exchange_2d(n_x=33, n_t=3, k=3, L=5, rho=0.2)
+    _run(lib, orc, wl, prec="fp32_comp", tol=TOL32)
