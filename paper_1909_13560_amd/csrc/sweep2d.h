@@ -21,10 +21,11 @@
 namespace bsde {
 
 constexpr int kTile2R = 1;    // tile rows (axis 0)
-constexpr int kTile2C = 512;  // tile columns (axis 1): one lane each, eight wavefronts
-constexpr int kThreads2 = kTile2R * kTile2C;     // threads of a sweep2d block
+constexpr int kTile2C = 512;  // tile columns (axis 1)
+constexpr int kCols2 = 2;     // adjacent columns per lane: their nodes share (U, V) records
+constexpr int kThreads2 = kTile2R * kTile2C / kCols2;  // threads of a sweep2d block
 constexpr int kWaves2 = kThreads2 / 64;            // wavefronts per block (statistics slots)
-static_assert(kTile2C % 64 == 0 && kThreads2 <= 1024, "whole wavefronts per row");
+static_assert((kTile2C / kCols2) % 64 == 0 && kThreads2 <= 1024, "whole wavefronts per row");
 constexpr int kMaxReach2d = 240;  // widest axis-1 node spread of one axis-0 node row
 constexpr int kWin2 = kTile2C + kMaxReach2d + 2;  // widest LDS window (36 KB of (U, V))
 constexpr int kPcrTaps = 2 * (1 + 2 + 4 + 8 + 16) + 1;  // 63: reach of the truncated PCR

@@ -62,39 +62,50 @@ __device__ inline Node2 load_node2(const Node2 *p)
 // clamped to the box.  The natural spline gets that from its ghost records
 // alone (its second derivatives vanish at the ends); the bicubic's first
 // derivatives do not, so its weights B1, C1, D1 are dropped there.
+// A lane holds kCols2 = 2 adjacent columns: the node of the second sits one
+// record further, so the two read three (U, V) records per function, not four.
 template <int NF, bool CLAMP>
 __device__ inline void node2_accumulate(const Sweep2Args &a, const double2 *uv, const Node2 &nd,
-                                        int r, int e, int q, double &Y, double &Z1, double &Z2)
+                                        int r, int e, int q, double (&Y)[kCols2],
+                                        double (&Z1)[kCols2], double (&Z2)[kCols2])
 {
-    double B1 = nd.B1, C1 = nd.C1, D1 = nd.D1;
-    if (CLAMP && !(q >= 0 && q < a.n1 - 1)) B1 = C1 = D1 = 0.0;
-    double h[3];
+    double2 p[3][kCols2 + 1];
 #pragma unroll
-    for (int f = 0; f < 3; ++f) {
-        const double2 p0 = uv[uv_index(a, f, r, e)], p1 = uv[uv_index(a, f, r, e + 1)];
-        h[f] = fma(B1, p1.x - p0.x, fma(C1, p0.y, fma(D1, p1.y, p0.x)));
-    }
-    const double fh = f_linear2(a.drv, h[0], h[1], h[2]);
-    Y = fma(nd.cfy, fh, Y);
-    if (NF & 1) Y = fma(nd.cy, h[0], Y);
-    Z1 = fma(nd.cfz1, fh, fma(nd.cz, h[1], Z1));
-    Z2 = fma(nd.cfz2, fh, fma(nd.cz, h[2], Z2));
-    if (NF & 2) {
-        Z1 = fma(nd.cyz1, h[0], Z1);
-        Z2 = fma(nd.cyz2, h[0], Z2);
+    for (int f = 0; f < 3; ++f)
+#pragma unroll
+        for (int k = 0; k <= kCols2; ++k) p[f][k] = uv[uv_index(a, f, r, e + k)];
+#pragma unroll
+    for (int k = 0; k < kCols2; ++k) {
+        double B1 = nd.B1, C1 = nd.C1, D1 = nd.D1;
+        if (CLAMP && !(q + k >= 0 && q + k < a.n1 - 1)) B1 = C1 = D1 = 0.0;
+        double h[3];
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            const double2 p0 = p[f][k], p1 = p[f][k + 1];
+            h[f] = fma(B1, p1.x - p0.x, fma(C1, p0.y, fma(D1, p1.y, p0.x)));
+        }
+        const double fh = f_linear2(a.drv, h[0], h[1], h[2]);
+        Y[k] = fma(nd.cfy, fh, Y[k]);
+        if (NF & 1) Y[k] = fma(nd.cy, h[0], Y[k]);
+        Z1[k] = fma(nd.cfz1, fh, fma(nd.cz, h[1], Z1[k]));
+        Z2[k] = fma(nd.cfz2, fh, fma(nd.cz, h[2], Z2[k]));
+        if (NF & 2) {
+            Z1[k] = fma(nd.cyz1, h[0], Z1[k]);
+            Z2[k] = fma(nd.cyz2, h[0], Z2[k]);
+        }
     }
 }
 
-// The L nodes l1 of one axis-0 row of layer j, for the lane's point.  The
+// The L nodes l1 of one axis-0 row of layer j, for the lane's points.  The
 // node records come through scalar loads and the axis-1 offsets, one per
 // lane in mv, through readlane, so the only per-node LDS reads are the
 // (U, V) records; two nodes per iteration share one wait.
-// i1 - m1lo: the lane's column index minus the window's first offset, so that
-// a node's axis-1 cell is q = e + i1 - m1lo - c.
+// c: the lane's first window column, i1 its first grid column, so that a
+// node's axis-1 cell is q = e + m1lo + i1 - c.
 template <int NF, bool CLAMP>
 __device__ inline void row_nodes(const Sweep2Args &a, const double2 *uv, const Node2 *ntab,
-                                 int mv, int r, int c, int m1lo, int i1, double &Y, double &Z1,
-                                 double &Z2)
+                                 int mv, int r, int c, int m1lo, int i1, double (&Y)[kCols2],
+                                 double (&Z1)[kCols2], double (&Z2)[kCols2])
 {
     const int qoff = i1 - c;
     int l1 = 0;
@@ -116,7 +127,7 @@ __device__ inline void row_nodes(const Sweep2Args &a, const double2 *uv, const N
 template <bool CLAMP>
 __device__ inline void row_nodes_nf(int nf, const Sweep2Args &a, const double2 *uv,
                                     const Node2 *ntab, int mv, int r, int c, int m1lo, int i1,
-                                    double &Y, double &Z1, double &Z2)
+                                    double (&Y)[kCols2], double (&Z1)[kCols2], double (&Z2)[kCols2])
 {
     if (nf == 0)
         row_nodes<0, CLAMP>(a, uv, ntab, mv, r, c, m1lo, i1, Y, Z1, Z2);
@@ -151,9 +162,12 @@ __global__ void __launch_bounds__(kThreads2) sweep2d(const Sweep2Args a)
     const int idx = xcd_tile(blockIdx.x, gridDim.x);
     const int t0 = (idx / tiles1) * kTile2R, t1 = (idx % tiles1) * kTile2C;
     const int tid = threadIdx.x;
-    const int r = __builtin_amdgcn_readfirstlane(tid / kTile2C), c = tid % kTile2C;
+    constexpr int kLanesRow = kTile2C / kCols2;  // lanes per tile row
+    const int r = __builtin_amdgcn_readfirstlane(tid / kLanesRow), c = (tid % kLanesRow) * kCols2;
     const int S = a.K + 1;
-    double Y = 0.0, Z1 = 0.0, Z2 = 0.0;
+    double Y[kCols2], Z1[kCols2], Z2[kCols2];
+#pragma unroll
+    for (int k = 0; k < kCols2; ++k) Y[k] = Z1[k] = Z2[k] = 0.0;
     for (int j = 1; j <= a.K; ++j) {
         const E *slot = plane2<E>(a, (a.n + j) % S, 0);
         for (int l0 = 0; l0 < a.L; ++l0) {
@@ -200,54 +214,58 @@ __global__ void __launch_bounds__(kThreads2) sweep2d(const Sweep2Args a)
             __syncthreads();
         }
     }
-    // implicit y equation by Picard iteration from y^{n+1}
-    const int i0 = t0 + r, i1 = t1 + c;
-    const bool valid = i0 < a.n0 && i1 < a.n1;
+    // implicit y equation by Picard iteration from y^{n+1}, per point of the lane
     const E *prev = plane2<E>(a, (a.n + 1) % S, 0);
     E *out = plane2<E>(a, a.n % S, 0);
-    const size_t o = pidx(a, min(i0, a.n0 - 1), min(i1, a.n1 - 1));
-    double y = prev[o];
-    int it = 0;
-    bool conv = true;
-    if (a.picard_tol > 0.0) {
-        conv = false;
-        while (it < a.picard_max) {
-            const double yn = fma(a.h0, f_linear2(a.drv, y, Z1, Z2), Y);
-            ++it;
-            const double dy = fabs(yn - y);
-            y = yn;
-            if (dy <= a.picard_tol * fmax(1.0, fabs(y))) {
-                conv = true;
-                break;
-            }
-        }
-    } else {
-        for (; it < a.picard_max; ++it) y = fma(a.h0, f_linear2(a.drv, y, Z1, Z2), Y);
-    }
+    const int i0 = t0 + r;
     unsigned int it_max = 0, it_sum = 0, nonconv = 0;
-    if (valid) {
-        if constexpr (std::is_same<E, float>::value) {
-            // residuals of y^{n+K_y} (y recurrence) and of z^{n+1} (z recurrence)
-            const float *ry = plane2<float>(a, (a.n + a.Ky) % S, 12);
-            const float *rz = plane2<float>(a, (a.n + 1) % S, 13);
-            float *res = plane2<float>(a, a.n % S, 12);
-            store_fed_back2(out, res, o, y, ry[o]);
-            store_fed_back2(out + 4 * a.plane, res + a.plane, o, Z1, rz[o]);
-            store_fed_back2(out + 8 * a.plane, res + 2 * a.plane, o, Z2, rz[o + a.plane]);
+#pragma unroll
+    for (int k = 0; k < kCols2; ++k) {
+        const int i1 = t1 + c + k;
+        const bool valid = i0 < a.n0 && i1 < a.n1;
+        const size_t o = pidx(a, min(i0, a.n0 - 1), min(i1, a.n1 - 1));
+        double y = prev[o];
+        int it = 0;
+        bool conv = true;
+        if (a.picard_tol > 0.0) {
+            conv = false;
+            while (it < a.picard_max) {
+                const double yn = fma(a.h0, f_linear2(a.drv, y, Z1[k], Z2[k]), Y[k]);
+                ++it;
+                const double dy = fabs(yn - y);
+                y = yn;
+                if (dy <= a.picard_tol * fmax(1.0, fabs(y))) {
+                    conv = true;
+                    break;
+                }
+            }
         } else {
-            out[o] = y;
-            out[o + 4 * a.plane] = Z1;
-            out[o + 8 * a.plane] = Z2;
+            for (; it < a.picard_max; ++it) y = fma(a.h0, f_linear2(a.drv, y, Z1[k], Z2[k]), Y[k]);
         }
-        if (a.n == a.n_stop) {
-            const size_t np = (size_t)a.n0 * a.n1, k = (size_t)i0 * a.n1 + i1;
-            a.fin[k] = y;
-            a.fin[np + k] = Z1;
-            a.fin[2 * np + k] = Z2;
+        if (valid) {
+            if constexpr (std::is_same<E, float>::value) {
+                // residuals of y^{n+K_y} (y recurrence) and of z^{n+1} (z recurrence)
+                const float *ry = plane2<float>(a, (a.n + a.Ky) % S, 12);
+                const float *rz = plane2<float>(a, (a.n + 1) % S, 13);
+                float *res = plane2<float>(a, a.n % S, 12);
+                store_fed_back2(out, res, o, y, ry[o]);
+                store_fed_back2(out + 4 * a.plane, res + a.plane, o, Z1[k], rz[o]);
+                store_fed_back2(out + 8 * a.plane, res + 2 * a.plane, o, Z2[k], rz[o + a.plane]);
+            } else {
+                out[o] = y;
+                out[o + 4 * a.plane] = Z1[k];
+                out[o + 8 * a.plane] = Z2[k];
+            }
+            if (a.n == a.n_stop) {
+                const size_t np = (size_t)a.n0 * a.n1, kk = (size_t)i0 * a.n1 + i1;
+                a.fin[kk] = y;
+                a.fin[np + kk] = Z1[k];
+                a.fin[2 * np + kk] = Z2[k];
+            }
+            it_max = max(it_max, (unsigned int)it);
+            it_sum += it;
+            nonconv += conv ? 0u : 1u;
         }
-        it_max = it;
-        it_sum = it;
-        nonconv = conv ? 0u : 1u;
     }
     if (a.st_iter_max) {
         it_max = wave_max_u32(it_max);
