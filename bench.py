@@ -80,8 +80,8 @@ def bytes_per_point_step(pb: dict) -> float:
     return 32.0 * (K - 1) + 16.0 + 32.0
 
 
-KERNEL_SOURCES = ["capi.hip", "sweep.hip", "sweep2d.hip", "sweep2d.h", "device_common.h", "kernels.h", "plan_math.cpp",
-                  "plan_math.h"]
+# the sources of the 1-D sweep kernel, its launch and its workspace layout
+KERNEL_SOURCES = ["capi.hip", "sweep.hip", "device_common.h", "kernels.h", "plan_math.cpp", "plan_math.h"]
 
 
 def sources_sha1() -> str:

@@ -510,7 +510,6 @@ bsde::Sweep2Args sweep2_args(const Instance2 &in, char *ws, bool stats)
     a.Ky = in.pb.k_y;
     a.L = in.pb.L;
     a.n_stop = in.pb.n_stop;
-    a.win = in.win;
     a.rows = in.d_rows;
     a.nodes = in.d_nodes;
     a.m1 = in.d_m1;
@@ -521,6 +520,7 @@ bsde::Sweep2Args sweep2_args(const Instance2 &in, char *ws, bool stats)
     a.picard_tol = in.pb.picard_tol;
     a.zform = in.pb.z_form;
     a.interp = in.pb.interp;
+    a.half = (in.win + 1) / 2;
     a.fin = reinterpret_cast<double *>(ws + in.fin_off);
     if (stats) {
         unsigned long long *sum = reinterpret_cast<unsigned long long *>(ws + in.stat_off);

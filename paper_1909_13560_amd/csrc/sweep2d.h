@@ -27,7 +27,13 @@ constexpr int kThreads2 = kTile2R * kTile2C / kCols2;  // threads of a sweep2d b
 constexpr int kWaves2 = kThreads2 / 64;            // wavefronts per block (statistics slots)
 static_assert((kTile2C / kCols2) % 64 == 0 && kThreads2 <= 1024, "whole wavefronts per row");
 constexpr int kMaxReach2d = 240;  // widest axis-1 node spread of one axis-0 node row
-constexpr int kWin2 = kTile2C + kMaxReach2d + 2;  // widest LDS window (36 KB of (U, V))
+constexpr int kWin2 = kTile2C + kMaxReach2d + 2;  // widest LDS window columns
+// LDS window of the sweep: per tile row, the even window columns, then the
+// odd ones, each column a slot of the (U, V) records of the 3 functions
+// (48 bytes).  A lane's two columns are adjacent, so its node records e, e+1,
+// e+2 are two of one parity and one of the other, and the lanes of a
+// wavefront read slots 48 bytes apart: 16 consecutive lanes cover all 64
+// banks once (48 bytes = 12 banks, 12 and 64 share only the factor 4).
 constexpr int kPcrTaps = 2 * (1 + 2 + 4 + 8 + 16) + 1;  // 63: reach of the truncated PCR
 
 // Per (j, l0): the axis-0 offset of the node row and its spline weights, and
@@ -100,7 +106,6 @@ struct Sweep2Args {
     size_t plane;
     int n0, n1, npad1, pad0, pad1;
     int K, Ky, L, n, n_stop;
-    int win;                // LDS window columns: kTile2C + widest m1 spread of a row + 2
     const Node2Row *rows;   // K*L
     const Node2 *nodes;     // K*L*L
     const int *m1;          // K*L*L
@@ -110,6 +115,7 @@ struct Sweep2Args {
     double picard_tol;
     int zform;              // first term of the z equation: 0 E[z^{n+1}], 1 E[y^{n+1} dW]/dt
     int interp;             // bsde_interp: the natural spline or the bicubic
+    int half;               // LDS window columns of one parity: ceil(widest window / 2)
     double *fin;            // layer n_stop: y, z1, z2 planes of n0*n1
     unsigned int *st_iter_max;
     unsigned long long *st_iter_sum, *st_nonconv;
@@ -126,7 +132,7 @@ __host__ __device__ inline E *plane2(const Sweep2Args &a, int slot, int p)
 
 // The launchers take the element type of the ring planes: f32 = the FP32
 // form (float planes, residual planes), else double.
-size_t sweep2d_lds(int win);  // dynamic LDS of the sweep kernel
+size_t sweep2d_lds(int half);  // dynamic LDS of the sweep kernel
 hipError_t launch_sweep2d(bool f32, const Sweep2Args &a, hipStream_t s);
 // splines and ghosts of the layer in slot `slot`
 hipError_t launch_spline2d(bool f32, const Sweep2Args &a, int slot, const SplineFilter &f,

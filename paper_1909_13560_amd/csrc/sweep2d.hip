@@ -27,11 +27,11 @@ __device__ inline size_t pidx(const Sweep2Args &a, int i0, int i1)
     return (size_t)(i0 + a.pad0) * a.npad1 + (size_t)(i1 + a.pad1);
 }
 
-// (U, V) of function f, tile row rr, window column cc in the LDS window of
-// width a.win (dynamic: the widest axis-1 node spread of the plan).
-__device__ inline int uv_index(const Sweep2Args &a, int f, int rr, int cc)
+// (U, V) of function f, tile row rr, window column cc in the LDS window:
+// column slots of 3 functions, the even columns of a row first.
+__device__ inline int uv_index(int half, int f, int rr, int cc)
 {
-    return (f * kTile2R + rr) * a.win + cc;
+    return ((rr * 2 + (cc & 1)) * half + (cc >> 1)) * 3 + f;
 }
 
 // Node record through the constant address space: the address is the same
@@ -62,18 +62,27 @@ __device__ inline Node2 load_node2(const Node2 *p)
 // clamped to the box.  The natural spline gets that from its ghost records
 // alone (its second derivatives vanish at the ends); the bicubic's first
 // derivatives do not, so its weights B1, C1, D1 are dropped there.
-// A lane holds kCols2 = 2 adjacent columns: the node of the second sits one
-// record further, so the two read three (U, V) records per function, not four.
+// A lane holds kCols2 = 2 adjacent columns c, c+1 (c even): the node of the
+// second sits one record further, so the two read three (U, V) records per
+// function, not four: window columns c+s, c+s+1, c+s+2, i.e. column slots
+// c/2 + (s >> 1) and c/2 + (s >> 1) + 1 of the parity of s and one slot of
+// the other parity (s, the node's window offset, is wavefront-uniform).
+static_assert(kCols2 == 2, "the parity-split window serves two columns per lane");
 template <int NF, bool CLAMP>
-__device__ inline void node2_accumulate(const Sweep2Args &a, const double2 *uv, const Node2 &nd,
-                                        int r, int e, int q, double (&Y)[kCols2],
+__device__ inline void node2_accumulate(const Sweep2Args &a, const double2 *uvl, const Node2 &nd,
+                                        int s, int q, double (&Y)[kCols2],
                                         double (&Z1)[kCols2], double (&Z2)[kCols2])
+// uvl: function 0 of the lane's column slot c/2 (even half of its tile row)
 {
+    const int h0 = ((s & 1) * a.half + (s >> 1)) * 3;              // records 0 and 2
+    const int h1 = (((s + 1) & 1) * a.half + ((s + 1) >> 1)) * 3;  // record 1
     double2 p[3][kCols2 + 1];
 #pragma unroll
-    for (int f = 0; f < 3; ++f)
-#pragma unroll
-        for (int k = 0; k <= kCols2; ++k) p[f][k] = uv[uv_index(a, f, r, e + k)];
+    for (int f = 0; f < 3; ++f) {
+        p[f][0] = uvl[h0 + f];
+        p[f][1] = uvl[h1 + f];
+        p[f][2] = uvl[h0 + 3 + f];
+    }
 #pragma unroll
     for (int k = 0; k < kCols2; ++k) {
         double B1 = nd.B1, C1 = nd.C1, D1 = nd.D1;
@@ -100,43 +109,42 @@ __device__ inline void node2_accumulate(const Sweep2Args &a, const double2 *uv, 
 // node records come through scalar loads and the axis-1 offsets, one per
 // lane in mv, through readlane, so the only per-node LDS reads are the
 // (U, V) records; two nodes per iteration share one wait.
-// c: the lane's first window column, i1 its first grid column, so that a
-// node's axis-1 cell is q = e + m1lo + i1 - c.
+// uvl: the lane's slot in the window (see node2_accumulate), i1 its first
+// grid column, so that a node's window offset is s = m1 - m1lo and its
+// axis-1 cell q = m1 + i1.
 template <int NF, bool CLAMP>
-__device__ inline void row_nodes(const Sweep2Args &a, const double2 *uv, const Node2 *ntab,
-                                 int mv, int r, int c, int m1lo, int i1, double (&Y)[kCols2],
+__device__ inline void row_nodes(const Sweep2Args &a, const double2 *uvl, const Node2 *ntab,
+                                 int mv, int m1lo, int i1, double (&Y)[kCols2],
                                  double (&Z1)[kCols2], double (&Z2)[kCols2])
 {
-    const int qoff = i1 - c;
     int l1 = 0;
 #pragma unroll 1
     for (; l1 + 1 < a.L; l1 += 2) {
         const Node2 n0 = load_node2(ntab + l1), n1 = load_node2(ntab + l1 + 1);
-        const int e0 = c + __builtin_amdgcn_readlane(mv, l1) - m1lo;
-        const int e1 = c + __builtin_amdgcn_readlane(mv, l1 + 1) - m1lo;
-        node2_accumulate<NF, CLAMP>(a, uv, n0, r, e0, e0 + m1lo + qoff, Y, Z1, Z2);
-        node2_accumulate<NF, CLAMP>(a, uv, n1, r, e1, e1 + m1lo + qoff, Y, Z1, Z2);
+        const int m0 = __builtin_amdgcn_readlane(mv, l1), m1 = __builtin_amdgcn_readlane(mv, l1 + 1);
+        node2_accumulate<NF, CLAMP>(a, uvl, n0, m0 - m1lo, m0 + i1, Y, Z1, Z2);
+        node2_accumulate<NF, CLAMP>(a, uvl, n1, m1 - m1lo, m1 + i1, Y, Z1, Z2);
     }
     if (l1 < a.L) {
         const Node2 n0 = load_node2(ntab + l1);
-        const int e0 = c + __builtin_amdgcn_readlane(mv, l1) - m1lo;
-        node2_accumulate<NF, CLAMP>(a, uv, n0, r, e0, e0 + m1lo + qoff, Y, Z1, Z2);
+        const int m0 = __builtin_amdgcn_readlane(mv, l1);
+        node2_accumulate<NF, CLAMP>(a, uvl, n0, m0 - m1lo, m0 + i1, Y, Z1, Z2);
     }
 }
 
 template <bool CLAMP>
-__device__ inline void row_nodes_nf(int nf, const Sweep2Args &a, const double2 *uv,
-                                    const Node2 *ntab, int mv, int r, int c, int m1lo, int i1,
+__device__ inline void row_nodes_nf(int nf, const Sweep2Args &a, const double2 *uvl,
+                                    const Node2 *ntab, int mv, int m1lo, int i1,
                                     double (&Y)[kCols2], double (&Z1)[kCols2], double (&Z2)[kCols2])
 {
     if (nf == 0)
-        row_nodes<0, CLAMP>(a, uv, ntab, mv, r, c, m1lo, i1, Y, Z1, Z2);
+        row_nodes<0, CLAMP>(a, uvl, ntab, mv, m1lo, i1, Y, Z1, Z2);
     else if (nf == 1)
-        row_nodes<1, CLAMP>(a, uv, ntab, mv, r, c, m1lo, i1, Y, Z1, Z2);
+        row_nodes<1, CLAMP>(a, uvl, ntab, mv, m1lo, i1, Y, Z1, Z2);
     else if (nf == 2)
-        row_nodes<2, CLAMP>(a, uv, ntab, mv, r, c, m1lo, i1, Y, Z1, Z2);
+        row_nodes<2, CLAMP>(a, uvl, ntab, mv, m1lo, i1, Y, Z1, Z2);
     else
-        row_nodes<3, CLAMP>(a, uv, ntab, mv, r, c, m1lo, i1, Y, Z1, Z2);
+        row_nodes<3, CLAMP>(a, uvl, ntab, mv, m1lo, i1, Y, Z1, Z2);
 }
 
 }  // namespace
@@ -152,10 +160,14 @@ __device__ inline void store_fed_back2(float *val, float *res, size_t o, double 
 }
 
 // One time step: layer n from layers n+1..n+K.  Block = kTile2R x kTile2C points.
-// Dynamic LDS: (U, V) of 3 functions x kTile2R rows x a.win columns.  E: the
+// Dynamic LDS: (U, V) of 3 functions x kTile2R rows x 2 a.half columns.  E: the
 // element type of the ring planes; the arithmetic is double in both forms.
+// The occupancy hint holds the kernel at 89 VGPRs (five waves per SIMD, no
+// scratch); left to itself the compiler takes 131 (three waves) for the
+// parity-split window addressing.
 template <typename E>
-__global__ void __launch_bounds__(kThreads2) sweep2d(const Sweep2Args a)
+__global__ void __launch_bounds__(kThreads2) __attribute__((amdgpu_waves_per_eu(4)))
+sweep2d(const Sweep2Args a)
 {
     extern __shared__ double2 uv[];
     const int tiles1 = (a.n1 + kTile2C - 1) / kTile2C;
@@ -197,7 +209,7 @@ __global__ void __launch_bounds__(kThreads2) sweep2d(const Sweep2Args a)
                                          fma(C0, (double)mxx[o], fma(D0, (double)mxx[o1], v0)));
                     const double V = fma(B0, (double)myy[o1] - y0,
                                          fma(C0, (double)mxy[o], fma(D0, (double)mxy[o1], y0)));
-                    uv[uv_index(a, f, rr, cc)] = make_double2(U, V);
+                    uv[uv_index(a.half, f, rr, cc)] = make_double2(U, V);
                 }
             }
             __syncthreads();
@@ -207,10 +219,11 @@ __global__ void __launch_bounds__(kThreads2) sweep2d(const Sweep2Args a)
             // node cells can leave the grid along axis 1 (block-uniform)
             const bool clamp = a.interp == BSDE_INTERP_BICUBIC_FD &&
                                (t1 + row.m1lo < 0 || t1 + kTile2C + row.m1hi > a.n1 - 1);
+            const double2 *uvl = uv + uv_index(a.half, 0, r, c);
             if (clamp)
-                row_nodes_nf<true>(nf, a, uv, ntab, mv, r, c, row.m1lo, t1 + c, Y, Z1, Z2);
+                row_nodes_nf<true>(nf, a, uvl, ntab, mv, row.m1lo, t1 + c, Y, Z1, Z2);
             else
-                row_nodes_nf<false>(nf, a, uv, ntab, mv, r, c, row.m1lo, t1 + c, Y, Z1, Z2);
+                row_nodes_nf<false>(nf, a, uvl, ntab, mv, row.m1lo, t1 + c, Y, Z1, Z2);
             __syncthreads();
         }
     }
@@ -589,7 +602,7 @@ __global__ void __launch_bounds__(256) gather2d(const Sweep2Args a, double *__re
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-size_t sweep2d_lds(int win) { return (size_t)3 * kTile2R * win * sizeof(double2); }
+size_t sweep2d_lds(int half) { return (size_t)3 * kTile2R * 2 * half * sizeof(double2); }
 
 // Checkpoint export: layers n_stop .. n_stop + K - 1 into the initial-layer
 // layout (y: K x n0 n1; z: K x 2 x n0 n1), the FP32 form as value plus residual.
@@ -620,7 +633,7 @@ template <typename E>
 hipError_t launch_sweep2d_t(const Sweep2Args &a, hipStream_t s)
 {
     const int tiles = ((a.n0 + kTile2R - 1) / kTile2R) * ((a.n1 + kTile2C - 1) / kTile2C);
-    hipLaunchKernelGGL(sweep2d<E>, dim3(tiles), dim3(kThreads2), sweep2d_lds(a.win), s, a);
+    hipLaunchKernelGGL(sweep2d<E>, dim3(tiles), dim3(kThreads2), sweep2d_lds(a.half), s, a);
     return hipGetLastError();
 }
 
