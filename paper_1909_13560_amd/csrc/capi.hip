@@ -482,7 +482,8 @@ bsde_status build_instance2(const bsde_problem &p, Instance2 &in)
         }
     }
     in.h0 = p.k_y * in.dt * gy[0];
-    // ghosts: node reach plus the overhang of the last tile (4 rows, 64 columns)
+    // ghosts: node reach plus the overhang of the last tile (kTile2R rows,
+    // kTile2C columns)
     in.pad0 = std::max(0, -m0min) + 1;
     in.pad0r = std::max(0, m0max) + bsde::kTile2R + 1;
     in.pad1 = std::max(0, -m1min) + 1;
