@@ -224,7 +224,8 @@ typedef struct {
  * different d in one batch; BSDE_EUNSUPPORTED for a d = 2 problem with
  * vol[0][1] != 0, a driver other than BSDE_DRIVER_LINEAR, the FP32 form
  * with BSDE_ZFORM_YDW, exact expectations or state-dependent coefficients,
- * and for a d = 1 grid whose ring plane would reach 4 GiB (about 2.7e8 points
+ * or nodes of one axis-0 row spread over more than 240 cells along axis 1
+ * (the sweep's LDS window), and for a d = 1 grid whose ring plane would reach 4 GiB (about 2.7e8 points
  * in FP64, 5.4e8 in FP32); BSDE_ENOMEM, BSDE_EDEVICE.  *out is set only on
  * success.
  */

@@ -104,7 +104,7 @@ def test_plan_rejects_empty_batch():
     assert B.load().bsde_plan(None, 1, ctypes.byref(h)) == B.BSDE_EINVAL
 
 
-@pytest.mark.parametrize("change", ["vol01", "driver", "fp32_ydw", "exact"])
+@pytest.mark.parametrize("change", ["vol01", "driver", "fp32_ydw", "exact", "spread"])
 def test_plan_2d_reports_unsupported_variants(change):
     # valid two-dimensional problems outside the implemented path are refused
     # before any device call
@@ -115,6 +115,11 @@ def test_plan_2d_reports_unsupported_variants(change):
         pb["driver"] = "cubic"
     elif change == "fp32_ydw":
         pb.update(prec="fp32_comp", z_form="yW", k_y=1, k_z=1)
+    elif change == "spread":
+        # axis-1 cells of 0.006: the 8 nodes of a row at j = 3 spread over
+        # 2 a_max vol11 sqrt(2 j dt) / dx1 = 253 cells, past the 240 of the
+        # sweep's LDS window (561 points, 226 cells, passes this check)
+        pb["n_x"] = [33, 601]
     else:
         pb["quad"] = "exact"
     with pytest.raises(B.BsdeError) as e:
