@@ -469,6 +469,19 @@ def test_2d_short_rows(lib, orc):
     assert rel_err(z[1], zo[1]) <= TOL64
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32_comp"])
+def test_2d_widest_window(lib, orc, prec):
+    # 741 columns (two sweep tiles per row, the second ragged): the 16 x 16
+    # nodes of a row at j = 3 spread over 239 cells along axis 1, the widest
+    # row the sweep's 240-cell LDS window takes (its largest even/odd column
+    # halves), at stability ratio 14.7; six steps to the checkpoint
+    wl = W.exchange_2d(n_x=17, n_t=32, k=3, L=16, rho=0.3)
+    wl.problem["n_x"] = [17, 741]
+    y, z, yo, zo, *_ = run_both(lib, orc, wl, n_stop=24, prec=prec,
+                                tol=TOL64 if prec == "fp64" else TOL32)
+    assert rel_err(z[1], zo[1]) <= (TOL64 if prec == "fp64" else TOL32)
+
+
 def test_2d_basket_checkpoint(lib, orc):
     wl = W.basket_2d(n_x=65, n_t=12, k=3, L=16)
     y, z, yo, zo, *_ = run_both(lib, orc, wl, n_stop=4)
