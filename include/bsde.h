@@ -39,7 +39,7 @@ typedef enum {
     BSDE_EINVAL = 1,       /* invalid argument or problem                         */
     BSDE_ENOMEM = 2,       /* host or device allocation failed                    */
     BSDE_EDEVICE = 3,      /* a HIP call failed (no device, launch failure, ...)  */
-    BSDE_EUNSUPPORTED = 4, /* valid problem outside what this build implements    */
+    BSDE_EUNSUPPORTED = 4, /* valid problem outside what the library implements  */
     BSDE_ENOCONV = 5,      /* Picard did not reach the tolerance at some point    */
     BSDE_ENONFINITE = 6,   /* a non-finite value appeared in the output layer     */
     BSDE_ESCRATCH = 7      /* plan's workspace exceeds the static workspace       */
