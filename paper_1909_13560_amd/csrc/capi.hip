@@ -741,7 +741,9 @@ bsde_status enqueue_step(const bsde_plan_s &pl, const Group &g, char *ws, int s,
         else
             HIP_OK(bsde::launch_sweep_direct(c.P, g.f32, g.driver, a, blocks, c.lds, st));
         if (tm) HIP_OK(tm->mark(tm->sweep, st));
-        // natural spline of the new layer (the fused kernel does this in-kernel)
+        // natural spline of the new layer (the fused kernel does this in-kernel,
+        // and so does the split Toeplitz sweep's finishing kernel)
+        if (c.path == PATH_TOEPLITZ && c.G > 1) return BSDE_OK;
         if (tm) HIP_OK(tm->mark(tm->spline, st));
         HIP_OK(bsde::launch_spline(g.f32, step_args(pl, g, ws, s, false, true), 1,
                                    g.spline_prefix[act], st));
