@@ -562,8 +562,10 @@ def test_edge_cases_of_the_newer_paths(lib, orc):
     from test_gpu_parity import TOL32
 
     # exact expectations (Toeplitz sweep) on the smallest grids, a ragged last
-    # tile, and a single backward step (N = K)
-    for nx, nt, k in ((4, 12, 3), (5, 10, 2), (257, 9, 3), (300, 4, 4)):
+    # tile, a last tile of one point after a full one whose spline window
+    # (33 points either side) crosses the domain end, and a single backward
+    # step (N = K)
+    for nx, nt, k in ((4, 12, 3), (5, 10, 2), (257, 9, 3), (1025, 8, 3), (300, 4, 4)):
         wl = W.sine_1d(n_x=nx, n_t=nt, k=k)
         wl.problem["quad"] = "exact"
         _run(lib, orc, wl)
