@@ -81,7 +81,8 @@ struct Group {
     int *d_tile_inst = nullptr;    // grid tile -> instance (sized for P = 1)
     int *d_spline_inst = nullptr;  // spline tile -> instance
     int max_steps = 0;
-    size_t part_off = 0;  // Toeplitz split partial sums in the workspace
+    size_t part_off = 0;  // partial sums in the workspace: Toeplitz splits or direct chunks
+    int dchunks = 0;      // direct sweep: node chunks per tile in that layout (0: no region)
     int active(int s, const std::vector<Instance> &inst) const
     {
         int lo = 0, hi = (int)members.size();  // members[0..lo) have steps > s
@@ -571,15 +572,31 @@ SweepConfig fused_config(const std::vector<Instance> &all, const std::vector<int
     return c;
 }
 
+// Blocks per tile of the direct sweep with one point per lane: enough for
+// about 1024 blocks on a small grid, at most 16 and at most the node chunks
+// of a tile (its chunk sums go through the workspace).
+int direct_splits(const std::vector<Instance> &all, const std::vector<int> &members)
+{
+    long tiles = 0;
+    int chunks = 1;
+    for (int b : members) {
+        tiles += (all[b].nx + kBlock - 1) / kBlock;
+        chunks = std::max(chunks, bsde::direct_chunks(all[b].K, all[b].pb.L));
+    }
+    const long want = (1024 + std::max(tiles, 1L) - 1) / std::max(tiles, 1L);
+    return (int)std::max(1L, std::min<long>({want, 16L, (long)chunks}));
+}
+
+// S: blocks per tile (P = 1 only); 0 picks direct_splits.
 SweepConfig direct_config(const std::vector<Instance> &all, const std::vector<int> &members,
-                          bool f32, int P)
+                          bool f32, int P, int S = 0)
 {
     SweepConfig c;
     c.path = PATH_DIRECT;
     c.P = P;
-    (void)all;
-    (void)members;
     (void)f32;
+    const int smax = P == 1 ? direct_splits(all, members) : 1;
+    c.G = S > 0 ? std::min(S, smax) : smax;
     c.lds = 0;  // the direct kernel uses no LDS
     return c;
 }
@@ -637,15 +654,18 @@ SweepConfig default_config(const std::vector<Instance> &all, const Group &g, siz
             SweepConfig c = fused_config(all, g.members, g.f32, P, G, max_lds);
             if (c.lds) return c;
         }
-        if (std::sscanf(env, "direct:%d", &P) == 1 && bsde::direct_p_supported(P))
-            return direct_config(all, g.members, g.f32, P);
+        int S = 0;
+        if (std::sscanf(env, "direct:%d:%d", &P, &S) >= 1 && bsde::direct_p_supported(P))
+            return direct_config(all, g.members, g.f32, P, S);
     }
     const int ps[3] = {1, 2, 4};
     for (int P : ps) {
         SweepConfig c = fused_config(all, g.members, g.f32, P, 1, max_lds);
         if (c.lds) return c;
     }
-    return direct_config(all, g.members, g.f32, 2);
+    // the direct kernel: split over blocks on a small grid, else two points per lane
+    const SweepConfig c1 = direct_config(all, g.members, g.f32, 1);
+    return c1.G > 1 ? c1 : direct_config(all, g.members, g.f32, 2);
 }
 
 int sweep_tiles(const Instance &in, int P) { return (in.nx + kBlock * P - 1) / (kBlock * P); }
@@ -715,8 +735,11 @@ bsde::StepArgs step_args(const bsde_plan_s &pl, const Group &g, char *ws, int s,
     }
     a.s = s;
     a.stats = stats ? 1 : 0;
-    a.part = g.cfg.path == PATH_TOEPLITZ && g.cfg.G > 1 ? reinterpret_cast<double *>(ws + g.part_off)
-                                                         : nullptr;
+    a.part = (g.cfg.path == PATH_TOEPLITZ || g.cfg.path == PATH_DIRECT) && g.cfg.G > 1
+                 ? reinterpret_cast<double *>(ws + g.part_off)
+                 : nullptr;
+    a.dsplit = g.cfg.path == PATH_DIRECT ? g.cfg.G : 1;
+    a.dchunks = g.dchunks;
     return a;
 }
 
@@ -1322,8 +1345,10 @@ bsde_status bsde_plan(const bsde_problem *pb, int batch, bsde_plan_t *out)
         for (size_t k = 0; k < pl->groups.size(); ++k) {
             const Group &g = pl->groups[k];
             const SweepConfig &c = own[g.members[0]];
+            // the split count of the Toeplitz and direct sweeps follows the group
             if (g.f32 == in.f32 && g.driver == in.pb.driver && c.path == own[b].path &&
-                (c.path == PATH_TOEPLITZ || (c.P == own[b].P && c.G == own[b].G)))
+                (c.path == PATH_TOEPLITZ || (c.path == PATH_DIRECT && c.P == own[b].P) ||
+                 (c.P == own[b].P && c.G == own[b].G)))
                 gi = (int)k;
         }
         if (gi < 0) {
@@ -1451,6 +1476,19 @@ bsde_status bsde_plan(const bsde_problem *pb, int batch, bsde_plan_t *out)
         for (int b : g.members) tiles += sweep_tiles(pl->inst[b], 1);
         g.part_off = off;
         off += align_up(tiles * S * 2 * bsde::kToepTile * sizeof(double), 256);
+    }
+    // chunk sums of the split direct sweep: 2 kBlock doubles per tile and
+    // node chunk (groups that may take it: neither exact nor gathering)
+    for (Group &g : pl->groups) {
+        if (group_exact(pl->inst, g.members) || group_gathers(pl->inst, g.members)) continue;
+        if (direct_splits(pl->inst, g.members) == 1) continue;
+        size_t tiles = 0;
+        for (int b : g.members) {
+            tiles += sweep_tiles(pl->inst[b], 1);
+            g.dchunks = std::max(g.dchunks, bsde::direct_chunks(pl->inst[b].K, pl->inst[b].pb.L));
+        }
+        g.part_off = off;
+        off += align_up(tiles * g.dchunks * 2 * kBlock * sizeof(double), 256);
     }
     pl->stats_off = off;
     for (Instance &in : pl->inst) {
@@ -1681,7 +1719,10 @@ bsde_status bsde_autotune(bsde_plan_t plan, void *ws, const bsde_io *io, void *s
             }
         if (group_gathers(plan->inst, g.members)) cand.assign(1, SweepConfig{PATH_GATHER, 1, 1, 0});
         if (group_exact(plan->inst, g.members)) cand.assign(1, toeplitz_config(plan->inst, g.members));
-        if (cand.empty()) cand.push_back(direct_config(plan->inst, g.members, g.f32, 2));
+        if (cand.empty()) {
+            cand.push_back(direct_config(plan->inst, g.members, g.f32, 1));
+            cand.push_back(direct_config(plan->inst, g.members, g.f32, 2));
+        }
         float best = 0.0f;
         SweepConfig best_c = g.cfg;
         // Timed steps: the first, and three more spread over the group's

@@ -210,8 +210,22 @@ struct StepArgs {
     const int *tile_inst;  // grid tile -> descriptor index; NULL: every tile is of desc[0]
     int s;                 // step: each instance computes layer n0 - s
     int stats;             // bind the statistics slots
-    double *part;          // Toeplitz sweep split over S blocks per tile: partial sums
+    double *part;          // partial sums: Toeplitz sweep split over S blocks per tile, or
+                           // the node chunks of a split direct sweep
+    int dsplit;            // direct sweep: blocks per tile (1: no split)
+    int dchunks;           // direct sweep: node chunks per tile in the partial-sum layout
 };
+
+// The direct sweep sums a tile's nodes chunk by chunk: kDirectChunk
+// consecutive nodes of one layer, each chunk's sums from zero, the chunks
+// added in order (layer by layer).  Split over S blocks (small grids), block
+// s of a tile takes the chunks c = s (mod S) and the chunk sums meet in order
+// in a finishing kernel, so the results do not depend on S.
+constexpr int kDirectChunk = 16;
+__host__ __device__ constexpr int direct_chunks(int K, int L)
+{
+    return K * ((L + kDirectChunk - 1) / kDirectChunk);
+}
 
 // ---------------------------------------------------------------------------
 // Drivers f(t, y, z) (problem statement eq (2); Examples 1-3 of Section 5)

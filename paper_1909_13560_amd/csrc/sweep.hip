@@ -98,7 +98,8 @@ struct GlobalWindow {
 // plan sends to the direct kernel.
 template <int P, int DRV, bool F32, bool YW, typename Src>
 __device__ inline void layer_dispatch(const Src &src, const int *tm, int j, int l0, int LS,
-                                      const SweepArgs &a, Acc<P> &acc)
+                                      const SweepArgs &a, Acc<P> &acc, int lend)
+// nodes l = l0, l0 + LS, ... < lend of layer j
 {
     using Node = typename Prec<F32>::Node;
     const Driver<DRV, typename Prec<F32>::Raw> f(a.drv, (a.n + j) * a.dt);
@@ -108,17 +109,17 @@ __device__ inline void layer_dispatch(const Src &src, const int *tm, int j, int 
     if constexpr (YW) {
         if (j == 1 && a.zform) {
             if (last_y)
-                layer_nodes<P, DRV, kNodeLastY | kNodeYW, F32>(src, nodes, tm + row, l0, LS, a.L,
+                layer_nodes<P, DRV, kNodeLastY | kNodeYW, F32>(src, nodes, tm + row, l0, LS, lend,
                                                                f, acc);
             else
-                layer_nodes<P, DRV, kNodeYW, F32>(src, nodes, tm + row, l0, LS, a.L, f, acc);
+                layer_nodes<P, DRV, kNodeYW, F32>(src, nodes, tm + row, l0, LS, lend, f, acc);
             return;
         }
     }
     if (last_y)
-        layer_nodes<P, DRV, kNodeLastY, F32>(src, nodes, tm + row, l0, LS, a.L, f, acc);
+        layer_nodes<P, DRV, kNodeLastY, F32>(src, nodes, tm + row, l0, LS, lend, f, acc);
     else
-        layer_nodes<P, DRV, 0, F32>(src, nodes, tm + row, l0, LS, a.L, f, acc);
+        layer_nodes<P, DRV, 0, F32>(src, nodes, tm + row, l0, LS, lend, f, acc);
 }
 
 // LDS bytes of the window arrays of the fused kernel.
@@ -276,7 +277,7 @@ __device__ inline void fused_tile(const SweepArgs &a, int tile, char *smem)
         const LdsWindow<P, F32> src{wbase, kHalo - mlo,
                                     WinLayout<P>::kPad ? lane_pt + lane_pt / P : lane_pt};
         node_loop_priority(a.K - 1 - jj);
-        layer_dispatch<P, DRV, F32, false>(src, tm, j, grp, G, a, acc);
+        layer_dispatch<P, DRV, F32, false>(src, tm, j, grp, G, a, acc, a.L);
         __builtin_amdgcn_s_setprio(3);
         __syncthreads();  // the window is reused by the next layer
     }
@@ -314,15 +315,21 @@ __global__ void __launch_bounds__(kBlock * G) sweep_fused(const StepArgs s)
 
 // ---------------------------------------------------------------------------
 // Direct sweep: records from HBM/L2, P consecutive points per lane.
-// Dynamic LDS: node table only.
+// Dynamic LDS: node table only.  The nodes are summed chunk by chunk
+// (kDirectChunk nodes of one layer, each chunk from zero, the chunks added in
+// order); on a small grid a tile's chunks are split over s.dsplit blocks
+// (P = 1), which write the chunk sums for direct_finish.
 // ---------------------------------------------------------------------------
-template <int P, int DRV, bool F32>
+template <int P, int DRV, bool F32, bool SPLIT>
 __global__ void __launch_bounds__(kBlock) sweep_direct(const StepArgs s)
 {
+    static_assert(!SPLIT || P == 1, "split direct steps take one point per lane");
+    const int S = SPLIT ? s.dsplit : 1;
     const int idx = xcd_tile(blockIdx.x, gridDim.x);
-    const InstDesc &d = block_desc(s, idx);
+    const int tg = SPLIT ? idx / S : idx, sp = SPLIT ? idx - tg * S : 0;  // tile of the group, split
+    const InstDesc &d = block_desc(s, tg);
     const SweepArgs a = bind_instance(d, s.ws, s.s, s.stats != 0);
-    const int tile = idx - d.tile_base;
+    const int tile = tg - d.tile_base;
     __shared__ int tm[kMaxNodes];
     for (int i = threadIdx.x; i < a.K * a.L; i += kBlock) tm[i] = a.tab.m[i];
     __syncthreads();
@@ -331,11 +338,62 @@ __global__ void __launch_bounds__(kBlock) sweep_direct(const StepArgs s)
     Acc<P> acc;
 #pragma unroll
     for (int q = 0; q < P; ++q) acc.Y[q] = acc.Z[q] = 0.0;
-    for (int j = 1; j <= a.K; ++j) {
+    const int nch = (a.L + kDirectChunk - 1) / kDirectChunk;  // chunks per layer
+    for (int j = 1, c = 0; j <= a.K; ++j) {
         const GlobalWindow<F32> src{ring_slot<F32>(a, a.n + j), i0};
-        layer_dispatch<P, DRV, F32, true>(src, tm, j, 0, 1, a, acc);
+        for (int h = 0; h < nch; ++h, ++c) {
+            if (SPLIT && c % S != sp) continue;
+            Acc<P> ch;
+#pragma unroll
+            for (int q = 0; q < P; ++q) ch.Y[q] = ch.Z[q] = 0.0;
+            layer_dispatch<P, DRV, F32, true>(src, tm, j, h * kDirectChunk, 1, a, ch,
+                                              min(a.L, (h + 1) * kDirectChunk));
+            if constexpr (SPLIT) {
+                double *p = s.part + ((size_t)tg * s.dchunks + c) * 2 * kBlock;
+                p[threadIdx.x] = ch.Y[0];
+                p[kBlock + threadIdx.x] = ch.Z[0];
+            } else {
+#pragma unroll
+                for (int q = 0; q < P; ++q) {
+                    acc.Y[q] += ch.Y[q];
+                    acc.Z[q] += ch.Z[q];
+                }
+            }
+        }
     }
-    finish_points<P, DRV, F32>(a, first, acc, (tile * kBlock + (int)threadIdx.x) >> 6);
+    if constexpr (!SPLIT)
+        finish_points<P, DRV, F32>(a, first, acc, (tile * kBlock + (int)threadIdx.x) >> 6);
+}
+
+// A split direct step: the chunk sums of a tile added in chunk order, then
+// the implicit y equation (Picard) of its points.  Loads go out four chunks
+// at a time.
+template <int DRV, bool F32>
+__global__ void __launch_bounds__(kBlock) direct_finish(const StepArgs s)
+{
+    const int tg = xcd_tile(blockIdx.x, gridDim.x);
+    const InstDesc &d = block_desc(s, tg);
+    const SweepArgs a = bind_instance(d, s.ws, s.s, s.stats != 0);
+    const int tile = tg - d.tile_base, tid = threadIdx.x;
+    const int C = direct_chunks(a.K, a.L);
+    const double *p = s.part + (size_t)tg * s.dchunks * 2 * kBlock + tid;
+    Acc<1> acc;
+    acc.Y[0] = acc.Z[0] = 0.0;
+    for (int c0 = 0; c0 < C; c0 += 4) {
+        double vy[4], vz[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            vy[q] = c0 + q < C ? p[(size_t)(c0 + q) * 2 * kBlock] : 0.0;
+            vz[q] = c0 + q < C ? p[(size_t)(c0 + q) * 2 * kBlock + kBlock] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (c0 + q < C) {
+                acc.Y[0] += vy[q];
+                acc.Z[0] += vz[q];
+            }
+    }
+    finish_points<1, DRV, F32>(a, tile * kBlock + tid, acc, (tile * kBlock + tid) >> 6);
 }
 
 // ---------------------------------------------------------------------------
@@ -609,8 +667,19 @@ hipError_t launch_fused_t(const StepArgs &a, int blocks, size_t lds, hipStream_t
 template <int P, int DRV, bool F32>
 hipError_t launch_direct_t(const StepArgs &a, int blocks, size_t lds, hipStream_t s)
 {
-    hipLaunchKernelGGL((sweep_direct<P, DRV, F32>), dim3(blocks), dim3(kBlock), lds, s, a);
-    return hipGetLastError();
+    if (a.dsplit == 1) {
+        hipLaunchKernelGGL((sweep_direct<P, DRV, F32, false>), dim3(blocks), dim3(kBlock), lds, s, a);
+        return hipGetLastError();
+    }
+    if constexpr (P == 1) {
+        hipLaunchKernelGGL((sweep_direct<1, DRV, F32, true>), dim3(blocks * a.dsplit), dim3(kBlock),
+                           lds, s, a);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((direct_finish<DRV, F32>), dim3(blocks), dim3(kBlock), 0, s, a);
+        return hipGetLastError();
+    }
+    return hipErrorInvalidValue;  // split steps take one point per lane
 }
 
 template <int P, int DRV, bool F32>

@@ -61,9 +61,11 @@ def test_bid_ask_put_lending_branch(lib, orc, prec, sign):
 # bsde_autotune chooses among the same shapes)
 # ----------------------------------------------------------------------------
 
+# direct: (P, blocks per tile); one point per lane splits a tile's node chunks
+# over up to four blocks on this grid (4 layers of one 16-node chunk)
 SHAPES = [("fused", 1, 1), ("fused", 1, 2), ("fused", 2, 1), ("fused", 2, 2),
-          ("fused", 4, 1), ("fused", 4, 2), ("direct", 1, 1), ("direct", 2, 1),
-          ("direct", 4, 1)]
+          ("fused", 4, 1), ("fused", 4, 2), ("direct", 1, 1), ("direct", 1, 4),
+          ("direct", 2, 1), ("direct", 4, 1)]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32_comp"])
@@ -78,7 +80,7 @@ def test_every_kernel_shape(lib, orc, monkeypatch, path, P, G, prec):
     wl = W.bidask_call_1d(n_x=nx, n_t=nt, half_width=twin_half_width(0.2, 0.5, nt, nx))
     pb = dict(wl.problem)
     pb["prec"] = prec
-    spec = f"fused:{P}:{G}" if path == "fused" else f"direct:{P}"
+    spec = f"{path}:{P}:{G}"
     monkeypatch.setenv("BSDE_SWEEP", spec)
     print(f"[case] shape {spec} {prec}", flush=True)
     plan = lib.bsde_plan(pb)
@@ -103,6 +105,26 @@ def test_every_kernel_shape(lib, orc, monkeypatch, path, P, G, prec):
     ey, ez = rel_err(y, yo), rel_err(z, zo[0])
     print(f"  rel err y {ey:.3e} z {ez:.3e}", flush=True)
     assert ey <= tol and ez <= tol
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_comp"])
+def test_direct_sweep_split_gives_the_same_bits(lib, monkeypatch, prec):
+    # the direct sweep sums its nodes chunk by chunk in a fixed order, so the
+    # number of blocks a tile's chunks are split over, and the points per
+    # lane, change no result bit (stability ratio 40: the direct kernel)
+    nx, nt = 3001, 10
+    wl = W.bidask_call_1d(n_x=nx, n_t=nt, half_width=twin_half_width(0.2, 0.5, nt, nx, 40.0))
+    pb = dict(wl.problem, prec=prec)
+    iy, iz = wl.init_layers()
+    outs = []
+    for spec in ("direct:1:1", "direct:1:3", "direct:1:4", "direct:2:1"):
+        monkeypatch.setenv("BSDE_SWEEP", spec)
+        print(f"[case] {spec} {prec}", flush=True)
+        y, z, rc, st = lib.solve(pb, iy, iz)
+        assert rc == lib.BSDE_OK
+        outs.append((y, z))
+    for y, z in outs[1:]:
+        assert np.array_equal(y, outs[0][0]) and np.array_equal(z, outs[0][1])
 
 
 # ----------------------------------------------------------------------------
