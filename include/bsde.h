@@ -362,11 +362,12 @@ bsde_status bsde_solve_batched_static(bsde_plan_t plan, const bsde_io *io, void 
 /* Per-kernel device time of one solve, from hipEvent pairs around launches. */
 typedef struct {
     double sweep_ms;      /* summed duration of the sweep launches (one per step
-                             and group)                                         */
+                             and group, with the launch that adds a split
+                             sweep's partial sums)                              */
     int sweep_launches;
     double spline_ms;     /* summed duration of the separate spline launches of
-                             the loop (0 launches when the sweep kernel builds
-                             the splines itself)                                  */
+                             the loop (0 launches when the sweep's own kernels
+                             build the splines: fused windows, split Toeplitz) */
     int spline_launches;
     int path;             /* sweep kernel of group 0: 0 = LDS-staged windows with
                              the spline of the newest layer in-kernel, 1 = direct
@@ -376,8 +377,9 @@ typedef struct {
                              on matrix cores (BSDE_QUAD_EXACT)                   */
     int points_per_lane;  /* grid points per lane of the sweep kernel            */
     int node_groups;      /* thread groups sharing the nodes of one tile; for
-                             path 4 the blocks that split one tile's band (their
-                             partial sums are added by a second launch when > 1) */
+                             paths 1 and 4 the blocks that split one tile's node
+                             chunks or band (their partial sums are added by a
+                             second launch when > 1)                             */
     int blocks;           /* tiles of the first sweep launch of group 0          */
     long long lds_bytes;  /* dynamic LDS per block of the sweep kernel           */
 } bsde_kernel_times;
@@ -403,7 +405,8 @@ typedef struct {
  * bsde_autotune -- choose the sweep kernel shape of every group of the plan
  * by measurement: the initial layers of io are loaded into ws, and for each
  * shape that fits (fused kernel with 1, 2 or 4 points per lane and 1 or 2
- * node groups; the direct kernel when none fits) the group's first time step
+ * node groups; when none fits, the direct kernel with one point per lane,
+ * split over blocks on a small grid, and with two) the group's first time step
  * and three more spread over its steps (so a batch's shrinking set of active
  * instances counts) are run `reps` times, replayed from a captured graph as
  * a solve would run them (directly when BSDE_GRAPH=0), and timed with
